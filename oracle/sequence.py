@@ -1,0 +1,87 @@
+"""Per-system driver of the sequence (test infrastructure, see package header).
+
+Alg. 1 produces one Poisson system per Runge-Kutta stage; Alg. 2 solves each one from an
+initial guess taken from the subspace of previous solutions; Alg. 4 keeps that subspace as
+an exponentially weighted sketch updated after every solve. Guess modes: 'cold' (x0 = 0),
+'previous' (x0 = the last solution: the paper's baseline, Sec. 5.1) and 'ewma'
+(x0 = Y z* once a solution has been stored and ``n_init`` solves have run; until then the
+previous solution, as the paper warms the history up with the baseline, Sec. 5.1).
+Every returned solution is stored, converged or not.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import gmres as _gmres
+from . import precond as _precond
+from .discretization import Grid, mixed_stage_operator
+from .subspace import TAU_DROP, EWMASketch, guess
+
+
+@dataclass
+class Options:
+    restart: int = 30
+    max_restarts: int = 200
+    rtol: float = 1e-8
+    precond: str = "mg"  # none | line | mg
+    nu1: int = 1
+    nu2: int = 1
+    omega: float = 0.5
+    max_levels: int = 32
+    guess: str = "ewma"  # cold | previous | ewma
+    k: int = 8
+    r: float = 0.9
+    seed: int = 0
+    n_init: int = 0
+    tau_drop: float = TAU_DROP
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    info: _gmres.Info
+    rank: int = 0
+    x0: np.ndarray = field(default=None, repr=False)
+
+
+class Simulation:
+    def __init__(self, nx, nz, bc, length, h_phys, opts: Options):
+        self.grid = Grid(nx, nz, bc, length)
+        self.h = np.asarray(h_phys, dtype=np.float64)
+        self.opts = opts
+        self.minv = _precond.make(self.grid, self.h, opts.precond, opts.nu1, opts.nu2, opts.omega,
+                                  opts.max_levels)
+        self.sketch = EWMASketch(self.grid.n, opts.k, opts.r, opts.seed) if opts.guess == "ewma" else None
+        self.x_prev = None
+        self.solves = 0
+
+    @classmethod
+    def from_workload(cls, w, **overrides):
+        kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, k=w.k, r=w.r, seed=w.seed)
+        kw.update(overrides)
+        return cls(w.nx, w.nz, w.bc, w.length, w.depth(), Options(**kw))
+
+    def operator(self, eta_prev, eta_cur):
+        return mixed_stage_operator(self.grid, self.h, eta_prev, eta_cur)
+
+    def initial_guess(self, A, b):
+        o, n = self.opts, self.grid.n
+        prev = self.x_prev if self.x_prev is not None else np.zeros(n)
+        if o.guess == "cold":
+            return np.zeros(n), 0
+        if o.guess == "previous" or self.sketch.pushes == 0 or self.solves < o.n_init:
+            return prev.copy(), 0
+        return guess(A, self.sketch.Y, b, o.tau_drop)
+
+    def solve(self, eta_prev, eta_cur, b) -> Result:
+        A = self.operator(eta_prev, eta_cur)
+        x0, rank = self.initial_guess(A, b)
+        x, info = _gmres.gmres(A, b, x0, self.minv, self.opts.restart, self.opts.rtol,
+                               self.opts.max_restarts)
+        if self.sketch is not None:
+            self.sketch.push(x)
+        self.x_prev = x
+        self.solves += 1
+        return Result(x=x, info=info, rank=rank, x0=x0)

@@ -1,0 +1,309 @@
+"""Seeded synthetic inputs for the sequence of sigma-transformed Poisson systems.
+
+For a named workload this module produces
+
+* the still-water depth h at the physical columns,
+* the free-surface elevation eta(x, tau) at the physical columns, sampled at the stage
+  times of the low-storage Runge-Kutta scheme LSERK45 (Carpenter & Kennedy 1994; the
+  paper's time integrator, Sec. 3 eqs. for the 2N-storage update and Sec. 5 setup),
+* a manufactured pressure p*(x, sigma, tau) at every grid node.
+
+It holds none of the solver's arithmetic: no difference weights, no operator, no Krylov
+or subspace step. The right-hand side b = A p* is formed by whichever side is exercised
+(the oracle in tests, the library's own operator in the benchmark).
+
+Grid conventions (shared by both sides because they define the inputs):
+
+* ``nx`` counts points on [0, L] inclusive. Periodic: ``ncol = nx - 1`` distinct columns
+  at x_c = c*dx. Walls: ``ncol = nx + 2``; column 0 and ``ncol - 1`` are ghost columns at
+  x = -dx and L + dx, physical column p sits at index p + 1, x = p*dx.
+* ``nz`` counts sigma levels from bed (sigma = 0) to surface (sigma = 1) inclusive; one
+  ghost level below the bed at sigma = -1/(nz-1). ``nl = nz + 1`` levels in total, level 0
+  is the ghost level, level ``nz`` the surface.
+* A node (level j, column c) has flat index ``j*ncol + c`` (x fastest).
+
+Inputs h and eta are given at the physical columns only (``nx - 1`` values periodic,
+``nx`` values walls); both sides extend them to ghost columns by even reflection.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from fractions import Fraction
+
+import numpy as np
+
+G = 9.81
+
+# LSERK45: five-stage, fourth-order, 2N-storage coefficients of Carpenter & Kennedy (1994),
+# the scheme the paper integrates with (Sec. 5). K_i = A_i K_{i-1} + dt f(t + C_i dt, u_{i-1});
+# u_i = u_{i-1} + B_i K_i. Only the stage times C_i shape the synthetic sequence.
+LSERK45_A = (
+    Fraction(0),
+    Fraction(-567301805773, 1357537059087),
+    Fraction(-2404267990393, 2016746695238),
+    Fraction(-3550918686646, 2091501179385),
+    Fraction(-1275806237668, 842570457699),
+)
+LSERK45_B = (
+    Fraction(1432997174477, 9575080441755),
+    Fraction(5161836677717, 13612068292357),
+    Fraction(1720146321549, 2090206949498),
+    Fraction(3134564353537, 4481467310338),
+    Fraction(2277821191437, 14882151754819),
+)
+LSERK45_C = (
+    Fraction(0),
+    Fraction(1432997174477, 9575080441755),
+    Fraction(2526269341429, 6820363962896),
+    Fraction(2006345519317, 3224310063776),
+    Fraction(2802321613138, 2924317926251),
+)
+STAGES = 5
+
+
+def battjes_max_steepness(kh: float) -> float:
+    """Limiting steepness (H/L)_max = 0.1401 tanh(0.8863 kh) (Sec. 5.1, Battjes 1974)."""
+    return 0.1401 * math.tanh(0.8863 * kh)
+
+
+def _smootherstep(t):
+    t = np.clip(t, 0.0, 1.0)
+    return t * t * t * (10.0 - 15.0 * t + 6.0 * t * t)
+
+
+def _wavenumber(omega: float, depth: np.ndarray) -> np.ndarray:
+    """Solve omega^2 = g k tanh(k h) for k by Newton's method (linear dispersion)."""
+    depth = np.asarray(depth, dtype=np.float64)
+    k = np.full_like(depth, omega * omega / G)
+    k = np.maximum(k, omega / np.sqrt(G * depth))
+    for _ in range(60):
+        t = np.tanh(k * depth)
+        f = G * k * t - omega * omega
+        df = G * t + G * k * depth * (1.0 - t * t)
+        k = k - f / df
+    return k
+
+
+@dataclass
+class Workload:
+    """One synthetic simulation: geometry, surface motion and solver sizes."""
+
+    name: str
+    nx: int
+    nz: int
+    bc: str  # "periodic" | "walls"
+    length: float
+    dtau: float
+    nsys: int
+    seed: int
+    restart: int = 30
+    k: int = 8
+    r: float = 0.9
+    rtol: float = 1e-8
+    precond: str = "mg"
+    kind: str = "stream"  # "stream" | "bar"
+    params: dict = field(default_factory=dict)
+
+    # ---- grid ---------------------------------------------------------------
+    @property
+    def ncol(self) -> int:
+        return self.nx - 1 if self.bc == "periodic" else self.nx + 2
+
+    @property
+    def nl(self) -> int:
+        return self.nz + 1
+
+    @property
+    def n(self) -> int:
+        return self.ncol * self.nl
+
+    @property
+    def dx(self) -> float:
+        return self.length / (self.nx - 1)
+
+    @property
+    def nphys(self) -> int:
+        """Number of physical columns at which h and eta are given."""
+        return self.nx - 1 if self.bc == "periodic" else self.nx
+
+    def x_phys(self) -> np.ndarray:
+        return np.arange(self.nphys, dtype=np.float64) * self.dx
+
+    def x_nodes_reflected(self) -> np.ndarray:
+        """x of every column with ghost columns mapped onto their mirror image."""
+        if self.bc == "periodic":
+            return self.x_phys()
+        xp = self.x_phys()
+        return np.concatenate(([xp[1]], xp, [xp[-2]]))
+
+    def sigma_levels(self) -> np.ndarray:
+        return (np.arange(self.nl, dtype=np.float64) - 1.0) / (self.nz - 1)
+
+    # ---- geometry and surface ------------------------------------------------
+    def depth(self, x=None) -> np.ndarray:
+        x = self.x_phys() if x is None else np.asarray(x, dtype=np.float64)
+        if self.kind == "bar":
+            p = self.params
+            h0, hb = p["h0"], p["h_bar"]
+            x1, x2, x3, x4 = p["bar_x"]
+            h = np.full_like(x, h0)
+            up = (x > x1) & (x < x2)
+            h[up] = h0 + (hb - h0) * (x[up] - x1) / (x2 - x1)
+            h[(x >= x2) & (x <= x3)] = hb
+            dn = (x > x3) & (x < x4)
+            h[dn] = hb + (h0 - hb) * (x[dn] - x3) / (x4 - x3)
+            return h
+        return np.full_like(x, self.params["h0"])
+
+    def surface(self, tau: float, x=None) -> np.ndarray:
+        x = self.x_phys() if x is None else np.asarray(x, dtype=np.float64)
+        p = self.params
+        if self.kind == "bar":
+            th = np.interp(x, p["theta_x"], p["theta"])
+            amp = np.interp(x, p["theta_x"], p["amp"])
+            env = _smootherstep(x / p["gen_len"]) * _smootherstep((self.length - x) / p["abs_len"])
+            ramp = float(_smootherstep(tau / (2.0 * p["period"])))
+            return amp * env * ramp * np.cos(th - p["omega"] * tau)
+        k0, c = p["kappa0"], p["celerity"]
+        xi = x - c * tau
+        eta = np.zeros_like(x)
+        for q, (a, ph) in enumerate(zip(p["amps"], p["phases"]), start=1):
+            eta += a * np.cos(q * k0 * xi + ph)
+        if p.get("modulation", 0.0):
+            eta *= 1.0 + p["modulation"] * np.cos(2.0 * math.pi * xi / self.length + p["mod_phase"])
+        return eta
+
+    def local_wavenumber(self, x=None) -> np.ndarray:
+        x = self.x_phys() if x is None else np.asarray(x, dtype=np.float64)
+        if self.kind == "bar":
+            return _wavenumber(self.params["omega"], self.depth(x))
+        return np.full_like(x, self.params["kappa0"])
+
+    def pressure(self, tau: float) -> np.ndarray:
+        """Manufactured p* = g eta (1 - sigma) cosh(k sigma d) / cosh(k d) at every node.
+
+        Smooth in x, sigma and tau, zero on the free surface, and nonlinear in eta through
+        d = h + eta, so a history of these fields is not exactly low-rank.
+        """
+        xr = self.x_nodes_reflected()
+        eta = self.surface(tau, xr)
+        d = self.depth(xr) + eta
+        kap = self.local_wavenumber(xr)
+        s = self.sigma_levels()[:, None]
+        p = G * eta[None, :] * (1.0 - s) * np.cosh(kap[None, :] * s * d[None, :]) / np.cosh(kap * d)[None, :]
+        return np.ascontiguousarray(p.reshape(-1))
+
+    # ---- the sequence of systems -----------------------------------------------
+    def stage_times(self, s: int) -> tuple[float, float]:
+        """(tau_prev, tau_cur) of system s: stage i of step n uses the surfaces of stages
+        i-1 and i, i.e. times tau_n + c_i dtau and tau_n + c_{i+1} dtau with c_6 = 1."""
+        n, i = divmod(s, STAGES)
+        c = [float(v) for v in LSERK45_C] + [1.0]
+        t0 = n * self.dtau + self.params.get("tau0", 0.0)
+        return t0 + c[i] * self.dtau, t0 + c[i + 1] * self.dtau
+
+    def system(self, s: int):
+        """Inputs of system s: (eta_prev, eta_cur, p_star) at physical columns / all nodes."""
+        tp, tc = self.stage_times(s)
+        return self.surface(tp), self.surface(tc), self.pressure(tp)
+
+
+def _stream(name, nx, nz, kh, length_wavelengths, nharm, steepness, seed, nsys, restart, k, r,
+            modulation=0.0, h0=1.0, precond="mg"):
+    kappa0 = kh / h0
+    lam = 2.0 * math.pi / kappa0
+    length = length_wavelengths * lam
+    rng = np.random.default_rng(seed)
+    phases = rng.uniform(0.0, 2.0 * math.pi, nharm)
+    mod_phase = float(rng.uniform(0.0, 2.0 * math.pi))
+    amps = np.array([0.3 ** q for q in range(nharm)])
+    celerity = math.sqrt(G * math.tanh(kappa0 * h0) / kappa0)
+    dx = length / (nx - 1)
+    w = Workload(name=name, nx=nx, nz=nz, bc="periodic", length=length, dtau=0.5 * dx / celerity,
+                 nsys=nsys, seed=seed, restart=restart, k=k, r=r, kind="stream", precond=precond,
+                 params=dict(h0=h0, kappa0=kappa0, celerity=celerity, amps=amps, phases=phases,
+                             modulation=modulation, mod_phase=mod_phase))
+    # scale the amplitudes so that (max - min) eta = steepness * carrier wavelength
+    eta = w.surface(0.0, np.linspace(0.0, length, 64 * (nx - 1), endpoint=False))
+    w.params["amps"] = amps * (steepness * lam / (eta.max() - eta.min()))
+    w.params["steepness"] = steepness
+    return w
+
+
+def _bar(name, nx, nz, seed, nsys, restart, k, r, scale=1.0, a0=0.01, dtau=0.025):
+    """Submerged-bar flume (Sec. 5.2 figure of the flume): length 29 m, depth 0.4 m, bar
+    crest depth 0.1 m between 12 and 14 m, slopes 1:20 up (6-12 m) and 1:10 down (14-17 m),
+    generation zone [0, 3] m, absorption zone [25, 29] m. ``scale`` shrinks every length
+    (and the period by sqrt(scale), keeping kh) for smaller test cases."""
+    period = 1.96 * math.sqrt(scale)
+    omega = 2.0 * math.pi / period
+    length = 29.0 * scale
+    w = Workload(name=name, nx=nx, nz=nz, bc="walls", length=length, dtau=dtau * math.sqrt(scale),
+                 nsys=nsys, seed=seed, restart=restart, k=k, r=r, kind="bar", precond="mg",
+                 params=dict(h0=0.4 * scale, h_bar=0.1 * scale,
+                             bar_x=tuple(v * scale for v in (6.0, 12.0, 14.0, 17.0)),
+                             period=period, omega=omega, gen_len=3.0 * scale, abs_len=4.0 * scale,
+                             tau0=2.0 * period))
+    # phase = integral of the local wavenumber, WKB shoaling amplitude a0*sqrt(cg(0)/cg(x))
+    xf = np.linspace(0.0, length, 20 * (nx - 1) + 1)
+    hf = w.depth(xf)
+    kf = _wavenumber(omega, hf)
+    theta = np.concatenate(([0.0], np.cumsum(0.5 * (kf[1:] + kf[:-1]) * np.diff(xf))))
+    theta += np.random.default_rng(seed).uniform(0.0, 2.0 * math.pi)
+    cg = 0.5 * omega / kf * (1.0 + 2.0 * kf * hf / np.sinh(2.0 * kf * hf))
+    w.params.update(theta_x=xf, theta=theta, amp=a0 * scale * np.sqrt(cg[0] / cg))
+    return w
+
+
+def serving_mix(nsims: int = 256, seed: int = 5, nsys: int = 50, nx_range=(257, 8193),
+                nz_choices=(9, 17, 33)) -> list[Workload]:
+    """Independent simulations of different sizes for the continuous-batching server:
+    nx uniform in nx_range rounded to 64 q + 1, nz from nz_choices, flat (periodic) or
+    submerged-bar (walls, bar scaled to the domain) bathymetry, H/L uniform in [0.01, 0.08],
+    history rank uniform in 8..16, forgetting factor 0.9."""
+    rng = np.random.default_rng(seed)
+    sims = []
+    for i in range(nsims):
+        q = int(rng.integers((nx_range[0] - 1) // 64, (nx_range[1] - 1) // 64 + 1))
+        nx = 64 * q + 1
+        nz = int(rng.choice(nz_choices))
+        k = int(rng.integers(8, 17))
+        steep = float(rng.uniform(0.01, 0.08))
+        if rng.uniform() < 0.5:
+            kh = float(rng.uniform(0.5, 2.0))
+            w = _stream(f"serve{i:03d}", nx, nz, kh, max(1, (nx - 1) // 256), 4, steep,
+                        seed * 1000 + i, nsys, 30, k, 0.9)
+        else:
+            w = _bar(f"serve{i:03d}", nx, nz, seed * 1000 + i, nsys, 30, k, 0.9,
+                     scale=(nx - 1) / 512.0, a0=0.01 * steep / 0.03)
+        sims.append(w)
+    return sims
+
+
+def get(name: str) -> Workload:
+    """Named workloads.
+
+    * ``periodic_65x9``: flat bed h=1, kh=1, L one wavelength, 3 harmonics, H/L=0.05,
+      20 systems (4 LSERK45 steps), GMRES(30), rank 8, forgetting 0.9.
+    * ``bar_513x17``: walls, submerged-bar bathymetry of the paper's flume (depth 0.4,
+      bar crest 0.1, slopes 1:20 up / 1:10 down), monochromatic shoaling wave of amplitude
+      0.01 m and period 1.96 s, dtau = 0.025 s, 2000 systems, GMRES(30), rank 10.
+    * ``periodic_16385x33``: flat bed h=1, kh=2, 64 carrier wavelengths, 8 harmonics with a
+      slow modulation, H/L=0.1, 500 systems, GMRES(40), rank 16.
+    * ``tiny_17x7``: 16 x 8 periodic grid for brute-force checks.
+    """
+    if name == "periodic_65x9":
+        return _stream(name, 65, 9, 1.0, 1, 3, 0.05, 1, 20, 30, 8, 0.9)
+    if name == "bar_513x17":
+        return _bar(name, 513, 17, 2, 2000, 30, 10, 0.9)
+    if name == "periodic_16385x33":
+        return _stream(name, 16385, 33, 2.0, 64, 8, 0.1, 3, 500, 40, 16, 0.9, modulation=0.2)
+    if name == "tiny_17x7":
+        return _stream(name, 17, 7, 1.0, 1, 2, 0.05, 7, 10, 10, 4, 0.9)
+    if name == "bar_65x9":
+        return _bar(name, 65, 9, 4, 40, 30, 6, 0.9, scale=1.0 / 8.0)
+    raise KeyError(name)
+
+
+NAMES = ("periodic_65x9", "bar_513x17", "periodic_16385x33", "tiny_17x7", "bar_65x9")
