@@ -1,0 +1,173 @@
+/*
+ * sawave.h - C ABI of the MI355X (gfx950) solver library for sequences of sigma-transformed
+ * Poisson systems with exponentially weighted subspace acceleration.
+ *
+ * What is computed (Sorensen, Guido, Engsig-Karup, Kressner, "Subspace Acceleration for
+ * Efficient Nonlinear Water Wave Simulation"):
+ *   - the mixed-stage operator A = grad^(i) . grad^(i-1) of the sigma-transformed pressure
+ *     Poisson problem (Sec. 2.1 push-forward of the gradient; Sec. 3 discrete pressure
+ *     equation), sixth-order first-derivative stencils (Sec. 5.2), p = 0 on the free surface,
+ *     the Neumann condition n . grad^(i-1) p imposed through ghost nodes (Sec. 3 discrete
+ *     Neumann equation);
+ *   - left-preconditioned restarted GMRES (Sec. 3) with a fixed still-water preconditioner;
+ *   - the initial guess of Alg. 2 with the basis V = Y of the EWMA sketch of Alg. 4,
+ *     Y <- r Y + x omega^T after every solve (Sec. 4.1.2).
+ *
+ * Grid and memory layout (all vectors of length n = ncol * (nz + 1), FP64 unless stated):
+ *   node (level j, column c) has index j * ncol + c (x fastest). Level 0 is the ghost level
+ *   below the bed (sigma = -1/(nz-1)), level 1 the bed (sigma = 0), level nz the free
+ *   surface (sigma = 1). Periodic grids: ncol = nx - 1 columns at x = c dx, dx = L/(nx-1).
+ *   Wall grids: ncol = nx + 2; columns 0 and ncol-1 are ghost columns, physical column p
+ *   (x = p dx) has index p + 1. Bathymetry h and surface eta are given at the physical
+ *   columns only (nx - 1 values periodic, nx values walls) and extended to ghost columns by
+ *   even reflection. Row kinds: free-surface nodes and the four grid corners carry identity
+ *   rows; the ghost level carries the bed condition -h_x G_x - G_z at the bed node above it;
+ *   ghost columns carry -G_x (left) / +G_x (right) at the wall node next to them, where
+ *   G_x = D_x p + sigma_x D_sigma p and G_z = D_sigma p / d use the previous stage's geometry.
+ *
+ * Errors: every function returns a status; 0 = success, > 0 = result produced but flagged,
+ * < 0 = hard error, nothing produced. Functions never throw or abort across the ABI. The
+ * message of the last hard error on the calling thread is available from sa_last_error().
+ *
+ * Ownership: the library owns every device buffer it allocates (operator data, preconditioner
+ * hierarchy, Krylov basis, sketch, solution). Host input arrays are copied before return.
+ * Device input pointers (mem = SA_MEM_DEVICE) are read on the problem's stream and must stay
+ * valid until that stream has passed the consuming call. One problem must not be used from
+ * two threads at once. All work is ordered on the hipStream_t given at creation
+ * (NULL = the default stream).
+ */
+#ifndef SAWAVE_H
+#define SAWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------- */
+enum {
+  SA_OK = 0,
+  SA_NOCONV = 1,     /* max_restarts reached: the last iterate is returned and stored   */
+  SA_EARG = -1,      /* invalid argument                                                 */
+  SA_EGEOM = -2,     /* h + eta <= 0 or non-finite surface/bathymetry                     */
+  SA_ENONFINITE = -3,/* NaN/Inf in the right-hand side or during the solve               */
+  SA_EOOM = -4,      /* device allocation failed                                         */
+  SA_EDEVICE = -5,   /* HIP runtime error or device-side fault flag; problem unusable     */
+  SA_ENOTBUILT = -6  /* no usable gfx950 device                                          */
+};
+
+enum { SA_PERIODIC = 0, SA_WALLS = 1 };
+enum { SA_PC_NONE = 0, SA_PC_LINE = 1, SA_PC_MG = 2 };
+enum { SA_GUESS_COLD = 0, SA_GUESS_PREVIOUS = 1, SA_GUESS_EWMA = 2 };
+enum { SA_FP64 = 0, SA_FP32_IR = 1 };
+enum { SA_MEM_HOST = 0, SA_MEM_DEVICE = 1 };
+enum { SA_SYNC = 0, SA_ASYNC = 1 };
+
+/* Grid: nx points on [0, length] (inclusive), nz sigma levels from bed to surface. */
+typedef struct {
+  int32_t nx, nz;
+  int32_t bc;       /* SA_PERIODIC | SA_WALLS                                               */
+  double length;
+} sa_grid;
+
+/* Solver options. sa_default_options() fills the defaults listed here. */
+typedef struct {
+  int32_t restart;      /* GMRES restart length m (1..64), default 30                      */
+  int32_t max_restarts; /* default 200                                                     */
+  double rtol;          /* true relative residual ||b - A x|| / ||b||, default 1e-8         */
+  int32_t precond;      /* SA_PC_*, default SA_PC_MG                                       */
+  int32_t nu1, nu2;     /* smoothing sweeps (MG) / sweeps (LINE: nu1), default 1, 1        */
+  double omega;         /* line-Jacobi damping, default 0.5                                */
+  int32_t max_levels;   /* MG levels including the finest, default 32 (as deep as possible)*/
+  int32_t guess;        /* SA_GUESS_*, default SA_GUESS_EWMA                               */
+  int32_t k;            /* sketch rank (1..16), default 8                                  */
+  double r;             /* forgetting factor per stored solution (0..1], default 0.9       */
+  uint64_t seed;        /* sketch stream seed, default 0                                   */
+  int32_t n_init;       /* solves that use the previous solution before the sketch, 0      */
+  double tau_drop;      /* least-squares column drop threshold, default 1e-7               */
+  int32_t precision;    /* SA_FP64 | SA_FP32_IR, default SA_FP64                            */
+  double rtol_inner;    /* FP32 inner solve tolerance (SA_FP32_IR), default 1e-4           */
+  int32_t max_refine;   /* refinement steps cap (SA_FP32_IR), default 20                   */
+  int32_t cluster;      /* workgroups cooperating on one solve; 0 = chosen from the size  */
+  int32_t profile;      /* 1: accumulate per-phase device time (sa_get_phase_times), 0      */
+} sa_options;
+
+/* Per-solve report. iters counts Arnoldi steps over all cycles (and refinement steps). */
+typedef struct {
+  int32_t iters, restarts, refinements, status;
+  int32_t rank;         /* sketch columns kept by the least-squares guess                  */
+  int32_t checks;       /* true-residual checks triggered by the Arnoldi estimate          */
+  double relres0;       /* ||b - A x0|| / ||b||                                            */
+  double relres;        /* ||b - A x|| / ||b|| of the returned solution                    */
+} sa_solve_info;
+
+typedef struct sa_problem sa_problem;
+
+void sa_default_options(sa_options* opt);
+
+/* Create a problem. h: bathymetry at the physical columns (host, nx-1 or nx values, > 0).
+ * hip_stream: hipStream_t to order all work on (NULL = default stream). */
+int sa_create(const sa_grid* grid, const double* h, const sa_options* opt, void* hip_stream,
+              sa_problem** out);
+void sa_destroy(sa_problem* p);
+
+/* Number of unknowns n = ncol * (nz + 1) and number of columns ncol. */
+int64_t sa_size(const sa_problem* p);
+int32_t sa_ncol(const sa_problem* p);
+
+/* Surfaces of the previous and current stage (Sec. 3: the solve at stage i uses eta^(i-1)
+ * and eta^(i)), nx-1 (periodic) or nx (walls) values each. Copied (host) or read on the
+ * stream (device). */
+int sa_set_surface(sa_problem* p, const double* eta_prev, const double* eta_cur, int32_t mem);
+
+/* Right-hand side b (n values). Host: copied. Device: referenced, not copied. */
+int sa_push_rhs(sa_problem* p, const double* b, int32_t mem);
+
+/* Solve A(eta_prev, eta_cur) x = b from the guess selected by the options, then store x in
+ * the sketch (Alg. 4). SA_SYNC: waits and fills *info (may be NULL). SA_ASYNC: enqueues only;
+ * the report is kept in an on-device log read by sa_read_log. */
+int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags);
+
+/* Reports of the solves enqueued since the last call (oldest first); waits for the stream.
+ * At most `max` are copied; *n_out receives the number copied. The log holds 4096 entries. */
+int sa_read_log(sa_problem* p, sa_solve_info* out, int32_t max, int32_t* n_out);
+
+/* Copy the last solution (n values) to host or device memory. */
+int sa_get_solution(sa_problem* p, double* x, int32_t mem);
+
+/* y = A(eta_prev, eta_cur) x with the current surfaces (Sec. 3 mixed-stage operator).
+ * x, y: n values in `mem` memory. */
+int sa_apply_operator(sa_problem* p, const double* x, double* y, int32_t mem);
+
+/* y = M^-1 x, the fixed still-water preconditioner of the problem. */
+int sa_apply_precond(sa_problem* p, const double* x, double* y, int32_t mem);
+
+/* The k sketch draws of stored solution `index` (SplitMix64 counter stream + Box-Muller),
+ * host only, no device needed: out[a] = omega_a, a < k (k <= 64). */
+int sa_sketch_draws(uint64_t seed, int64_t index, int32_t k, double* out);
+
+/* Copy the sketch Y (n x k, column-major: Y[a * n + i]) to host or device memory. */
+int sa_get_sketch(sa_problem* p, double* y, int32_t mem);
+
+/* Number of solutions stored in the sketch so far. */
+int64_t sa_sketch_count(const sa_problem* p);
+
+/* Device time spent in each phase of the solves run so far with opt.profile = 1, in
+ * milliseconds of the device's constant-rate clock, measured by the first workgroup:
+ * out[0] geometry, [1] sketch guess (block operator, Gram, x0), [2] k x k solve,
+ * [3] operator applications, [4] preconditioner, [5] orthogonalisation, [6] other
+ * (Givens, updates, checks), [7] total. n = entries wanted (<= 8). */
+int sa_get_phase_times(sa_problem* p, double* out, int32_t n);
+
+/* Thread-local message of the last hard error ("" if none). */
+const char* sa_last_error(void);
+
+/* Library build identification (gfx target, HIP version), static string. */
+const char* sa_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAWAVE_H */

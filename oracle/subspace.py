@@ -24,7 +24,7 @@ import numpy as np
 
 from . import rng
 
-TAU_DROP = 1e-6
+TAU_DROP = 1e-7
 
 
 class EWMASketch:

@@ -1,0 +1,632 @@
+// C ABI of the solver library (declared in include/sawave.h): problem set-up, buffer
+// ownership, kernel launches and the per-solve report log.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace sa {
+extern "C" __global__ void sa_solve_kernel(const Problem*, SolveArgs);
+extern "C" __global__ void sa_geometry_kernel(const Problem*, const double*, const double*);
+extern "C" __global__ void sa_operator_kernel(const Problem*, const double*, double*);
+extern "C" __global__ void sa_precond_kernel(const Problem*, const double*, double*);
+extern "C" __global__ void sa_push_kernel(const Problem*, SolveArgs);
+}  // namespace sa
+
+using namespace sa;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(SA_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct sa_problem {
+  sa_grid grid;
+  sa_options opt;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int ncol = 0, nl = 0, n = 0, nphys = 0;
+  Problem hp{};                  // host copy of the device descriptor
+  Problem* dp = nullptr;         // device descriptor
+  char* arena = nullptr;         // one device allocation holding every buffer
+  size_t arena_bytes = 0;
+  double* b_own = nullptr;       // internal right-hand side (host pushes)
+  double* eta_own = nullptr;     // 2 x nphys internal surfaces (host pushes)
+  const double* b = nullptr;     // current right-hand side (device)
+  const double* eta_p = nullptr;
+  const double* eta_c = nullptr;
+  size_t lds_solve = 0, lds_op = 0, lds_pc = 0;
+  int G = 1;
+  int ycur = 0;
+  int64_t pushes = 0, solves = 0;
+  bool unpushed = false;         // the last solution is not in the sketch yet
+  bool have_solution = false;
+  int64_t log_pos = 0, log_read = 0;
+  bool broken = false;
+  unsigned long long* prof = nullptr;  // NPHASE device counters (opt.profile)
+  double clock_khz = 100000.0;
+};
+
+extern "C" void sa_default_options(sa_options* o) {
+  memset(o, 0, sizeof *o);
+  o->restart = 30;
+  o->max_restarts = 200;
+  o->rtol = 1e-8;
+  o->precond = SA_PC_MG;
+  o->nu1 = 1;
+  o->nu2 = 1;
+  o->omega = 0.5;
+  o->max_levels = 32;
+  o->guess = SA_GUESS_EWMA;
+  o->k = 8;
+  o->r = 0.9;
+  o->seed = 0;
+  o->n_init = 0;
+  o->tau_drop = 1e-7;
+  o->precision = SA_FP64;
+  o->rtol_inner = 1e-4;
+  o->max_refine = 20;
+  o->cluster = 0;
+  o->profile = 0;
+}
+
+extern "C" const char* sa_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* sa_build_info(void) {
+  static char info[128];
+  snprintf(info, sizeof info, "sawave gfx950 HIP %d.%d block=%d kmax=%d", HIP_VERSION_MAJOR, HIP_VERSION_MINOR,
+           BLOCK, KMAX);
+  return info;
+}
+
+extern "C" int sa_sketch_draws(uint64_t seed, int64_t index, int32_t k, double* out) {
+  if (!out || k < 1 || k > 64 || index < 0) return fail(SA_EARG, "sa_sketch_draws: bad arguments");
+  splitmix_gaussians(seed, index, k, out);
+  return SA_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// host-side tables
+
+static void sigma_table(int nl, double dsig, std::vector<double>& w, std::vector<int>& s) {
+  w.assign((size_t)nl * 7, 0.0);
+  s.assign(nl, 0);
+  double nodes[7], c[14];
+  for (int j = 0; j < nl; ++j) {
+    const int st = window_start(j, nl, 7);
+    for (int m = 0; m < 7; ++m) nodes[m] = (double)(st + m);
+    fornberg((double)j, nodes, 7, 1, c);
+    for (int m = 0; m < 7; ++m) w[(size_t)j * 7 + m] = c[m * 2 + 1] / dsig;
+    s[j] = st;
+  }
+}
+
+static void chi_table(int ncol, double dx, std::vector<double>& w) {
+  w.assign(49, 0.0);
+  double nodes[7], c[14];
+  for (int m = 0; m < 7; ++m) nodes[m] = (double)m;
+  for (int row = 0; row < 7; ++row) {
+    // rows 0-2: node 0,1,2 of a left window; 3: centre; 4-6: nodes 4,5,6 of a right window
+    const double z = row < 3 ? row : (row == 3 ? 3.0 : (double)row);
+    fornberg(z, nodes, 7, 1, c);
+    for (int m = 0; m < 7; ++m) w[row * 7 + m] = c[m * 2 + 1] / dx;
+  }
+  (void)ncol;
+}
+
+static std::vector<double> extend(const double* v, int nphys, int periodic) {
+  std::vector<double> e;
+  if (periodic) {
+    e.assign(v, v + nphys);
+  } else {
+    e.resize(nphys + 2);
+    e[0] = v[1];
+    for (int i = 0; i < nphys; ++i) e[i + 1] = v[i];
+    e[nphys + 1] = v[nphys - 2];
+  }
+  return e;
+}
+
+// second-order centred dh/dx, d2h/dx2 on the extended column grid
+static void centred_h(const std::vector<double>& h, int periodic, double dx, std::vector<double>& hx,
+                      std::vector<double>& hxx) {
+  const int nc = (int)h.size();
+  hx.assign(nc, 0.0);
+  hxx.assign(nc, 0.0);
+  for (int c = 0; c < nc; ++c) {
+    int cm = c - 1, cp = c + 1;
+    if (periodic) {
+      cm = (cm + nc) % nc;
+      cp = cp % nc;
+    } else if (c == 0 || c == nc - 1) {
+      continue;  // ghost columns: never used by a row that survives
+    }
+    hx[c] = (h[cp] - h[cm]) / (2.0 * dx);
+    hxx[c] = (h[cp] - 2.0 * h[c] + h[cm]) / (dx * dx);
+  }
+}
+
+static size_t round_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static int tiles_host(int ncol, int periodic, int tw) {
+  int nt = (ncol + tw - 1) / tw;
+  if (!periodic && nt > 1 && ncol - (nt - 1) * tw < 4) --nt;
+  return nt;
+}
+
+// ---------------------------------------------------------------------------------------
+
+extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options* optin, void* hip_stream,
+                         sa_problem** out) {
+  if (!grid || !h || !out) return fail(SA_EARG, "sa_create: null argument");
+  *out = nullptr;
+  sa_options opt;
+  if (optin) opt = *optin; else sa_default_options(&opt);
+  const int periodic = grid->bc == SA_PERIODIC;
+  if (grid->bc != SA_PERIODIC && grid->bc != SA_WALLS) return fail(SA_EARG, "sa_create: bc must be SA_PERIODIC or SA_WALLS");
+  if (grid->nz < 6 || grid->nz + 1 > NLMAX) return fail(SA_EARG, "sa_create: nz must be in [6, %d]", NLMAX - 1);
+  const int ncol = periodic ? grid->nx - 1 : grid->nx + 2;
+  if ((periodic && ncol < 8) || (!periodic && grid->nx < 7))
+    return fail(SA_EARG, "sa_create: nx too small for seven-point stencils");
+  if (!(grid->length > 0.0) || !isfinite(grid->length)) return fail(SA_EARG, "sa_create: length must be positive");
+  if (opt.restart < 1 || opt.restart > MMAX) return fail(SA_EARG, "sa_create: restart must be in [1, %d]", MMAX);
+  if (opt.max_restarts < 0) return fail(SA_EARG, "sa_create: max_restarts < 0");
+  if (!(opt.rtol >= 0.0)) return fail(SA_EARG, "sa_create: rtol must be >= 0");
+  if (opt.precond < SA_PC_NONE || opt.precond > SA_PC_MG) return fail(SA_EARG, "sa_create: unknown precond");
+  if (opt.nu1 < 0 || opt.nu2 < 0 || opt.nu1 > 8 || opt.nu2 > 8) return fail(SA_EARG, "sa_create: sweeps in [0, 8]");
+  if (opt.precond == SA_PC_LINE && opt.nu1 < 1) return fail(SA_EARG, "sa_create: line preconditioner needs nu1 >= 1");
+  if (opt.guess < SA_GUESS_COLD || opt.guess > SA_GUESS_EWMA) return fail(SA_EARG, "sa_create: unknown guess mode");
+  if (opt.k < 1 || opt.k > KMAX) return fail(SA_EARG, "sa_create: k must be in [1, %d]", KMAX);
+  if (!(opt.r >= 0.0 && opt.r <= 1.0)) return fail(SA_EARG, "sa_create: r must be in [0, 1]");
+  if (opt.precision != SA_FP64) return fail(SA_EARG, "sa_create: only SA_FP64 is available in this build");
+  if (opt.max_levels < 1) return fail(SA_EARG, "sa_create: max_levels >= 1");
+  const int nphys = periodic ? grid->nx - 1 : grid->nx;
+  for (int i = 0; i < nphys; ++i)
+    if (!(h[i] > 0.0) || !isfinite(h[i])) return fail(SA_EGEOM, "sa_create: depth must be positive and finite");
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(SA_ENOTBUILT, "sa_create: no HIP device");
+
+  sa_problem* p = new sa_problem();
+  p->grid = *grid;
+  p->opt = opt;
+  p->stream = (hipStream_t)hip_stream;
+  hipGetDevice(&p->device);
+  p->ncol = ncol;
+  p->nl = grid->nz + 1;
+  p->n = ncol * p->nl;
+  p->nphys = nphys;
+  const int nl = p->nl, n = p->n;
+  const double dx = grid->length / (grid->nx - 1), dsig = 1.0 / (grid->nz - 1);
+
+  // ---- tables
+  std::vector<double> wsig, wchi, sig(nl);
+  std::vector<int> ssig;
+  sigma_table(nl, dsig, wsig, ssig);
+  chi_table(ncol, dx, wchi);
+  for (int j = 0; j < nl; ++j) sig[j] = (j - 1) * dsig;
+  std::vector<double> hext = extend(h, nphys, periodic);
+  std::vector<double> hchi(ncol, 0.0);
+  for (int c = 0; c < ncol; ++c) {
+    int row, start;
+    if (periodic) { row = 3; start = c - 3; }
+    else if (c < 3) { row = c; start = 0; }
+    else if (c > ncol - 4) { row = 4 + c - (ncol - 3); start = ncol - 7; }
+    else { row = 3; start = c - 3; }
+    double s = 0.0;
+    for (int m = 0; m < 7; ++m) s += wchi[row * 7 + m] * hext[((start + m) % ncol + ncol) % ncol];
+    hchi[c] = s;
+  }
+
+  // ---- still-water hierarchy
+  struct HL { int nx, ncol; double dx; std::vector<double> h, hx, hxx; };
+  std::vector<HL> levs;
+  {
+    HL l0;
+    l0.nx = grid->nx; l0.ncol = ncol; l0.dx = dx;
+    l0.h = hext;
+    centred_h(l0.h, periodic, dx, l0.hx, l0.hxx);
+    levs.push_back(l0);
+    std::vector<double> hphys(h, h + nphys);
+    const int maxlev = opt.precond == SA_PC_MG ? (opt.max_levels < MAXLEV ? opt.max_levels : MAXLEV) : 1;
+    while ((int)levs.size() < maxlev) {
+      const HL& f = levs.back();
+      HL c;
+      if (periodic) {
+        if (f.ncol % 2 || f.ncol / 2 < 4) break;
+        c.ncol = f.ncol / 2; c.nx = c.ncol + 1;
+      } else {
+        if ((f.nx - 1) % 2 || (f.nx - 1) / 2 + 1 < 3) break;
+        c.nx = (f.nx - 1) / 2 + 1; c.ncol = c.nx + 2;
+      }
+      c.dx = grid->length / (c.nx - 1);
+      std::vector<double> hc;
+      for (size_t i = 0; i < hphys.size(); i += 2) hc.push_back(hphys[i]);
+      hphys = hc;
+      c.h = extend(hphys.data(), (int)hphys.size(), periodic);
+      centred_h(c.h, periodic, c.dx, c.hx, c.hxx);
+      levs.push_back(c);
+    }
+  }
+  const int nlev = (int)levs.size();
+  const int cn = levs.back().ncol * nl;
+  std::vector<double> cinv;
+  if (opt.precond == SA_PC_MG) {
+    if (cn > COARSE_MAX) {
+      delete p;
+      return fail(SA_EARG, "sa_create: coarsest grid has %d unknowns (> %d); allow more levels", cn, COARSE_MAX);
+    }
+    cinv.resize((size_t)cn * cn);
+    const HL& L = levs.back();
+    if (dense_still_water_inverse(L.ncol, L.nx, nl, periodic, L.dx, dsig, L.h.data(), L.hx.data(), L.hxx.data(),
+                                  cinv.data()) != 0) {
+      delete p;
+      return fail(SA_EARG, "sa_create: singular coarsest operator");
+    }
+  }
+
+  // ---- cluster size and LDS
+  const int m = opt.restart, k = opt.k;
+  int G = opt.cluster;
+  if (G <= 0) G = 1;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) { delete p; return fail(SA_EDEVICE, "hipGetDeviceProperties failed"); }
+  const size_t head = (size_t)PSTRIDE + 4 * (MMAX + 2) + (size_t)(m + 1) * m + 2 * m + 2 * (m + 1) + m + KMAX +
+                      4 * KMAX * KMAX + 8;
+  const int TWMh = TX + 3, TWGMh = TXG + 3;
+  const size_t need_op = (size_t)(TWMh + 12 + 2 * (TWMh + 6)) * nl + 4;
+  const size_t need_gram = opt.guess == SA_GUESS_EWMA ? (size_t)(k * TWGMh + TWGMh + TWGMh + 12 + 2 * (TWGMh + 6)) * nl : 0;
+  const size_t need_pc = (size_t)nl * BLOCK;
+  size_t big = need_op;
+  if (need_gram > big) big = need_gram;
+  if (need_pc > big) big = need_pc;
+  p->lds_solve = (head + big) * sizeof(double);
+  p->lds_op = need_op * sizeof(double);
+  p->lds_pc = need_pc * sizeof(double);
+  if (p->lds_solve > (size_t)prop.sharedMemPerBlock && p->lds_solve > 160 * 1024) {
+    delete p;
+    return fail(SA_EARG, "sa_create: %zu bytes of LDS needed (nz, k or restart too large)", p->lds_solve);
+  }
+  if (G > 1) {
+    int per_cu = 0;
+    hipFuncSetAttribute((const void*)sa_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)sa_solve_kernel, BLOCK, p->lds_solve) != hipSuccess ||
+        per_cu < 1 || G > per_cu * prop.multiProcessorCount) {
+      delete p;
+      return fail(SA_EARG, "sa_create: cluster of %d workgroups cannot be co-resident", G);
+    }
+  }
+  p->G = G;
+
+  // ---- device arena
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += round_up(bytes); return o; };
+  const size_t o_wsig = take(wsig.size() * 8), o_ssig = take(ssig.size() * 4), o_wchi = take(49 * 8),
+               o_sig = take(nl * 8), o_h = take(ncol * 8), o_hchi = take(ncol * 8), o_geo = take(4 * (size_t)ncol * 8);
+  std::vector<size_t> o_lh(nlev), o_lhx(nlev), o_lhxx(nlev), o_lf(nlev), o_lu(nlev), o_lo(nlev);
+  for (int l = 0; l < nlev; ++l) {
+    const size_t nlv = (size_t)levs[l].ncol * nl;
+    o_lh[l] = take(levs[l].ncol * 8); o_lhx[l] = take(levs[l].ncol * 8); o_lhxx[l] = take(levs[l].ncol * 8);
+    o_lf[l] = take(nlv * 8); o_lu[l] = take(nlv * 8); o_lo[l] = take(nlv * 8);
+  }
+  const size_t o_cinv = take(cinv.size() * 8 + 8);
+  const size_t o_x = take((size_t)n * 8), o_xc = take((size_t)n * 8), o_r = take((size_t)n * 8),
+               o_rc = take((size_t)n * 8), o_t = take((size_t)n * 8), o_V = take((size_t)(m + 1) * n * 8);
+  const size_t ysz = opt.guess == SA_GUESS_EWMA ? (size_t)k * n * 8 : 8;
+  const size_t o_Y0 = take(ysz), o_Y1 = take(ysz);
+  const size_t o_part = take((size_t)2 * G * PSTRIDE * 8), o_bar = take(64), o_flags = take(NFLAGS * 4),
+               o_log = take(LOGCAP * sizeof(sa_solve_info)), o_b = take((size_t)n * 8), o_eta = take(2 * (size_t)nphys * 8),
+               o_prob = take(sizeof(Problem)), o_prof = take(NPHASE * 8);
+  p->arena_bytes = off;
+  if (hipMalloc((void**)&p->arena, off) != hipSuccess) {
+    delete p;
+    return fail(SA_EOOM, "sa_create: cannot allocate %zu bytes of device memory", off);
+  }
+  char* A = p->arena;
+  auto up = [&](size_t o, const void* src, size_t bytes) {
+    return hipMemcpy(A + o, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipMemsetAsync(A, 0, off, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e == hipSuccess) e = up(o_wsig, wsig.data(), wsig.size() * 8);
+  if (e == hipSuccess) e = up(o_ssig, ssig.data(), ssig.size() * 4);
+  if (e == hipSuccess) e = up(o_wchi, wchi.data(), 49 * 8);
+  if (e == hipSuccess) e = up(o_sig, sig.data(), nl * 8);
+  if (e == hipSuccess) e = up(o_h, hext.data(), ncol * 8);
+  if (e == hipSuccess) e = up(o_hchi, hchi.data(), ncol * 8);
+  for (int l = 0; l < nlev && e == hipSuccess; ++l) {
+    e = up(o_lh[l], levs[l].h.data(), levs[l].ncol * 8);
+    if (e == hipSuccess) e = up(o_lhx[l], levs[l].hx.data(), levs[l].ncol * 8);
+    if (e == hipSuccess) e = up(o_lhxx[l], levs[l].hxx.data(), levs[l].ncol * 8);
+  }
+  if (e == hipSuccess && !cinv.empty()) e = up(o_cinv, cinv.data(), cinv.size() * 8);
+
+  Problem& P = p->hp;
+  P.ncol = ncol; P.nl = nl; P.nz = grid->nz; P.n = n; P.nphys = nphys; P.periodic = periodic;
+  P.dx = dx; P.dsig = dsig;
+  P.wsig = (const double*)(A + o_wsig); P.ssig = (const int*)(A + o_ssig); P.wchi = (const double*)(A + o_wchi);
+  P.sig = (const double*)(A + o_sig); P.h = (const double*)(A + o_h); P.hchi = (const double*)(A + o_hchi);
+  P.geo = (double*)(A + o_geo);
+  P.pc = opt.precond; P.nu1 = opt.nu1; P.nu2 = opt.nu2; P.nlev = nlev; P.omega = opt.omega;
+  for (int l = 0; l < nlev; ++l) {
+    Level& L = P.lev[l];
+    L.ncol = levs[l].ncol; L.nx = levs[l].nx; L.dx = levs[l].dx;
+    L.h = (const double*)(A + o_lh[l]); L.hx = (const double*)(A + o_lhx[l]); L.hxx = (const double*)(A + o_lhxx[l]);
+    L.f = (double*)(A + o_lf[l]); L.u = (double*)(A + o_lu[l]); L.o = (double*)(A + o_lo[l]);
+  }
+  P.cinv = (const double*)(A + o_cinv); P.cn = cn;
+  P.x = (double*)(A + o_x); P.xc = (double*)(A + o_xc); P.r = (double*)(A + o_r); P.rc = (double*)(A + o_rc);
+  P.t = (double*)(A + o_t); P.V = (double*)(A + o_V);
+  P.Y[0] = (double*)(A + o_Y0); P.Y[1] = (double*)(A + o_Y1);
+  P.k = k; P.m = m; P.max_restarts = opt.max_restarts; P.tau_drop = opt.tau_drop;
+  P.partials = (double*)(A + o_part); P.bar = (unsigned*)(A + o_bar); P.flags = (int*)(A + o_flags);
+  P.log = (sa_solve_info*)(A + o_log); P.G = G;
+  p->dp = (Problem*)(A + o_prob);
+  p->b_own = (double*)(A + o_b);
+  p->eta_own = (double*)(A + o_eta);
+  if (opt.profile) p->prof = (unsigned long long*)(A + o_prof);
+  {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) == hipSuccess && khz > 0) p->clock_khz = khz;
+  }
+  if (e == hipSuccess) e = up(o_prob, &P, sizeof(Problem));
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_operator_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_op);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_precond_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_pc);
+  if (e != hipSuccess) {
+    hipFree(p->arena);
+    delete p;
+    return fail(SA_EDEVICE, "sa_create: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return SA_OK;
+}
+
+extern "C" void sa_destroy(sa_problem* p) {
+  if (!p) return;
+  if (p->stream) hipStreamSynchronize(p->stream); else hipDeviceSynchronize();
+  hipFree(p->arena);
+  delete p;
+}
+
+extern "C" int64_t sa_size(const sa_problem* p) { return p ? p->n : -1; }
+extern "C" int32_t sa_ncol(const sa_problem* p) { return p ? p->ncol : -1; }
+extern "C" int64_t sa_sketch_count(const sa_problem* p) { return p ? p->pushes + (p->unpushed ? 1 : 0) : -1; }
+
+static int check_flags(sa_problem* p) {
+  int f[NFLAGS];
+  HIPCHK(hipMemcpyAsync(f, p->hp.flags, sizeof f, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  if (f[FLAG_ABORT]) {
+    p->broken = true;
+    return fail(SA_EDEVICE, "device barrier timed out; problem unusable");
+  }
+  int code = SA_OK;
+  if (f[FLAG_GEOM]) code = fail(SA_EGEOM, "h + eta <= 0 or non-finite surface");
+  else if (f[FLAG_NONFINITE]) code = fail(SA_ENONFINITE, "non-finite value in the right-hand side or solve");
+  if (code != SA_OK) {
+    int z[NFLAGS] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(p->hp.flags, z, sizeof z, hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  }
+  return code;
+}
+
+extern "C" int sa_set_surface(sa_problem* p, const double* eta_prev, const double* eta_cur, int32_t mem) {
+  if (!p || !eta_prev || !eta_cur) return fail(SA_EARG, "sa_set_surface: null argument");
+  if (p->broken) return fail(SA_EDEVICE, "problem unusable after a device error");
+  if (mem == SA_MEM_HOST) {
+    for (int i = 0; i < p->nphys; ++i) {
+      const double hp = eta_prev[i], hc = eta_cur[i];
+      if (!isfinite(hp) || !isfinite(hc)) return fail(SA_EGEOM, "sa_set_surface: non-finite surface");
+    }
+    HIPCHK(hipMemcpyAsync(p->eta_own, eta_prev, p->nphys * 8, hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(p->eta_own + p->nphys, eta_cur, p->nphys * 8, hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->eta_p = p->eta_own;
+    p->eta_c = p->eta_own + p->nphys;
+  } else if (mem == SA_MEM_DEVICE) {
+    p->eta_p = eta_prev;
+    p->eta_c = eta_cur;
+  } else {
+    return fail(SA_EARG, "sa_set_surface: bad mem");
+  }
+  return SA_OK;
+}
+
+extern "C" int sa_push_rhs(sa_problem* p, const double* b, int32_t mem) {
+  if (!p || !b) return fail(SA_EARG, "sa_push_rhs: null argument");
+  if (p->broken) return fail(SA_EDEVICE, "problem unusable after a device error");
+  if (mem == SA_MEM_HOST) {
+    HIPCHK(hipMemcpyAsync(p->b_own, b, (size_t)p->n * 8, hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->b = p->b_own;
+  } else if (mem == SA_MEM_DEVICE) {
+    p->b = b;
+  } else {
+    return fail(SA_EARG, "sa_push_rhs: bad mem");
+  }
+  return SA_OK;
+}
+
+static SolveArgs base_args(sa_problem* p) {
+  SolveArgs a;
+  memset(&a, 0, sizeof a);
+  a.ycur = p->ycur;
+  a.r = p->opt.r;
+  a.rtol = p->opt.rtol;
+  a.b = p->b;
+  a.eta_p = p->eta_p;
+  a.eta_c = p->eta_c;
+  a.prof = p->prof;
+  return a;
+}
+
+static hipError_t launch_cluster(sa_problem* p, const void* fn, void** args, size_t lds) {
+  if (p->G == 1) return hipLaunchKernel(fn, dim3(1), dim3(BLOCK), args, lds, p->stream);
+  return hipLaunchCooperativeKernel(fn, dim3(p->G), dim3(BLOCK), args, (unsigned)lds, p->stream);
+}
+
+extern "C" int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags) {
+  if (!p) return fail(SA_EARG, "sa_solve: null problem");
+  if (p->broken) return fail(SA_EDEVICE, "problem unusable after a device error");
+  if (!p->b || !p->eta_p || !p->eta_c) return fail(SA_EARG, "sa_solve: set the surfaces and the right-hand side first");
+  SolveArgs a = base_args(p);
+  const sa_options& o = p->opt;
+  const bool ewma = o.guess == SA_GUESS_EWMA;
+  a.push = ewma && p->unpushed;
+  if (a.push) splitmix_gaussians(o.seed, p->pushes, o.k, a.om);
+  const int64_t pushes_after = p->pushes + (a.push ? 1 : 0);
+  a.sketch_guess = ewma && pushes_after > 0 && p->solves >= o.n_init;
+  a.prev_guess = p->have_solution && (o.guess == SA_GUESS_PREVIOUS || (ewma && !a.sketch_guess));
+  a.log_slot = (int)(p->log_pos % LOGCAP);
+  void* args[] = {(void*)&p->dp, (void*)&a};
+  HIPCHK(launch_cluster(p, (const void*)sa_solve_kernel, args, p->lds_solve));
+  if (a.push) {
+    p->ycur ^= 1;
+    p->pushes += 1;
+  }
+  p->unpushed = ewma;
+  p->have_solution = true;
+  p->solves += 1;
+  p->log_pos += 1;
+  if (flags & SA_ASYNC) return SA_OK;
+  HIPCHK(hipStreamSynchronize(p->stream));
+  int code = check_flags(p);
+  sa_solve_info rep;
+  HIPCHK(hipMemcpy(&rep, p->hp.log + a.log_slot, sizeof rep, hipMemcpyDeviceToHost));
+  p->log_read = p->log_pos;
+  if (info) *info = rep;
+  if (code != SA_OK) return code;
+  if (rep.status == SA_EDEVICE) {
+    p->broken = true;
+    return fail(SA_EDEVICE, "device barrier timed out");
+  }
+  return rep.status;
+}
+
+extern "C" int sa_read_log(sa_problem* p, sa_solve_info* out, int32_t max, int32_t* n_out) {
+  if (!p || !n_out || (max > 0 && !out)) return fail(SA_EARG, "sa_read_log: bad arguments");
+  HIPCHK(hipStreamSynchronize(p->stream));
+  int code = check_flags(p);
+  int64_t avail = p->log_pos - p->log_read;
+  if (avail > LOGCAP) {
+    p->log_read = p->log_pos - LOGCAP;
+    avail = LOGCAP;
+  }
+  int32_t cnt = 0;
+  while (cnt < max && p->log_read < p->log_pos) {
+    HIPCHK(hipMemcpy(out + cnt, p->hp.log + (p->log_read % LOGCAP), sizeof(sa_solve_info), hipMemcpyDeviceToHost));
+    ++cnt;
+    ++p->log_read;
+  }
+  *n_out = cnt;
+  return code;
+}
+
+static hipMemcpyKind kind_from(int32_t mem, bool to_device) {
+  if (mem == SA_MEM_HOST) return to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+  return hipMemcpyDeviceToDevice;
+}
+
+extern "C" int sa_get_solution(sa_problem* p, double* x, int32_t mem) {
+  if (!p || !x || (mem != SA_MEM_HOST && mem != SA_MEM_DEVICE)) return fail(SA_EARG, "sa_get_solution: bad arguments");
+  HIPCHK(hipMemcpyAsync(x, p->hp.x, (size_t)p->n * 8, kind_from(mem, false), p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return SA_OK;
+}
+
+// copy an input into a device scratch vector when it lives on the host
+static int stage_in(sa_problem* p, const double* src, int32_t mem, double* scratch, const double** dev) {
+  if (mem == SA_MEM_DEVICE) { *dev = src; return SA_OK; }
+  if (mem != SA_MEM_HOST) return fail(SA_EARG, "bad mem");
+  HIPCHK(hipMemcpyAsync(scratch, src, (size_t)p->n * 8, hipMemcpyHostToDevice, p->stream));
+  *dev = scratch;
+  return SA_OK;
+}
+
+extern "C" int sa_apply_operator(sa_problem* p, const double* x, double* y, int32_t mem) {
+  if (!p || !x || !y) return fail(SA_EARG, "sa_apply_operator: null argument");
+  if (!p->eta_p || !p->eta_c) return fail(SA_EARG, "sa_apply_operator: set the surfaces first");
+  const double* xd;
+  int rc = stage_in(p, x, mem, p->hp.xc, &xd);
+  if (rc) return rc;
+  double* yd = mem == SA_MEM_DEVICE ? y : p->hp.rc;
+  const int gb = (p->ncol + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(sa_geometry_kernel, dim3(gb), dim3(BLOCK), 0, p->stream, p->dp, p->eta_p, p->eta_c);
+  HIPCHK(hipGetLastError());
+  const int nt = tiles_host(p->ncol, p->grid.bc == SA_PERIODIC, TX);
+  hipLaunchKernelGGL(sa_operator_kernel, dim3(nt), dim3(BLOCK), p->lds_op, p->stream, p->dp, xd, yd);
+  HIPCHK(hipGetLastError());
+  if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 8, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return check_flags(p);
+}
+
+extern "C" int sa_apply_precond(sa_problem* p, const double* x, double* y, int32_t mem) {
+  if (!p || !x || !y) return fail(SA_EARG, "sa_apply_precond: null argument");
+  const double* xd;
+  int rc = stage_in(p, x, mem, p->hp.xc, &xd);
+  if (rc) return rc;
+  double* yd = mem == SA_MEM_DEVICE ? y : p->hp.rc;
+  void* args[] = {(void*)&p->dp, (void*)&xd, (void*)&yd};
+  HIPCHK(launch_cluster(p, (const void*)sa_precond_kernel, args, p->lds_pc));
+  if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 8, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return check_flags(p);
+}
+
+// store a solution that is still waiting for the next solve's fused push
+static int flush_push(sa_problem* p) {
+  if (!p->unpushed || p->opt.guess != SA_GUESS_EWMA) return SA_OK;
+  SolveArgs a = base_args(p);
+  a.push = 1;
+  splitmix_gaussians(p->opt.seed, p->pushes, p->opt.k, a.om);
+  const int gb = (p->n + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(sa_push_kernel, dim3(gb < 1024 ? gb : 1024), dim3(BLOCK), 0, p->stream, p->dp, a);
+  HIPCHK(hipGetLastError());
+  p->ycur ^= 1;
+  p->pushes += 1;
+  p->unpushed = false;
+  return SA_OK;
+}
+
+extern "C" int sa_get_sketch(sa_problem* p, double* y, int32_t mem) {
+  if (!p || !y || (mem != SA_MEM_HOST && mem != SA_MEM_DEVICE)) return fail(SA_EARG, "sa_get_sketch: bad arguments");
+  if (p->opt.guess != SA_GUESS_EWMA) return fail(SA_EARG, "sa_get_sketch: no sketch in this guess mode");
+  int rc = flush_push(p);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(y, p->hp.Y[p->ycur], (size_t)p->n * p->opt.k * 8, kind_from(mem, false), p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return SA_OK;
+}
+
+extern "C" int sa_get_phase_times(sa_problem* p, double* out, int32_t n) {
+  if (!p || !out || n < 1 || n > NPHASE) return fail(SA_EARG, "sa_get_phase_times: bad arguments");
+  if (!p->prof) return fail(SA_EARG, "sa_get_phase_times: problem created without profile = 1");
+  unsigned long long t[NPHASE];
+  HIPCHK(hipMemcpyAsync(t, p->prof, sizeof t, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  for (int i = 0; i < n; ++i) out[i] = (double)t[i] / p->clock_khz;
+  return SA_OK;
+}

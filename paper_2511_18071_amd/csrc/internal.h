@@ -1,0 +1,93 @@
+// Internal data structures shared by the host setup code and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/sawave.h"
+
+namespace sa {
+
+constexpr int BLOCK = 256;        // threads per workgroup (4 wave64)
+constexpr int KMAX = 16;          // largest sketch rank handled on the device
+constexpr int MMAX = 64;          // largest restart length
+constexpr int MAXLEV = 24;        // multigrid levels
+constexpr int TX = 64;            // columns per operator tile
+constexpr int TXG = 16;           // columns per tile of the block operator (sketch guess)
+constexpr int HW = 3;             // stencil half width (seven-point first derivatives)
+constexpr int NLMAX = 66;         // largest number of levels nz + 1
+constexpr int PSTRIDE = 320;      // doubles per workgroup in the reduction scratch
+constexpr int LOGCAP = 4096;      // solve reports kept on the device
+constexpr int COARSE_MAX = 1024;  // largest coarsest-grid size solved by a dense inverse
+
+// Flags written by kernels (device int array).
+enum { FLAG_GEOM = 0, FLAG_NONFINITE = 1, FLAG_ABORT = 2, NFLAGS = 4 };
+
+// One level of the still-water preconditioner hierarchy (level 0 = the problem grid).
+struct Level {
+  int ncol, nx;              // columns (ghosts included), physical points
+  double dx;
+  const double* h;           // depth per column (ghost columns by reflection)
+  const double* hx;          // second-order centred dh/dx per column
+  const double* hxx;         // second-order centred d2h/dx2 per column
+  double* f;                 // right-hand side of this level (level 0: unused, the input)
+  double* u;                 // smoothed iterate
+  double* o;                 // output of this level's cycle (level 0: unused, the output)
+};
+
+// Everything a kernel needs about one problem. Lives in device memory.
+struct Problem {
+  int ncol, nl, nz, n, nphys, periodic;
+  double dx, dsig;
+  const double* wsig;        // nl x 7 first-derivative weights in sigma (1/dsig included)
+  const int* ssig;           // nl window starts in sigma
+  const double* wchi;        // 7 x 7: rows 0-2 left windows, 3 centred, 4-6 right windows
+  const double* sig;         // nl sigma values
+  const double* h;           // ncol depth (extended)
+  const double* hchi;        // ncol sixth-order dh/dchi
+  double* geo;               // 4 x ncol: 1/d_prev, d_chi prev, 1/d_cur, d_chi cur
+  // preconditioner
+  int pc, nu1, nu2, nlev;
+  double omega;
+  Level lev[MAXLEV];
+  const double* cinv;        // dense inverse of the coarsest operator, cn x cn row-major
+  int cn;
+  // solver vectors
+  double *x, *xc, *r, *rc, *t, *V, *Y[2];
+  // sketch / options
+  int k, m, max_restarts;
+  double tau_drop;
+  // synchronisation and reports
+  double* partials;          // 2 x G x PSTRIDE
+  unsigned* bar;             // barrier counter, generation
+  int* flags;                // NFLAGS
+  sa_solve_info* log;        // LOGCAP
+  int G;                     // workgroups per solve
+};
+
+struct SolveArgs {
+  int push;          // store the previous solution in the sketch first
+  int sketch_guess;  // x0 from the sketch (Alg. 2 with V = Y)
+  int prev_guess;    // x0 = previous solution (else zero) when no sketch guess
+  int ycur;          // sketch buffer holding Y before this call
+  int log_slot;
+  const double* b;      // right-hand side (n)
+  const double* eta_p;  // previous-stage surface (nphys)
+  const double* eta_c;  // current-stage surface (nphys)
+  double r;          // forgetting factor
+  double rtol;
+  double om[KMAX];   // sketch draws of the stored solution
+  unsigned long long* prof;  // NPHASE accumulated wall-clock ticks, or nullptr
+};
+
+// phase-time categories of the solve kernel (sa_get_phase_times)
+enum { PH_GEOM = 0, PH_GUESS = 1, PH_SMALL = 2, PH_OPER = 3, PH_PREC = 4, PH_ORTH = 5, PH_OTHER = 6, PH_TOTAL = 7,
+       NPHASE = 8 };
+
+// ---- host-side setup (setup.cpp) ----------------------------------------------------
+void fornberg(double z, const double* x, int n, int mmax, double* c /* n*(mmax+1) */);
+int window_start(int i, int npts, int width);
+void splitmix_gaussians(uint64_t seed, int64_t index, int k, double* out);
+// assemble the coarsest still-water operator densely (row-major cn x cn) and invert it
+int dense_still_water_inverse(int ncol, int nx, int nl, int periodic, double dx, double dsig,
+                              const double* h, const double* hx, const double* hxx, double* inv);
+
+}  // namespace sa

@@ -1,0 +1,159 @@
+// Host-side setup of a problem: difference weights, still-water coarse-grid inverse and the
+// sketch random stream. Plain C++ (no device code).
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace sa {
+
+// Fornberg's recursion for finite-difference weights on arbitrary nodes (Fornberg 1988):
+// c[i*(mmax+1) + m] weights node i for the m-th derivative at z.
+void fornberg(double z, const double* x, int n, int mmax, double* c) {
+  const int M = mmax + 1;
+  for (int i = 0; i < n * M; ++i) c[i] = 0.0;
+  double c1 = 1.0, c4 = x[0] - z;
+  c[0] = 1.0;
+  for (int i = 1; i < n; ++i) {
+    const int mn = i < mmax ? i : mmax;
+    double c2 = 1.0;
+    const double c5 = c4;
+    c4 = x[i] - z;
+    for (int j = 0; j < i; ++j) {
+      const double c3 = x[i] - x[j];
+      c2 *= c3;
+      if (j == i - 1) {
+        for (int k = mn; k >= 1; --k) c[i * M + k] = c1 * (k * c[(i - 1) * M + k - 1] - c5 * c[(i - 1) * M + k]) / c2;
+        c[i * M] = -c1 * c5 * c[(i - 1) * M] / c2;
+      }
+      for (int k = mn; k >= 1; --k) c[j * M + k] = (c4 * c[j * M + k] - k * c[j * M + k - 1]) / c3;
+      c[j * M] = c4 * c[j * M] / c3;
+    }
+    c1 = c2;
+  }
+}
+
+int window_start(int i, int npts, int width) {
+  int s = i - width / 2;
+  if (s > npts - width) s = npts - width;
+  if (s < 0) s = 0;
+  return s;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based stream: output i of seed s is
+// mix(s + i * golden_gamma). Draw a of stored solution `index` takes outputs 2(64 index + a) + 1
+// and + 2, maps them to (0, 1] and applies the Box-Muller transform.
+static inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+static inline double unit_interval(uint64_t seed, uint64_t i) {
+  const uint64_t v = mix64(seed + i * 0x9E3779B97F4A7C15ULL);
+  return (double)((v >> 11) + 1) * 0x1.0p-53;
+}
+
+void splitmix_gaussians(uint64_t seed, int64_t index, int k, double* out) {
+  for (int a = 0; a < k; ++a) {
+    const uint64_t i = 2ULL * (64ULL * (uint64_t)index + (uint64_t)a) + 1ULL;
+    const double u1 = unit_interval(seed, i), u2 = unit_interval(seed, i + 1);
+    out[a] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+  }
+}
+
+// Still-water operator rows (second-order direct form, same row kinds as the mixed-stage
+// operator), assembled densely for the coarsest multigrid grid.
+int dense_still_water_inverse(int ncol, int nx, int nl, int periodic, double dx, double dsig,
+                              const double* h, const double* hx, const double* hxx, double* inv) {
+  const int nz = nl - 1, n = ncol * nl;
+  std::vector<double> a((size_t)n * n, 0.0);
+  auto at = [&](int row, int c, int j, double v) {
+    if (periodic) c = (c % ncol + ncol) % ncol;
+    a[(size_t)row * n + (size_t)j * ncol + c] += v;
+  };
+  const double rdx = 1.0 / dx, rds = 1.0 / dsig;
+  for (int j = 0; j < nl; ++j) {
+    const double sg = (j - 1) * dsig;
+    for (int c = 0; c < ncol; ++c) {
+      const int row = j * ncol + c;
+      const bool ghostcol = !periodic && (c == 0 || c == ncol - 1);
+      if (j == nz || (ghostcol && j == 0)) {
+        at(row, c, j, 1.0);
+        continue;
+      }
+      if (ghostcol) {  // -G_x at the left wall node, +G_x at the right wall node
+        const int w = c == 0 ? 1 : ncol - 2;
+        const double sgn = c == 0 ? -1.0 : 1.0;
+        const double s = hx[w] * (1.0 - sg) / h[w];
+        at(row, w + 1, j, sgn * 0.5 * rdx);
+        at(row, w - 1, j, -sgn * 0.5 * rdx);
+        at(row, w, j + 1, sgn * s * 0.5 * rds);
+        at(row, w, j - 1, -sgn * s * 0.5 * rds);
+        continue;
+      }
+      if (j == 0) {  // bed: -h_x G_x - G_z at the bed node (level 1)
+        const double s1 = hx[c] / h[c];
+        at(row, c + 1, 1, -hx[c] * 0.5 * rdx);
+        at(row, c - 1, 1, hx[c] * 0.5 * rdx);
+        const double q = hx[c] * s1 + 1.0 / h[c];
+        at(row, c, 2, -q * 0.5 * rds);
+        at(row, c, 0, q * 0.5 * rds);
+        continue;
+      }
+      const double oms = 1.0 - sg, hh = h[c], hc = hx[c];
+      const double s = hc * oms / hh;
+      const double sxx = oms * hxx[c] / hh - 2.0 * oms * hc * hc / (hh * hh);
+      const double azz = (s * s + 1.0 / (hh * hh)) * rds * rds;
+      at(row, c + 1, j, rdx * rdx);
+      at(row, c - 1, j, rdx * rdx);
+      at(row, c, j, -2.0 * rdx * rdx - 2.0 * azz);
+      const double cx = 2.0 * s * 0.25 * rdx * rds;
+      at(row, c + 1, j + 1, cx);
+      at(row, c + 1, j - 1, -cx);
+      at(row, c - 1, j + 1, -cx);
+      at(row, c - 1, j - 1, cx);
+      at(row, c, j + 1, azz + sxx * 0.5 * rds);
+      at(row, c, j - 1, azz - sxx * 0.5 * rds);
+    }
+  }
+  // Gauss-Jordan elimination with partial pivoting: inv = a^-1
+  std::vector<double> e((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) e[(size_t)i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    double best = fabs(a[(size_t)col * n + col]);
+    for (int r = col + 1; r < n; ++r) {
+      const double v = fabs(a[(size_t)r * n + col]);
+      if (v > best) best = v, piv = r;
+    }
+    if (!(best > 0.0)) return -1;
+    if (piv != col) {
+      for (int q = 0; q < n; ++q) {
+        double t = a[(size_t)col * n + q]; a[(size_t)col * n + q] = a[(size_t)piv * n + q]; a[(size_t)piv * n + q] = t;
+        t = e[(size_t)col * n + q]; e[(size_t)col * n + q] = e[(size_t)piv * n + q]; e[(size_t)piv * n + q] = t;
+      }
+    }
+    const double d = 1.0 / a[(size_t)col * n + col];
+    for (int q = 0; q < n; ++q) a[(size_t)col * n + q] *= d, e[(size_t)col * n + q] *= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = a[(size_t)r * n + col];
+      if (f == 0.0) continue;
+      for (int q = 0; q < n; ++q) {
+        a[(size_t)r * n + q] -= f * a[(size_t)col * n + q];
+        e[(size_t)r * n + q] -= f * e[(size_t)col * n + q];
+      }
+    }
+  }
+  // stored transposed: inv[j * n + i] = (a^-1)[i][j], so device rows read coalesced
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) inv[(size_t)j * n + i] = e[(size_t)i * n + j];
+  (void)nx;
+  return 0;
+}
+
+}  // namespace sa

@@ -1,0 +1,1217 @@
+// gfx950 kernels of the subspace-accelerated sigma-transformed Poisson solver.
+//
+// One solve (guess + restarted GMRES) is one persistent launch: a cluster of G workgroups
+// owns the problem, walks through the phases below in order, and meets at a cluster barrier
+// between phases (G = 1: a workgroup barrier only). Reductions are deterministic: every
+// workgroup writes its partial sums, and after the barrier every workgroup adds the G
+// partials in the same order, so all workgroups take bit-identical decisions without a
+// broadcast.
+//
+// Phases and what they compute:
+//   geometry   per-column 1/d and d_chi of both stages (Sec. 2.1, surface-subgrid D_chi)
+//   operator   y = A x, the mixed-stage grad^(i) . grad^(i-1) with ghost-node boundary rows
+//              (Sec. 3), LDS-staged tiles of TX columns x all levels, 7-point stencils
+//   guess      Y <- r Y + x omega^T fused with W = A Y, Gram W^T W and W^T b over LDS tiles,
+//              then the k x k least-squares solve and x0 = Y z (Alg. 2 with Alg. 4's V = Y)
+//   precond    fixed still-water V-cycle: column (line) solves, x-semicoarsening, dense
+//              coarsest inverse (thread per column, coalesced level-major rows)
+//   arnoldi    classical Gram-Schmidt twice, wavefront-shuffle reductions, Givens in LDS
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace sa {
+
+#define DEV __device__ __forceinline__
+
+constexpr long SPIN_LIMIT = 1L << 25;
+constexpr int TWM = TX + 3;   // widest operator tile (a last wall tile absorbs up to 3 columns)
+constexpr int TWGM = TXG + 3;
+
+// ------------------------------------------------------------------------------------------
+// cluster of workgroups cooperating on one problem
+struct Cl {
+  int rank, G;
+  unsigned* bar;
+  int* flags;
+  double* partials;
+  int pbuf;
+};
+
+DEV bool aborted(const Cl& cl) {
+  return __hip_atomic_load(cl.flags + FLAG_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Barrier across the workgroups of the cluster (sense by generation counter). Every wait is
+// bounded: after SPIN_LIMIT polls the abort flag is raised and all waiters leave.
+DEV void csync(Cl& cl) {
+  __syncthreads();
+  if (cl.G == 1) return;
+  if (threadIdx.x == 0) {
+    unsigned* count = cl.bar;
+    unsigned* gen = cl.bar + 1;
+    const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == (unsigned)cl.G - 1u) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > SPIN_LIMIT || aborted(cl)) {
+          __hip_atomic_store(cl.flags + FLAG_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+DEV double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// red[0..nv) holds this workgroup's sums; afterwards it holds the cluster sums (same on all
+// workgroups, summed in rank order).
+DEV void cluster_sum(Cl& cl, double* red, int nv) {
+  __syncthreads();
+  if (cl.G == 1) return;
+  double* part = cl.partials + (size_t)cl.pbuf * cl.G * PSTRIDE;
+  for (int i = threadIdx.x; i < nv; i += BLOCK) part[cl.rank * PSTRIDE + i] = red[i];
+  cl.pbuf ^= 1;
+  csync(cl);
+  for (int i = threadIdx.x; i < nv; i += BLOCK) {
+    double s = 0.0;
+    for (int g = 0; g < cl.G; ++g) s += part[g * PSTRIDE + i];
+    red[i] = s;
+  }
+  __syncthreads();
+}
+
+// per-thread value v -> red[slot] = workgroup sum (fixed tree), all threads must call
+DEV void block_sum_to(double v, double* wsum /*LDS 4*/, double* red, int slot) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) wsum[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) red[slot] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------------------------------
+// geometry of both stages, per column
+DEV double eta_ext(const Problem& P, const double* eta, int c) {
+  if (P.periodic) return eta[c];
+  if (c == 0) return eta[1];
+  if (c == P.ncol - 1) return eta[P.nphys - 2];
+  return eta[c - 1];
+}
+
+// window of the seven-point x derivative at column c: weight row and first column (unwrapped)
+DEV void chi_window(const Problem& P, int c, int& row, int& start) {
+  if (P.periodic) { row = 3; start = c - HW; return; }
+  if (c < HW) { row = c; start = 0; return; }
+  if (c > P.ncol - 1 - HW) { row = 4 + c - (P.ncol - HW); start = P.ncol - 7; return; }
+  row = 3; start = c - HW;
+}
+
+DEV int wrapc(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
+
+DEV void phase_geometry(const Problem& P, Cl& cl, const double* __restrict__ eta_p, const double* __restrict__ eta_c) {
+  const int nc = P.ncol;
+  for (int c = cl.rank * BLOCK + threadIdx.x; c < nc; c += cl.G * BLOCK) {
+    int row, start;
+    chi_window(P, c, row, start);
+    double dp = 0.0, dc = 0.0;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      int cc = start + m;
+      if (P.periodic) cc = ((cc % nc) + nc) % nc;
+      const double w = P.wchi[row * 7 + m];
+      dp += w * (P.h[cc] + eta_ext(P, eta_p, cc));
+      dc += w * (P.h[cc] + eta_ext(P, eta_c, cc));
+    }
+    const double d_p = P.h[c] + eta_ext(P, eta_p, c);
+    const double d_c = P.h[c] + eta_ext(P, eta_c, c);
+    if (!(d_p > 0.0) || !(d_c > 0.0) || !isfinite(d_p) || !isfinite(d_c) || !isfinite(dp) || !isfinite(dc))
+      atomicOr(P.flags + FLAG_GEOM, 1);
+    P.geo[c] = 1.0 / d_p;
+    P.geo[nc + c] = dp;
+    P.geo[2 * nc + c] = 1.0 / d_c;
+    P.geo[3 * nc + c] = dc;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// operator tiles
+struct Tiles {
+  int nt, tw;
+};
+
+DEV Tiles tiles_of(const Problem& P, int tw) {
+  int nt = (P.ncol + tw - 1) / tw;
+  if (!P.periodic && nt > 1 && P.ncol - (nt - 1) * tw < 4) --nt;  // last wall tile >= 4 wide
+  return Tiles{nt, tw};
+}
+
+// A x on the columns [c0, c0 + w) of one tile, all levels. x is multiplied by xs on load.
+// LDS: sx (W+12) x nl, sgx/sgz (W+6) x nl with W = tw + 3. The output functor receives
+// (level, column, A x value) for every node of the tile.
+template <int W, class Load, class Out>
+DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, double* sgx, double* sgz, Out out) {
+  const int nc = P.ncol, nl = P.nl, nz = P.nz;
+  constexpr int LX = W + 12, LG = W + 6;
+  // stage the input with a 6-column halo: load(level, column, tile-local column)
+  for (int i = threadIdx.x; i < LX * nl; i += BLOCK) {
+    const int lj = i / LX, lc = i - lj * LX;
+    int c = c0 - 6 + lc;
+    double v = 0.0;
+    if (lc < w + 12) {
+      if (P.periodic) {
+        c = ((c % nc) + nc) % nc;
+        v = load(lj, c, lc);
+      } else if (c >= 0 && c < nc) {
+        v = load(lj, c, lc);
+      }
+    }
+    sx[i] = v;
+  }
+  __syncthreads();
+  // gradient of the previous stage: G_x = D_x p + sigma_x D_sigma p, G_z = D_sigma p / d
+  for (int i = threadIdx.x; i < LG * nl; i += BLOCK) {
+    const int lj = i / LG, lc = i - lj * LG;
+    const int c = c0 - 3 + lc;
+    if (lc >= w + 6) continue;
+    if (!P.periodic && (c < 0 || c >= nc)) continue;
+    const int cg = P.periodic ? ((c % nc) + nc) % nc : c;
+    int row, start;
+    chi_window(P, c, row, start);
+    const int sidx = start - c0 + 6;
+    double dxv = 0.0;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) dxv += P.wchi[row * 7 + m] * sx[lj * LX + sidx + m];
+    const int s0 = P.ssig[lj];
+    double dsv = 0.0;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) dsv += P.wsig[lj * 7 + m] * sx[(s0 + m) * LX + lc + 3];
+    const double invd = P.geo[cg];
+    const double sxp = (P.hchi[cg] - P.sig[lj] * P.geo[nc + cg]) * invd;
+    sgx[i] = dxv + sxp * dsv;
+    sgz[i] = invd * dsv;
+  }
+  __syncthreads();
+  // divergence of the current stage, boundary rows, identity rows
+  for (int i = threadIdx.x; i < W * nl; i += BLOCK) {
+    const int lj = i / W, lc = i - lj * W;
+    if (lc >= w) continue;
+    const int c = c0 + lc;
+    const bool ghostcol = !P.periodic && (c == 0 || c == nc - 1);
+    double v;
+    if (lj == nz || (ghostcol && lj == 0)) {
+      v = sx[lj * LX + lc + 6];
+    } else if (ghostcol) {
+      v = (c == 0) ? -sgx[lj * LG + (1 - c0) + 3] : sgx[lj * LG + (nc - 2 - c0) + 3];
+    } else if (lj == 0) {
+      v = -P.hchi[c] * sgx[LG + lc + 3] - sgz[LG + lc + 3];
+    } else {
+      int row, start;
+      chi_window(P, c, row, start);
+      const int gidx = start - c0 + 3;
+      double dxg = 0.0;
+#pragma unroll
+      for (int m = 0; m < 7; ++m) dxg += P.wchi[row * 7 + m] * sgx[lj * LG + gidx + m];
+      const int s0 = P.ssig[lj];
+      double dsg = 0.0, dsz = 0.0;
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        const double ws = P.wsig[lj * 7 + m];
+        dsg += ws * sgx[(s0 + m) * LG + lc + 3];
+        dsz += ws * sgz[(s0 + m) * LG + lc + 3];
+      }
+      const double invd = P.geo[2 * nc + c];
+      const double sxc = (P.hchi[c] - P.sig[lj] * P.geo[3 * nc + c]) * invd;
+      v = dxg + sxc * dsg + invd * dsz;
+    }
+    out(lj, lc, c, v);
+  }
+  __syncthreads();
+}
+
+// y = A x (b == nullptr) or y = b - A x with ||y||^2 and ||b||^2 into red[slot], red[slot+1]
+DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, double xs, double* y,
+                        const double* __restrict__ b, double* lds, double* red, int slot) {
+  const bool resid = b != nullptr;
+  const Tiles T = tiles_of(P, TX);
+  double* sx = lds;
+  double* sgx = sx + (TWM + 12) * P.nl;
+  double* sgz = sgx + (TWM + 6) * P.nl;
+  double* wsum = sgz + (TWM + 6) * P.nl;
+  const int nc = P.ncol;
+  double acc = 0.0, accb = 0.0;
+  for (int t = cl.rank; t < T.nt; t += cl.G) {
+    const int c0 = t * TX;
+    const int w = (t == T.nt - 1) ? nc - c0 : TX;
+    auto load = [&](int lj, int c, int) { return x[(size_t)lj * nc + c] * xs; };
+    tile_operator<TWM>(P, c0, w, load, sx, sgx, sgz, [&](int lj, int lc, int c, double v) {
+      const size_t e = (size_t)lj * nc + c;
+      if (resid) {
+        const double bb = b[e];
+        const double rr = bb - v;
+        y[e] = rr;
+        acc += rr * rr;
+        accb += bb * bb;
+      } else {
+        y[e] = v;
+      }
+    });
+  }
+  if (resid) {
+    block_sum_to(acc, wsum, red, slot);
+    block_sum_to(accb, wsum, red, slot + 1);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// still-water preconditioner (second-order direct form at eta = 0)
+struct Lv {
+  int nc;
+  double rdx;
+  const double *h, *hx, *hxx;
+};
+
+DEV Lv level_view(const Problem& P, int l) {
+  const Level& L = P.lev[l];
+  return Lv{L.ncol, 1.0 / L.dx, L.h, L.hx, L.hxx};
+}
+
+// (M u)(c, j) on one level
+DEV double m_row(const Problem& P, const Lv& L, const double* __restrict__ u, int c, int j) {
+  const int nc = L.nc, nz = P.nz;
+  const double rdx = L.rdx, rds = 1.0 / P.dsig;
+  auto U = [&](int cc, int jj) {
+    if (P.periodic) cc = wrapc(cc, nc);
+    return u[(size_t)jj * nc + cc];
+  };
+  if (j == nz) return U(c, j);
+  if (!P.periodic && (c == 0 || c == nc - 1)) {
+    if (j == 0) return U(c, j);
+    const int w = (c == 0) ? 1 : nc - 2;
+    const double s = L.hx[w] * (1.0 - P.sig[j]) / L.h[w];
+    const double gx = (U(w + 1, j) - U(w - 1, j)) * 0.5 * rdx + s * (U(w, j + 1) - U(w, j - 1)) * 0.5 * rds;
+    return c == 0 ? -gx : gx;
+  }
+  const double h = L.h[c], hx = L.hx[c];
+  if (j == 0) {
+    const double s1 = hx / h;
+    const double dz = (U(c, 2) - U(c, 0)) * 0.5 * rds;
+    const double gx = (U(c + 1, 1) - U(c - 1, 1)) * 0.5 * rdx + s1 * dz;
+    return -hx * gx - dz / h;
+  }
+  const double oms = 1.0 - P.sig[j];
+  const double s = hx * oms / h;
+  const double sxx = oms * L.hxx[c] / h - 2.0 * oms * hx * hx / (h * h);
+  const double uc = U(c, j);
+  const double dxx = (U(c + 1, j) - 2.0 * uc + U(c - 1, j)) * rdx * rdx;
+  const double dxz = (U(c + 1, j + 1) - U(c + 1, j - 1) - U(c - 1, j + 1) + U(c - 1, j - 1)) * 0.25 * rdx * rds;
+  const double dzz = (U(c, j + 1) - 2.0 * uc + U(c, j - 1)) * rds * rds;
+  const double dz = (U(c, j + 1) - U(c, j - 1)) * 0.5 * rds;
+  return dxx + 2.0 * s * dxz + (s * s + 1.0 / (h * h)) * dzz + sxx * dz;
+}
+
+// same-column coefficients of an interior (PDE) row: u(c, j-1), u(c, j), u(c, j+1)
+DEV void m_col(const Problem& P, const Lv& L, int c, int j, double& lo, double& di, double& up) {
+  const double rds = 1.0 / P.dsig;
+  const double h = L.h[c], hx = L.hx[c], oms = 1.0 - P.sig[j];
+  const double s = hx * oms / h;
+  const double sxx = oms * L.hxx[c] / h - 2.0 * oms * hx * hx / (h * h);
+  const double a = (s * s + 1.0 / (h * h)) * rds * rds, b = sxx * 0.5 * rds;
+  lo = a - b;
+  up = a + b;
+  di = -2.0 * L.rdx * L.rdx - 2.0 * a;
+}
+
+// One line-Jacobi sweep on column c: o = u + omega L^-1 (f - M u) (u == nullptr: u = 0).
+// L keeps the same-column entries of M. The bed row couples levels 0 and 2; it is first
+// combined with row 1 to make the column system tridiagonal, then solved by elimination.
+// Forward results go to o (the thread's own column), the elimination ratios to cp (LDS).
+DEV void line_sweep(const Problem& P, const Lv& L, const double* __restrict__ f, const double* __restrict__ u,
+                    double* __restrict__ o, int c, double omega, double* cp) {
+  const int nc = L.nc, nz = P.nz, tid = threadIdx.x;
+  auto R = [&](int j) {
+    const size_t e = (size_t)j * nc + c;
+    return u ? f[e] - m_row(P, L, u, c, j) : f[e];
+  };
+  auto Uo = [&](int j) { return u ? u[(size_t)j * nc + c] : 0.0; };
+  if (!P.periodic && (c == 0 || c == nc - 1)) {
+    for (int j = 0; j <= nz; ++j) {
+      const double dg = (j == 0 || j == nz) ? 1.0 : 0.5 * L.rdx;
+      o[(size_t)j * nc + c] = Uo(j) + omega * (R(j) / dg);
+    }
+    return;
+  }
+  const double rds = 1.0 / P.dsig;
+  const double q = L.hx[c] * (L.hx[c] / L.h[c]) + 1.0 / L.h[c];
+  const double a0 = 0.5 * rds * q, c0 = -0.5 * rds * q;
+  double l1, d1, u1;
+  m_col(P, L, c, 1, l1, d1, u1);
+  const double r0 = R(0), r1 = R(1);
+  const double a0p = a0 - c0 * l1 / u1;
+  const double b0p = -c0 * d1 / u1;
+  const double f0p = r0 - c0 * r1 / u1;
+  double pc = b0p / a0p, pd = f0p / a0p;
+  cp[tid] = pc;
+  o[c] = pd;
+  for (int j = 1; j < nz; ++j) {
+    double lo, di, up, rj;
+    if (j == 1) { lo = l1; di = d1; up = u1; rj = r1; }
+    else { m_col(P, L, c, j, lo, di, up); rj = R(j); }
+    const double den = di - lo * pc;
+    pc = up / den;
+    pd = (rj - lo * pd) / den;
+    cp[j * BLOCK + tid] = pc;
+    o[(size_t)j * nc + c] = pd;
+  }
+  double dlt = R(nz);  // free surface: identity row
+  o[(size_t)nz * nc + c] = Uo(nz) + omega * dlt;
+  for (int j = nz - 1; j >= 0; --j) {
+    const size_t e = (size_t)j * nc + c;
+    dlt = o[e] - cp[j * BLOCK + tid] * dlt;
+    o[e] = Uo(j) + omega * dlt;
+  }
+}
+
+DEV void phase_sweep(const Problem& P, Cl& cl, int l, const double* f, const double* u, double* o, double* cp) {
+  const Lv L = level_view(P, l);
+  // whole workgroups take consecutive columns so that a level's rows are read coalesced
+  for (int base = cl.rank * BLOCK; base < L.nc; base += cl.G * BLOCK) {
+    const int c = base + threadIdx.x;
+    if (c < L.nc) line_sweep(P, L, f, u, o, c, P.omega, cp);
+  }
+}
+
+// coarse right-hand side: full weighting in x of the fine residual f - M u
+DEV void phase_restrict(const Problem& P, Cl& cl, int l, const double* f, const double* u, double* fc) {
+  const Lv L = level_view(P, l);
+  const int ncc = P.lev[l + 1].ncol, nxc = P.lev[l + 1].nx, nc = L.nc;
+  for (int C = cl.rank * BLOCK + threadIdx.x; C < ncc; C += cl.G * BLOCK) {
+    for (int j = 0; j <= P.nz; ++j) {
+      auto Rr = [&](int cc) {
+        if (P.periodic) cc = wrapc(cc, nc);
+        return f[(size_t)j * nc + cc] - m_row(P, L, u, cc, j);
+      };
+      double v;
+      if (P.periodic) {
+        const int c = 2 * C;
+        v = 0.25 * Rr(c - 1) + 0.5 * Rr(c) + 0.25 * Rr(c + 1);
+      } else if (C == 0) {
+        v = Rr(0);
+      } else if (C == ncc - 1) {
+        v = Rr(nc - 1);
+      } else {
+        const int pc = C - 1, p = 2 * pc;
+        if (pc == 0) v = 0.5 * Rr(1) + 0.5 * Rr(2);
+        else if (pc == nxc - 1) v = 0.5 * Rr(p + 1) + 0.5 * Rr(p);
+        else v = 0.25 * Rr(p) + 0.5 * Rr(p + 1) + 0.25 * Rr(p + 2);
+      }
+      fc[(size_t)j * ncc + C] = v;
+    }
+  }
+}
+
+// u += P e: linear interpolation in x of the coarse correction
+DEV void phase_prolong(const Problem& P, Cl& cl, int l, const double* e, double* u) {
+  const int nc = P.lev[l].ncol, ncc = P.lev[l + 1].ncol;
+  const int total = nc * P.nl;
+  for (int i = cl.rank * BLOCK + threadIdx.x; i < total; i += cl.G * BLOCK) {
+    const int j = i / nc, c = i - j * nc;
+    const double* ec = e + (size_t)j * ncc;
+    double v;
+    if (P.periodic) {
+      v = (c & 1) ? 0.5 * (ec[(c - 1) >> 1] + ec[wrapc((c + 1) >> 1, ncc)]) : ec[c >> 1];
+    } else if (c == 0 || c == nc - 1) {
+      v = ec[c == 0 ? 0 : ncc - 1];
+    } else {
+      const int p = c - 1;
+      v = (p & 1) ? 0.5 * (ec[((p - 1) >> 1) + 1] + ec[((p + 1) >> 1) + 1]) : ec[(p >> 1) + 1];
+    }
+    u[i] += v;
+  }
+}
+
+DEV void phase_coarse(const Problem& P, Cl& cl, const double* f, double* o) {
+  const int cn = P.cn;
+  for (int i = cl.rank * BLOCK + threadIdx.x; i < cn; i += cl.G * BLOCK) {
+    double s = 0.0;
+    for (int j = 0; j < cn; ++j) s += P.cinv[(size_t)j * cn + i] * f[j];
+    o[i] = s;
+  }
+}
+
+DEV void phase_zero(const Problem& P, Cl& cl, double* v, int len) {
+  for (int i = cl.rank * BLOCK + threadIdx.x; i < len; i += cl.G * BLOCK) v[i] = 0.0;
+}
+
+DEV void phase_copy(const Problem& P, Cl& cl, const double* src, double* dst, int len) {
+  for (int i = cl.rank * BLOCK + threadIdx.x; i < len; i += cl.G * BLOCK) dst[i] = src[i];
+}
+
+// z = M^-1 v. v and z are level-0 vectors distinct from each other and from the level-0
+// scratch (lev[0].u, lev[0].o). Ends with a cluster barrier.
+DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* cp) {
+  const int n = P.n;
+  if (P.pc == SA_PC_NONE) {
+    phase_copy(P, cl, v, z, n);
+    csync(cl);
+    return;
+  }
+  double* A0 = P.lev[0].u;
+  double* B0 = P.lev[0].o;
+  if (P.pc == SA_PC_LINE) {  // nu1 sweeps from zero, the last one writes z
+    const double* prev = nullptr;
+    for (int s = 0; s < P.nu1; ++s) {
+      double* dst = (s == P.nu1 - 1) ? z : ((prev == A0) ? B0 : A0);
+      phase_sweep(P, cl, 0, v, prev, dst, cp);
+      csync(cl);
+      prev = dst;
+    }
+    return;
+  }
+  const int L = P.nlev;
+  if (L == 1) {
+    phase_coarse(P, cl, v, z);
+    csync(cl);
+    return;
+  }
+  const double* f[MAXLEV];
+  const double* outp[MAXLEV];
+  double* uc[MAXLEV];
+  f[0] = v;
+  for (int l = 1; l < L; ++l) f[l] = P.lev[l].f;
+  for (int l = 0; l < L - 1; ++l) {
+    double* A = P.lev[l].u;
+    double* B = P.lev[l].o;
+    const int len = P.lev[l].ncol * P.nl;
+    const double* prev = nullptr;
+    double* dst = A;
+    if (P.nu1 == 0) {
+      phase_zero(P, cl, A, len);
+      csync(cl);
+    }
+    for (int s = 0; s < P.nu1; ++s) {
+      dst = (prev == A) ? B : A;
+      phase_sweep(P, cl, l, f[l], prev, dst, cp);
+      csync(cl);
+      prev = dst;
+    }
+    uc[l] = dst;
+    phase_restrict(P, cl, l, f[l], uc[l], P.lev[l + 1].f);
+    csync(cl);
+  }
+  phase_coarse(P, cl, f[L - 1], P.lev[L - 1].o);
+  csync(cl);
+  outp[L - 1] = P.lev[L - 1].o;
+  for (int l = L - 2; l >= 0; --l) {
+    phase_prolong(P, cl, l, outp[l + 1], uc[l]);
+    csync(cl);
+    double* A = P.lev[l].u;
+    double* B = P.lev[l].o;
+    const double* prev = uc[l];
+    for (int s = 0; s < P.nu2; ++s) {
+      double* dst = (l == 0 && s == P.nu2 - 1) ? z : ((prev == A) ? B : A);
+      phase_sweep(P, cl, l, f[l], prev, dst, cp);
+      csync(cl);
+      prev = dst;
+    }
+    if (l == 0 && P.nu2 == 0) {
+      phase_copy(P, cl, uc[0], z, n);
+      csync(cl);
+      prev = z;
+    }
+    outp[l] = prev;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Arnoldi pieces. V holds raw (unnormalised) basis vectors; vs[i] scales V_i to unit norm.
+
+// red[i] = vs[i] * (V_i . w), i < nv; red[nv] = ||w||^2 if with_norm
+DEV void phase_dots(const Problem& P, Cl& cl, const double* V, const double* vs, int nv, const double* w,
+                    bool with_norm, double* wsum, double* red) {
+  const int n = P.n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int stride = cl.G * BLOCK;
+  const int nred = nv + (with_norm ? 1 : 0);
+  for (int i = 0; i < nred; ++i) {
+    const double* a = (i < nv) ? V + (size_t)i * n : w;
+    double s = 0.0;
+    for (int e = cl.rank * BLOCK + threadIdx.x; e < n; e += stride) s += a[e] * w[e];
+    s = wave_sum(s);
+    if (lane == 0) wsum[i * 4 + wave] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nred; i += BLOCK) {
+    const double s = (wsum[i * 4] + wsum[i * 4 + 1]) + (wsum[i * 4 + 2] + wsum[i * 4 + 3]);
+    red[i] = (i < nv) ? vs[i] * s : s;
+  }
+  __syncthreads();
+}
+
+// w -= sum_i h[i] vs[i] V_i (in place); then red[i] = vs[i] (V_i . w) for i < nv when dots,
+// or red[0] = ||w||^2 when !dots.
+DEV void phase_update(const Problem& P, Cl& cl, const double* V, const double* vs, const double* h, int nv,
+                      double* w, bool dots, double* wsum, double* red) {
+  const int n = P.n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int stride = cl.G * BLOCK;
+  double nrm = 0.0;
+  if (dots)
+    for (int i = threadIdx.x; i < nv * 4; i += BLOCK) wsum[i] = 0.0;
+  __syncthreads();
+  // each wave walks its own 64-element chunks so that per-chunk sums stay in one order
+  for (int base = cl.rank * BLOCK + wave * 64; base < n; base += stride) {
+    const int e = base + lane;
+    const bool ok = e < n;
+    double we = ok ? w[e] : 0.0;
+    for (int i = 0; i < nv; ++i) we -= (ok ? V[(size_t)i * n + e] : 0.0) * (h[i] * vs[i]);
+    if (ok) w[e] = we;
+    if (dots) {
+      for (int i = 0; i < nv; ++i) {
+        double p = (ok ? V[(size_t)i * n + e] : 0.0) * we;
+        p = wave_sum(p);
+        if (lane == 0) wsum[i * 4 + wave] += p;
+      }
+    } else {
+      nrm += we * we;
+    }
+  }
+  __syncthreads();
+  if (dots) {
+    for (int i = threadIdx.x; i < nv; i += BLOCK)
+      red[i] = vs[i] * ((wsum[i * 4] + wsum[i * 4 + 1]) + (wsum[i * 4 + 2] + wsum[i * 4 + 3]));
+    __syncthreads();
+  } else {
+    block_sum_to(nrm, wsum, red, 0);
+  }
+}
+
+// dst = src + sum_i y[i] vs[i] V_i
+DEV void phase_combine(const Problem& P, Cl& cl, const double* V, const double* vs, const double* y, int nv,
+                       const double* src, double* dst) {
+  const int n = P.n;
+  for (int e = cl.rank * BLOCK + threadIdx.x; e < n; e += cl.G * BLOCK) {
+    double v = src[e];
+    for (int i = 0; i < nv; ++i) v += V[(size_t)i * n + e] * (y[i] * vs[i]);
+    dst[e] = v;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// sketch guess (Alg. 2 with V = Y of Alg. 4)
+
+// Y_new = r Y_old + x omega^T (all k columns, elementwise)
+DEV void phase_push(const Problem& P, Cl& cl, const SolveArgs& a, const double* Yo, double* Yn) {
+  const size_t n = P.n;
+  for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK) {
+    const double xe = P.x[e];
+    for (int c = 0; c < P.k; ++c) Yn[c * n + e] = a.r * Yo[c * n + e] + a.om[c] * xe;
+  }
+}
+
+// ---- double-double helpers (error-free transformations, Dekker / Knuth / Bailey) -------
+struct dd {
+  double hi, lo;
+};
+
+DEV dd two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b;
+  const double bb = s - a;
+  return dd{s, (a - (s - bb)) + (b - bb)};
+}
+
+DEV dd quick_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b;
+  return dd{s, b - (s - a)};
+}
+
+DEV dd two_prod(double a, double b) {
+  const double p = a * b;
+  return dd{p, fma(a, b, -p)};
+}
+
+DEV dd dd_add(dd a, dd b) {
+#pragma clang fp contract(off)
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = quick_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+
+DEV dd dd_neg(dd a) { return dd{-a.hi, -a.lo}; }
+DEV dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
+
+DEV dd dd_mul(dd a, dd b) {
+#pragma clang fp contract(off)
+  dd p = two_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return quick_two_sum(p.hi, p.lo);
+}
+
+DEV dd dd_mul_d(dd a, double b) {
+#pragma clang fp contract(off)
+  dd p = two_prod(a.hi, b);
+  p.lo += a.lo * b;
+  return quick_two_sum(p.hi, p.lo);
+}
+
+DEV dd dd_div(dd a, dd b) {
+  const double q1 = a.hi / b.hi;
+  dd r = dd_sub(a, dd_mul_d(b, q1));
+  const double q2 = r.hi / b.hi;
+  r = dd_sub(r, dd_mul_d(b, q2));
+  const double q3 = r.hi / b.hi;
+  dd q = quick_two_sum(q1, q2);
+  return dd_add(q, dd{q3, 0.0});
+}
+
+DEV dd dd_sqrt(dd a) {
+  if (!(a.hi > 0.0)) return dd{0.0, 0.0};
+  const double x = sqrt(a.hi);
+  const dd r = dd_sub(a, two_prod(x, x));
+  return quick_two_sum(x, r.hi / (2.0 * x));
+}
+
+// For every tile: Y_new (fused push), W_a = A Y_new_a into LDS, then the products
+// G_ab = W_a . W_b (a <= b) and c_a = W_a . b. Products are exact (FMA TwoProduct) and
+// sums compensated (TwoSum), so the Gram carries the accuracy a QR of W would: its
+// condition number is the square of W's, and the sketch's columns are nearly dependent.
+// Output: red[2 i], red[2 i + 1] = hi, lo of item i (pairs in row order, then c).
+DEV void phase_block_gram(const Problem& P, Cl& cl, const SolveArgs& a, const double* Yo, double* Yn,
+                          double* lds, double* red) {
+  const int nc = P.ncol, nl = P.nl, k = P.k;
+  const size_t n = P.n;
+  const Tiles T = tiles_of(P, TXG);
+  constexpr int W = TWGM;
+  double* sW = lds;                         // k x W x nl
+  double* sb = sW + (size_t)k * W * nl;     // W x nl
+  double* sx = sb + W * nl;                 // (W+12) x nl
+  double* sgx = sx + (W + 12) * nl;         // (W+6) x nl
+  double* sgz = sgx + (W + 6) * nl;         // (W+6) x nl
+  const int npair = k * (k + 1) / 2;
+  const int nitem = npair + k;
+  const int Q = BLOCK / nitem > 0 ? BLOCK / nitem : 1;  // threads per item
+  const int item = threadIdx.x % nitem, qq = threadIdx.x / nitem;
+  const bool active = qq < Q;
+  int pa = 0, pb = -1;
+  if (item < npair) {
+    int t = item, rowlen = k;
+    while (t >= rowlen) { t -= rowlen; ++pa; --rowlen; }
+    pb = pa + t;
+  } else {
+    pa = item - npair;
+  }
+  double accS = 0.0, accC = 0.0;
+  for (int t = cl.rank; t < T.nt; t += cl.G) {
+    const int c0 = t * TXG;
+    const int w = (t == T.nt - 1) ? nc - c0 : TXG;
+    for (int i = threadIdx.x; i < W * nl; i += BLOCK) {
+      const int lj = i / W, lc = i - lj * W;
+      sb[i] = (lc < w) ? a.b[(size_t)lj * nc + c0 + lc] : 0.0;
+    }
+    for (int col = 0; col < k; ++col) {
+      const double* yo = Yo + (size_t)col * n;
+      double* yn = Yn + (size_t)col * n;
+      const double om = a.om[col];
+      // Y_new = r Y_old + omega x, recomputed on the halo (no race with other tiles); the
+      // tile's own columns are written back
+      auto load = [&](int lj, int c, int lc) {
+        const size_t e = (size_t)lj * nc + c;
+        if (!a.push) return yo[e];
+        const double v = a.r * yo[e] + om * P.x[e];
+        if (lc >= 6 && lc < w + 6) yn[e] = v;
+        return v;
+      };
+      double* wcol = sW + (size_t)col * W * nl;
+      tile_operator<W>(P, c0, w, load, sx, sgx, sgz, [&](int lj, int lc, int, double v) {
+        wcol[lj * W + lc] = v;
+      });
+    }
+    // zero the unused tile columns so that the products can run over the full W x nl
+    for (int i = threadIdx.x; i < k * W * nl; i += BLOCK) {
+      const int lc = i % W;
+      if (lc >= w) sW[i] = 0.0;
+    }
+    __syncthreads();
+    if (active) {
+      const double* wa = sW + (size_t)pa * W * nl;
+      const double* wb = (pb >= 0) ? sW + (size_t)pb * W * nl : sb;
+      for (int p = qq; p < W * nl; p += Q) {
+        const dd pr = two_prod(wa[p], wb[p]);
+        const dd s = two_sum(accS, pr.hi);
+        accS = s.hi;
+        accC += s.lo + pr.lo;
+      }
+    }
+    __syncthreads();
+  }
+  // combine the Q partials of each item in a fixed order
+  double* sS = lds;
+  double* sC = lds + BLOCK;
+  sS[threadIdx.x] = active ? accS : 0.0;
+  sC[threadIdx.x] = active ? accC : 0.0;
+  __syncthreads();
+  if (threadIdx.x < nitem) {
+    dd acc{0.0, 0.0};
+    for (int q = 0; q < Q; ++q) acc = dd_add(acc, quick_two_sum(sS[q * nitem + threadIdx.x], sC[q * nitem + threadIdx.x]));
+    red[2 * threadIdx.x] = acc.hi;
+    red[2 * threadIdx.x + 1] = acc.lo;
+  }
+  __syncthreads();
+}
+
+// red holds nv double-double values (hi, lo interleaved) of this workgroup; afterwards the
+// cluster sums, added in rank order with double-double arithmetic.
+DEV void cluster_sum_dd(Cl& cl, double* red, int nv) {
+  __syncthreads();
+  if (cl.G == 1) return;
+  double* part = cl.partials + (size_t)cl.pbuf * cl.G * PSTRIDE;
+  for (int i = threadIdx.x; i < 2 * nv; i += BLOCK) part[cl.rank * PSTRIDE + i] = red[i];
+  cl.pbuf ^= 1;
+  csync(cl);
+  for (int i = threadIdx.x; i < nv; i += BLOCK) {
+    dd s{0.0, 0.0};
+    for (int g = 0; g < cl.G; ++g) s = dd_add(s, dd{part[g * PSTRIDE + 2 * i], part[g * PSTRIDE + 2 * i + 1]});
+    red[2 * i] = s.hi;
+    red[2 * i + 1] = s.lo;
+  }
+  __syncthreads();
+}
+
+// k x k least squares from the Gram: column scaling D = diag(G_aa)^-1/2, right-looking
+// double-double Cholesky of D G D taking columns in order and dropping a column whose pivot
+// falls below tau^2 (the projected norm of the unit column below tau, as in a QR with the
+// same drop rule), then z = D (L L^T)^-1 D c over the kept columns. The whole workgroup
+// runs it on identical inputs in every workgroup of the cluster. Returns the rank.
+DEV int small_solve(const Problem& P, const double* red, double tau, double* z, double* scr) {
+  const int k = P.k, tid = threadIdx.x;
+  double* gh = scr;               // k x k hi (lower part becomes L)
+  double* gl = gh + k * k;        // k x k lo
+  double* dsc = gl + k * k;       // k
+  double* vh = dsc + k;           // k rhs / solution hi
+  double* vl = vh + k;            // k lo
+  int* kept = (int*)(vl + k);     // k
+  auto item = [&](int i, int j) {
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    return a * k - a * (a - 1) / 2 + (b - a);
+  };
+  const int npair = k * (k + 1) / 2;
+  if (tid < k) {
+    const double gii = red[2 * item(tid, tid)];
+    dsc[tid] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += BLOCK) {
+    const int i = e / k, j = e - i * k;
+    const int it = item(i, j);
+    const dd g = dd_mul_d(dd_mul_d(dd{red[2 * it], red[2 * it + 1]}, dsc[i]), dsc[j]);
+    gh[e] = g.hi;
+    gl[e] = g.lo;
+  }
+  if (tid < k) {
+    const dd c = dd_mul_d(dd{red[2 * (npair + tid)], red[2 * (npair + tid) + 1]}, dsc[tid]);
+    vh[tid] = c.hi;
+    vl[tid] = c.lo;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      const dd d{gh[j * k + j], gl[j * k + j]};
+      const bool keep = dsc[j] > 0.0 && d.hi >= tau * tau;
+      kept[j] = keep;
+      const dd ljj = keep ? dd_sqrt(d) : dd{0.0, 0.0};
+      gh[j * k + j] = ljj.hi;
+      gl[j * k + j] = ljj.lo;
+    }
+    __syncthreads();
+    if (!kept[j]) continue;
+    const dd ljj{gh[j * k + j], gl[j * k + j]};
+    if (tid > j && tid < k) {
+      const dd lij = dd_div(dd{gh[tid * k + j], gl[tid * k + j]}, ljj);
+      gh[tid * k + j] = lij.hi;
+      gl[tid * k + j] = lij.lo;
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += BLOCK) {
+      const int i = e / k, l = e - i * k;
+      if (l > j && i >= l) {
+        const dd upd = dd_mul(dd{gh[i * k + j], gl[i * k + j]}, dd{gh[l * k + j], gl[l * k + j]});
+        const dd g = dd_sub(dd{gh[e], gl[e]}, upd);
+        gh[e] = g.hi;
+        gl[e] = g.lo;
+      }
+    }
+    __syncthreads();
+  }
+  // forward substitution L y = D c, then L^T z = y (kept columns only)
+  for (int j = 0; j < k; ++j) {
+    if (kept[j]) {
+      if (tid == 0) {
+        const dd y = dd_div(dd{vh[j], vl[j]}, dd{gh[j * k + j], gl[j * k + j]});
+        vh[j] = y.hi;
+        vl[j] = y.lo;
+      }
+      __syncthreads();
+      if (tid > j && tid < k && kept[tid]) {
+        const dd v = dd_sub(dd{vh[tid], vl[tid]}, dd_mul(dd{gh[tid * k + j], gl[tid * k + j]}, dd{vh[j], vl[j]}));
+        vh[tid] = v.hi;
+        vl[tid] = v.lo;
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    if (kept[j]) {
+      if (tid == 0) {
+        const dd y = dd_div(dd{vh[j], vl[j]}, dd{gh[j * k + j], gl[j * k + j]});
+        vh[j] = y.hi;
+        vl[j] = y.lo;
+      }
+      __syncthreads();
+      if (tid < j && kept[tid]) {
+        const dd v = dd_sub(dd{vh[tid], vl[tid]}, dd_mul(dd{gh[j * k + tid], gl[j * k + tid]}, dd{vh[j], vl[j]}));
+        vh[tid] = v.hi;
+        vl[tid] = v.lo;
+      }
+    }
+    __syncthreads();
+  }
+  int rank = 0;
+  for (int j = 0; j < k; ++j) rank += kept[j];
+  if (tid < k) z[tid] = kept[tid] ? (vh[tid] + vl[tid]) * dsc[tid] : 0.0;
+  __syncthreads();
+  return rank;
+}
+
+// x = Y z
+DEV void phase_sketch_combine(const Problem& P, Cl& cl, const double* Yn, const double* z) {
+  const size_t n = P.n;
+  for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK) {
+    double v = 0.0;
+    for (int c = 0; c < P.k; ++c) v += Yn[c * n + e] * z[c];
+    P.x[e] = v;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// per-phase wall-clock accounting (workgroup 0, thread 0), enabled when a.prof != nullptr
+struct PhaseClock {
+  unsigned long long acc[NPHASE];
+  unsigned long long last, start;
+  bool on;
+  DEV void begin(bool enable) {
+    on = enable && blockIdx.x == 0 && threadIdx.x == 0;
+    for (int i = 0; i < NPHASE; ++i) acc[i] = 0;
+    last = start = on ? wall_clock64() : 0;
+  }
+  DEV void tick(int cat) {
+    if (!on) return;
+    const unsigned long long now = wall_clock64();
+    acc[cat] += now - last;
+    last = now;
+  }
+  DEV void flush(unsigned long long* out) {
+    if (!on) return;
+    acc[PH_TOTAL] = wall_clock64() - start;
+    for (int i = 0; i < NPHASE; ++i) atomicAdd(out + i, acc[i]);
+  }
+};
+
+// LDS layout of the solve kernel
+struct Smem {
+  double* red;    // PSTRIDE
+  double* wsum;   // 4 * (MMAX + 2)
+  double* H;      // (m+1) x m, column j at j*(m+1)
+  double* cs;     // m
+  double* sn;     // m
+  double* g;      // m+1
+  double* vs;     // m+1
+  double* y;      // m
+  double* z;      // KMAX
+  double* scr;    // 4 KMAX^2 + 8
+  double* big;    // phase scratch
+};
+
+DEV Smem carve(double* s, int m) {
+  Smem S;
+  S.red = s;
+  S.wsum = S.red + PSTRIDE;
+  S.H = S.wsum + 4 * (MMAX + 2);
+  S.cs = S.H + (m + 1) * m;
+  S.sn = S.cs + m;
+  S.g = S.sn + m;
+  S.vs = S.g + m + 1;
+  S.y = S.vs + m + 1;
+  S.z = S.y + m;
+  S.scr = S.z + KMAX;
+  S.big = S.scr + 4 * KMAX * KMAX + 8;
+  return S;
+}
+
+// back substitution R y = g on the leading jj x jj block of H (thread 0), y in LDS
+DEV void back_substitute(const Smem& S, int m, int jj) {
+  if (threadIdx.x == 0) {
+    for (int i = jj - 1; i >= 0; --i) {
+      double s = S.g[i];
+      for (int q = i + 1; q < jj; ++q) s -= S.H[q * (m + 1) + i] * S.y[q];
+      S.y[i] = s / S.H[i * (m + 1) + i];
+    }
+  }
+  __syncthreads();
+}
+
+extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Problem* __restrict__ PP, SolveArgs a) {
+  const Problem& P = *PP;
+  extern __shared__ double smem[];
+  const int m = P.m;
+  Smem S = carve(smem, m);
+  Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
+  const int tid = threadIdx.x;
+  const size_t n = P.n;
+
+  PhaseClock clk;
+  clk.begin(a.prof != nullptr);
+  phase_geometry(P, cl, a.eta_p, a.eta_c);
+  csync(cl);
+  clk.tick(PH_GEOM);
+
+  // ---------------- initial guess
+  const double* Yo = P.Y[a.ycur];
+  double* Yn = P.Y[a.ycur ^ 1];
+  int rank = 0;
+  if (a.sketch_guess) {
+    phase_block_gram(P, cl, a, Yo, Yn, S.big, S.red);
+    const int nv = P.k * (P.k + 1) / 2 + P.k;
+    cluster_sum_dd(cl, S.red, nv);
+    clk.tick(PH_GUESS);
+    rank = small_solve(P, S.red, P.tau_drop, S.z, S.scr);
+    csync(cl);  // every tile has read x (the previous solution) before it is overwritten
+    clk.tick(PH_SMALL);
+    phase_sketch_combine(P, cl, a.push ? Yn : Yo, S.z);
+  } else {
+    if (a.push) phase_push(P, cl, a, Yo, Yn);
+    if (!a.prev_guess) {
+      csync(cl);
+      for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) P.x[e] = 0.0;
+    }
+  }
+  csync(cl);
+  clk.tick(PH_GUESS);
+
+  // ---------------- r0 = b - A x0
+  phase_operator(P, cl, P.x, 1.0, P.r, a.b, S.big, S.red, 0);
+  cluster_sum(cl, S.red, 2);
+  clk.tick(PH_OPER);
+  const double nb = sqrt(S.red[1]);
+  double rn = sqrt(S.red[0]);
+  sa_solve_info info;
+  info.iters = 0; info.restarts = 0; info.refinements = 0; info.status = SA_OK; info.rank = rank; info.checks = 0;
+  info.relres0 = nb > 0.0 ? rn / nb : 0.0;
+  info.relres = info.relres0;
+  const double rtol = a.rtol;
+  bool done = false;
+  double* x = P.x;
+  double* xc = P.xc;
+  double* r = P.r;
+  double* rc = P.rc;
+  if (!(nb > 0.0)) {
+    if (!(nb == 0.0)) atomicOr(P.flags + FLAG_NONFINITE, 1);
+    for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) x[e] = 0.0;
+    info.relres0 = info.relres = 0.0;
+    done = true;
+  } else if (!isfinite(rn)) {
+    atomicOr(P.flags + FLAG_NONFINITE, 1);
+    done = true;
+  } else if (rn <= rtol * nb) {
+    done = true;
+  }
+  double trigger = 0.0;
+  if (!done) {
+    // trigger of the true-residual check: rtol ||M^-1 b||
+    precond(P, cl, a.b, P.t, S.big);
+    clk.tick(PH_PREC);
+    block_sum_to([&] {
+      double s = 0.0;
+      for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) s += P.t[e] * P.t[e];
+      return s;
+    }(), S.wsum, S.red, 0);
+    cluster_sum(cl, S.red, 1);
+    trigger = rtol * sqrt(S.red[0]);
+  }
+  // ---------------- restarted GMRES
+  while (!done && !aborted(cl)) {
+    double* V = P.V;
+    clk.tick(PH_OTHER);
+    precond(P, cl, r, V, S.big);
+    clk.tick(PH_PREC);
+    block_sum_to([&] {
+      double s = 0.0;
+      for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) s += V[e] * V[e];
+      return s;
+    }(), S.wsum, S.red, 0);
+    cluster_sum(cl, S.red, 1);
+    const double beta = sqrt(S.red[0]);
+    if (tid == 0) {
+      S.vs[0] = 1.0 / beta;
+      S.g[0] = beta;
+    }
+    __syncthreads();
+    bool restart_now = false;
+    int jend = m;
+    for (int j = 0; j < m && !aborted(cl); ++j) {
+      info.iters += 1;
+      double* wv = V + (size_t)(j + 1) * n;
+      clk.tick(PH_OTHER);
+      phase_operator(P, cl, V + (size_t)j * n, S.vs[j], P.t, nullptr, S.big, S.red, 0);
+      csync(cl);
+      clk.tick(PH_OPER);
+      precond(P, cl, P.t, wv, S.big);
+      clk.tick(PH_PREC);
+      // CGS2: h1 = V^T w (and ||w||), w -= V h1, h2 = V^T w, w -= V h2
+      phase_dots(P, cl, V, S.vs, j + 1, wv, true, S.wsum, S.red);
+      cluster_sum(cl, S.red, j + 2);
+      const double w0 = sqrt(S.red[j + 1]);
+      if (tid < j + 1) S.H[j * (m + 1) + tid] = S.red[tid];
+      __syncthreads();
+      phase_update(P, cl, V, S.vs, S.H + j * (m + 1), j + 1, wv, true, S.wsum, S.red);
+      cluster_sum(cl, S.red, j + 1);
+      if (tid < j + 1) S.y[tid] = S.red[tid];  // h2 (y is free here)
+      __syncthreads();
+      phase_update(P, cl, V, S.vs, S.y, j + 1, wv, false, S.wsum, S.red);
+      cluster_sum(cl, S.red, 1);
+      clk.tick(PH_ORTH);
+      const double hn = sqrt(S.red[0]);
+      // Givens rotations (identical in every workgroup)
+      if (tid == 0) {
+        double* col = S.H + j * (m + 1);
+        for (int i = 0; i <= j; ++i) col[i] += S.y[i];
+        col[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+          const double t0 = S.cs[i] * col[i] + S.sn[i] * col[i + 1];
+          col[i + 1] = -S.sn[i] * col[i] + S.cs[i] * col[i + 1];
+          col[i] = t0;
+        }
+        const double den = hypot(col[j], col[j + 1]);
+        S.cs[j] = col[j] / den;
+        S.sn[j] = col[j + 1] / den;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        S.g[j + 1] = -S.sn[j] * S.g[j];
+        S.g[j] = S.cs[j] * S.g[j];
+        S.vs[j + 1] = 1.0 / hn;
+      }
+      __syncthreads();
+      const bool breakdown = hn <= 1e-14 * w0;
+      if (breakdown || fabs(S.g[j + 1]) <= trigger) {
+        back_substitute(S, m, j + 1);
+        phase_combine(P, cl, V, S.vs, S.y, j + 1, x, xc);
+        csync(cl);
+        clk.tick(PH_OTHER);
+        phase_operator(P, cl, xc, 1.0, rc, a.b, S.big, S.red, 0);
+        cluster_sum(cl, S.red, 2);
+        clk.tick(PH_OPER);
+        const double rcn = sqrt(S.red[0]);
+        info.checks += 1;
+        if (rcn <= rtol * nb) {
+          double* t = x; x = xc; xc = t;
+          info.relres = rcn / nb;
+          done = true;
+          break;
+        }
+        if (breakdown || !isfinite(rcn)) {
+          double* t = x; x = xc; xc = t;
+          t = r; r = rc; rc = t;
+          rn = rcn;
+          restart_now = true;
+          if (!isfinite(rcn)) { atomicOr(P.flags + FLAG_NONFINITE, 1); done = true; }
+          break;
+        }
+        trigger = fabs(S.g[j + 1]) * rtol * nb / rcn;
+      }
+    }
+    if (done) break;
+    if (!restart_now) {
+      back_substitute(S, m, jend);
+      phase_combine(P, cl, V, S.vs, S.y, jend, x, x);
+      csync(cl);
+      clk.tick(PH_OTHER);
+      phase_operator(P, cl, x, 1.0, r, a.b, S.big, S.red, 0);
+      cluster_sum(cl, S.red, 2);
+      clk.tick(PH_OPER);
+      rn = sqrt(S.red[0]);
+      info.relres = rn / nb;
+      if (rn <= rtol * nb) break;
+      if (!isfinite(rn)) { atomicOr(P.flags + FLAG_NONFINITE, 1); break; }
+    }
+    info.relres = rn / nb;
+    info.restarts += 1;
+    if (info.restarts > P.max_restarts) {
+      info.status = SA_NOCONV;
+      break;
+    }
+  }
+  // the solution must end in P.x (the next solve's previous solution)
+  if (x != P.x) {
+    csync(cl);
+    phase_copy(P, cl, x, P.x, P.n);
+  }
+  clk.tick(PH_OTHER);
+  if (cl.rank == 0 && tid == 0) {
+    if (aborted(cl)) info.status = SA_EDEVICE;
+    P.log[a.log_slot] = info;
+  }
+  clk.flush(a.prof);
+}
+
+// ------------------------------------------------------------------------------------------
+// standalone entry kernels (operator and preconditioner applications, sketch push)
+
+extern "C" __global__ void __launch_bounds__(BLOCK) sa_geometry_kernel(const Problem* __restrict__ PP,
+                                                                       const double* eta_p, const double* eta_c) {
+  const Problem& P = *PP;
+  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
+  phase_geometry(P, cl, eta_p, eta_c);
+}
+
+extern "C" __global__ void __launch_bounds__(BLOCK) sa_operator_kernel(const Problem* __restrict__ PP,
+                                                                       const double* x, double* y) {
+  const Problem& P = *PP;
+  extern __shared__ double smem[];
+  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
+  phase_operator(P, cl, x, 1.0, y, nullptr, smem, smem, 0);
+}
+
+extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond_kernel(const Problem* __restrict__ PP,
+                                                                      const double* v, double* z) {
+  const Problem& P = *PP;
+  extern __shared__ double smem[];
+  Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
+  precond(P, cl, v, z, smem);
+}
+
+extern "C" __global__ void __launch_bounds__(BLOCK) sa_push_kernel(const Problem* __restrict__ PP, SolveArgs a) {
+  const Problem& P = *PP;
+  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
+  phase_push(P, cl, a, P.Y[a.ycur], P.Y[a.ycur ^ 1]);
+}
+
+}  // namespace sa

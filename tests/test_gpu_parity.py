@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element.
+
+Every input is seeded and synthetic (paper_2511_18071_amd.workload). The right-hand sides
+are formed by the oracle (b = A p*) and handed to both sides, so both solve the same system.
+Tolerances follow from the FP64 arithmetic:
+
+* operator: |y_gpu - y_oracle|_i <= 1e-11 max((|A| |x|)_i, 1e-4 max_j (|A| |x|)_j) (both sides
+  sum O(100) products; the GPU composes two seven-point passes, the oracle applies the
+  assembled product; the floor covers rows where the field vanishes locally);
+* preconditioner: 1e-11 max|z| (column eliminations on the GPU vs sparse LU in the oracle);
+* solves: identical decisions (iterations, restarts, residual checks, guess rank) on the
+  small cases, relative residual <= rtol, and solution difference <= 1e-7 relative
+  (the stated solution-error bar).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import precond as opc
+from oracle.discretization import Grid, mixed_stage_operator
+from oracle.sequence import Simulation
+from paper_2511_18071_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2511_18071_amd import binding
+    return binding
+
+
+def _gpu_problem(B, w, **kw):
+    return B.Problem.from_workload(w, stream=0, **kw)
+
+
+OPERATOR_CASES = ["tiny_17x7", "periodic_65x9", "bar_65x9", "bar_513x17", "walls_131x9", "periodic_101x11"]
+
+
+def _workload(name):
+    if name == "walls_131x9":  # ncol = 133 = 2 tiles of 64 + 5: a ragged last tile
+        w = W.get("bar_65x9")
+        w.nx = 131
+        return w
+    if name == "periodic_101x11":  # ncol = 100: one full tile and a ragged one
+        w = W.get("periodic_65x9")
+        w.nx, w.nz = 101, 11
+        return w
+    return W.get(name)
+
+
+@pytest.mark.parametrize("name", OPERATOR_CASES)
+def test_operator_parity(B, name):
+    w = _workload(name)
+    _say(f"[operator] {name} n={w.n}")
+    g = Grid(w.nx, w.nz, w.bc, w.length)
+    kind = g.row_kinds()
+    rs = np.random.default_rng(11)
+    p = _gpu_problem(B, w)
+    worst = 0.0
+    for s in (0, 3):
+        ep, ec, ps = w.system(s)
+        ec = ec * 1.3  # make the two stages clearly different
+        A = mixed_stage_operator(g, w.depth(), ep, ec)
+        absA = abs(A)
+        p.set_surface(ep, ec)
+        for label, x in (("p*", ps), ("random", rs.standard_normal(w.n))):
+            y = p.apply_operator(x)
+            ref = A @ x
+            # rounding bound of row i, floored at 1e-15 of the largest row bound: where the
+            # field vanishes locally (p* under the bar's envelopes) both sides return rounding
+            # noise of the geometry terms (h_x of a flat bed is itself noise)
+            bound = absA @ np.abs(x)
+            bound = np.maximum(bound, 1e-4 * bound.max())
+            err = np.abs(y - ref)
+            ratio = err / bound
+            worst = max(worst, ratio.max())
+            _say(f"   system {s} {label}: max err {err.max():.3e}, max err/(|A||x|) {ratio.max():.3e}")
+            if ratio.max() > 1e-11:
+                for r in np.argsort(-ratio)[:6]:
+                    _say(f"      row level {r // g.ncol} col {r % g.ncol} kind {kind[r]}: gpu {y[r]:.6e} "
+                         f"oracle {ref[r]:.6e} bound {bound[r]:.3e}")
+    p.close()
+    assert worst <= 1e-11, worst
+
+
+@pytest.mark.parametrize("name,pc,nu,omega", [
+    ("tiny_17x7", "line", 1, 1.0), ("bar_65x9", "line", 1, 1.0), ("periodic_65x9", "line", 2, 0.7),
+    ("tiny_17x7", "mg", 1, 0.5), ("periodic_65x9", "mg", 1, 0.5), ("bar_65x9", "mg", 1, 0.5),
+    ("bar_513x17", "mg", 1, 0.5), ("periodic_65x9", "mg", 2, 0.6), ("bar_65x9", "none", 1, 1.0),
+])
+def test_precond_parity(B, name, pc, nu, omega):
+    w = W.get(name)
+    _say(f"[precond] {name} {pc} nu={nu} omega={omega}")
+    g = Grid(w.nx, w.nz, w.bc, w.length)
+    minv = opc.make(g, w.depth(), pc, nu, nu, omega)
+    p = _gpu_problem(B, w, precond=pc, nu1=nu, nu2=nu, omega=omega)
+    rs = np.random.default_rng(5)
+    for v in (rs.standard_normal(w.n), w.system(2)[2]):
+        z = p.apply_precond(v)
+        ref = minv(v)
+        err = np.abs(z - ref).max() / np.abs(ref).max()
+        _say(f"   rel err {err:.3e}")
+        assert err <= 1e-11
+    p.close()
+
+
+@pytest.mark.parametrize("cluster", [2, 5])
+def test_precond_parity_cluster(B, cluster):
+    w = W.get("bar_513x17")
+    _say(f"[precond cluster] bar_513x17 mg G={cluster}")
+    g = Grid(w.nx, w.nz, w.bc, w.length)
+    minv = opc.make(g, w.depth(), "mg")
+    p = _gpu_problem(B, w, cluster=cluster)
+    v = np.random.default_rng(3).standard_normal(w.n)
+    z = p.apply_precond(v)
+    ref = minv(v)
+    err = np.abs(z - ref).max() / np.abs(ref).max()
+    _say(f"   rel err {err:.3e}")
+    assert err <= 1e-11
+    p.close()
+
+
+def test_precond_one_level_is_exact_solve(B):
+    w = W.get("tiny_17x7")
+    g = Grid(w.nx, w.nz, w.bc, w.length)
+    from oracle.discretization import low_order_operator
+    M = low_order_operator(g, w.depth()).toarray()
+    p = _gpu_problem(B, w, precond="mg", max_levels=1)
+    v = np.random.default_rng(9).standard_normal(w.n)
+    z = p.apply_precond(v)
+    ref = np.linalg.solve(M, v)
+    assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+    p.close()
+
+
+SOLVE_CASES = [
+    ("tiny_17x7", dict(precond="none"), 10),
+    ("tiny_17x7", dict(precond="line", nu1=1, omega=1.0), 10),
+    ("tiny_17x7", dict(precond="mg"), 10),
+    ("periodic_65x9", dict(), 20),
+    ("periodic_65x9", dict(guess="cold"), 6),
+    ("periodic_65x9", dict(guess="previous"), 6),
+    ("bar_65x9", dict(), 20),
+    ("bar_65x9", dict(k=4, r=0.5, restart=8), 12),
+    ("periodic_65x9", dict(cluster=4), 8),
+    ("bar_65x9", dict(cluster=3), 8),
+    ("bar_513x17", dict(), 8),
+    ("bar_513x17", dict(cluster=8), 8),
+]
+
+
+@pytest.mark.parametrize("name,kw,nsys", SOLVE_CASES)
+def test_solve_sequence_parity(B, name, kw, nsys):
+    w = W.get(name)
+    _say(f"[solve] {name} {kw} nsys={nsys}")
+    ora = Simulation.from_workload(w, **{k: v for k, v in kw.items() if k != "cluster"})
+    p = _gpu_problem(B, w, **kw)
+    for s in range(nsys):
+        ep, ec, ps = w.system(s)
+        b = ora.operator(ep, ec) @ ps
+        ro = ora.solve(ep, ec, b)
+        p.set_surface(ep, ec)
+        p.push_rhs(b)
+        info = p.solve()
+        x = p.solution()
+        dx = np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x)
+        _say(f"   sys {s:2d}: gpu it={info.iters} rs={info.restarts} ck={info.checks} rank={info.rank} "
+             f"r0={info.relres0:.2e} r={info.relres:.2e} | oracle it={ro.info.iters} rs={ro.info.restarts} "
+             f"ck={ro.info.checks} rank={ro.rank} r0={ro.info.relres0:.2e} | dx={dx:.2e}")
+        assert info.status == 0
+        assert (info.iters, info.restarts, info.checks, info.rank) == \
+            (ro.info.iters, ro.info.restarts, ro.info.checks, ro.rank)
+        assert info.relres <= w.rtol
+        assert dx <= 1e-7
+    p.close()
+
+
+def test_sketch_matches_oracle(B):
+    w = W.get("tiny_17x7")
+    ora = Simulation.from_workload(w)
+    p = _gpu_problem(B, w)
+    for s in range(4):
+        ep, ec, ps = w.system(s)
+        b = ora.operator(ep, ec) @ ps
+        ora.solve(ep, ec, b)
+        p.set_surface(ep, ec)
+        p.push_rhs(b)
+        p.solve()
+    Y = p.sketch()
+    assert p.sketch_count == 4 == ora.sketch.pushes
+    assert np.abs(Y - ora.sketch.Y).max() <= 1e-9 * np.abs(ora.sketch.Y).max()
+    p.close()

@@ -1,0 +1,71 @@
+"""The C-ABI library loads and exports what include/sawave.h declares (no GPU work here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import rng
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sawave.h")
+
+
+@pytest.fixture(scope="module")
+def binding():
+    from paper_2511_18071_amd import binding
+    return binding
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(sa_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("sa_create", "sa_set_surface", "sa_push_rhs", "sa_solve", "sa_get_solution", "sa_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(binding):
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_options(binding):
+    o = binding.default_options()
+    assert (o.restart, o.max_restarts, o.rtol, o.precond, o.guess, o.k, o.r) == (30, 200, 1e-8, 2, 2, 8, 0.9)
+    assert o.omega == 0.5 and o.tau_drop == 1e-7
+
+
+def test_sketch_draws_bitwise_equal_to_oracle_stream(binding):
+    for seed in (0, 7, 2**63 + 12345):
+        for index in (0, 1, 17, 100000):
+            lib_draws = binding.sketch_draws(seed, index, 16)
+            ref = np.array(rng.omega(seed, index, 16))
+            assert np.array_equal(lib_draws, ref), (seed, index)
+
+
+def test_argument_errors_need_no_gpu(binding):
+    with pytest.raises(binding.SawaveError) as e:
+        binding.Problem(65, 3, "periodic", 1.0, np.ones(64))  # nz too small
+    assert e.value.code == -1
+    with pytest.raises(binding.SawaveError) as e:
+        binding.Problem(65, 9, "periodic", 1.0, -np.ones(64))  # non-positive depth
+    assert e.value.code == -2
+    with pytest.raises(binding.SawaveError):
+        binding.Problem(65, 9, "periodic", 1.0, np.ones(64), k=17)
+    with pytest.raises(binding.SawaveError):
+        binding.Problem(65, 9, "periodic", 1.0, np.ones(64), restart=0)
+
+
+def test_ctypes_struct_layout(binding):
+    # field offsets follow the C rules for the declared order (int32 then double gets padded)
+    assert binding.SaGrid.length.offset == 16
+    assert ctypes.sizeof(binding.SaSolveInfo) == 6 * 4 + 2 * 8
+    assert binding.SaOptions.rtol.offset == 8
