@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the subspace-accelerated Poisson sequence on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bar_513x17]
+
+A step is one LSERK45 time step of the synthetic simulation: five sequential mixed-stage
+Poisson solves (one per Runge-Kutta stage), each from the EWMA-subspace initial guess,
+GMRES to relative residual 1e-8 with the still-water V-cycle preconditioner, FP64.
+Inputs (surfaces at the stage times, manufactured right-hand sides b = A p* formed by the
+library's own operator) are resident in HBM before the timed region starts. The same K
+steps are then solved by the plain path (cold start x0 = 0, same GMRES) for the
+subspace-vs-plain comparison. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="bar_513x17")
+    ap.add_argument("--cluster", type=int, default=0, help="workgroups per solve (0 = size rule)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-solves", type=int, default=30)
+    return ap.parse_args()
+
+
+def default_cluster(w) -> int:
+    # one workgroup per ~4 operator tiles, at least 1, at most 64
+    return int(min(64, max(1, (w.ncol + 255) // 256 * 2)))
+
+
+def traffic_bytes(w, infos, pcv, k) -> float:
+    """Algorithmic HBM bytes of the solves in `infos`, in vectors of n FP64 values.
+
+    guess            3k + 3   read Y_old and x, write Y_new, read b (block operator + Gram),
+                              read Y_new, write x0
+    r0 = b - A x0    3        read x0 and b, write r0
+    trigger M^-1 b   pcv + 1  one V-cycle and the norm of its output
+    cycle start      pcv + 1  V-cycle of r and its norm (once per cycle)
+    Arnoldi step j   2 + pcv + 3j + 8
+                              operator (read v_j, write t), V-cycle, CGS2 in three passes over
+                              V_0..V_j and w: dots (j+2), update + dots (j+3), update + norm (j+3)
+    check / cycle end  j + 6  x + V y (read j+1 basis vectors and x, write) and b - A x (3)
+    """
+    vb = 8.0 * w.n
+    m = w.restart
+    total = 0.0
+    for inf in infos:
+        v = (3 * k + 3) + 3
+        if inf.iters > 0:
+            v += pcv + 1
+            cycles = inf.restarts + 1
+            v += cycles * (pcv + 1)
+            for step in range(inf.iters):
+                j = step % m
+                v += 2 + pcv + 3 * j + 8
+            jbar = min(inf.iters, m) / 2.0
+            v += (inf.checks + cycles) * (jbar + 6)
+        total += v * vb
+    return total
+
+
+def precond_vectors(w) -> float:
+    """Vectors moved by one V(1,1) cycle of the still-water preconditioner: per level the
+    down pass reads f and writes u and the coarse f (2.5), the up pass reads u, f and the
+    coarse correction and writes the output (3.5); levels halve in size, so the hierarchy
+    moves 6 x (1 + 1/2 + 1/4 + ...) ~ 12 fine-grid vectors."""
+    return 12.0
+
+
+def run_gpu(args, w):
+    import torch
+    from paper_2511_18071_amd import binding as B
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    nsys = 5 * (args.warmup + args.steps)
+    G = args.cluster or default_cluster(w)
+    # ---- stage the inputs: surfaces at the stage times and b = A p*
+    etas = torch.empty((nsys, 2, w.nphys), dtype=torch.float64, device=dev)
+    bs = torch.empty((nsys, w.n), dtype=torch.float64, device=dev)
+    with B.Problem.from_workload(w, stream=stream, cluster=G) as gen:
+        for s in range(nsys):
+            ep, ec, ps = w.system(s)
+            etas[s, 0].copy_(torch.from_numpy(ep))
+            etas[s, 1].copy_(torch.from_numpy(ec))
+            pst = torch.from_numpy(ps).to(dev)
+            gen.set_surface(etas[s, 0], etas[s, 1])
+            gen.apply_operator(pst, bs[s])
+    torch.cuda.synchronize()
+
+    def run(mode):
+        p = B.Problem.from_workload(w, stream=stream, cluster=G, guess=mode)
+        nw = 5 * args.warmup
+        for s in range(nw):
+            p.set_surface(etas[s, 0], etas[s, 1])
+            p.push_rhs(bs[s])
+            p.solve(sync=False)
+        p.read_log()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * 5 * args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, s in enumerate(range(nw, nsys)):
+            p.set_surface(etas[s, 0], etas[s, 1])
+            p.push_rhs(bs[s])
+            ev[2 * i].record(stream)
+            p.solve(sync=False)
+            ev[2 * i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        infos = p.read_log()
+        lat = np.array([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(5 * args.steps)])
+        x = p.solution()
+        p.close()
+        bad = [i for i in infos if i.status != 0 or i.relres > w.rtol]
+        return dict(wall=wall, infos=infos, lat=lat, failed=len(bad), x=x)
+
+    ewma = run("ewma")
+    plain = run("cold")
+    return ewma, plain, G
+
+
+def cpu_baseline(w, nsolves):
+    from threadpoolctl import threadpool_limits
+
+    from oracle.sequence import Simulation
+
+    with threadpool_limits(limits=1):
+        sim = Simulation.from_workload(w)
+        systems = []
+        for s in range(nsolves):
+            ep, ec, ps = w.system(s)
+            systems.append((ep, ec, sim.operator(ep, ec) @ ps))
+        t0 = time.perf_counter()
+        its = []
+        for ep, ec, b in systems:
+            its.append(sim.solve(ep, ec, b).info.iters)
+        dt = time.perf_counter() - t0
+    return dict(value=nsolves / dt, unit="solves/s", cores=1, kind="oracle",
+                sample=f"first {nsolves} systems of {w.name} (FP64 oracle: assembled CSR operator, "
+                       f"V-cycle, GMRES(30), EWMA rank {w.k} guess by Householder QR), "
+                       f"{np.mean(its):.2f} iterations/solve, one thread")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build measures the one-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    from paper_2511_18071_amd import workload as W
+
+    w = W.get(args.workload)
+    ewma, plain, G = run_gpu(args, w)
+    nsol = 5 * args.steps
+    value = nsol / ewma["wall"]
+    its = np.array([i.iters for i in ewma["infos"]])
+    its_plain = np.array([i.iters for i in plain["infos"]])
+    kernel_ms = float(ewma["lat"].mean())
+    pcv = precond_vectors(w)
+    bytes_per = traffic_bytes(w, ewma["infos"], pcv, w.k) / nsol
+    achieved = bytes_per / (kernel_ms * 1e-3) / 1e9
+    out = {
+        "metric": "solves/s @relres 1e-8 (subspace vs plain), iters/solve, p99 solve latency",
+        "value": round(value, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * ewma["wall"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "nz": w.nz, "bc": w.bc, "unknowns": w.n,
+                   "systems_per_step": 5, "restart": w.restart, "rtol": w.rtol, "precond": "still-water V(1,1)",
+                   "guess": f"EWMA rank {w.k}, r={w.r}", "cluster_workgroups": G},
+        "iters_per_solve": round(float(its.mean()), 3),
+        "p50_solve_ms": round(float(np.percentile(ewma["lat"], 50)), 4),
+        "p99_solve_ms": round(float(np.percentile(ewma["lat"], 99)), 4),
+        "failed_solves": ewma["failed"],
+        "plain": {"value": round(nsol / plain["wall"], 2), "iters_per_solve": round(float(its_plain.mean()), 3),
+                  "p99_solve_ms": round(float(np.percentile(plain["lat"], 99)), 4), "guess": "cold (x0 = 0)",
+                  "failed_solves": plain["failed"]},
+        "speedup_vs_plain": round(plain["wall"] / ewma["wall"], 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "sa_solve_kernel", "kernel_ms": round(kernel_ms, 4),
+                     "algorithmic_bytes_per_launch": round(bytes_per)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_solves)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -239,12 +239,13 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   }
 
   // ---- still-water hierarchy
-  struct HL { int nx, ncol; double dx; std::vector<double> h, hx, hxx; };
+  struct HL { int nx, ncol; double dx; std::vector<double> h, ih, hx, hxx; };
   std::vector<HL> levs;
   {
     HL l0;
     l0.nx = grid->nx; l0.ncol = ncol; l0.dx = dx;
     l0.h = hext;
+    for (double v : l0.h) l0.ih.push_back(1.0 / v);
     centred_h(l0.h, periodic, dx, l0.hx, l0.hxx);
     levs.push_back(l0);
     std::vector<double> hphys(h, h + nphys);
@@ -264,6 +265,7 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
       for (size_t i = 0; i < hphys.size(); i += 2) hc.push_back(hphys[i]);
       hphys = hc;
       c.h = extend(hphys.data(), (int)hphys.size(), periodic);
+      for (double v : c.h) c.ih.push_back(1.0 / v);
       centred_h(c.h, periodic, c.dx, c.hx, c.hxx);
       levs.push_back(c);
     }
@@ -296,7 +298,8 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   const int TWMh = TX + 3, TWGMh = TXG + 3;
   const size_t need_op = (size_t)(TWMh + 12 + 2 * (TWMh + 6)) * nl + 4;
   const size_t need_gram = opt.guess == SA_GUESS_EWMA ? (size_t)(k * TWGMh + TWGMh + TWGMh + 12 + 2 * (TWGMh + 6)) * nl : 0;
-  const size_t need_pc = (size_t)nl * BLOCK;
+  const int TMSh = 64 + 4;  // preconditioner tile with its 2-column halo
+  const size_t need_pc = (size_t)4 * TMSh * nl + 4 * TMSh;
   size_t big = need_op;
   if (need_gram > big) big = need_gram;
   if (need_pc > big) big = need_pc;
@@ -323,10 +326,11 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   auto take = [&](size_t bytes) { size_t o = off; off += round_up(bytes); return o; };
   const size_t o_wsig = take(wsig.size() * 8), o_ssig = take(ssig.size() * 4), o_wchi = take(49 * 8),
                o_sig = take(nl * 8), o_h = take(ncol * 8), o_hchi = take(ncol * 8), o_geo = take(4 * (size_t)ncol * 8);
-  std::vector<size_t> o_lh(nlev), o_lhx(nlev), o_lhxx(nlev), o_lf(nlev), o_lu(nlev), o_lo(nlev);
+  std::vector<size_t> o_lh(nlev), o_lih(nlev), o_lhx(nlev), o_lhxx(nlev), o_lf(nlev), o_lu(nlev), o_lo(nlev);
   for (int l = 0; l < nlev; ++l) {
     const size_t nlv = (size_t)levs[l].ncol * nl;
     o_lh[l] = take(levs[l].ncol * 8); o_lhx[l] = take(levs[l].ncol * 8); o_lhxx[l] = take(levs[l].ncol * 8);
+    o_lih[l] = take(levs[l].ncol * 8);
     o_lf[l] = take(nlv * 8); o_lu[l] = take(nlv * 8); o_lo[l] = take(nlv * 8);
   }
   const size_t o_cinv = take(cinv.size() * 8 + 8);
@@ -358,6 +362,7 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
     e = up(o_lh[l], levs[l].h.data(), levs[l].ncol * 8);
     if (e == hipSuccess) e = up(o_lhx[l], levs[l].hx.data(), levs[l].ncol * 8);
     if (e == hipSuccess) e = up(o_lhxx[l], levs[l].hxx.data(), levs[l].ncol * 8);
+    if (e == hipSuccess) e = up(o_lih[l], levs[l].ih.data(), levs[l].ncol * 8);
   }
   if (e == hipSuccess && !cinv.empty()) e = up(o_cinv, cinv.data(), cinv.size() * 8);
 
@@ -372,6 +377,7 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
     Level& L = P.lev[l];
     L.ncol = levs[l].ncol; L.nx = levs[l].nx; L.dx = levs[l].dx;
     L.h = (const double*)(A + o_lh[l]); L.hx = (const double*)(A + o_lhx[l]); L.hxx = (const double*)(A + o_lhxx[l]);
+    L.ih = (const double*)(A + o_lih[l]);
     L.f = (double*)(A + o_lf[l]); L.u = (double*)(A + o_lu[l]); L.o = (double*)(A + o_lo[l]);
   }
   P.cinv = (const double*)(A + o_cinv); P.cn = cn;

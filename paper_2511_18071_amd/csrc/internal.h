@@ -26,6 +26,7 @@ struct Level {
   int ncol, nx;              // columns (ghosts included), physical points
   double dx;
   const double* h;           // depth per column (ghost columns by reflection)
+  const double* ih;          // 1/h per column
   const double* hx;          // second-order centred dh/dx per column
   const double* hxx;         // second-order centred d2h/dx2 per column
   double* f;                 // right-hand side of this level (level 0: unused, the input)

@@ -279,169 +279,323 @@ DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, 
 }
 
 // ------------------------------------------------------------------------------------------
-// still-water preconditioner (second-order direct form at eta = 0)
+// still-water preconditioner (second-order direct form at eta = 0), LDS-staged tiles of TM
+// columns x all levels. A column's data (h, 1/h, h_x, h_xx) and the fields it touches are
+// staged with coalesced loads; residuals are formed in parallel from LDS; the vertical line
+// solves run one thread per column from LDS with a single division per level.
+constexpr int TM = 64;
+constexpr int TMS = TM + 4;  // stride of the per-thread line-solve scratch
+
 struct Lv {
-  int nc;
+  int nc, nx;
   double rdx;
-  const double *h, *hx, *hxx;
+  const double *h, *ih, *hx, *hxx;
 };
 
 DEV Lv level_view(const Problem& P, int l) {
   const Level& L = P.lev[l];
-  return Lv{L.ncol, 1.0 / L.dx, L.h, L.hx, L.hxx};
+  return Lv{L.ncol, L.nx, 1.0 / L.dx, L.h, L.ih, L.hx, L.hxx};
 }
 
-// (M u)(c, j) on one level
-DEV double m_row(const Problem& P, const Lv& L, const double* __restrict__ u, int c, int j) {
-  const int nc = L.nc, nz = P.nz;
-  const double rdx = L.rdx, rds = 1.0 / P.dsig;
-  auto U = [&](int cc, int jj) {
-    if (P.periodic) cc = wrapc(cc, nc);
-    return u[(size_t)jj * nc + cc];
-  };
-  if (j == nz) return U(c, j);
+// tile-local staging: column c (unwrapped) <-> slot c - base
+struct Stage {
+  int base, width, nc, periodic;
+  DEV int slot(int c) const { return c - base; }
+  DEV int col(int c) const { return periodic ? wrapc(c, nc) : c; }
+  DEV bool has(int c) const { return periodic || (c >= 0 && c < nc); }
+};
+
+// (M u)(c, j): U(cc, jj) returns the staged field at unwrapped column cc; CD(cc, q) the
+// staged column data q = 0 h, 1 1/h, 2 h_x, 3 h_xx of unwrapped column cc.
+template <class U, class CD>
+DEV double m_apply(const Problem& P, int nc, double rdx, int c, int j, U u, CD cd) {
+  const int nz = P.nz;
+  const double rds = 1.0 / P.dsig;
+  if (j == nz) return u(c, j);
   if (!P.periodic && (c == 0 || c == nc - 1)) {
-    if (j == 0) return U(c, j);
+    if (j == 0) return u(c, j);
     const int w = (c == 0) ? 1 : nc - 2;
-    const double s = L.hx[w] * (1.0 - P.sig[j]) / L.h[w];
-    const double gx = (U(w + 1, j) - U(w - 1, j)) * 0.5 * rdx + s * (U(w, j + 1) - U(w, j - 1)) * 0.5 * rds;
+    const double s = cd(w, 2) * (1.0 - P.sig[j]) * cd(w, 1);
+    const double gx = (u(w + 1, j) - u(w - 1, j)) * 0.5 * rdx + s * (u(w, j + 1) - u(w, j - 1)) * 0.5 * rds;
     return c == 0 ? -gx : gx;
   }
-  const double h = L.h[c], hx = L.hx[c];
+  const double ih = cd(c, 1), hx = cd(c, 2);
   if (j == 0) {
-    const double s1 = hx / h;
-    const double dz = (U(c, 2) - U(c, 0)) * 0.5 * rds;
-    const double gx = (U(c + 1, 1) - U(c - 1, 1)) * 0.5 * rdx + s1 * dz;
-    return -hx * gx - dz / h;
+    const double s1 = hx * ih;
+    const double dz = (u(c, 2) - u(c, 0)) * 0.5 * rds;
+    const double gx = (u(c + 1, 1) - u(c - 1, 1)) * 0.5 * rdx + s1 * dz;
+    return -hx * gx - dz * ih;
   }
   const double oms = 1.0 - P.sig[j];
-  const double s = hx * oms / h;
-  const double sxx = oms * L.hxx[c] / h - 2.0 * oms * hx * hx / (h * h);
-  const double uc = U(c, j);
-  const double dxx = (U(c + 1, j) - 2.0 * uc + U(c - 1, j)) * rdx * rdx;
-  const double dxz = (U(c + 1, j + 1) - U(c + 1, j - 1) - U(c - 1, j + 1) + U(c - 1, j - 1)) * 0.25 * rdx * rds;
-  const double dzz = (U(c, j + 1) - 2.0 * uc + U(c, j - 1)) * rds * rds;
-  const double dz = (U(c, j + 1) - U(c, j - 1)) * 0.5 * rds;
-  return dxx + 2.0 * s * dxz + (s * s + 1.0 / (h * h)) * dzz + sxx * dz;
+  const double s = hx * oms * ih;
+  const double sxx = oms * cd(c, 3) * ih - 2.0 * oms * hx * hx * ih * ih;
+  const double uc = u(c, j);
+  const double dxx = (u(c + 1, j) - 2.0 * uc + u(c - 1, j)) * rdx * rdx;
+  const double dxz = (u(c + 1, j + 1) - u(c + 1, j - 1) - u(c - 1, j + 1) + u(c - 1, j - 1)) * 0.25 * rdx * rds;
+  const double dzz = (u(c, j + 1) - 2.0 * uc + u(c, j - 1)) * rds * rds;
+  const double dz = (u(c, j + 1) - u(c, j - 1)) * 0.5 * rds;
+  return dxx + 2.0 * s * dxz + (s * s + ih * ih) * dzz + sxx * dz;
 }
 
-// same-column coefficients of an interior (PDE) row: u(c, j-1), u(c, j), u(c, j+1)
-DEV void m_col(const Problem& P, const Lv& L, int c, int j, double& lo, double& di, double& up) {
-  const double rds = 1.0 / P.dsig;
-  const double h = L.h[c], hx = L.hx[c], oms = 1.0 - P.sig[j];
-  const double s = hx * oms / h;
-  const double sxx = oms * L.hxx[c] / h - 2.0 * oms * hx * hx / (h * h);
-  const double a = (s * s + 1.0 / (h * h)) * rds * rds, b = sxx * 0.5 * rds;
-  lo = a - b;
-  up = a + b;
-  di = -2.0 * L.rdx * L.rdx - 2.0 * a;
-}
-
-// One line-Jacobi sweep on column c: o = u + omega L^-1 (f - M u) (u == nullptr: u = 0).
-// L keeps the same-column entries of M. The bed row couples levels 0 and 2; it is first
-// combined with row 1 to make the column system tridiagonal, then solved by elimination.
-// Forward results go to o (the thread's own column), the elimination ratios to cp (LDS).
-DEV void line_sweep(const Problem& P, const Lv& L, const double* __restrict__ f, const double* __restrict__ u,
-                    double* __restrict__ o, int c, double omega, double* cp) {
-  const int nc = L.nc, nz = P.nz, tid = threadIdx.x;
-  auto R = [&](int j) {
-    const size_t e = (size_t)j * nc + c;
-    return u ? f[e] - m_row(P, L, u, c, j) : f[e];
-  };
-  auto Uo = [&](int j) { return u ? u[(size_t)j * nc + c] : 0.0; };
+// Line solve of column c: delta = L^-1 rhs, L = same-column part of M. rhs(j) gives the
+// right-hand side, put(j, delta) receives the result; cp, dpv are the thread's LDS scratch
+// with stride TMS. The bed row couples levels 0 and 2: it is first combined with row 1 so the
+// column system becomes tridiagonal, then eliminated downwards and substituted upwards.
+template <class R, class CD, class Put>
+DEV void column_solve(const Problem& P, int nc, double rdx, int c, R rhs, CD cd, Put put, double* cp, double* dpv) {
+  const int nz = P.nz;
   if (!P.periodic && (c == 0 || c == nc - 1)) {
-    for (int j = 0; j <= nz; ++j) {
-      const double dg = (j == 0 || j == nz) ? 1.0 : 0.5 * L.rdx;
-      o[(size_t)j * nc + c] = Uo(j) + omega * (R(j) / dg);
-    }
+    for (int j = 0; j <= nz; ++j) put(j, rhs(j) / ((j == 0 || j == nz) ? 1.0 : 0.5 * rdx));
     return;
   }
   const double rds = 1.0 / P.dsig;
-  const double q = L.hx[c] * (L.hx[c] / L.h[c]) + 1.0 / L.h[c];
+  const double ih = cd(c, 1), hx = cd(c, 2), hxx = cd(c, 3);
+  auto coefs = [&](int j, double& lo, double& di, double& up) {
+    const double oms = 1.0 - P.sig[j];
+    const double s = hx * oms * ih;
+    const double sxx = oms * hxx * ih - 2.0 * oms * hx * hx * ih * ih;
+    const double a = (s * s + ih * ih) * rds * rds, b = sxx * 0.5 * rds;
+    lo = a - b;
+    up = a + b;
+    di = -2.0 * rdx * rdx - 2.0 * a;
+  };
+  const double q = hx * (hx * ih) + ih;
   const double a0 = 0.5 * rds * q, c0 = -0.5 * rds * q;
   double l1, d1, u1;
-  m_col(P, L, c, 1, l1, d1, u1);
-  const double r0 = R(0), r1 = R(1);
+  coefs(1, l1, d1, u1);
+  const double r0 = rhs(0), r1 = rhs(1);
   const double a0p = a0 - c0 * l1 / u1;
   const double b0p = -c0 * d1 / u1;
-  const double f0p = r0 - c0 * r1 / u1;
-  double pc = b0p / a0p, pd = f0p / a0p;
-  cp[tid] = pc;
-  o[c] = pd;
+  double pc = b0p / a0p, pd = (r0 - c0 * r1 / u1) / a0p;
+  cp[0] = pc;
+  dpv[0] = pd;
   for (int j = 1; j < nz; ++j) {
-    double lo, di, up, rj;
-    if (j == 1) { lo = l1; di = d1; up = u1; rj = r1; }
-    else { m_col(P, L, c, j, lo, di, up); rj = R(j); }
-    const double den = di - lo * pc;
-    pc = up / den;
-    pd = (rj - lo * pd) / den;
-    cp[j * BLOCK + tid] = pc;
-    o[(size_t)j * nc + c] = pd;
+    double lo, di, up;
+    if (j == 1) { lo = l1; di = d1; up = u1; }
+    else coefs(j, lo, di, up);
+    const double rj = (j == 1) ? r1 : rhs(j);
+    const double inv = 1.0 / (di - lo * pc);
+    pc = up * inv;
+    pd = (rj - lo * pd) * inv;
+    cp[j * TMS] = pc;
+    dpv[j * TMS] = pd;
   }
-  double dlt = R(nz);  // free surface: identity row
-  o[(size_t)nz * nc + c] = Uo(nz) + omega * dlt;
+  double dlt = rhs(nz);  // free surface: identity row
+  put(nz, dlt);
   for (int j = nz - 1; j >= 0; --j) {
-    const size_t e = (size_t)j * nc + c;
-    dlt = o[e] - cp[j * BLOCK + tid] * dlt;
-    o[e] = Uo(j) + omega * dlt;
+    dlt = dpv[j * TMS] - cp[j * TMS] * dlt;
+    put(j, dlt);
   }
 }
 
-DEV void phase_sweep(const Problem& P, Cl& cl, int l, const double* f, const double* u, double* o, double* cp) {
+// coarse value interpolated to fine column c (linear in x), level j
+DEV double prolong_at(const Problem& P, int ncf, int ncc, const double* e, int c, int j) {
+  const double* ec = e + (size_t)j * ncc;
+  if (P.periodic) return (c & 1) ? 0.5 * (ec[(c - 1) >> 1] + ec[wrapc((c + 1) >> 1, ncc)]) : ec[c >> 1];
+  if (c == 0 || c == ncf - 1) return ec[c == 0 ? 0 : ncc - 1];
+  const int p = c - 1;
+  return (p & 1) ? 0.5 * (ec[((p - 1) >> 1) + 1] + ec[((p + 1) >> 1) + 1]) : ec[(p >> 1) + 1];
+}
+
+// number of tiles of a level and the fine column of coarse column C (walls: index shift)
+DEV int ptiles(int nc) { return (nc + TM - 1) / TM; }
+DEV int coarse_centre(const Problem& P, int C, int ncc, int ncf) {
+  if (P.periodic) return 2 * C;
+  if (C == 0) return 0;
+  if (C == ncc - 1) return ncf - 1;
+  return 2 * C - 1;
+}
+
+// o = u + omega L^-1 (f - M u) on level l, u = (uin or 0) + (e ? P e : 0) formed on load.
+// LDS: su (TM+2) nl, sf TM nl, scd 4 (TM+2), cp/dp TMS nl each.
+DEV void phase_sweep(const Problem& P, Cl& cl, int l, const double* f, const double* uin, const double* e,
+                     double* o, double* lds) {
   const Lv L = level_view(P, l);
-  // whole workgroups take consecutive columns so that a level's rows are read coalesced
-  for (int base = cl.rank * BLOCK; base < L.nc; base += cl.G * BLOCK) {
-    const int c = base + threadIdx.x;
-    if (c < L.nc) line_sweep(P, L, f, u, o, c, P.omega, cp);
+  const int nc = L.nc, nl = P.nl;
+  const int ncc = e ? P.lev[l + 1].ncol : 0;
+  constexpr int LW = TM + 2;
+  double* su = lds;
+  double* sf = su + LW * nl;
+  double* scd = sf + TM * nl;
+  double* cp = scd + 4 * LW;
+  double* dpv = cp + TMS * nl;
+  for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
+    const int c0 = t * TM, w = min(TM, nc - c0);
+    const Stage st{c0 - 1, w + 2, nc, P.periodic};
+    for (int i = threadIdx.x; i < LW * nl; i += BLOCK) {
+      const int j = i / LW, lc = i - j * LW;
+      const int c = c0 - 1 + lc;
+      double v = 0.0;
+      if (lc < w + 2 && st.has(c)) {
+        const int cg = st.col(c);
+        if (uin) v = uin[(size_t)j * nc + cg];
+        if (e) v += prolong_at(P, nc, ncc, e, cg, j);
+      }
+      su[i] = v;
+    }
+    for (int i = threadIdx.x; i < TM * nl; i += BLOCK) {
+      const int j = i / TM, lc = i - j * TM;
+      sf[i] = lc < w ? f[(size_t)j * nc + c0 + lc] : 0.0;
+    }
+    for (int lc = threadIdx.x; lc < LW; lc += BLOCK) {
+      const int c = c0 - 1 + lc;
+      if (lc < w + 2 && st.has(c)) {
+        const int cg = st.col(c);
+        scd[lc] = L.h[cg]; scd[LW + lc] = L.ih[cg]; scd[2 * LW + lc] = L.hx[cg]; scd[3 * LW + lc] = L.hxx[cg];
+      }
+    }
+    __syncthreads();
+    const bool zero = !uin && !e;
+    auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
+    auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
+    if (threadIdx.x < w) {
+      const int lc = threadIdx.x, c = c0 + lc;
+      auto rhs = [&](int j) { return sf[j * TM + lc] - (zero ? 0.0 : m_apply(P, nc, L.rdx, c, j, U, CD)); };
+      auto put = [&](int j, double d) { o[(size_t)j * nc + c] = U(c, j) + P.omega * d; };
+      column_solve(P, nc, L.rdx, c, rhs, CD, put, cp + threadIdx.x, dpv + threadIdx.x);
+    }
+    __syncthreads();
   }
 }
 
-// coarse right-hand side: full weighting in x of the fine residual f - M u
-DEV void phase_restrict(const Problem& P, Cl& cl, int l, const double* f, const double* u, double* fc) {
+// Pre-smoothing from zero, residual and restriction in one pass (nu1 = 1):
+// u = omega L^-1 f on the tile plus a 2-column halo, u written for the tile's columns,
+// fc(C) = full weighting of f - M u at the fine columns around C's centre.
+// LDS: sf, su (TM+4) nl, scd 4 (TM+4), cp/dp TMS nl each.
+DEV void phase_down(const Problem& P, Cl& cl, int l, const double* f, double* u, double* fc, double* lds) {
   const Lv L = level_view(P, l);
-  const int ncc = P.lev[l + 1].ncol, nxc = P.lev[l + 1].nx, nc = L.nc;
-  for (int C = cl.rank * BLOCK + threadIdx.x; C < ncc; C += cl.G * BLOCK) {
-    for (int j = 0; j <= P.nz; ++j) {
-      auto Rr = [&](int cc) {
-        if (P.periodic) cc = wrapc(cc, nc);
-        return f[(size_t)j * nc + cc] - m_row(P, L, u, cc, j);
-      };
+  const int nc = L.nc, nl = P.nl;
+  const int ncc = P.lev[l + 1].ncol, nxc = P.lev[l + 1].nx;
+  constexpr int LW = TM + 4;
+  double* sf = lds;
+  double* su = sf + LW * nl;
+  double* scd = su + LW * nl;
+  double* cp = scd + 4 * LW;
+  double* dpv = cp + TMS * nl;
+  for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
+    const int c0 = t * TM, w = min(TM, nc - c0);
+    const Stage st{c0 - 2, w + 4, nc, P.periodic};
+    for (int i = threadIdx.x; i < LW * nl; i += BLOCK) {
+      const int j = i / LW, lc = i - j * LW;
+      const int c = c0 - 2 + lc;
+      sf[i] = (lc < w + 4 && st.has(c)) ? f[(size_t)j * nc + st.col(c)] : 0.0;
+      su[i] = 0.0;
+    }
+    for (int lc = threadIdx.x; lc < LW; lc += BLOCK) {
+      const int c = c0 - 2 + lc;
+      if (lc < w + 4 && st.has(c)) {
+        const int cg = st.col(c);
+        scd[lc] = L.h[cg]; scd[LW + lc] = L.ih[cg]; scd[2 * LW + lc] = L.hx[cg]; scd[3 * LW + lc] = L.hxx[cg];
+      }
+    }
+    __syncthreads();
+    auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
+    auto F = [&](int cc, int jj) { return sf[jj * LW + st.slot(cc)]; };
+    auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
+    if (threadIdx.x < w + 4) {
+      const int lc = threadIdx.x, c = c0 - 2 + lc;
+      if (st.has(c)) {
+        auto rhs = [&](int j) { return F(c, j); };
+        auto put = [&](int j, double d) { su[j * LW + lc] = P.omega * d; };
+        column_solve(P, nc, L.rdx, c, rhs, CD, put, cp + threadIdx.x, dpv + threadIdx.x);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < w * nl; i += BLOCK) {
+      const int j = i / w, lc = i - j * w;
+      u[(size_t)j * nc + c0 + lc] = su[j * LW + lc + 2];
+    }
+    // coarse columns whose centre lies in this tile
+    int Cfirst, Clast;
+    if (P.periodic) { Cfirst = (c0 + 1) / 2; Clast = (c0 + w - 1) / 2; }
+    else {
+      Cfirst = (c0 == 0) ? 0 : (c0 + 2) / 2;
+      Clast = (c0 + w >= nc) ? ncc - 1 : (c0 + w) / 2;
+    }
+    const int ncw = Clast - Cfirst + 1;
+    for (int i = threadIdx.x; i < ncw * nl; i += BLOCK) {
+      const int j = i / ncw, C = Cfirst + i - j * ncw;
+      auto Rr = [&](int cc) { return F(cc, j) - m_apply(P, nc, L.rdx, cc, j, U, CD); };
+      const int cf = coarse_centre(P, C, ncc, nc);
       double v;
       if (P.periodic) {
-        const int c = 2 * C;
-        v = 0.25 * Rr(c - 1) + 0.5 * Rr(c) + 0.25 * Rr(c + 1);
-      } else if (C == 0) {
-        v = Rr(0);
-      } else if (C == ncc - 1) {
-        v = Rr(nc - 1);
+        v = 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
+      } else if (C == 0 || C == ncc - 1) {
+        v = Rr(cf);
+      } else if (C == 1) {
+        v = 0.5 * Rr(1) + 0.5 * Rr(2);
+      } else if (C == nxc) {
+        v = 0.5 * Rr(cf) + 0.5 * Rr(cf - 1);
       } else {
-        const int pc = C - 1, p = 2 * pc;
-        if (pc == 0) v = 0.5 * Rr(1) + 0.5 * Rr(2);
-        else if (pc == nxc - 1) v = 0.5 * Rr(p + 1) + 0.5 * Rr(p);
-        else v = 0.25 * Rr(p) + 0.5 * Rr(p + 1) + 0.25 * Rr(p + 2);
+        v = 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
       }
       fc[(size_t)j * ncc + C] = v;
     }
+    __syncthreads();
   }
 }
 
-// u += P e: linear interpolation in x of the coarse correction
+// fc = full weighting of f - M u (used when nu1 != 1)
+DEV void phase_restrict(const Problem& P, Cl& cl, int l, const double* f, const double* u, double* fc,
+                        double* lds) {
+  const Lv L = level_view(P, l);
+  const int nc = L.nc, nl = P.nl;
+  const int ncc = P.lev[l + 1].ncol, nxc = P.lev[l + 1].nx;
+  constexpr int LW = TM + 4;
+  double* sf = lds;
+  double* su = sf + LW * nl;
+  double* scd = su + LW * nl;
+  for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
+    const int c0 = t * TM, w = min(TM, nc - c0);
+    const Stage st{c0 - 2, w + 4, nc, P.periodic};
+    for (int i = threadIdx.x; i < LW * nl; i += BLOCK) {
+      const int j = i / LW, lc = i - j * LW;
+      const int c = c0 - 2 + lc;
+      const bool ok = lc < w + 4 && st.has(c);
+      sf[i] = ok ? f[(size_t)j * nc + st.col(c)] : 0.0;
+      su[i] = ok ? u[(size_t)j * nc + st.col(c)] : 0.0;
+    }
+    for (int lc = threadIdx.x; lc < LW; lc += BLOCK) {
+      const int c = c0 - 2 + lc;
+      if (lc < w + 4 && st.has(c)) {
+        const int cg = st.col(c);
+        scd[lc] = L.h[cg]; scd[LW + lc] = L.ih[cg]; scd[2 * LW + lc] = L.hx[cg]; scd[3 * LW + lc] = L.hxx[cg];
+      }
+    }
+    __syncthreads();
+    auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
+    auto F = [&](int cc, int jj) { return sf[jj * LW + st.slot(cc)]; };
+    auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
+    int Cfirst, Clast;
+    if (P.periodic) { Cfirst = (c0 + 1) / 2; Clast = (c0 + w - 1) / 2; }
+    else {
+      Cfirst = (c0 == 0) ? 0 : (c0 + 2) / 2;
+      Clast = (c0 + w >= nc) ? ncc - 1 : (c0 + w) / 2;
+    }
+    const int ncw = Clast - Cfirst + 1;
+    for (int i = threadIdx.x; i < ncw * nl; i += BLOCK) {
+      const int j = i / ncw, C = Cfirst + i - j * ncw;
+      auto Rr = [&](int cc) { return F(cc, j) - m_apply(P, nc, L.rdx, cc, j, U, CD); };
+      const int cf = coarse_centre(P, C, ncc, nc);
+      double v;
+      if (P.periodic) v = 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
+      else if (C == 0 || C == ncc - 1) v = Rr(cf);
+      else if (C == 1) v = 0.5 * Rr(1) + 0.5 * Rr(2);
+      else if (C == nxc) v = 0.5 * Rr(cf) + 0.5 * Rr(cf - 1);
+      else v = 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
+      fc[(size_t)j * ncc + C] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// u += P e on level l
 DEV void phase_prolong(const Problem& P, Cl& cl, int l, const double* e, double* u) {
   const int nc = P.lev[l].ncol, ncc = P.lev[l + 1].ncol;
   const int total = nc * P.nl;
   for (int i = cl.rank * BLOCK + threadIdx.x; i < total; i += cl.G * BLOCK) {
     const int j = i / nc, c = i - j * nc;
-    const double* ec = e + (size_t)j * ncc;
-    double v;
-    if (P.periodic) {
-      v = (c & 1) ? 0.5 * (ec[(c - 1) >> 1] + ec[wrapc((c + 1) >> 1, ncc)]) : ec[c >> 1];
-    } else if (c == 0 || c == nc - 1) {
-      v = ec[c == 0 ? 0 : ncc - 1];
-    } else {
-      const int p = c - 1;
-      v = (p & 1) ? 0.5 * (ec[((p - 1) >> 1) + 1] + ec[((p + 1) >> 1) + 1]) : ec[(p >> 1) + 1];
-    }
-    u[i] += v;
+    u[i] += prolong_at(P, nc, ncc, e, c, j);
   }
 }
 
@@ -464,7 +618,7 @@ DEV void phase_copy(const Problem& P, Cl& cl, const double* src, double* dst, in
 
 // z = M^-1 v. v and z are level-0 vectors distinct from each other and from the level-0
 // scratch (lev[0].u, lev[0].o). Ends with a cluster barrier.
-DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* cp) {
+DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* lds) {
   const int n = P.n;
   if (P.pc == SA_PC_NONE) {
     phase_copy(P, cl, v, z, n);
@@ -477,7 +631,7 @@ DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* c
     const double* prev = nullptr;
     for (int s = 0; s < P.nu1; ++s) {
       double* dst = (s == P.nu1 - 1) ? z : ((prev == A0) ? B0 : A0);
-      phase_sweep(P, cl, 0, v, prev, dst, cp);
+      phase_sweep(P, cl, 0, v, prev, nullptr, dst, lds);
       csync(cl);
       prev = dst;
     }
@@ -489,52 +643,68 @@ DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* c
     csync(cl);
     return;
   }
-  const double* f[MAXLEV];
-  const double* outp[MAXLEV];
-  double* uc[MAXLEV];
-  f[0] = v;
-  for (int l = 1; l < L; ++l) f[l] = P.lev[l].f;
+  // level vectors: f (right-hand side), u (pre-smoothed), o (output)
   for (int l = 0; l < L - 1; ++l) {
+    const double* f = l == 0 ? v : P.lev[l].f;
     double* A = P.lev[l].u;
     double* B = P.lev[l].o;
-    const int len = P.lev[l].ncol * P.nl;
+    if (P.nu1 == 1) {
+      phase_down(P, cl, l, f, A, P.lev[l + 1].f, lds);
+      csync(cl);
+      continue;
+    }
     const double* prev = nullptr;
     double* dst = A;
     if (P.nu1 == 0) {
-      phase_zero(P, cl, A, len);
+      phase_zero(P, cl, A, P.lev[l].ncol * P.nl);
       csync(cl);
     }
     for (int s = 0; s < P.nu1; ++s) {
       dst = (prev == A) ? B : A;
-      phase_sweep(P, cl, l, f[l], prev, dst, cp);
+      phase_sweep(P, cl, l, f, prev, nullptr, dst, lds);
       csync(cl);
       prev = dst;
     }
-    uc[l] = dst;
-    phase_restrict(P, cl, l, f[l], uc[l], P.lev[l + 1].f);
+    if (dst != A) {
+      phase_copy(P, cl, dst, A, P.lev[l].ncol * P.nl);
+      csync(cl);
+    }
+    phase_restrict(P, cl, l, f, A, P.lev[l + 1].f, lds);
     csync(cl);
   }
-  phase_coarse(P, cl, f[L - 1], P.lev[L - 1].o);
+  phase_coarse(P, cl, P.lev[L - 1].f, P.lev[L - 1].o);
   csync(cl);
-  outp[L - 1] = P.lev[L - 1].o;
+  const double* e = P.lev[L - 1].o;  // correction coming from the coarser level
   for (int l = L - 2; l >= 0; --l) {
-    phase_prolong(P, cl, l, outp[l + 1], uc[l]);
-    csync(cl);
+    const double* f = l == 0 ? v : P.lev[l].f;
     double* A = P.lev[l].u;
     double* B = P.lev[l].o;
-    const double* prev = uc[l];
-    for (int s = 0; s < P.nu2; ++s) {
-      double* dst = (l == 0 && s == P.nu2 - 1) ? z : ((prev == A) ? B : A);
-      phase_sweep(P, cl, l, f[l], prev, dst, cp);
+    double* out = (l == 0) ? z : B;
+    if (P.nu2 == 0) {
+      phase_prolong(P, cl, l, e, A);
       csync(cl);
-      prev = dst;
+      if (l == 0) {
+        phase_copy(P, cl, A, z, n);
+        csync(cl);
+        e = z;
+      } else {
+        e = A;
+      }
+      continue;
     }
-    if (l == 0 && P.nu2 == 0) {
-      phase_copy(P, cl, uc[0], z, n);
+    // first post-sweep with the prolongated correction added on load
+    double* dst = (P.nu2 == 1) ? out : B;
+    if (l == 0 && P.nu2 > 1) dst = B0;
+    phase_sweep(P, cl, l, f, A, e, dst, lds);
+    csync(cl);
+    const double* prev = dst;
+    for (int s = 1; s < P.nu2; ++s) {
+      double* nd = (s == P.nu2 - 1) ? out : ((prev == B) ? A : B);
+      phase_sweep(P, cl, l, f, prev, nullptr, nd, lds);
       csync(cl);
-      prev = z;
+      prev = nd;
     }
-    outp[l] = prev;
+    e = out;
   }
 }
 
