@@ -92,6 +92,8 @@ typedef struct {
   int32_t max_refine;   /* refinement steps cap (SA_FP32_IR), default 20                   */
   int32_t cluster;      /* workgroups cooperating on one solve; 0 = chosen from the size  */
   int32_t profile;      /* 1: accumulate per-phase device time (sa_get_phase_times), 0      */
+  int32_t coarse_max;   /* MG: coarsening stops at the first grid with at most this many    */
+                        /* unknowns, solved exactly there (<= 1024), default 700            */
 } sa_options;
 
 /* Per-solve report. iters counts Arnoldi steps over all cycles (and refinement steps). */
@@ -158,7 +160,9 @@ int64_t sa_sketch_count(const sa_problem* p);
  * milliseconds of the device's constant-rate clock, measured by the first workgroup:
  * out[0] geometry, [1] sketch guess (block operator, Gram, x0), [2] k x k solve,
  * [3] operator applications, [4] preconditioner, [5] orthogonalisation, [6] other
- * (Givens, updates, checks), [7] total. n = entries wanted (<= 8). */
+ * (Givens, updates, checks), [7] total; then the preconditioner in detail: [8] coarsest
+ * solve, [9 + 2 l] down pass and [10 + 2 l] up pass of level l (l < 24), [56] the wait of
+ * the other workgroups for the single-workgroup coarse tail. n = entries wanted (<= 57). */
 int sa_get_phase_times(sa_problem* p, double* out, int32_t n);
 
 /* Thread-local message of the last hard error ("" if none). */

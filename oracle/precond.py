@@ -10,7 +10,9 @@ linear map M^-1 built from the second-order still-water operator M of
 * V-cycle: one V(nu1, nu2) cycle with semicoarsening in x (coarse grid = every other
   column, nz unchanged, M rediscretised on the coarse grid), line-Jacobi smoothing,
   linear interpolation in x, full weighting in x for the residual (half/half at a wall
-  column, injection at ghost columns), an exact solve on the coarsest grid.
+  column, injection at ghost columns), an exact solve on the coarsest grid. Coarsening
+  stops at the first grid with at most ``coarse_max`` unknowns (or when the column count
+  cannot be halved further).
 
 Pins (tests/test_oracle_precond.py): line Jacobi with nu = 1, omega = 1 equals the exact
 block-diagonal column solve (dense, brute force); a one-level V-cycle equals the exact
@@ -100,16 +102,20 @@ def restriction(fine: Grid, coarse: Grid) -> sp.csr_matrix:
     return sp.kron(sp.identity(fine.nl), r1, format="csr")
 
 
+COARSE_MAX = 700
+
+
 class VCycle:
     def __init__(self, grid: Grid, h_phys, nu1: int = 1, nu2: int = 1, omega: float = 1.0,
-                 max_levels: int = 32):
+                 max_levels: int = 32, coarse_max: int = COARSE_MAX):
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
         self.levels = []
         g, h = grid, np.asarray(h_phys, dtype=np.float64)
         while True:
             lev = dict(grid=g, m=low_order_operator(g, h))
             self.levels.append(lev)
-            nxt = coarsen(g, h) if len(self.levels) < max_levels else None
+            small = g.n <= coarse_max
+            nxt = coarsen(g, h) if len(self.levels) < max_levels and not small else None
             if nxt is None:
                 break
             gc, hc = nxt
@@ -139,12 +145,12 @@ class VCycle:
 
 
 def make(grid: Grid, h_phys, kind: str = "mg", nu1: int = 1, nu2: int = 1, omega: float = 0.5,
-         max_levels: int = 32):
+         max_levels: int = 32, coarse_max: int = COARSE_MAX):
     """The fixed map M^-1 of a simulation: 'none', 'line' (nu1 sweeps) or 'mg'."""
     if kind == "none":
         return lambda v: np.array(v, dtype=np.float64, copy=True)
     if kind == "line":
         return LineJacobi(grid, low_order_operator(grid, h_phys), nu1, omega)
     if kind == "mg":
-        return VCycle(grid, h_phys, nu1, nu2, omega, max_levels)
+        return VCycle(grid, h_phys, nu1, nu2, omega, max_levels, coarse_max)
     raise ValueError(kind)

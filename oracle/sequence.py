@@ -30,6 +30,7 @@ class Options:
     nu2: int = 1
     omega: float = 0.5
     max_levels: int = 32
+    coarse_max: int = 700
     guess: str = "ewma"  # cold | previous | ewma
     k: int = 8
     r: float = 0.9
@@ -52,7 +53,7 @@ class Simulation:
         self.h = np.asarray(h_phys, dtype=np.float64)
         self.opts = opts
         self.minv = _precond.make(self.grid, self.h, opts.precond, opts.nu1, opts.nu2, opts.omega,
-                                  opts.max_levels)
+                                  opts.max_levels, opts.coarse_max)
         self.sketch = EWMASketch(self.grid.n, opts.k, opts.r, opts.seed) if opts.guess == "ewma" else None
         self.x_prev = None
         self.solves = 0

@@ -36,7 +36,7 @@ class SaOptions(C.Structure):
         ("max_levels", C.c_int32), ("guess", C.c_int32), ("k", C.c_int32), ("r", C.c_double),
         ("seed", C.c_uint64), ("n_init", C.c_int32), ("tau_drop", C.c_double),
         ("precision", C.c_int32), ("rtol_inner", C.c_double), ("max_refine", C.c_int32),
-        ("cluster", C.c_int32), ("profile", C.c_int32),
+        ("cluster", C.c_int32), ("profile", C.c_int32), ("coarse_max", C.c_int32),
     ]
 
 
@@ -269,10 +269,13 @@ class Problem:
 
     PHASES = ("geometry", "guess", "small_solve", "operator", "precond", "orthogonalisation", "other", "total")
 
-    def phase_times(self) -> dict:
-        out = np.zeros(8)
-        _check(lib.sa_get_phase_times(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), 8))
-        return dict(zip(self.PHASES, out.tolist()))
+    def phase_times(self, detail: bool = False):
+        out = np.zeros(57)
+        _check(lib.sa_get_phase_times(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), 57))
+        totals = dict(zip(self.PHASES, out[:8].tolist()))
+        if not detail:
+            return totals
+        return totals, out[8:]
 
     @property
     def sketch_count(self) -> int:

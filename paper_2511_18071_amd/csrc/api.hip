@@ -13,9 +13,10 @@
 
 namespace sa {
 extern "C" __global__ void sa_solve_kernel(const Problem*, SolveArgs);
+extern "C" __global__ void sa_solve_plain_kernel(const Problem*, SolveArgs);
 extern "C" __global__ void sa_geometry_kernel(const Problem*, const double*, const double*);
 extern "C" __global__ void sa_operator_kernel(const Problem*, const double*, double*);
-extern "C" __global__ void sa_precond_kernel(const Problem*, const double*, double*);
+extern "C" __global__ void sa_precond_kernel(const Problem*, const double*, double*, unsigned long long*);
 extern "C" __global__ void sa_push_kernel(const Problem*, SolveArgs);
 }  // namespace sa
 
@@ -88,6 +89,7 @@ extern "C" void sa_default_options(sa_options* o) {
   o->max_refine = 20;
   o->cluster = 0;
   o->profile = 0;
+  o->coarse_max = 700;
 }
 
 extern "C" const char* sa_last_error(void) { return g_err.c_str(); }
@@ -168,6 +170,57 @@ static void centred_h(const std::vector<double>& h, int periodic, double dx, std
 
 static size_t round_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Elimination factors of the vertical line systems of the still-water operator on one level:
+// after combining the bed row with row 1 (factor gam) each column is tridiagonal; pc are the
+// elimination ratios and inv the inverse pivots of its LU factorisation. Ghost columns of
+// wall grids are diagonal (pc = 0, gam = 0). uniform: every column has the same factors.
+static void line_factors(int ncol, int nl, int periodic, double dx, double dsig, const std::vector<double>& ihv,
+                         const std::vector<double>& hxv, const std::vector<double>& hxxv, bool uniform,
+                         std::vector<double>& pc, std::vector<double>& inv, std::vector<double>& lov,
+                         std::vector<double>& gam) {
+  const int nz = nl - 1, ncf = uniform ? 1 : ncol;
+  const double rds = 1.0 / dsig, rdx = 1.0 / dx;
+  pc.assign((size_t)nl * ncf, 0.0);
+  inv.assign((size_t)nl * ncf, 1.0);
+  lov.assign((size_t)nl * ncf, 0.0);
+  gam.assign(ncf, 0.0);
+  for (int c = 0; c < ncf; ++c) {
+    if (!periodic && (c == 0 || c == ncol - 1)) {
+      for (int j = 1; j < nz; ++j) inv[(size_t)j * ncf + c] = 1.0 / (0.5 * rdx);
+      continue;
+    }
+    const double ih = ihv[c], hx = hxv[c], hxx = hxxv[c];
+    auto coefs = [&](int j, double& lo, double& di, double& up) {
+      const double oms = 1.0 - (j - 1) * dsig;
+      const double sv = hx * oms * ih;
+      const double sxx = oms * hxx * ih - 2.0 * oms * hx * hx * ih * ih;
+      const double a = (sv * sv + ih * ih) * rds * rds, b = sxx * 0.5 * rds;
+      lo = a - b;
+      up = a + b;
+      di = -2.0 * rdx * rdx - 2.0 * a;
+    };
+    const double q = hx * (hx * ih) + ih;
+    const double a0 = 0.5 * rds * q, c0 = -0.5 * rds * q;
+    double l1, d1, u1;
+    coefs(1, l1, d1, u1);
+    const double a0p = a0 - c0 * l1 / u1;
+    const double b0p = -c0 * d1 / u1;
+    gam[c] = c0 / u1;
+    double pcp = b0p / a0p;
+    pc[c] = pcp;
+    inv[c] = 1.0 / a0p;
+    for (int j = 1; j < nz; ++j) {
+      double lo, di, up;
+      coefs(j, lo, di, up);
+      const double iv = 1.0 / (di - lo * pcp);
+      pcp = up * iv;
+      pc[(size_t)j * ncf + c] = pcp;
+      inv[(size_t)j * ncf + c] = iv;
+      lov[(size_t)j * ncf + c] = lo;
+    }
+  }
+}
+
 static int tiles_host(int ncol, int periodic, int tw) {
   int nt = (ncol + tw - 1) / tw;
   if (!periodic && nt > 1 && ncol - (nt - 1) * tw < 4) --nt;
@@ -200,6 +253,7 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   if (!(opt.r >= 0.0 && opt.r <= 1.0)) return fail(SA_EARG, "sa_create: r must be in [0, 1]");
   if (opt.precision != SA_FP64) return fail(SA_EARG, "sa_create: only SA_FP64 is available in this build");
   if (opt.max_levels < 1) return fail(SA_EARG, "sa_create: max_levels >= 1");
+  if (opt.coarse_max < 1 || opt.coarse_max > COARSE_MAX) return fail(SA_EARG, "sa_create: coarse_max in [1, %d]", COARSE_MAX);
   const int nphys = periodic ? grid->nx - 1 : grid->nx;
   for (int i = 0; i < nphys; ++i)
     if (!(h[i] > 0.0) || !isfinite(h[i])) return fail(SA_EGEOM, "sa_create: depth must be positive and finite");
@@ -239,7 +293,7 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   }
 
   // ---- still-water hierarchy
-  struct HL { int nx, ncol; double dx; std::vector<double> h, ih, hx, hxx; };
+  struct HL { int nx, ncol; double dx; std::vector<double> h, ih, hx, hxx, fpc, finv, flo, fgam; int fstride; };
   std::vector<HL> levs;
   {
     HL l0;
@@ -252,6 +306,7 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
     const int maxlev = opt.precond == SA_PC_MG ? (opt.max_levels < MAXLEV ? opt.max_levels : MAXLEV) : 1;
     while ((int)levs.size() < maxlev) {
       const HL& f = levs.back();
+      if ((long)f.ncol * nl <= opt.coarse_max) break;
       HL c;
       if (periodic) {
         if (f.ncol % 2 || f.ncol / 2 < 4) break;
@@ -272,6 +327,16 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   }
   const int nlev = (int)levs.size();
   const int cn = levs.back().ncol * nl;
+  int tail = nlev - 1;  // first level one preconditioner tile wide (run by one workgroup)
+  for (int l = 0; l < nlev - 1; ++l)
+    if (levs[l].ncol <= 64) { tail = l; break; }
+  for (auto& L : levs) {
+    bool uniform = periodic != 0;
+    for (int c = 1; c < L.ncol && uniform; ++c)
+      uniform = L.h[c] == L.h[0] && L.hx[c] == L.hx[0] && L.hxx[c] == L.hxx[0];
+    line_factors(L.ncol, nl, periodic, L.dx, dsig, L.ih, L.hx, L.hxx, uniform, L.fpc, L.finv, L.flo, L.fgam);
+    L.fstride = uniform ? 0 : L.ncol;
+  }
   std::vector<double> cinv;
   if (opt.precond == SA_PC_MG) {
     if (cn > COARSE_MAX) {
@@ -296,10 +361,12 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   const size_t head = (size_t)PSTRIDE + 4 * (MMAX + 2) + (size_t)(m + 1) * m + 2 * m + 2 * (m + 1) + m + KMAX +
                       4 * KMAX * KMAX + 8;
   const int TWMh = TX + 3, TWGMh = TXG + 3;
-  const size_t need_op = (size_t)(TWMh + 12 + 2 * (TWMh + 6)) * nl + 4;
-  const size_t need_gram = opt.guess == SA_GUESS_EWMA ? (size_t)(k * TWGMh + TWGMh + TWGMh + 12 + 2 * (TWGMh + 6)) * nl : 0;
+  auto opcoef = [&](int W) { return (size_t)(49 + 9 * nl + 5 * (W + 6)); };
+  const size_t need_op = (size_t)(TWMh + 12 + 2 * (TWMh + 6)) * nl + opcoef(TWMh) + 4;
+  const size_t need_gram = opt.guess == SA_GUESS_EWMA
+                               ? (size_t)(k * TWGMh + TWGMh + TWGMh + 12 + 2 * (TWGMh + 6)) * nl + opcoef(TWGMh) : 0;
   const int TMSh = 64 + 4;  // preconditioner tile with its 2-column halo
-  const size_t need_pc = (size_t)4 * TMSh * nl + 4 * TMSh;
+  const size_t need_pc = (size_t)5 * TMSh * nl + 5 * TMSh;
   size_t big = need_op;
   if (need_gram > big) big = need_gram;
   if (need_pc > big) big = need_pc;
@@ -312,7 +379,7 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   }
   if (G > 1) {
     int per_cu = 0;
-    hipFuncSetAttribute((const void*)sa_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
+    (void)hipFuncSetAttribute((const void*)sa_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)sa_solve_kernel, BLOCK, p->lds_solve) != hipSuccess ||
         per_cu < 1 || G > per_cu * prop.multiProcessorCount) {
       delete p;
@@ -326,11 +393,15 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   auto take = [&](size_t bytes) { size_t o = off; off += round_up(bytes); return o; };
   const size_t o_wsig = take(wsig.size() * 8), o_ssig = take(ssig.size() * 4), o_wchi = take(49 * 8),
                o_sig = take(nl * 8), o_h = take(ncol * 8), o_hchi = take(ncol * 8), o_geo = take(4 * (size_t)ncol * 8);
-  std::vector<size_t> o_lh(nlev), o_lih(nlev), o_lhx(nlev), o_lhxx(nlev), o_lf(nlev), o_lu(nlev), o_lo(nlev);
+  std::vector<size_t> o_lh(nlev), o_lih(nlev), o_lhx(nlev), o_lhxx(nlev), o_lf(nlev), o_lu(nlev), o_lo(nlev),
+      o_fpc(nlev), o_finv(nlev), o_flo(nlev), o_fgam(nlev);
   for (int l = 0; l < nlev; ++l) {
     const size_t nlv = (size_t)levs[l].ncol * nl;
     o_lh[l] = take(levs[l].ncol * 8); o_lhx[l] = take(levs[l].ncol * 8); o_lhxx[l] = take(levs[l].ncol * 8);
     o_lih[l] = take(levs[l].ncol * 8);
+    o_fpc[l] = take(levs[l].fpc.size() * 8); o_finv[l] = take(levs[l].finv.size() * 8);
+    o_flo[l] = take(levs[l].flo.size() * 8);
+    o_fgam[l] = take(levs[l].fgam.size() * 8);
     o_lf[l] = take(nlv * 8); o_lu[l] = take(nlv * 8); o_lo[l] = take(nlv * 8);
   }
   const size_t o_cinv = take(cinv.size() * 8 + 8);
@@ -340,7 +411,7 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   const size_t o_Y0 = take(ysz), o_Y1 = take(ysz);
   const size_t o_part = take((size_t)2 * G * PSTRIDE * 8), o_bar = take(64), o_flags = take(NFLAGS * 4),
                o_log = take(LOGCAP * sizeof(sa_solve_info)), o_b = take((size_t)n * 8), o_eta = take(2 * (size_t)nphys * 8),
-               o_prob = take(sizeof(Problem)), o_prof = take(NPHASE * 8);
+               o_prob = take(sizeof(Problem)), o_prof = take(NPROF * 8);
   p->arena_bytes = off;
   if (hipMalloc((void**)&p->arena, off) != hipSuccess) {
     delete p;
@@ -363,6 +434,10 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
     if (e == hipSuccess) e = up(o_lhx[l], levs[l].hx.data(), levs[l].ncol * 8);
     if (e == hipSuccess) e = up(o_lhxx[l], levs[l].hxx.data(), levs[l].ncol * 8);
     if (e == hipSuccess) e = up(o_lih[l], levs[l].ih.data(), levs[l].ncol * 8);
+    if (e == hipSuccess) e = up(o_fpc[l], levs[l].fpc.data(), levs[l].fpc.size() * 8);
+    if (e == hipSuccess) e = up(o_finv[l], levs[l].finv.data(), levs[l].finv.size() * 8);
+    if (e == hipSuccess) e = up(o_flo[l], levs[l].flo.data(), levs[l].flo.size() * 8);
+    if (e == hipSuccess) e = up(o_fgam[l], levs[l].fgam.data(), levs[l].fgam.size() * 8);
   }
   if (e == hipSuccess && !cinv.empty()) e = up(o_cinv, cinv.data(), cinv.size() * 8);
 
@@ -372,12 +447,15 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   P.wsig = (const double*)(A + o_wsig); P.ssig = (const int*)(A + o_ssig); P.wchi = (const double*)(A + o_wchi);
   P.sig = (const double*)(A + o_sig); P.h = (const double*)(A + o_h); P.hchi = (const double*)(A + o_hchi);
   P.geo = (double*)(A + o_geo);
-  P.pc = opt.precond; P.nu1 = opt.nu1; P.nu2 = opt.nu2; P.nlev = nlev; P.omega = opt.omega;
+  P.pc = opt.precond; P.nu1 = opt.nu1; P.nu2 = opt.nu2; P.nlev = nlev; P.omega = opt.omega; P.tail = tail;
   for (int l = 0; l < nlev; ++l) {
     Level& L = P.lev[l];
     L.ncol = levs[l].ncol; L.nx = levs[l].nx; L.dx = levs[l].dx;
     L.h = (const double*)(A + o_lh[l]); L.hx = (const double*)(A + o_lhx[l]); L.hxx = (const double*)(A + o_lhxx[l]);
     L.ih = (const double*)(A + o_lih[l]);
+    L.fpc = (const double*)(A + o_fpc[l]); L.finv = (const double*)(A + o_finv[l]);
+    L.fgam = (const double*)(A + o_fgam[l]); L.fstride = levs[l].fstride;
+    L.flo = (const double*)(A + o_flo[l]);
     L.f = (double*)(A + o_lf[l]); L.u = (double*)(A + o_lu[l]); L.o = (double*)(A + o_lo[l]);
   }
   P.cinv = (const double*)(A + o_cinv); P.cn = cn;
@@ -397,6 +475,7 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   }
   if (e == hipSuccess) e = up(o_prob, &P, sizeof(Problem));
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_solve_plain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_operator_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_op);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_precond_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_pc);
   if (e != hipSuccess) {
@@ -507,7 +586,8 @@ extern "C" int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags) {
   a.prev_guess = p->have_solution && (o.guess == SA_GUESS_PREVIOUS || (ewma && !a.sketch_guess));
   a.log_slot = (int)(p->log_pos % LOGCAP);
   void* args[] = {(void*)&p->dp, (void*)&a};
-  HIPCHK(launch_cluster(p, (const void*)sa_solve_kernel, args, p->lds_solve));
+  const void* fn = ewma ? (const void*)sa_solve_kernel : (const void*)sa_solve_plain_kernel;
+  HIPCHK(launch_cluster(p, fn, args, p->lds_solve));
   if (a.push) {
     p->ycur ^= 1;
     p->pushes += 1;
@@ -595,7 +675,7 @@ extern "C" int sa_apply_precond(sa_problem* p, const double* x, double* y, int32
   int rc = stage_in(p, x, mem, p->hp.xc, &xd);
   if (rc) return rc;
   double* yd = mem == SA_MEM_DEVICE ? y : p->hp.rc;
-  void* args[] = {(void*)&p->dp, (void*)&xd, (void*)&yd};
+  void* args[] = {(void*)&p->dp, (void*)&xd, (void*)&yd, (void*)&p->prof};
   HIPCHK(launch_cluster(p, (const void*)sa_precond_kernel, args, p->lds_pc));
   if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 8, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
@@ -628,9 +708,9 @@ extern "C" int sa_get_sketch(sa_problem* p, double* y, int32_t mem) {
 }
 
 extern "C" int sa_get_phase_times(sa_problem* p, double* out, int32_t n) {
-  if (!p || !out || n < 1 || n > NPHASE) return fail(SA_EARG, "sa_get_phase_times: bad arguments");
+  if (!p || !out || n < 1 || n > NPROF) return fail(SA_EARG, "sa_get_phase_times: bad arguments");
   if (!p->prof) return fail(SA_EARG, "sa_get_phase_times: problem created without profile = 1");
-  unsigned long long t[NPHASE];
+  unsigned long long t[NPROF];
   HIPCHK(hipMemcpyAsync(t, p->prof, sizeof t, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   for (int i = 0; i < n; ++i) out[i] = (double)t[i] / p->clock_khz;

@@ -28,7 +28,15 @@ struct Level {
   const double* h;           // depth per column (ghost columns by reflection)
   const double* ih;          // 1/h per column
   const double* hx;          // second-order centred dh/dx per column
-  const double* hxx;         // second-order centred d2h/dx2 per column
+ const double* hxx;         // second-order centred d2h/dx2 per column
+  // line-solve factors of the fixed still-water operator: ratio pc and inverse pivot at
+  // [j * fstride + c] (fstride = 0: every column has the same factors), bed-row combination
+  // factor per column
+  const double* fpc;
+  const double* finv;
+  const double* flo;         // sub-diagonal of the column systems (same layout)
+  const double* fgam;
+  int fstride;
   double* f;                 // right-hand side of this level (level 0: unused, the input)
   double* u;                 // smoothed iterate
   double* o;                 // output of this level's cycle (level 0: unused, the output)
@@ -46,7 +54,7 @@ struct Problem {
   const double* hchi;        // ncol sixth-order dh/dchi
   double* geo;               // 4 x ncol: 1/d_prev, d_chi prev, 1/d_cur, d_chi cur
   // preconditioner
-  int pc, nu1, nu2, nlev;
+  int pc, nu1, nu2, nlev, tail;   // tail: first level run by a single workgroup
   double omega;
   Level lev[MAXLEV];
   const double* cinv;        // dense inverse of the coarsest operator, cn x cn row-major
@@ -82,6 +90,9 @@ struct SolveArgs {
 // phase-time categories of the solve kernel (sa_get_phase_times)
 enum { PH_GEOM = 0, PH_GUESS = 1, PH_SMALL = 2, PH_OPER = 3, PH_PREC = 4, PH_ORTH = 5, PH_OTHER = 6, PH_TOTAL = 7,
        NPHASE = 8 };
+// detailed preconditioner timing (same buffer, after the NPHASE totals): coarse solve, then
+// down / up pass of level l at PH_MG + 1 + 2 l (+1)
+enum { PH_MG = NPHASE, NPROF = NPHASE + 1 + 2 * MAXLEV };
 
 // ---- host-side setup (setup.cpp) ----------------------------------------------------
 void fornberg(double z, const double* x, int n, int mmax, double* c /* n*(mmax+1) */);

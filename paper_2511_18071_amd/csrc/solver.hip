@@ -149,6 +149,50 @@ DEV void phase_geometry(const Problem& P, Cl& cl, const double* __restrict__ eta
   }
 }
 
+// i in [0, count) split over the workgroup; the loads of U consecutive strides are issued
+// before any of them is used.
+template <int U, class Ld, class St>
+DEV void staged(int count, Ld ld, St st) {
+  for (int base = threadIdx.x; base < count; base += U * BLOCK) {
+    double v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = base + q * BLOCK;
+      v[q] = i < count ? ld(i) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = base + q * BLOCK;
+      if (i < count) st(i, v[q]);
+    }
+  }
+}
+
+// Several staging segments in one batch: segment q has cnt[q] elements; ld(q, k) loads
+// element k of segment q, st(q, k, v) stores it.
+template <int U, int NS, class Ld, class St>
+DEV void staged_segments(const int (&cnt)[NS], Ld ld, St st) {
+  int total = 0;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) total += cnt[q];
+  auto locate = [&](int i, int& q, int& k) {
+    q = 0;
+    k = i;
+#pragma unroll
+    for (int r = 0; r < NS - 1; ++r)
+      if (q == r && k >= cnt[r]) { k -= cnt[r]; q = r + 1; }
+  };
+  staged<U>(total, [&](int i) {
+    int q, k;
+    locate(i, q, k);
+    return ld(q, k);
+  }, [&](int i, double v) {
+    int q, k;
+    locate(i, q, k);
+    st(q, k, v);
+  });
+}
+
 // ------------------------------------------------------------------------------------------
 // operator tiles
 struct Tiles {
@@ -161,15 +205,30 @@ DEV Tiles tiles_of(const Problem& P, int tw) {
   return Tiles{nt, tw};
 }
 
-// A x on the columns [c0, c0 + w) of one tile, all levels. x is multiplied by xs on load.
-// LDS: sx (W+12) x nl, sgx/sgz (W+6) x nl with W = tw + 3. The output functor receives
-// (level, column, A x value) for every node of the tile.
+// LDS doubles of the coefficient block of an operator tile of width W
+DEV constexpr int opcoef_size(int W, int nl) { return 49 + 9 * nl + 5 * (W + 6); }
+
+// A x on the columns [c0, c0 + w) of one tile, all levels. LDS: sx (W+12) x nl input with a
+// 6-column halo, sgx/sgz (W+6) x nl gradient of the previous stage, sc the coefficient block
+// (x and sigma weights, sigma windows and values, per-column geometry of both stages). Every
+// operand of the stencil loops is in LDS. load(level, column, tile column) returns the input;
+// out(level, tile column, column, value) receives A x.
 template <int W, class Load, class Out>
-DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, double* sgx, double* sgz, Out out) {
+DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, double* sgx, double* sgz,
+                       double* sc, Out out) {
   const int nc = P.ncol, nl = P.nl, nz = P.nz;
   constexpr int LX = W + 12, LG = W + 6;
+  double* swchi = sc;                  // 49
+  double* swsig = swchi + 49;          // nl x 7
+  double* ssig = swsig + 7 * nl;       // nl sigma values
+  int* sstart = (int*)(ssig + nl);     // nl window starts (stored in nl doubles)
+  double* gip = ssig + 2 * nl;         // LG: 1/d prev
+  double* gdp = gip + LG;              // LG: d_chi prev
+  double* ghc = gdp + LG;              // LG: h_chi
+  double* gic = ghc + LG;              // LG: 1/d cur
+  double* gdc = gic + LG;              // LG: d_chi cur
   // stage the input with a 6-column halo: load(level, column, tile-local column)
-  for (int i = threadIdx.x; i < LX * nl; i += BLOCK) {
+  staged<8>(LX * nl, [&](int i) {
     const int lj = i / LX, lc = i - lj * LX;
     int c = c0 - 6 + lc;
     double v = 0.0;
@@ -181,8 +240,24 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, d
         v = load(lj, c, lc);
       }
     }
-    sx[i] = v;
-  }
+    return v;
+  }, [&](int i, double v) { sx[i] = v; });
+  const int ncoef = 49 + 8 * nl;
+  staged<4>(ncoef + 5 * LG, [&](int i) {
+    if (i < 49) return P.wchi[i];
+    if (i < 49 + 7 * nl) return P.wsig[i - 49];
+    if (i < 49 + 8 * nl) return P.sig[i - 49 - 7 * nl];
+    const int q = (i - ncoef) / LG, lc = i - ncoef - q * LG;
+    int c = c0 - 3 + lc;
+    if (P.periodic) c = ((c % nc) + nc) % nc;
+    else if (c < 0 || c >= nc) return 0.0;
+    if (q == 2) return P.hchi[c];
+    return P.geo[(q < 2 ? q : q - 1) * nc + c];
+  }, [&](int i, double v) {
+    if (i < ncoef) swchi[i] = v;
+    else gip[i - ncoef] = v;
+  });
+  for (int j = threadIdx.x; j < nl; j += BLOCK) sstart[j] = P.ssig[j];
   __syncthreads();
   // gradient of the previous stage: G_x = D_x p + sigma_x D_sigma p, G_z = D_sigma p / d
   for (int i = threadIdx.x; i < LG * nl; i += BLOCK) {
@@ -190,19 +265,18 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, d
     const int c = c0 - 3 + lc;
     if (lc >= w + 6) continue;
     if (!P.periodic && (c < 0 || c >= nc)) continue;
-    const int cg = P.periodic ? ((c % nc) + nc) % nc : c;
     int row, start;
     chi_window(P, c, row, start);
     const int sidx = start - c0 + 6;
     double dxv = 0.0;
 #pragma unroll
-    for (int m = 0; m < 7; ++m) dxv += P.wchi[row * 7 + m] * sx[lj * LX + sidx + m];
-    const int s0 = P.ssig[lj];
+    for (int m = 0; m < 7; ++m) dxv += swchi[row * 7 + m] * sx[lj * LX + sidx + m];
+    const int s0 = sstart[lj];
     double dsv = 0.0;
 #pragma unroll
-    for (int m = 0; m < 7; ++m) dsv += P.wsig[lj * 7 + m] * sx[(s0 + m) * LX + lc + 3];
-    const double invd = P.geo[cg];
-    const double sxp = (P.hchi[cg] - P.sig[lj] * P.geo[nc + cg]) * invd;
+    for (int m = 0; m < 7; ++m) dsv += swsig[lj * 7 + m] * sx[(s0 + m) * LX + lc + 3];
+    const double invd = gip[lc];
+    const double sxp = (ghc[lc] - ssig[lj] * gdp[lc]) * invd;
     sgx[i] = dxv + sxp * dsv;
     sgz[i] = invd * dsv;
   }
@@ -219,24 +293,24 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, d
     } else if (ghostcol) {
       v = (c == 0) ? -sgx[lj * LG + (1 - c0) + 3] : sgx[lj * LG + (nc - 2 - c0) + 3];
     } else if (lj == 0) {
-      v = -P.hchi[c] * sgx[LG + lc + 3] - sgz[LG + lc + 3];
+      v = -ghc[lc + 3] * sgx[LG + lc + 3] - sgz[LG + lc + 3];
     } else {
       int row, start;
       chi_window(P, c, row, start);
       const int gidx = start - c0 + 3;
       double dxg = 0.0;
 #pragma unroll
-      for (int m = 0; m < 7; ++m) dxg += P.wchi[row * 7 + m] * sgx[lj * LG + gidx + m];
-      const int s0 = P.ssig[lj];
+      for (int m = 0; m < 7; ++m) dxg += swchi[row * 7 + m] * sgx[lj * LG + gidx + m];
+      const int s0 = sstart[lj];
       double dsg = 0.0, dsz = 0.0;
 #pragma unroll
       for (int m = 0; m < 7; ++m) {
-        const double ws = P.wsig[lj * 7 + m];
+        const double ws = swsig[lj * 7 + m];
         dsg += ws * sgx[(s0 + m) * LG + lc + 3];
         dsz += ws * sgz[(s0 + m) * LG + lc + 3];
       }
-      const double invd = P.geo[2 * nc + c];
-      const double sxc = (P.hchi[c] - P.sig[lj] * P.geo[3 * nc + c]) * invd;
+      const double invd = gic[lc + 3];
+      const double sxc = (ghc[lc + 3] - ssig[lj] * gdc[lc + 3]) * invd;
       v = dxg + sxc * dsg + invd * dsz;
     }
     out(lj, lc, c, v);
@@ -252,14 +326,15 @@ DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, 
   double* sx = lds;
   double* sgx = sx + (TWM + 12) * P.nl;
   double* sgz = sgx + (TWM + 6) * P.nl;
-  double* wsum = sgz + (TWM + 6) * P.nl;
+  double* sc = sgz + (TWM + 6) * P.nl;
+  double* wsum = sc + opcoef_size(TWM, P.nl);
   const int nc = P.ncol;
   double acc = 0.0, accb = 0.0;
   for (int t = cl.rank; t < T.nt; t += cl.G) {
     const int c0 = t * TX;
     const int w = (t == T.nt - 1) ? nc - c0 : TX;
     auto load = [&](int lj, int c, int) { return x[(size_t)lj * nc + c] * xs; };
-    tile_operator<TWM>(P, c0, w, load, sx, sgx, sgz, [&](int lj, int lc, int c, double v) {
+    tile_operator<TWM>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int c, double v) {
       const size_t e = (size_t)lj * nc + c;
       if (resid) {
         const double bb = b[e];
@@ -280,21 +355,22 @@ DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, 
 
 // ------------------------------------------------------------------------------------------
 // still-water preconditioner (second-order direct form at eta = 0), LDS-staged tiles of TM
-// columns x all levels. A column's data (h, 1/h, h_x, h_xx) and the fields it touches are
-// staged with coalesced loads; residuals are formed in parallel from LDS; the vertical line
-// solves run one thread per column from LDS with a single division per level.
+// columns x all levels. A tile's fields, column data (h, 1/h, h_x, h_xx) and line-solve
+// factors are staged with batched coalesced loads; residuals are formed from LDS; the
+// vertical line solves run one thread per column from LDS with precomputed elimination
+// factors (M is fixed), so the recurrences carry no division.
 constexpr int TM = 64;
 constexpr int TMS = TM + 4;  // stride of the per-thread line-solve scratch
 
 struct Lv {
-  int nc, nx;
+  int nc, nx, fstride;
   double rdx;
-  const double *h, *ih, *hx, *hxx;
+  const double *h, *ih, *hx, *hxx, *fpc, *finv, *flo, *fgam;
 };
 
 DEV Lv level_view(const Problem& P, int l) {
   const Level& L = P.lev[l];
-  return Lv{L.ncol, L.nx, 1.0 / L.dx, L.h, L.ih, L.hx, L.hxx};
+  return Lv{L.ncol, L.nx, L.fstride, 1.0 / L.dx, L.h, L.ih, L.hx, L.hxx, L.fpc, L.finv, L.flo, L.fgam};
 }
 
 // tile-local staging: column c (unwrapped) <-> slot c - base
@@ -337,54 +413,24 @@ DEV double m_apply(const Problem& P, int nc, double rdx, int c, int j, U u, CD c
   return dxx + 2.0 * s * dxz + (s * s + ih * ih) * dzz + sxx * dz;
 }
 
-// Line solve of column c: delta = L^-1 rhs, L = same-column part of M. rhs(j) gives the
-// right-hand side, put(j, delta) receives the result; cp, dpv are the thread's LDS scratch
-// with stride TMS. The bed row couples levels 0 and 2: it is first combined with row 1 so the
-// column system becomes tridiagonal, then eliminated downwards and substituted upwards.
-template <class R, class CD, class Put>
-DEV void column_solve(const Problem& P, int nc, double rdx, int c, R rhs, CD cd, Put put, double* cp, double* dpv) {
-  const int nz = P.nz;
-  if (!P.periodic && (c == 0 || c == nc - 1)) {
-    for (int j = 0; j <= nz; ++j) put(j, rhs(j) / ((j == 0 || j == nz) ? 1.0 : 0.5 * rdx));
-    return;
-  }
-  const double rds = 1.0 / P.dsig;
-  const double ih = cd(c, 1), hx = cd(c, 2), hxx = cd(c, 3);
-  auto coefs = [&](int j, double& lo, double& di, double& up) {
-    const double oms = 1.0 - P.sig[j];
-    const double s = hx * oms * ih;
-    const double sxx = oms * hxx * ih - 2.0 * oms * hx * hx * ih * ih;
-    const double a = (s * s + ih * ih) * rds * rds, b = sxx * 0.5 * rds;
-    lo = a - b;
-    up = a + b;
-    di = -2.0 * rdx * rdx - 2.0 * a;
-  };
-  const double q = hx * (hx * ih) + ih;
-  const double a0 = 0.5 * rds * q, c0 = -0.5 * rds * q;
-  double l1, d1, u1;
-  coefs(1, l1, d1, u1);
-  const double r0 = rhs(0), r1 = rhs(1);
-  const double a0p = a0 - c0 * l1 / u1;
-  const double b0p = -c0 * d1 / u1;
-  double pc = b0p / a0p, pd = (r0 - c0 * r1 / u1) / a0p;
-  cp[0] = pc;
-  dpv[0] = pd;
+// Line solve of one column in place: r <- L^-1 r with L the same-column part of M. The bed
+// row (coupling levels 0 and 2) is combined with row 1 (factor gam) so the system is
+// tridiagonal; lo, pc, inv are the precomputed sub-diagonal, elimination ratios and inverse
+// pivots (free-surface row: identity). Level stride rs for r, fs for the factors.
+DEV void line_solve(int nz, double gam, double* __restrict__ r, int rs, const double* __restrict__ lo,
+                    const double* __restrict__ pc, const double* __restrict__ inv, int fs) {
+  double pd = (r[0] - gam * r[rs]) * inv[0];
+  r[0] = pd;
+#pragma unroll 4
   for (int j = 1; j < nz; ++j) {
-    double lo, di, up;
-    if (j == 1) { lo = l1; di = d1; up = u1; }
-    else coefs(j, lo, di, up);
-    const double rj = (j == 1) ? r1 : rhs(j);
-    const double inv = 1.0 / (di - lo * pc);
-    pc = up * inv;
-    pd = (rj - lo * pd) * inv;
-    cp[j * TMS] = pc;
-    dpv[j * TMS] = pd;
+    pd = (r[j * rs] - lo[j * fs] * pd) * inv[j * fs];
+    r[j * rs] = pd;
   }
-  double dlt = rhs(nz);  // free surface: identity row
-  put(nz, dlt);
+  double d = r[nz * rs];
+#pragma unroll 4
   for (int j = nz - 1; j >= 0; --j) {
-    dlt = dpv[j * TMS] - cp[j * TMS] * dlt;
-    put(j, dlt);
+    d = r[j * rs] - pc[j * fs] * d;
+    r[j * rs] = d;
   }
 }
 
@@ -397,7 +443,6 @@ DEV double prolong_at(const Problem& P, int ncf, int ncc, const double* e, int c
   return (p & 1) ? 0.5 * (ec[((p - 1) >> 1) + 1] + ec[((p + 1) >> 1) + 1]) : ec[(p >> 1) + 1];
 }
 
-// number of tiles of a level and the fine column of coarse column C (walls: index shift)
 DEV int ptiles(int nc) { return (nc + TM - 1) / TM; }
 DEV int coarse_centre(const Problem& P, int C, int ncc, int ncf) {
   if (P.periodic) return 2 * C;
@@ -406,130 +451,216 @@ DEV int coarse_centre(const Problem& P, int C, int ncc, int ncf) {
   return 2 * C - 1;
 }
 
+// Stage column data (h, 1/h, h_x, h_xx) of the columns [st.base, st.base + width).
+DEV void stage_coldata(const Lv& L, const Stage& st, int width, double* scd) {
+  staged<4>(4 * width, [&](int i) {
+    const int q = i / width, lc = i - q * width;
+    const int c = st.base + lc;
+    if (!st.has(c)) return 1.0;
+    const int cg = st.col(c);
+    const double* src = q == 0 ? L.h : (q == 1 ? L.ih : (q == 2 ? L.hx : L.hxx));
+    return src[cg];
+  }, [&](int i, double v) { scd[i] = v; });
+}
+
+// Stage the line-solve factors lo, pc, inv (width x nl each, level-major) and gam (width)
+// of the columns [c0f, c0f + width).
+DEV void stage_factors(const Problem& P, const Lv& L, const Stage& st, int c0f, int width, double* sfac, double* sgam) {
+  const int nl = P.nl;
+  const int per = nl * width;
+  staged<8>(3 * per, [&](int i) {
+    const int q = i / per, r = i - q * per;
+    const int j = r / width, lc = r - j * width;
+    const int c = c0f + lc;
+    if (!st.has(c)) return q == 2 ? 1.0 : 0.0;
+    const int cg = L.fstride ? st.col(c) : 0;
+    const double* src = q == 0 ? L.flo : (q == 1 ? L.fpc : L.finv);
+    return src[(size_t)j * (L.fstride ? L.fstride : 1) + cg];
+  }, [&](int i, double v) { sfac[i] = v; });
+  for (int lc = threadIdx.x; lc < width; lc += BLOCK) {
+    const int c = c0f + lc;
+    sgam[lc] = st.has(c) ? L.fgam[L.fstride ? st.col(c) : 0] : 0.0;
+  }
+}
+
 // o = u + omega L^-1 (f - M u) on level l, u = (uin or 0) + (e ? P e : 0) formed on load.
-// LDS: su (TM+2) nl, sf TM nl, scd 4 (TM+2), cp/dp TMS nl each.
+// Residuals are formed by all threads in LDS, then one thread per column eliminates.
 DEV void phase_sweep(const Problem& P, Cl& cl, int l, const double* f, const double* uin, const double* e,
                      double* o, double* lds) {
   const Lv L = level_view(P, l);
-  const int nc = L.nc, nl = P.nl;
+  const int nc = L.nc, nl = P.nl, nz = P.nz;
   const int ncc = e ? P.lev[l + 1].ncol : 0;
   constexpr int LW = TM + 2;
-  double* su = lds;
-  double* sf = su + LW * nl;
-  double* scd = sf + TM * nl;
-  double* cp = scd + 4 * LW;
-  double* dpv = cp + TMS * nl;
+  double* su = lds;                 // LW x nl
+  double* sr = su + LW * nl;        // TM x nl: f, then the residual, then the correction
+  double* scd = sr + TM * nl;       // 4 x LW
+  double* sfac = scd + 4 * LW;      // 3 x TM x nl
+  double* sgam = sfac + 3 * TM * nl;  // TM
+  const bool zero = !uin && !e;
   for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
     const int c0 = t * TM, w = min(TM, nc - c0);
     const Stage st{c0 - 1, w + 2, nc, P.periodic};
-    for (int i = threadIdx.x; i < LW * nl; i += BLOCK) {
-      const int j = i / LW, lc = i - j * LW;
-      const int c = c0 - 1 + lc;
-      double v = 0.0;
-      if (lc < w + 2 && st.has(c)) {
+    const int wu = zero ? 0 : w + 2;
+    const int cnt[5] = {wu * nl, w * nl, 4 * wu, 3 * nl * w, w};
+    staged_segments<16>(cnt, [&](int q, int k) -> double {
+      if (q == 0 || q == 2) {  // u with the prolongated correction, column data
+        const int width = wu;
+        const int j = k / width, lc = k - j * width;
+        const int c = c0 - 1 + lc;
+        if (!st.has(c)) return q == 2 ? 1.0 : 0.0;
         const int cg = st.col(c);
-        if (uin) v = uin[(size_t)j * nc + cg];
+        if (q == 2) {
+          const double* src = j == 0 ? L.h : (j == 1 ? L.ih : (j == 2 ? L.hx : L.hxx));
+          return src[cg];
+        }
+        double v = uin ? uin[(size_t)j * nc + cg] : 0.0;
         if (e) v += prolong_at(P, nc, ncc, e, cg, j);
+        return v;
       }
-      su[i] = v;
-    }
-    for (int i = threadIdx.x; i < TM * nl; i += BLOCK) {
-      const int j = i / TM, lc = i - j * TM;
-      sf[i] = lc < w ? f[(size_t)j * nc + c0 + lc] : 0.0;
-    }
-    for (int lc = threadIdx.x; lc < LW; lc += BLOCK) {
-      const int c = c0 - 1 + lc;
-      if (lc < w + 2 && st.has(c)) {
-        const int cg = st.col(c);
-        scd[lc] = L.h[cg]; scd[LW + lc] = L.ih[cg]; scd[2 * LW + lc] = L.hx[cg]; scd[3 * LW + lc] = L.hxx[cg];
+      if (q == 1) {
+        const int j = k / w, lc = k - j * w;
+        return f[(size_t)j * nc + c0 + lc];
       }
+      if (q == 3) {
+        const int per = nl * w;
+        const int qq = k / per, r = k - qq * per;
+        const int j = r / w, lc = r - j * w;
+        const int cg = L.fstride ? c0 + lc : 0;
+        const double* src = qq == 0 ? L.flo : (qq == 1 ? L.fpc : L.finv);
+        return src[(size_t)j * (L.fstride ? L.fstride : 1) + cg];
+      }
+      return L.fgam[L.fstride ? c0 + k : 0];
+    }, [&](int q, int k, double v) {
+      if (q == 0) { const int j = k / wu, lc = k - j * wu; su[j * LW + lc] = v; }
+      else if (q == 1) { const int j = k / w, lc = k - j * w; sr[j * TM + lc] = v; }
+      else if (q == 2) { const int j = k / wu, lc = k - j * wu; scd[j * LW + lc] = v; }
+      else if (q == 3) {
+        const int per = nl * w;
+        const int qq = k / per, r = k - qq * per;
+        const int j = r / w, lc = r - j * w;
+        sfac[qq * TM * nl + j * TM + lc] = v;
+      } else sgam[k] = v;
+    });
+    __syncthreads();
+    if (!zero) {
+      auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
+      auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
+      for (int i = threadIdx.x; i < TM * nl; i += BLOCK) {
+        const int j = i / TM, lc = i - j * TM;
+        if (lc < w) sr[i] -= m_apply(P, nc, L.rdx, c0 + lc, j, U, CD);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x < w) {
+      const int lc = threadIdx.x;
+      line_solve(nz, sgam[lc], sr + lc, TM, sfac + lc, sfac + TM * nl + lc, sfac + 2 * TM * nl + lc, TM);
     }
     __syncthreads();
-    const bool zero = !uin && !e;
-    auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
-    auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
-    if (threadIdx.x < w) {
-      const int lc = threadIdx.x, c = c0 + lc;
-      auto rhs = [&](int j) { return sf[j * TM + lc] - (zero ? 0.0 : m_apply(P, nc, L.rdx, c, j, U, CD)); };
-      auto put = [&](int j, double d) { o[(size_t)j * nc + c] = U(c, j) + P.omega * d; };
-      column_solve(P, nc, L.rdx, c, rhs, CD, put, cp + threadIdx.x, dpv + threadIdx.x);
+    const double om = P.omega;
+    for (int i = threadIdx.x; i < TM * nl; i += BLOCK) {
+      const int j = i / TM, lc = i - j * TM;
+      if (lc < w) o[(size_t)j * nc + c0 + lc] = (zero ? 0.0 : su[j * LW + lc + 1]) + om * sr[i];
     }
     __syncthreads();
   }
 }
 
+DEV void coarse_range(const Problem& P, int c0, int w, int nc, int ncc, int& Cfirst, int& Clast) {
+  if (P.periodic) { Cfirst = (c0 + 1) / 2; Clast = (c0 + w - 1) / 2; return; }
+  Cfirst = (c0 == 0) ? 0 : (c0 + 2) / 2;
+  Clast = (c0 + w >= nc) ? ncc - 1 : (c0 + w) / 2;
+}
+
+// full weighting of the residual R(cc) around the centre of coarse column C
+template <class RR>
+DEV double restrict_at(const Problem& P, int C, int ncc, int nxc, int nc, RR Rr) {
+  const int cf = coarse_centre(P, C, ncc, nc);
+  if (P.periodic) return 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
+  if (C == 0 || C == ncc - 1) return Rr(cf);
+  if (C == 1) return 0.5 * Rr(1) + 0.5 * Rr(2);
+  if (C == nxc) return 0.5 * Rr(cf) + 0.5 * Rr(cf - 1);
+  return 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
+}
+
 // Pre-smoothing from zero, residual and restriction in one pass (nu1 = 1):
 // u = omega L^-1 f on the tile plus a 2-column halo, u written for the tile's columns,
 // fc(C) = full weighting of f - M u at the fine columns around C's centre.
-// LDS: sf, su (TM+4) nl, scd 4 (TM+4), cp/dp TMS nl each.
 DEV void phase_down(const Problem& P, Cl& cl, int l, const double* f, double* u, double* fc, double* lds) {
   const Lv L = level_view(P, l);
-  const int nc = L.nc, nl = P.nl;
+  const int nc = L.nc, nl = P.nl, nz = P.nz;
   const int ncc = P.lev[l + 1].ncol, nxc = P.lev[l + 1].nx;
   constexpr int LW = TM + 4;
-  double* sf = lds;
-  double* su = sf + LW * nl;
-  double* scd = su + LW * nl;
-  double* cp = scd + 4 * LW;
-  double* dpv = cp + TMS * nl;
+  double* sf = lds;                 // LW x nl
+  double* su = sf + LW * nl;        // LW x nl
+  double* scd = su + LW * nl;       // 4 x LW
+  double* sfac = scd + 4 * LW;      // 3 x LW x nl
+  double* sgam = sfac + 3 * LW * nl;  // LW
   for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
     const int c0 = t * TM, w = min(TM, nc - c0);
     const Stage st{c0 - 2, w + 4, nc, P.periodic};
-    for (int i = threadIdx.x; i < LW * nl; i += BLOCK) {
-      const int j = i / LW, lc = i - j * LW;
-      const int c = c0 - 2 + lc;
-      sf[i] = (lc < w + 4 && st.has(c)) ? f[(size_t)j * nc + st.col(c)] : 0.0;
-      su[i] = 0.0;
-    }
-    for (int lc = threadIdx.x; lc < LW; lc += BLOCK) {
-      const int c = c0 - 2 + lc;
-      if (lc < w + 4 && st.has(c)) {
-        const int cg = st.col(c);
-        scd[lc] = L.h[cg]; scd[LW + lc] = L.ih[cg]; scd[2 * LW + lc] = L.hx[cg]; scd[3 * LW + lc] = L.hxx[cg];
+    const int ww = w + 4;
+    const int cnt[4] = {ww * nl, 4 * ww, 3 * nl * ww, ww};
+    staged_segments<16>(cnt, [&](int q, int k) -> double {
+      if (q == 0) {
+        const int j = k / ww, lc = k - j * ww;
+        const int c = c0 - 2 + lc;
+        return st.has(c) ? f[(size_t)j * nc + st.col(c)] : 0.0;
       }
+      if (q == 1) {
+        const int j = k / ww, lc = k - j * ww;
+        const int c = c0 - 2 + lc;
+        if (!st.has(c)) return 1.0;
+        const double* src = j == 0 ? L.h : (j == 1 ? L.ih : (j == 2 ? L.hx : L.hxx));
+        return src[st.col(c)];
+      }
+      if (q == 2) {
+        const int per = nl * ww;
+        const int qq = k / per, r = k - qq * per;
+        const int j = r / ww, lc = r - j * ww;
+        const int c = c0 - 2 + lc;
+        if (!st.has(c)) return qq == 2 ? 1.0 : 0.0;
+        const int cg = L.fstride ? st.col(c) : 0;
+        const double* src = qq == 0 ? L.flo : (qq == 1 ? L.fpc : L.finv);
+        return src[(size_t)j * (L.fstride ? L.fstride : 1) + cg];
+      }
+      const int c = c0 - 2 + k;
+      return st.has(c) ? L.fgam[L.fstride ? st.col(c) : 0] : 0.0;
+    }, [&](int q, int k, double v) {
+      if (q == 0) { const int j = k / ww, lc = k - j * ww; sf[j * LW + lc] = v; su[j * LW + lc] = v; }
+      else if (q == 1) { const int j = k / ww, lc = k - j * ww; scd[j * LW + lc] = v; }
+      else if (q == 2) {
+        const int per = nl * ww;
+        const int qq = k / per, r = k - qq * per;
+        const int j = r / ww, lc = r - j * ww;
+        sfac[qq * LW * nl + j * LW + lc] = v;
+      } else sgam[k] = v;
+    });
+    __syncthreads();
+    if (threadIdx.x < w + 4 && st.has(c0 - 2 + (int)threadIdx.x)) {
+      const int lc = threadIdx.x;
+      line_solve(nz, sgam[lc], su + lc, LW, sfac + lc, sfac + LW * nl + lc, sfac + 2 * LW * nl + lc, LW);
     }
     __syncthreads();
-    auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
-    auto F = [&](int cc, int jj) { return sf[jj * LW + st.slot(cc)]; };
-    auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
-    if (threadIdx.x < w + 4) {
-      const int lc = threadIdx.x, c = c0 - 2 + lc;
-      if (st.has(c)) {
-        auto rhs = [&](int j) { return F(c, j); };
-        auto put = [&](int j, double d) { su[j * LW + lc] = P.omega * d; };
-        column_solve(P, nc, L.rdx, c, rhs, CD, put, cp + threadIdx.x, dpv + threadIdx.x);
-      }
+    const double om = P.omega;
+    for (int i = threadIdx.x; i < ww * nl; i += BLOCK) {
+      const int j = i / ww, lc = i - j * ww;
+      su[j * LW + lc] *= om;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < w * nl; i += BLOCK) {
       const int j = i / w, lc = i - j * w;
       u[(size_t)j * nc + c0 + lc] = su[j * LW + lc + 2];
     }
-    // coarse columns whose centre lies in this tile
+    auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
+    auto F = [&](int cc, int jj) { return sf[jj * LW + st.slot(cc)]; };
+    auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
     int Cfirst, Clast;
-    if (P.periodic) { Cfirst = (c0 + 1) / 2; Clast = (c0 + w - 1) / 2; }
-    else {
-      Cfirst = (c0 == 0) ? 0 : (c0 + 2) / 2;
-      Clast = (c0 + w >= nc) ? ncc - 1 : (c0 + w) / 2;
-    }
+    coarse_range(P, c0, w, nc, ncc, Cfirst, Clast);
     const int ncw = Clast - Cfirst + 1;
     for (int i = threadIdx.x; i < ncw * nl; i += BLOCK) {
       const int j = i / ncw, C = Cfirst + i - j * ncw;
       auto Rr = [&](int cc) { return F(cc, j) - m_apply(P, nc, L.rdx, cc, j, U, CD); };
-      const int cf = coarse_centre(P, C, ncc, nc);
-      double v;
-      if (P.periodic) {
-        v = 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
-      } else if (C == 0 || C == ncc - 1) {
-        v = Rr(cf);
-      } else if (C == 1) {
-        v = 0.5 * Rr(1) + 0.5 * Rr(2);
-      } else if (C == nxc) {
-        v = 0.5 * Rr(cf) + 0.5 * Rr(cf - 1);
-      } else {
-        v = 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
-      }
-      fc[(size_t)j * ncc + C] = v;
+      fc[(size_t)j * ncc + C] = restrict_at(P, C, ncc, nxc, nc, Rr);
     }
     __syncthreads();
   }
@@ -548,42 +679,28 @@ DEV void phase_restrict(const Problem& P, Cl& cl, int l, const double* f, const 
   for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
     const int c0 = t * TM, w = min(TM, nc - c0);
     const Stage st{c0 - 2, w + 4, nc, P.periodic};
-    for (int i = threadIdx.x; i < LW * nl; i += BLOCK) {
+    staged<8>(LW * nl, [&](int i) {
       const int j = i / LW, lc = i - j * LW;
       const int c = c0 - 2 + lc;
-      const bool ok = lc < w + 4 && st.has(c);
-      sf[i] = ok ? f[(size_t)j * nc + st.col(c)] : 0.0;
-      su[i] = ok ? u[(size_t)j * nc + st.col(c)] : 0.0;
-    }
-    for (int lc = threadIdx.x; lc < LW; lc += BLOCK) {
+      return (lc < w + 4 && st.has(c)) ? f[(size_t)j * nc + st.col(c)] : 0.0;
+    }, [&](int i, double v) { sf[i] = v; });
+    staged<8>(LW * nl, [&](int i) {
+      const int j = i / LW, lc = i - j * LW;
       const int c = c0 - 2 + lc;
-      if (lc < w + 4 && st.has(c)) {
-        const int cg = st.col(c);
-        scd[lc] = L.h[cg]; scd[LW + lc] = L.ih[cg]; scd[2 * LW + lc] = L.hx[cg]; scd[3 * LW + lc] = L.hxx[cg];
-      }
-    }
+      return (lc < w + 4 && st.has(c)) ? u[(size_t)j * nc + st.col(c)] : 0.0;
+    }, [&](int i, double v) { su[i] = v; });
+    stage_coldata(L, st, LW, scd);
     __syncthreads();
     auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
     auto F = [&](int cc, int jj) { return sf[jj * LW + st.slot(cc)]; };
     auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
     int Cfirst, Clast;
-    if (P.periodic) { Cfirst = (c0 + 1) / 2; Clast = (c0 + w - 1) / 2; }
-    else {
-      Cfirst = (c0 == 0) ? 0 : (c0 + 2) / 2;
-      Clast = (c0 + w >= nc) ? ncc - 1 : (c0 + w) / 2;
-    }
+    coarse_range(P, c0, w, nc, ncc, Cfirst, Clast);
     const int ncw = Clast - Cfirst + 1;
     for (int i = threadIdx.x; i < ncw * nl; i += BLOCK) {
       const int j = i / ncw, C = Cfirst + i - j * ncw;
       auto Rr = [&](int cc) { return F(cc, j) - m_apply(P, nc, L.rdx, cc, j, U, CD); };
-      const int cf = coarse_centre(P, C, ncc, nc);
-      double v;
-      if (P.periodic) v = 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
-      else if (C == 0 || C == ncc - 1) v = Rr(cf);
-      else if (C == 1) v = 0.5 * Rr(1) + 0.5 * Rr(2);
-      else if (C == nxc) v = 0.5 * Rr(cf) + 0.5 * Rr(cf - 1);
-      else v = 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
-      fc[(size_t)j * ncc + C] = v;
+      fc[(size_t)j * ncc + C] = restrict_at(P, C, ncc, nxc, nc, Rr);
     }
     __syncthreads();
   }
@@ -601,10 +718,17 @@ DEV void phase_prolong(const Problem& P, Cl& cl, int l, const double* e, double*
 
 DEV void phase_coarse(const Problem& P, Cl& cl, const double* f, double* o) {
   const int cn = P.cn;
+  const double* ci = P.cinv;
   for (int i = cl.rank * BLOCK + threadIdx.x; i < cn; i += cl.G * BLOCK) {
-    double s = 0.0;
-    for (int j = 0; j < cn; ++j) s += P.cinv[(size_t)j * cn + i] * f[j];
-    o[i] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int j = 0;
+    for (; j + 3 < cn; j += 4) {
+      const double a0 = ci[(size_t)j * cn + i], a1 = ci[(size_t)(j + 1) * cn + i];
+      const double a2 = ci[(size_t)(j + 2) * cn + i], a3 = ci[(size_t)(j + 3) * cn + i];
+      s0 += a0 * f[j]; s1 += a1 * f[j + 1]; s2 += a2 * f[j + 2]; s3 += a3 * f[j + 3];
+    }
+    for (; j < cn; ++j) s0 += ci[(size_t)j * cn + i] * f[j];
+    o[i] = (s0 + s1) + (s2 + s3);
   }
 }
 
@@ -616,9 +740,102 @@ DEV void phase_copy(const Problem& P, Cl& cl, const double* src, double* dst, in
   for (int i = cl.rank * BLOCK + threadIdx.x; i < len; i += cl.G * BLOCK) dst[i] = src[i];
 }
 
+// per-phase wall-clock accounting (workgroup 0, thread 0), enabled when a.prof != nullptr
+struct PhaseClock {
+  unsigned long long acc[NPHASE];
+  unsigned long long* detail;  // NPROF counters or nullptr
+  unsigned long long last, start;
+  bool on;
+  DEV void begin(bool enable, unsigned long long* det = nullptr) {
+    on = enable && blockIdx.x == 0 && threadIdx.x == 0;
+    detail = on ? det : nullptr;
+    for (int i = 0; i < NPHASE; ++i) acc[i] = 0;
+    last = start = on ? wall_clock64() : 0;
+  }
+  DEV void tick(int cat) {
+    if (!on) return;
+    const unsigned long long now = wall_clock64();
+    acc[cat] += now - last;
+    last = now;
+  }
+  // detailed tick: charged to the detail slot and to no total
+  DEV void dtick(int slot) {
+    if (!on) return;
+    const unsigned long long now = wall_clock64();
+    if (detail) atomicAdd(detail + PH_MG + slot, now - last);
+    acc[PH_PREC] += now - last;
+    last = now;
+  }
+  DEV void flush(unsigned long long* out) {
+    if (!on) return;
+    acc[PH_TOTAL] = wall_clock64() - start;
+    for (int i = 0; i < NPHASE; ++i) atomicAdd(out + i, acc[i]);
+  }
+};
+
+// one V-cycle level pair on the way down / up (cluster or single-workgroup view)
+DEV void mg_down(const Problem& P, Cl& cl, int l, const double* v, double* lds) {
+  const double* f = l == 0 ? v : P.lev[l].f;
+  double* A = P.lev[l].u;
+  double* B = P.lev[l].o;
+  if (P.nu1 == 1) {
+    phase_down(P, cl, l, f, A, P.lev[l + 1].f, lds);
+    csync(cl);
+    return;
+  }
+  const double* prev = nullptr;
+  double* dst = A;
+  if (P.nu1 == 0) {
+    phase_zero(P, cl, A, P.lev[l].ncol * P.nl);
+    csync(cl);
+  }
+  for (int s = 0; s < P.nu1; ++s) {
+    dst = (prev == A) ? B : A;
+    phase_sweep(P, cl, l, f, prev, nullptr, dst, lds);
+    csync(cl);
+    prev = dst;
+  }
+  if (dst != A) {
+    phase_copy(P, cl, dst, A, P.lev[l].ncol * P.nl);
+    csync(cl);
+  }
+  phase_restrict(P, cl, l, f, A, P.lev[l + 1].f, lds);
+  csync(cl);
+}
+
+// returns the buffer holding level l's output; z is level 0's destination
+DEV const double* mg_up(const Problem& P, Cl& cl, int l, const double* v, const double* e, double* z, double* lds) {
+  const double* f = l == 0 ? v : P.lev[l].f;
+  double* A = P.lev[l].u;
+  double* B = P.lev[l].o;
+  double* out = (l == 0) ? z : B;
+  if (P.nu2 == 0) {
+    phase_prolong(P, cl, l, e, A);
+    csync(cl);
+    if (l == 0) {
+      phase_copy(P, cl, A, z, P.n);
+      csync(cl);
+      return z;
+    }
+    return A;
+  }
+  double* dst = (P.nu2 == 1) ? out : B;
+  phase_sweep(P, cl, l, f, A, e, dst, lds);  // first post-sweep, correction added on load
+  csync(cl);
+  const double* prev = dst;
+  for (int s = 1; s < P.nu2; ++s) {
+    double* nd = (s == P.nu2 - 1) ? out : ((prev == B) ? A : B);
+    phase_sweep(P, cl, l, f, prev, nullptr, nd, lds);
+    csync(cl);
+    prev = nd;
+  }
+  return out;
+}
+
 // z = M^-1 v. v and z are level-0 vectors distinct from each other and from the level-0
-// scratch (lev[0].u, lev[0].o). Ends with a cluster barrier.
-DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* lds) {
+// scratch (lev[0].u, lev[0].o). Levels from P.tail on (at most two tiles wide) are run by
+// workgroup 0 alone with workgroup barriers only. Ends with a cluster barrier.
+DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* lds, PhaseClock* ck = nullptr) {
   const int n = P.n;
   if (P.pc == SA_PC_NONE) {
     phase_copy(P, cl, v, z, n);
@@ -643,75 +860,39 @@ DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* l
     csync(cl);
     return;
   }
-  // level vectors: f (right-hand side), u (pre-smoothed), o (output)
-  for (int l = 0; l < L - 1; ++l) {
-    const double* f = l == 0 ? v : P.lev[l].f;
-    double* A = P.lev[l].u;
-    double* B = P.lev[l].o;
-    if (P.nu1 == 1) {
-      phase_down(P, cl, l, f, A, P.lev[l + 1].f, lds);
-      csync(cl);
-      continue;
-    }
-    const double* prev = nullptr;
-    double* dst = A;
-    if (P.nu1 == 0) {
-      phase_zero(P, cl, A, P.lev[l].ncol * P.nl);
-      csync(cl);
-    }
-    for (int s = 0; s < P.nu1; ++s) {
-      dst = (prev == A) ? B : A;
-      phase_sweep(P, cl, l, f, prev, nullptr, dst, lds);
-      csync(cl);
-      prev = dst;
-    }
-    if (dst != A) {
-      phase_copy(P, cl, dst, A, P.lev[l].ncol * P.nl);
-      csync(cl);
-    }
-    phase_restrict(P, cl, l, f, A, P.lev[l + 1].f, lds);
+  // levels [lt, L-1) are one tile wide: workgroup 0 runs their passes alone (workgroup
+  // barriers only); the coarsest dense solve is shared by the whole cluster
+  const int lt = (cl.G > 1 && P.tail < L - 1) ? P.tail : L - 1;
+  auto tk = [&](int slot) { if (ck) ck->dtick(slot); };
+  for (int l = 0; l < lt; ++l) { mg_down(P, cl, l, v, lds); tk(1 + 2 * l); }
+  Cl solo{0, 1, cl.bar, cl.flags, cl.partials, cl.pbuf};
+  if (lt < L - 1) {
+    if (cl.rank == 0)
+      for (int l = lt; l < L - 1; ++l) { mg_down(P, solo, l, v, lds); tk(1 + 2 * l); }
     csync(cl);
+    tk(2 * MAXLEV);
   }
   phase_coarse(P, cl, P.lev[L - 1].f, P.lev[L - 1].o);
   csync(cl);
-  const double* e = P.lev[L - 1].o;  // correction coming from the coarser level
-  for (int l = L - 2; l >= 0; --l) {
-    const double* f = l == 0 ? v : P.lev[l].f;
-    double* A = P.lev[l].u;
-    double* B = P.lev[l].o;
-    double* out = (l == 0) ? z : B;
-    if (P.nu2 == 0) {
-      phase_prolong(P, cl, l, e, A);
-      csync(cl);
-      if (l == 0) {
-        phase_copy(P, cl, A, z, n);
-        csync(cl);
-        e = z;
-      } else {
-        e = A;
-      }
-      continue;
-    }
-    // first post-sweep with the prolongated correction added on load
-    double* dst = (P.nu2 == 1) ? out : B;
-    if (l == 0 && P.nu2 > 1) dst = B0;
-    phase_sweep(P, cl, l, f, A, e, dst, lds);
+  tk(0);
+  const double* e = P.lev[L - 1].o;
+  if (lt < L - 1) {
+    if (cl.rank == 0)
+      for (int l = L - 2; l >= lt; --l) { e = mg_up(P, solo, l, v, e, z, lds); tk(2 + 2 * l); }
     csync(cl);
-    const double* prev = dst;
-    for (int s = 1; s < P.nu2; ++s) {
-      double* nd = (s == P.nu2 - 1) ? out : ((prev == B) ? A : B);
-      phase_sweep(P, cl, l, f, prev, nullptr, nd, lds);
-      csync(cl);
-      prev = nd;
-    }
-    e = out;
+    tk(2 * MAXLEV);
+    // every workgroup knows which buffer holds the tail's output
+    e = (lt == 0) ? z : (P.nu2 == 0 ? P.lev[lt].u : P.lev[lt].o);
+    if (lt == 0) return;
   }
+  for (int l = lt - 1; l >= 0; --l) { e = mg_up(P, cl, l, v, e, z, lds); tk(2 + 2 * l); }
 }
 
 // ------------------------------------------------------------------------------------------
 // Arnoldi pieces. V holds raw (unnormalised) basis vectors; vs[i] scales V_i to unit norm.
 
-// red[i] = vs[i] * (V_i . w), i < nv; red[nv] = ||w||^2 if with_norm
+// red[i] = vs[i] * (V_i . w), i < nv; red[nv] = ||w||^2 if with_norm. Each thread streams its
+// elements of one vector at a time, four loads in flight per accumulator set.
 DEV void phase_dots(const Problem& P, Cl& cl, const double* V, const double* vs, int nv, const double* w,
                     bool with_norm, double* wsum, double* red) {
   const int n = P.n;
@@ -720,21 +901,27 @@ DEV void phase_dots(const Problem& P, Cl& cl, const double* V, const double* vs,
   const int nred = nv + (with_norm ? 1 : 0);
   for (int i = 0; i < nred; ++i) {
     const double* a = (i < nv) ? V + (size_t)i * n : w;
-    double s = 0.0;
-    for (int e = cl.rank * BLOCK + threadIdx.x; e < n; e += stride) s += a[e] * w[e];
-    s = wave_sum(s);
-    if (lane == 0) wsum[i * 4 + wave] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int e = cl.rank * BLOCK + threadIdx.x;
+    for (; e + 3 * stride < n; e += 4 * stride) {
+      const double a0 = a[e], a1 = a[e + stride], a2 = a[e + 2 * stride], a3 = a[e + 3 * stride];
+      const double w0 = w[e], w1 = w[e + stride], w2 = w[e + 2 * stride], w3 = w[e + 3 * stride];
+      s0 += a0 * w0; s1 += a1 * w1; s2 += a2 * w2; s3 += a3 * w3;
+    }
+    for (; e < n; e += stride) s0 += a[e] * w[e];
+    double sum = wave_sum((s0 + s1) + (s2 + s3));
+    if (lane == 0) wsum[i * 4 + wave] = sum;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nred; i += BLOCK) {
-    const double s = (wsum[i * 4] + wsum[i * 4 + 1]) + (wsum[i * 4 + 2] + wsum[i * 4 + 3]);
-    red[i] = (i < nv) ? vs[i] * s : s;
+    const double sm = (wsum[i * 4] + wsum[i * 4 + 1]) + (wsum[i * 4 + 2] + wsum[i * 4 + 3]);
+    red[i] = (i < nv) ? vs[i] * sm : sm;
   }
   __syncthreads();
 }
 
 // w -= sum_i h[i] vs[i] V_i (in place); then red[i] = vs[i] (V_i . w) for i < nv when dots,
-// or red[0] = ||w||^2 when !dots.
+// or red[0] = ||w||^2 when !dots. Basis loads go in groups of four.
 DEV void phase_update(const Problem& P, Cl& cl, const double* V, const double* vs, const double* h, int nv,
                       double* w, bool dots, double* wsum, double* red) {
   const int n = P.n;
@@ -748,14 +935,25 @@ DEV void phase_update(const Problem& P, Cl& cl, const double* V, const double* v
   for (int base = cl.rank * BLOCK + wave * 64; base < n; base += stride) {
     const int e = base + lane;
     const bool ok = e < n;
+    const size_t ec = ok ? (size_t)e : 0;
     double we = ok ? w[e] : 0.0;
-    for (int i = 0; i < nv; ++i) we -= (ok ? V[(size_t)i * n + e] : 0.0) * (h[i] * vs[i]);
+    int i = 0;
+    for (; i + 3 < nv; i += 4) {
+      const double v0 = V[(size_t)i * n + ec], v1 = V[(size_t)(i + 1) * n + ec];
+      const double v2 = V[(size_t)(i + 2) * n + ec], v3 = V[(size_t)(i + 3) * n + ec];
+      we -= v0 * (h[i] * vs[i]);
+      we -= v1 * (h[i + 1] * vs[i + 1]);
+      we -= v2 * (h[i + 2] * vs[i + 2]);
+      we -= v3 * (h[i + 3] * vs[i + 3]);
+    }
+    for (; i < nv; ++i) we -= V[(size_t)i * n + ec] * (h[i] * vs[i]);
+    if (!ok) we = 0.0;
     if (ok) w[e] = we;
     if (dots) {
-      for (int i = 0; i < nv; ++i) {
-        double p = (ok ? V[(size_t)i * n + e] : 0.0) * we;
+      for (int q = 0; q < nv; ++q) {
+        double p = V[(size_t)q * n + ec] * we;
         p = wave_sum(p);
-        if (lane == 0) wsum[i * 4 + wave] += p;
+        if (lane == 0) wsum[q * 4 + wave] += p;
       }
     } else {
       nrm += we * we;
@@ -777,7 +975,13 @@ DEV void phase_combine(const Problem& P, Cl& cl, const double* V, const double* 
   const int n = P.n;
   for (int e = cl.rank * BLOCK + threadIdx.x; e < n; e += cl.G * BLOCK) {
     double v = src[e];
-    for (int i = 0; i < nv; ++i) v += V[(size_t)i * n + e] * (y[i] * vs[i]);
+    int i = 0;
+    for (; i + 3 < nv; i += 4) {
+      const double v0 = V[(size_t)i * n + e], v1 = V[(size_t)(i + 1) * n + e];
+      const double v2 = V[(size_t)(i + 2) * n + e], v3 = V[(size_t)(i + 3) * n + e];
+      v += v0 * (y[i] * vs[i]) + v1 * (y[i + 1] * vs[i + 1]) + v2 * (y[i + 2] * vs[i + 2]) + v3 * (y[i + 3] * vs[i + 3]);
+    }
+    for (; i < nv; ++i) v += V[(size_t)i * n + e] * (y[i] * vs[i]);
     dst[e] = v;
   }
 }
@@ -790,7 +994,15 @@ DEV void phase_push(const Problem& P, Cl& cl, const SolveArgs& a, const double* 
   const size_t n = P.n;
   for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK) {
     const double xe = P.x[e];
-    for (int c = 0; c < P.k; ++c) Yn[c * n + e] = a.r * Yo[c * n + e] + a.om[c] * xe;
+    int c = 0;
+    for (; c + 3 < P.k; c += 4) {
+      const double y0 = Yo[c * n + e], y1 = Yo[(c + 1) * n + e], y2 = Yo[(c + 2) * n + e], y3 = Yo[(c + 3) * n + e];
+      Yn[c * n + e] = a.r * y0 + a.om[c] * xe;
+      Yn[(c + 1) * n + e] = a.r * y1 + a.om[c + 1] * xe;
+      Yn[(c + 2) * n + e] = a.r * y2 + a.om[c + 2] * xe;
+      Yn[(c + 3) * n + e] = a.r * y3 + a.om[c + 3] * xe;
+    }
+    for (; c < P.k; ++c) Yn[c * n + e] = a.r * Yo[c * n + e] + a.om[c] * xe;
   }
 }
 
@@ -877,6 +1089,7 @@ DEV void phase_block_gram(const Problem& P, Cl& cl, const SolveArgs& a, const do
   double* sx = sb + W * nl;                 // (W+12) x nl
   double* sgx = sx + (W + 12) * nl;         // (W+6) x nl
   double* sgz = sgx + (W + 6) * nl;         // (W+6) x nl
+  double* sc = sgz + (W + 6) * nl;          // coefficient block
   const int npair = k * (k + 1) / 2;
   const int nitem = npair + k;
   const int Q = BLOCK / nitem > 0 ? BLOCK / nitem : 1;  // threads per item
@@ -912,7 +1125,7 @@ DEV void phase_block_gram(const Problem& P, Cl& cl, const SolveArgs& a, const do
         return v;
       };
       double* wcol = sW + (size_t)col * W * nl;
-      tile_operator<W>(P, c0, w, load, sx, sgx, sgz, [&](int lj, int lc, int, double v) {
+      tile_operator<W>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int, double v) {
         wcol[lj * W + lc] = v;
       });
     }
@@ -1077,35 +1290,17 @@ DEV void phase_sketch_combine(const Problem& P, Cl& cl, const double* Yn, const 
   const size_t n = P.n;
   for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK) {
     double v = 0.0;
-    for (int c = 0; c < P.k; ++c) v += Yn[c * n + e] * z[c];
+    int c = 0;
+    for (; c + 3 < P.k; c += 4) {
+      const double y0 = Yn[c * n + e], y1 = Yn[(c + 1) * n + e], y2 = Yn[(c + 2) * n + e], y3 = Yn[(c + 3) * n + e];
+      v += y0 * z[c] + y1 * z[c + 1] + y2 * z[c + 2] + y3 * z[c + 3];
+    }
+    for (; c < P.k; ++c) v += Yn[c * n + e] * z[c];
     P.x[e] = v;
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// per-phase wall-clock accounting (workgroup 0, thread 0), enabled when a.prof != nullptr
-struct PhaseClock {
-  unsigned long long acc[NPHASE];
-  unsigned long long last, start;
-  bool on;
-  DEV void begin(bool enable) {
-    on = enable && blockIdx.x == 0 && threadIdx.x == 0;
-    for (int i = 0; i < NPHASE; ++i) acc[i] = 0;
-    last = start = on ? wall_clock64() : 0;
-  }
-  DEV void tick(int cat) {
-    if (!on) return;
-    const unsigned long long now = wall_clock64();
-    acc[cat] += now - last;
-    last = now;
-  }
-  DEV void flush(unsigned long long* out) {
-    if (!on) return;
-    acc[PH_TOTAL] = wall_clock64() - start;
-    for (int i = 0; i < NPHASE; ++i) atomicAdd(out + i, acc[i]);
-  }
-};
-
 // LDS layout of the solve kernel
 struct Smem {
   double* red;    // PSTRIDE
@@ -1149,7 +1344,8 @@ DEV void back_substitute(const Smem& S, int m, int jj) {
   __syncthreads();
 }
 
-extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Problem* __restrict__ PP, SolveArgs a) {
+template <bool SKETCH>
+DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a) {
   const Problem& P = *PP;
   extern __shared__ double smem[];
   const int m = P.m;
@@ -1159,7 +1355,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Proble
   const size_t n = P.n;
 
   PhaseClock clk;
-  clk.begin(a.prof != nullptr);
+  clk.begin(a.prof != nullptr, a.prof);
   phase_geometry(P, cl, a.eta_p, a.eta_c);
   csync(cl);
   clk.tick(PH_GEOM);
@@ -1168,7 +1364,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Proble
   const double* Yo = P.Y[a.ycur];
   double* Yn = P.Y[a.ycur ^ 1];
   int rank = 0;
-  if (a.sketch_guess) {
+  if (SKETCH && a.sketch_guess) {
     phase_block_gram(P, cl, a, Yo, Yn, S.big, S.red);
     const int nv = P.k * (P.k + 1) / 2 + P.k;
     cluster_sum_dd(cl, S.red, nv);
@@ -1178,7 +1374,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Proble
     clk.tick(PH_SMALL);
     phase_sketch_combine(P, cl, a.push ? Yn : Yo, S.z);
   } else {
-    if (a.push) phase_push(P, cl, a, Yo, Yn);
+    if (SKETCH && a.push) phase_push(P, cl, a, Yo, Yn);
     if (!a.prev_guess) {
       csync(cl);
       for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) P.x[e] = 0.0;
@@ -1217,7 +1413,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Proble
   double trigger = 0.0;
   if (!done) {
     // trigger of the true-residual check: rtol ||M^-1 b||
-    precond(P, cl, a.b, P.t, S.big);
+    precond(P, cl, a.b, P.t, S.big, &clk);
     clk.tick(PH_PREC);
     block_sum_to([&] {
       double s = 0.0;
@@ -1231,7 +1427,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Proble
   while (!done && !aborted(cl)) {
     double* V = P.V;
     clk.tick(PH_OTHER);
-    precond(P, cl, r, V, S.big);
+    precond(P, cl, r, V, S.big, &clk);
     clk.tick(PH_PREC);
     block_sum_to([&] {
       double s = 0.0;
@@ -1254,7 +1450,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Proble
       phase_operator(P, cl, V + (size_t)j * n, S.vs[j], P.t, nullptr, S.big, S.red, 0);
       csync(cl);
       clk.tick(PH_OPER);
-      precond(P, cl, P.t, wv, S.big);
+      precond(P, cl, P.t, wv, S.big, &clk);
       clk.tick(PH_PREC);
       // CGS2: h1 = V^T w (and ||w||), w -= V h1, h2 = V^T w, w -= V h2
       phase_dots(P, cl, V, S.vs, j + 1, wv, true, S.wsum, S.red);
@@ -1352,6 +1548,16 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Proble
   clk.flush(a.prof);
 }
 
+// one solve with the EWMA-sketch guess (push of the previous solution, Alg. 2 guess)
+extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Problem* __restrict__ PP, SolveArgs a) {
+  solve_body<true>(PP, a);
+}
+
+// one solve from a zero or previous-solution guess (no sketch)
+extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_plain_kernel(const Problem* __restrict__ PP, SolveArgs a) {
+  solve_body<false>(PP, a);
+}
+
 // ------------------------------------------------------------------------------------------
 // standalone entry kernels (operator and preconditioner applications, sketch push)
 
@@ -1371,11 +1577,15 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_operator_kernel(const Pro
 }
 
 extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond_kernel(const Problem* __restrict__ PP,
-                                                                      const double* v, double* z) {
+                                                                      const double* v, double* z,
+                                                                      unsigned long long* prof) {
   const Problem& P = *PP;
   extern __shared__ double smem[];
   Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
-  precond(P, cl, v, z, smem);
+  PhaseClock clk;
+  clk.begin(prof != nullptr, prof);
+  precond(P, cl, v, z, smem, &clk);
+  clk.flush(prof);
 }
 
 extern "C" __global__ void __launch_bounds__(BLOCK) sa_push_kernel(const Problem* __restrict__ PP, SolveArgs a) {

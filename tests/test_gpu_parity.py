@@ -7,10 +7,16 @@ Tolerances follow from the FP64 arithmetic:
 * operator: |y_gpu - y_oracle|_i <= 1e-11 max((|A| |x|)_i, 1e-4 max_j (|A| |x|)_j) (both sides
   sum O(100) products; the GPU composes two seven-point passes, the oracle applies the
   assembled product; the floor covers rows where the field vanishes locally);
-* preconditioner: 1e-11 max|z| (column eliminations on the GPU vs sparse LU in the oracle);
-* solves: identical decisions (iterations, restarts, residual checks, guess rank) on the
-  small cases, relative residual <= rtol, and solution difference <= 1e-7 relative
-  (the stated solution-error bar).
+* preconditioner: max(1e-11, 8 kappa(M_c) eps) max|z|, where M_c is the coarsest-level
+  operator solved exactly (an explicit inverse on the GPU, sparse LU in the oracle): both are
+  forward-stable only to kappa eps, and the scaled bar's one-level hierarchy has
+  kappa(M_c) ~ 6e6;
+* solves: identical decisions (iterations, restarts, residual checks, guess rank),
+  relative residual <= rtol, and solution difference <= 1e-7 relative (the stated
+  solution-error bar). A decision may differ only at a tie: the side that stopped first
+  passed its residual check by less than 1 % of rtol, the other side failed the same check
+  from a solution that differs in the last digits, and needed at most two more Arnoldi
+  steps. At most two ties are accepted in a sequence.
 """
 import sys
 
@@ -90,40 +96,53 @@ def test_operator_parity(B, name):
     assert worst <= 1e-11, worst
 
 
-@pytest.mark.parametrize("name,pc,nu,omega", [
-    ("tiny_17x7", "line", 1, 1.0), ("bar_65x9", "line", 1, 1.0), ("periodic_65x9", "line", 2, 0.7),
-    ("tiny_17x7", "mg", 1, 0.5), ("periodic_65x9", "mg", 1, 0.5), ("bar_65x9", "mg", 1, 0.5),
-    ("bar_513x17", "mg", 1, 0.5), ("periodic_65x9", "mg", 2, 0.6), ("bar_65x9", "none", 1, 1.0),
+def _coarse_tol(minv) -> float:
+    """Relative tolerance of a preconditioner application: the coarsest exact solve limits
+    both sides to kappa(M_c) eps."""
+    if not isinstance(minv, opc.VCycle):
+        return 1e-11
+    kappa = np.linalg.cond(minv.levels[-1]["m"].toarray())
+    return max(1e-11, 8.0 * kappa * np.finfo(float).eps)
+
+
+@pytest.mark.parametrize("name,pc,nu,omega,cmax", [
+    ("tiny_17x7", "line", 1, 1.0, 700), ("bar_65x9", "line", 1, 1.0, 700), ("periodic_65x9", "line", 2, 0.7, 700),
+    ("tiny_17x7", "mg", 1, 0.5, 40), ("periodic_65x9", "mg", 1, 0.5, 40), ("bar_65x9", "mg", 1, 0.5, 50),
+    ("periodic_65x9", "mg", 1, 0.5, 700), ("bar_65x9", "mg", 1, 0.5, 700),
+    ("bar_513x17", "mg", 1, 0.5, 700), ("bar_513x17", "mg", 1, 0.5, 100), ("periodic_65x9", "mg", 2, 0.6, 40),
+    ("bar_65x9", "mg", 0, 0.5, 50), ("bar_65x9", "none", 1, 1.0, 700),
 ])
-def test_precond_parity(B, name, pc, nu, omega):
+def test_precond_parity(B, name, pc, nu, omega, cmax):
     w = W.get(name)
-    _say(f"[precond] {name} {pc} nu={nu} omega={omega}")
+    _say(f"[precond] {name} {pc} nu={nu} omega={omega} coarse_max={cmax}")
     g = Grid(w.nx, w.nz, w.bc, w.length)
-    minv = opc.make(g, w.depth(), pc, nu, nu, omega)
-    p = _gpu_problem(B, w, precond=pc, nu1=nu, nu2=nu, omega=omega)
+    minv = opc.make(g, w.depth(), pc, nu, nu, omega, coarse_max=cmax)
+    tol = _coarse_tol(minv)
+    p = _gpu_problem(B, w, precond=pc, nu1=nu, nu2=nu, omega=omega, coarse_max=cmax)
     rs = np.random.default_rng(5)
     for v in (rs.standard_normal(w.n), w.system(2)[2]):
         z = p.apply_precond(v)
         ref = minv(v)
         err = np.abs(z - ref).max() / np.abs(ref).max()
-        _say(f"   rel err {err:.3e}")
-        assert err <= 1e-11
+        _say(f"   rel err {err:.3e} (tol {tol:.1e})")
+        assert err <= tol
     p.close()
 
 
-@pytest.mark.parametrize("cluster", [2, 5])
-def test_precond_parity_cluster(B, cluster):
+@pytest.mark.parametrize("cluster,cmax", [(2, 700), (5, 700), (3, 100), (8, 40)])
+def test_precond_parity_cluster(B, cluster, cmax):
     w = W.get("bar_513x17")
-    _say(f"[precond cluster] bar_513x17 mg G={cluster}")
+    _say(f"[precond cluster] bar_513x17 mg G={cluster} coarse_max={cmax}")
     g = Grid(w.nx, w.nz, w.bc, w.length)
-    minv = opc.make(g, w.depth(), "mg")
-    p = _gpu_problem(B, w, cluster=cluster)
+    minv = opc.make(g, w.depth(), "mg", coarse_max=cmax)
+    tol = _coarse_tol(minv)
+    p = _gpu_problem(B, w, cluster=cluster, coarse_max=cmax)
     v = np.random.default_rng(3).standard_normal(w.n)
     z = p.apply_precond(v)
     ref = minv(v)
     err = np.abs(z - ref).max() / np.abs(ref).max()
-    _say(f"   rel err {err:.3e}")
-    assert err <= 1e-11
+    _say(f"   rel err {err:.3e} (tol {tol:.1e})")
+    assert err <= tol
     p.close()
 
 
@@ -151,6 +170,8 @@ SOLVE_CASES = [
     ("bar_65x9", dict(k=4, r=0.5, restart=8), 12),
     ("periodic_65x9", dict(cluster=4), 8),
     ("bar_65x9", dict(cluster=3), 8),
+    ("periodic_65x9", dict(coarse_max=40), 10),
+    ("bar_65x9", dict(coarse_max=50, cluster=2), 10),
     ("bar_513x17", dict(), 8),
     ("bar_513x17", dict(cluster=8), 8),
 ]
@@ -160,8 +181,9 @@ SOLVE_CASES = [
 def test_solve_sequence_parity(B, name, kw, nsys):
     w = W.get(name)
     _say(f"[solve] {name} {kw} nsys={nsys}")
-    ora = Simulation.from_workload(w, **{k: v for k, v in kw.items() if k != "cluster"})
+    ora = Simulation.from_workload(w, **{k: v for k, v in kw.items() if k not in ("cluster",)})
     p = _gpu_problem(B, w, **kw)
+    ties = 0
     for s in range(nsys):
         ep, ec, ps = w.system(s)
         b = ora.operator(ep, ec) @ ps
@@ -175,8 +197,16 @@ def test_solve_sequence_parity(B, name, kw, nsys):
              f"r0={info.relres0:.2e} r={info.relres:.2e} | oracle it={ro.info.iters} rs={ro.info.restarts} "
              f"ck={ro.info.checks} rank={ro.rank} r0={ro.info.relres0:.2e} | dx={dx:.2e}")
         assert info.status == 0
-        assert (info.iters, info.restarts, info.checks, info.rank) == \
-            (ro.info.iters, ro.info.restarts, ro.info.checks, ro.rank)
+        gd = (info.iters, info.restarts, info.checks, info.rank)
+        od = (ro.info.iters, ro.info.restarts, ro.info.checks, ro.rank)
+        if gd != od:
+            first = info if info.iters < ro.info.iters else ro.info
+            assert info.rank == ro.rank and info.restarts == ro.info.restarts, (gd, od)
+            assert 0 < abs(info.iters - ro.info.iters) <= 2, (gd, od)
+            assert first.relres >= 0.99 * w.rtol, (gd, od, first.relres)
+            ties += 1
+            _say(f"   tie at sys {s}: first stop at relres {first.relres:.6e}")
+        assert ties <= 2
         assert info.relres <= w.rtol
         assert dx <= 1e-7
     p.close()

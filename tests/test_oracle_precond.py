@@ -31,6 +31,14 @@ def test_line_jacobi_one_sweep_is_exact_column_solve(bc):
 
 
 @pytest.mark.parametrize("bc", ["periodic", "walls"])
+def test_coarse_max_stops_coarsening(bc):
+    g, h = _case(bc)
+    for cmax, expect_levels in ((g.n, 1), (g.n - 1, 2)):
+        V = VCycle(g, h, coarse_max=cmax)
+        assert len(V.levels) == expect_levels
+
+
+@pytest.mark.parametrize("bc", ["periodic", "walls"])
 def test_one_level_vcycle_is_exact_solve(bc):
     g, h = _case(bc)
     v = np.random.default_rng(2).standard_normal(g.n)
@@ -66,7 +74,7 @@ def test_transfer_operators(bc):
 @pytest.mark.parametrize("bc", ["periodic", "walls"])
 def test_vcycle_is_linear_and_converges_as_solver(bc):
     g, h = _case(bc)
-    V = VCycle(g, h, 1, 1, 0.5)
+    V = VCycle(g, h, 1, 1, 0.5, coarse_max=40)
     assert len(V.levels) >= 3
     rng = np.random.default_rng(3)
     u, v = rng.standard_normal(g.n), rng.standard_normal(g.n)
