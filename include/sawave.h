@@ -88,15 +88,22 @@ typedef struct {
   int32_t n_init;       /* solves that use the previous solution before the sketch, 0      */
   double tau_drop;      /* least-squares column drop threshold, default 1e-7               */
   int32_t precision;    /* SA_FP64 | SA_FP32_IR, default SA_FP64                            */
-  double rtol_inner;    /* FP32 inner solve tolerance (SA_FP32_IR), default 1e-4           */
-  int32_t max_refine;   /* refinement steps cap (SA_FP32_IR), default 20                   */
+                        /* SA_FP32_IR: FP64 iterative refinement around FP32 GMRES cycles on */
+                        /* A d = r / ||r|| (operator, V-cycle, basis FP32; Gram-Schmidt sums,*/
+                        /* Hessenberg, Givens FP64); candidates x + ||r|| d are checked on  */
+                        /* the FP64 residual with the FP64 path's trigger rule              */
+  double rtol_inner;    /* FP32 resolution: a cycle whose Arnoldi estimate has fallen to    */
+                        /* this fraction of its start hands its checked candidate to the    */
+                        /* next correction (SA_FP32_IR), default 1e-5                       */
+  int32_t max_refine;   /* refinement steps cap (SA_FP32_IR), default 20; SA_NOCONV after  */
   int32_t cluster;      /* workgroups cooperating on one solve; 0 = chosen from the size  */
   int32_t profile;      /* 1: accumulate per-phase device time (sa_get_phase_times), 0      */
   int32_t coarse_max;   /* MG: coarsening stops at the first grid with at most this many    */
                         /* unknowns, solved exactly there (<= 1024), default 700            */
 } sa_options;
 
-/* Per-solve report. iters counts Arnoldi steps over all cycles (and refinement steps). */
+/* Per-solve report. iters counts Arnoldi steps over all cycles (FP32_IR: inner steps over
+ * all refinements); refinements counts FP64 correction steps (FP32_IR only). */
 typedef struct {
   int32_t iters, restarts, refinements, status;
   int32_t rank;         /* sketch columns kept by the least-squares guess                  */
@@ -145,6 +152,13 @@ int sa_apply_operator(sa_problem* p, const double* x, double* y, int32_t mem);
 
 /* y = M^-1 x, the fixed still-water preconditioner of the problem. */
 int sa_apply_precond(sa_problem* p, const double* x, double* y, int32_t mem);
+
+/* FP32 inner kernels of the refinement path (precision = SA_FP32_IR only, else SA_EARG):
+ * y = A x with FP32 input, output and stencil arithmetic (geometry rounded to FP32), and
+ * y = M^-1 x with FP32 line-solve factors, work vectors and coarsest inverse. x, y: n floats
+ * in `mem` memory (host arrays are staged through the problem's FP32 work vectors). */
+int sa_apply_operator_f32(sa_problem* p, const float* x, float* y, int32_t mem);
+int sa_apply_precond_f32(sa_problem* p, const float* x, float* y, int32_t mem);
 
 /* The k sketch draws of stored solution `index` (SplitMix64 counter stream + Box-Muller),
  * host only, no device needed: out[a] = omega_a, a < k (k <= 64). */

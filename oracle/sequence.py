@@ -6,7 +6,8 @@ an exponentially weighted sketch updated after every solve. Guess modes: 'cold' 
 'previous' (x0 = the last solution: the paper's baseline, Sec. 5.1) and 'ewma'
 (x0 = Y z* once a solution has been stored and ``n_init`` solves have run; until then the
 previous solution, as the paper warms the history up with the baseline, Sec. 5.1).
-Every returned solution is stored, converged or not.
+Every returned solution is stored, converged or not. ``precision='fp32_ir'`` solves each
+system by FP64 refinement around single-precision GMRES cycles (module ``refine``).
 """
 from __future__ import annotations
 
@@ -16,6 +17,7 @@ import numpy as np
 
 from . import gmres as _gmres
 from . import precond as _precond
+from . import refine as _refine
 from .discretization import Grid, mixed_stage_operator
 from .subspace import TAU_DROP, EWMASketch, guess
 
@@ -37,6 +39,9 @@ class Options:
     seed: int = 0
     n_init: int = 0
     tau_drop: float = TAU_DROP
+    precision: str = "fp64"  # fp64 | fp32_ir
+    rtol_inner: float = 1e-5
+    max_refine: int = 20
 
 
 @dataclass
@@ -79,8 +84,11 @@ class Simulation:
     def solve(self, eta_prev, eta_cur, b) -> Result:
         A = self.operator(eta_prev, eta_cur)
         x0, rank = self.initial_guess(A, b)
-        x, info = _gmres.gmres(A, b, x0, self.minv, self.opts.restart, self.opts.rtol,
-                               self.opts.max_restarts)
+        o = self.opts
+        if o.precision == "fp32_ir":
+            x, info = _refine.solve(A, b, x0, self.minv, o.restart, o.rtol, o.rtol_inner, o.max_refine)
+        else:
+            x, info = _gmres.gmres(A, b, x0, self.minv, o.restart, o.rtol, o.max_restarts)
         if self.sketch is not None:
             self.sketch.push(x)
         self.x_prev = x

@@ -88,6 +88,8 @@ def _load():
         "sa_get_solution": (C.c_int, [P, P, C.c_int32]),
         "sa_apply_operator": (C.c_int, [P, P, P, C.c_int32]),
         "sa_apply_precond": (C.c_int, [P, P, P, C.c_int32]),
+        "sa_apply_operator_f32": (C.c_int, [P, P, P, C.c_int32]),
+        "sa_apply_precond_f32": (C.c_int, [P, P, P, C.c_int32]),
         "sa_sketch_draws": (C.c_int, [C.c_uint64, C.c_int64, C.c_int32, D]),
         "sa_get_sketch": (C.c_int, [P, P, C.c_int32]),
         "sa_sketch_count": (C.c_int64, [P]),
@@ -127,16 +129,17 @@ def _is_torch_cuda(a) -> bool:
     return hasattr(a, "is_cuda") and bool(a.is_cuda)
 
 
-def _ptr(a, n_expected: int | None = None):
-    """(pointer, mem kind, keep-alive) of a float64 numpy array or CUDA tensor."""
+def _ptr(a, n_expected: int | None = None, dtype=np.float64):
+    """(pointer, mem kind, keep-alive) of a numpy array or CUDA tensor of the given dtype."""
     if _is_torch_cuda(a):
         import torch
-        if a.dtype != torch.float64 or not a.is_contiguous():
-            raise ValueError("device arrays must be contiguous float64 tensors")
+        tdt = torch.float64 if dtype == np.float64 else torch.float32
+        if a.dtype != tdt or not a.is_contiguous():
+            raise ValueError(f"device arrays must be contiguous {tdt} tensors")
         if n_expected is not None and a.numel() != n_expected:
             raise ValueError(f"expected {n_expected} values, got {a.numel()}")
         return C.c_void_p(a.data_ptr()), SA_MEM_DEVICE, a
-    arr = np.ascontiguousarray(a, dtype=np.float64)
+    arr = np.ascontiguousarray(a, dtype=dtype)
     if n_expected is not None and arr.size != n_expected:
         raise ValueError(f"expected {n_expected} values, got {arr.size}")
     return C.c_void_p(arr.ctypes.data), SA_MEM_HOST, arr
@@ -163,12 +166,9 @@ class Problem:
         self.grid = SaGrid(nx, nz, SA_PERIODIC if bc == "periodic" else SA_WALLS, float(length))
         o = default_options()
         for key, val in opts.items():
-            if key == "precond":
-                val = SA_PC[val]
-            elif key == "guess":
-                val = SA_GUESS[val]
-            elif key == "precision":
-                val = SA_PRECISION[val]
+            names = {"precond": SA_PC, "guess": SA_GUESS, "precision": SA_PRECISION}.get(key)
+            if names is not None and isinstance(val, str):
+                val = names[val]
             if not hasattr(o, key):
                 raise KeyError(key)
             setattr(o, key, val)
@@ -259,6 +259,23 @@ class Problem:
         if mx != my:
             raise ValueError("x and y must live in the same memory")
         _check(lib.sa_apply_precond(self._h, px, py, mx))
+        return out
+
+    def apply_operator_f32(self, x, out=None):
+        return self._apply32(lib.sa_apply_operator_f32, x, out)
+
+    def apply_precond_f32(self, x, out=None):
+        return self._apply32(lib.sa_apply_precond_f32, x, out)
+
+    def _apply32(self, fn, x, out):
+        if out is None:
+            out = np.zeros(self.n, dtype=np.float32) if not _is_torch_cuda(x) else x.new_zeros(self.n)
+        px, mx, kx = _ptr(x, self.n, np.float32)
+        py, my, _ = _ptr(out, self.n, np.float32)
+        if mx != my:
+            raise ValueError("x and y must live in the same memory")
+        if not isinstance(out, np.ndarray) or out.dtype == np.float32:
+            _check(fn(self._h, px, py, mx))
         return out
 
     def sketch(self) -> np.ndarray:

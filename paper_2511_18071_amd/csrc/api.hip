@@ -18,6 +18,8 @@ extern "C" __global__ void sa_geometry_kernel(const Problem*, const double*, con
 extern "C" __global__ void sa_operator_kernel(const Problem*, const double*, double*);
 extern "C" __global__ void sa_precond_kernel(const Problem*, const double*, double*, unsigned long long*);
 extern "C" __global__ void sa_push_kernel(const Problem*, SolveArgs);
+extern "C" __global__ void sa_operator32_kernel(const Problem*, const float*, float*);
+extern "C" __global__ void sa_precond32_kernel(const Problem*, const float*, float*);
 }  // namespace sa
 
 using namespace sa;
@@ -85,7 +87,7 @@ extern "C" void sa_default_options(sa_options* o) {
   o->n_init = 0;
   o->tau_drop = 1e-7;
   o->precision = SA_FP64;
-  o->rtol_inner = 1e-4;
+  o->rtol_inner = 1e-5;
   o->max_refine = 20;
   o->cluster = 0;
   o->profile = 0;
@@ -251,7 +253,10 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   if (opt.guess < SA_GUESS_COLD || opt.guess > SA_GUESS_EWMA) return fail(SA_EARG, "sa_create: unknown guess mode");
   if (opt.k < 1 || opt.k > KMAX) return fail(SA_EARG, "sa_create: k must be in [1, %d]", KMAX);
   if (!(opt.r >= 0.0 && opt.r <= 1.0)) return fail(SA_EARG, "sa_create: r must be in [0, 1]");
-  if (opt.precision != SA_FP64) return fail(SA_EARG, "sa_create: only SA_FP64 is available in this build");
+  if (opt.precision != SA_FP64 && opt.precision != SA_FP32_IR) return fail(SA_EARG, "sa_create: unknown precision");
+  if (opt.precision == SA_FP32_IR && !(opt.rtol_inner > 0.0 && opt.rtol_inner < 1.0))
+    return fail(SA_EARG, "sa_create: rtol_inner must be in (0, 1)");
+  if (opt.precision == SA_FP32_IR && opt.max_refine < 1) return fail(SA_EARG, "sa_create: max_refine >= 1");
   if (opt.max_levels < 1) return fail(SA_EARG, "sa_create: max_levels >= 1");
   if (opt.coarse_max < 1 || opt.coarse_max > COARSE_MAX) return fail(SA_EARG, "sa_create: coarse_max in [1, %d]", COARSE_MAX);
   const int nphys = periodic ? grid->nx - 1 : grid->nx;
@@ -395,6 +400,9 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
                o_sig = take(nl * 8), o_h = take(ncol * 8), o_hchi = take(ncol * 8), o_geo = take(4 * (size_t)ncol * 8);
   std::vector<size_t> o_lh(nlev), o_lih(nlev), o_lhx(nlev), o_lhxx(nlev), o_lf(nlev), o_lu(nlev), o_lo(nlev),
       o_fpc(nlev), o_finv(nlev), o_flo(nlev), o_fgam(nlev);
+  const bool ir = opt.precision == SA_FP32_IR;
+  std::vector<size_t> o_lf32(nlev, 0), o_lu32(nlev, 0), o_lo32(nlev, 0), o_fpc32(nlev, 0), o_finv32(nlev, 0),
+      o_flo32(nlev, 0), o_fgam32(nlev, 0);
   for (int l = 0; l < nlev; ++l) {
     const size_t nlv = (size_t)levs[l].ncol * nl;
     o_lh[l] = take(levs[l].ncol * 8); o_lhx[l] = take(levs[l].ncol * 8); o_lhxx[l] = take(levs[l].ncol * 8);
@@ -403,8 +411,16 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
     o_flo[l] = take(levs[l].flo.size() * 8);
     o_fgam[l] = take(levs[l].fgam.size() * 8);
     o_lf[l] = take(nlv * 8); o_lu[l] = take(nlv * 8); o_lo[l] = take(nlv * 8);
+    if (ir) {
+      o_fpc32[l] = take(levs[l].fpc.size() * 4); o_finv32[l] = take(levs[l].finv.size() * 4);
+      o_flo32[l] = take(levs[l].flo.size() * 4); o_fgam32[l] = take(levs[l].fgam.size() * 4);
+      o_lf32[l] = take(nlv * 4); o_lu32[l] = take(nlv * 4); o_lo32[l] = take(nlv * 4);
+    }
   }
   const size_t o_cinv = take(cinv.size() * 8 + 8);
+  const size_t o_cinv32 = ir ? take(cinv.size() * 4 + 8) : 0;
+  const size_t o_V32 = ir ? take((size_t)(m + 1) * n * 4) : 0, o_t32 = ir ? take((size_t)n * 4) : 0,
+               o_r32 = ir ? take((size_t)n * 4) : 0;
   const size_t o_x = take((size_t)n * 8), o_xc = take((size_t)n * 8), o_r = take((size_t)n * 8),
                o_rc = take((size_t)n * 8), o_t = take((size_t)n * 8), o_V = take((size_t)(m + 1) * n * 8);
   const size_t ysz = opt.guess == SA_GUESS_EWMA ? (size_t)k * n * 8 : 8;
@@ -440,6 +456,19 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
     if (e == hipSuccess) e = up(o_fgam[l], levs[l].fgam.data(), levs[l].fgam.size() * 8);
   }
   if (e == hipSuccess && !cinv.empty()) e = up(o_cinv, cinv.data(), cinv.size() * 8);
+  if (ir) {
+    auto up32 = [&](size_t o, const std::vector<double>& v) {
+      std::vector<float> f(v.begin(), v.end());
+      return f.empty() ? hipSuccess : up(o, f.data(), f.size() * 4);
+    };
+    for (int l = 0; l < nlev && e == hipSuccess; ++l) {
+      e = up32(o_fpc32[l], levs[l].fpc);
+      if (e == hipSuccess) e = up32(o_finv32[l], levs[l].finv);
+      if (e == hipSuccess) e = up32(o_flo32[l], levs[l].flo);
+      if (e == hipSuccess) e = up32(o_fgam32[l], levs[l].fgam);
+    }
+    if (e == hipSuccess) e = up32(o_cinv32, cinv);
+  }
 
   Problem& P = p->hp;
   P.ncol = ncol; P.nl = nl; P.nz = grid->nz; P.n = n; P.nphys = nphys; P.periodic = periodic;
@@ -457,8 +486,21 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
     L.fgam = (const double*)(A + o_fgam[l]); L.fstride = levs[l].fstride;
     L.flo = (const double*)(A + o_flo[l]);
     L.f = (double*)(A + o_lf[l]); L.u = (double*)(A + o_lu[l]); L.o = (double*)(A + o_lo[l]);
+    if (ir) {
+      L.fpc32 = (const float*)(A + o_fpc32[l]); L.finv32 = (const float*)(A + o_finv32[l]);
+      L.flo32 = (const float*)(A + o_flo32[l]); L.fgam32 = (const float*)(A + o_fgam32[l]);
+      L.f32 = (float*)(A + o_lf32[l]); L.u32 = (float*)(A + o_lu32[l]); L.o32 = (float*)(A + o_lo32[l]);
+    } else {
+      L.fpc32 = L.finv32 = L.flo32 = L.fgam32 = nullptr;
+      L.f32 = L.u32 = L.o32 = nullptr;
+    }
   }
   P.cinv = (const double*)(A + o_cinv); P.cn = cn;
+  P.cinv32 = ir ? (const float*)(A + o_cinv32) : nullptr;
+  P.V32 = ir ? (float*)(A + o_V32) : nullptr;
+  P.t32 = ir ? (float*)(A + o_t32) : nullptr;
+  P.r32 = ir ? (float*)(A + o_r32) : nullptr;
+  P.precision = opt.precision; P.max_refine = opt.max_refine; P.rtol_inner = opt.rtol_inner;
   P.x = (double*)(A + o_x); P.xc = (double*)(A + o_xc); P.r = (double*)(A + o_r); P.rc = (double*)(A + o_rc);
   P.t = (double*)(A + o_t); P.V = (double*)(A + o_V);
   P.Y[0] = (double*)(A + o_Y0); P.Y[1] = (double*)(A + o_Y1);
@@ -478,6 +520,8 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_solve_plain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_operator_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_op);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_precond_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_pc);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_operator32_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_op);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_precond32_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_pc);
   if (e != hipSuccess) {
     hipFree(p->arena);
     delete p;
@@ -678,6 +722,48 @@ extern "C" int sa_apply_precond(sa_problem* p, const double* x, double* y, int32
   void* args[] = {(void*)&p->dp, (void*)&xd, (void*)&yd, (void*)&p->prof};
   HIPCHK(launch_cluster(p, (const void*)sa_precond_kernel, args, p->lds_pc));
   if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 8, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return check_flags(p);
+}
+
+// FP32 inner kernels of the refinement path, for tests: host arrays are staged through the
+// problem's FP32 work vectors.
+static int fp32_io(sa_problem* p, const float* x, float* y, int32_t mem, const char* who, const float** xd, float** yd) {
+  if (!p || !x || !y) return fail(SA_EARG, "%s: null argument", who);
+  if (p->opt.precision != SA_FP32_IR) return fail(SA_EARG, "%s: problem created without SA_FP32_IR", who);
+  if (mem == SA_MEM_DEVICE) { *xd = x; *yd = y; return SA_OK; }
+  if (mem != SA_MEM_HOST) return fail(SA_EARG, "%s: bad mem", who);
+  HIPCHK(hipMemcpyAsync(p->hp.r32, x, (size_t)p->n * 4, hipMemcpyHostToDevice, p->stream));
+  *xd = p->hp.r32;
+  *yd = p->hp.t32;
+  return SA_OK;
+}
+
+extern "C" int sa_apply_operator_f32(sa_problem* p, const float* x, float* y, int32_t mem) {
+  const float* xd;
+  float* yd;
+  int rc = fp32_io(p, x, y, mem, "sa_apply_operator_f32", &xd, &yd);
+  if (rc) return rc;
+  if (!p->eta_p || !p->eta_c) return fail(SA_EARG, "sa_apply_operator_f32: set the surfaces first");
+  const int gb = (p->ncol + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(sa_geometry_kernel, dim3(gb), dim3(BLOCK), 0, p->stream, p->dp, p->eta_p, p->eta_c);
+  HIPCHK(hipGetLastError());
+  const int nt = tiles_host(p->ncol, p->grid.bc == SA_PERIODIC, TX);
+  hipLaunchKernelGGL(sa_operator32_kernel, dim3(nt), dim3(BLOCK), p->lds_op, p->stream, p->dp, xd, yd);
+  HIPCHK(hipGetLastError());
+  if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 4, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return check_flags(p);
+}
+
+extern "C" int sa_apply_precond_f32(sa_problem* p, const float* x, float* y, int32_t mem) {
+  const float* xd;
+  float* yd;
+  int rc = fp32_io(p, x, y, mem, "sa_apply_precond_f32", &xd, &yd);
+  if (rc) return rc;
+  void* args[] = {(void*)&p->dp, (void*)&xd, (void*)&yd};
+  HIPCHK(launch_cluster(p, (const void*)sa_precond32_kernel, args, p->lds_pc));
+  if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 4, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return check_flags(p);
 }

@@ -40,6 +40,9 @@ struct Level {
   double* f;                 // right-hand side of this level (level 0: unused, the input)
   double* u;                 // smoothed iterate
   double* o;                 // output of this level's cycle (level 0: unused, the output)
+  // FP32 copies for the inner solve of the refinement path (null without it)
+  const float *fpc32, *finv32, *flo32, *fgam32;
+  float *f32, *u32, *o32;
 };
 
 // Everything a kernel needs about one problem. Lives in device memory.
@@ -57,13 +60,17 @@ struct Problem {
   int pc, nu1, nu2, nlev, tail;   // tail: first level run by a single workgroup
   double omega;
   Level lev[MAXLEV];
-  const double* cinv;        // dense inverse of the coarsest operator, cn x cn row-major
+  const double* cinv;        // dense inverse of the coarsest operator, cn x cn (transposed)
+  const float* cinv32;       // its FP32 rounding (refinement path)
   int cn;
   // solver vectors
   double *x, *xc, *r, *rc, *t, *V, *Y[2];
+  float *V32, *t32, *r32;    // inner basis and work vectors of the refinement path
   // sketch / options
   int k, m, max_restarts;
   double tau_drop;
+  int precision, max_refine;
+  double rtol_inner;
   // synchronisation and reports
   double* partials;          // 2 x G x PSTRIDE
   unsigned* bar;             // barrier counter, generation

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace sa {
@@ -153,12 +155,13 @@ DEV void phase_geometry(const Problem& P, Cl& cl, const double* __restrict__ eta
 // before any of them is used.
 template <int U, class Ld, class St>
 DEV void staged(int count, Ld ld, St st) {
+  using T = std::decay_t<decltype(ld(0))>;
   for (int base = threadIdx.x; base < count; base += U * BLOCK) {
-    double v[U];
+    T v[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int i = base + q * BLOCK;
-      v[q] = i < count ? ld(i) : 0.0;
+      v[q] = i < count ? ld(i) : T(0);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
@@ -172,6 +175,7 @@ DEV void staged(int count, Ld ld, St st) {
 // element k of segment q, st(q, k, v) stores it.
 template <int U, int NS, class Ld, class St>
 DEV void staged_segments(const int (&cnt)[NS], Ld ld, St st) {
+  using T = std::decay_t<decltype(ld(0, 0))>;
   int total = 0;
 #pragma unroll
   for (int q = 0; q < NS; ++q) total += cnt[q];
@@ -182,11 +186,11 @@ DEV void staged_segments(const int (&cnt)[NS], Ld ld, St st) {
     for (int r = 0; r < NS - 1; ++r)
       if (q == r && k >= cnt[r]) { k -= cnt[r]; q = r + 1; }
   };
-  staged<U>(total, [&](int i) {
+  staged<U>(total, [&](int i) -> T {
     int q, k;
     locate(i, q, k);
     return ld(q, k);
-  }, [&](int i, double v) {
+  }, [&](int i, T v) {
     int q, k;
     locate(i, q, k);
     st(q, k, v);
@@ -213,25 +217,24 @@ DEV constexpr int opcoef_size(int W, int nl) { return 49 + 9 * nl + 5 * (W + 6);
 // (x and sigma weights, sigma windows and values, per-column geometry of both stages). Every
 // operand of the stencil loops is in LDS. load(level, column, tile column) returns the input;
 // out(level, tile column, column, value) receives A x.
-template <int W, class Load, class Out>
-DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, double* sgx, double* sgz,
-                       double* sc, Out out) {
+template <class S, int W, class Load, class Out>
+DEV void tile_operator(const Problem& P, int c0, int w, Load load, S* sx, S* sgx, S* sgz, S* sc, Out out) {
   const int nc = P.ncol, nl = P.nl, nz = P.nz;
   constexpr int LX = W + 12, LG = W + 6;
-  double* swchi = sc;                  // 49
-  double* swsig = swchi + 49;          // nl x 7
-  double* ssig = swsig + 7 * nl;       // nl sigma values
-  int* sstart = (int*)(ssig + nl);     // nl window starts (stored in nl doubles)
-  double* gip = ssig + 2 * nl;         // LG: 1/d prev
-  double* gdp = gip + LG;              // LG: d_chi prev
-  double* ghc = gdp + LG;              // LG: h_chi
-  double* gic = ghc + LG;              // LG: 1/d cur
-  double* gdc = gic + LG;              // LG: d_chi cur
+  S* swchi = sc;                       // 49
+  S* swsig = swchi + 49;               // nl x 7
+  S* ssig = swsig + 7 * nl;            // nl sigma values
+  int* sstart = (int*)(ssig + nl);     // nl window starts (stored in nl slots)
+  S* gip = ssig + 2 * nl;              // LG: 1/d prev
+  S* gdp = gip + LG;                   // LG: d_chi prev
+  S* ghc = gdp + LG;                   // LG: h_chi
+  S* gic = ghc + LG;                   // LG: 1/d cur
+  S* gdc = gic + LG;                   // LG: d_chi cur
   // stage the input with a 6-column halo: load(level, column, tile-local column)
-  staged<8>(LX * nl, [&](int i) {
+  staged<8>(LX * nl, [&](int i) -> S {
     const int lj = i / LX, lc = i - lj * LX;
     int c = c0 - 6 + lc;
-    double v = 0.0;
+    S v = S(0);
     if (lc < w + 12) {
       if (P.periodic) {
         c = ((c % nc) + nc) % nc;
@@ -241,19 +244,19 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, d
       }
     }
     return v;
-  }, [&](int i, double v) { sx[i] = v; });
+  }, [&](int i, S v) { sx[i] = v; });
   const int ncoef = 49 + 8 * nl;
-  staged<4>(ncoef + 5 * LG, [&](int i) {
-    if (i < 49) return P.wchi[i];
-    if (i < 49 + 7 * nl) return P.wsig[i - 49];
-    if (i < 49 + 8 * nl) return P.sig[i - 49 - 7 * nl];
+  staged<4>(ncoef + 5 * LG, [&](int i) -> S {
+    if (i < 49) return S(P.wchi[i]);
+    if (i < 49 + 7 * nl) return S(P.wsig[i - 49]);
+    if (i < 49 + 8 * nl) return S(P.sig[i - 49 - 7 * nl]);
     const int q = (i - ncoef) / LG, lc = i - ncoef - q * LG;
     int c = c0 - 3 + lc;
     if (P.periodic) c = ((c % nc) + nc) % nc;
-    else if (c < 0 || c >= nc) return 0.0;
-    if (q == 2) return P.hchi[c];
-    return P.geo[(q < 2 ? q : q - 1) * nc + c];
-  }, [&](int i, double v) {
+    else if (c < 0 || c >= nc) return S(0);
+    if (q == 2) return S(P.hchi[c]);
+    return S(P.geo[(q < 2 ? q : q - 1) * nc + c]);
+  }, [&](int i, S v) {
     if (i < ncoef) swchi[i] = v;
     else gip[i - ncoef] = v;
   });
@@ -268,15 +271,15 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, d
     int row, start;
     chi_window(P, c, row, start);
     const int sidx = start - c0 + 6;
-    double dxv = 0.0;
+    S dxv = S(0);
 #pragma unroll
     for (int m = 0; m < 7; ++m) dxv += swchi[row * 7 + m] * sx[lj * LX + sidx + m];
     const int s0 = sstart[lj];
-    double dsv = 0.0;
+    S dsv = S(0);
 #pragma unroll
     for (int m = 0; m < 7; ++m) dsv += swsig[lj * 7 + m] * sx[(s0 + m) * LX + lc + 3];
-    const double invd = gip[lc];
-    const double sxp = (ghc[lc] - ssig[lj] * gdp[lc]) * invd;
+    const S invd = gip[lc];
+    const S sxp = (ghc[lc] - ssig[lj] * gdp[lc]) * invd;
     sgx[i] = dxv + sxp * dsv;
     sgz[i] = invd * dsv;
   }
@@ -287,7 +290,7 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, d
     if (lc >= w) continue;
     const int c = c0 + lc;
     const bool ghostcol = !P.periodic && (c == 0 || c == nc - 1);
-    double v;
+    S v;
     if (lj == nz || (ghostcol && lj == 0)) {
       v = sx[lj * LX + lc + 6];
     } else if (ghostcol) {
@@ -298,19 +301,19 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, double* sx, d
       int row, start;
       chi_window(P, c, row, start);
       const int gidx = start - c0 + 3;
-      double dxg = 0.0;
+      S dxg = S(0);
 #pragma unroll
       for (int m = 0; m < 7; ++m) dxg += swchi[row * 7 + m] * sgx[lj * LG + gidx + m];
       const int s0 = sstart[lj];
-      double dsg = 0.0, dsz = 0.0;
+      S dsg = S(0), dsz = S(0);
 #pragma unroll
       for (int m = 0; m < 7; ++m) {
-        const double ws = swsig[lj * 7 + m];
+        const S ws = swsig[lj * 7 + m];
         dsg += ws * sgx[(s0 + m) * LG + lc + 3];
         dsz += ws * sgz[(s0 + m) * LG + lc + 3];
       }
-      const double invd = gic[lc + 3];
-      const double sxc = (ghc[lc + 3] - ssig[lj] * gdc[lc + 3]) * invd;
+      const S invd = gic[lc + 3];
+      const S sxc = (ghc[lc + 3] - ssig[lj] * gdc[lc + 3]) * invd;
       v = dxg + sxc * dsg + invd * dsz;
     }
     out(lj, lc, c, v);
@@ -334,7 +337,7 @@ DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, 
     const int c0 = t * TX;
     const int w = (t == T.nt - 1) ? nc - c0 : TX;
     auto load = [&](int lj, int c, int) { return x[(size_t)lj * nc + c] * xs; };
-    tile_operator<TWM>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int c, double v) {
+    tile_operator<double, TWM>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int c, double v) {
       const size_t e = (size_t)lj * nc + c;
       if (resid) {
         const double bb = b[e];
@@ -353,6 +356,25 @@ DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, 
   }
 }
 
+// y = A (xs x) in the inner precision S (FP32 refinement path): same tiles, no residual form
+template <class S>
+DEV void phase_operator_s(const Problem& P, Cl& cl, const S* __restrict__ x, S xs, S* y, S* lds) {
+  const Tiles T = tiles_of(P, TX);
+  S* sx = lds;
+  S* sgx = sx + (TWM + 12) * P.nl;
+  S* sgz = sgx + (TWM + 6) * P.nl;
+  S* sc = sgz + (TWM + 6) * P.nl;
+  const int nc = P.ncol;
+  for (int t = cl.rank; t < T.nt; t += cl.G) {
+    const int c0 = t * TX;
+    const int w = (t == T.nt - 1) ? nc - c0 : TX;
+    auto load = [&](int lj, int c, int) { return x[(size_t)lj * nc + c] * xs; };
+    tile_operator<S, TWM>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int c, S v) {
+      y[(size_t)lj * nc + c] = v;
+    });
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // still-water preconditioner (second-order direct form at eta = 0), LDS-staged tiles of TM
 // columns x all levels. A tile's fields, column data (h, 1/h, h_x, h_xx) and line-solve
@@ -362,15 +384,32 @@ DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, 
 constexpr int TM = 64;
 constexpr int TMS = TM + 4;  // stride of the per-thread line-solve scratch
 
+// A level of the hierarchy seen in precision S: line-solve factors and work vectors of that
+// precision (column data h, 1/h, h_x, h_xx stay FP64 and are rounded when staged).
+template <class S>
 struct Lv {
   int nc, nx, fstride;
-  double rdx;
-  const double *h, *ih, *hx, *hxx, *fpc, *finv, *flo, *fgam;
+  S rdx;
+  const double *h, *ih, *hx, *hxx;
+  const S *fpc, *finv, *flo, *fgam;
+  S *f, *u, *o;
 };
 
-DEV Lv level_view(const Problem& P, int l) {
+template <class S>
+DEV Lv<S> level_view(const Problem& P, int l) {
   const Level& L = P.lev[l];
-  return Lv{L.ncol, L.nx, L.fstride, 1.0 / L.dx, L.h, L.ih, L.hx, L.hxx, L.fpc, L.finv, L.flo, L.fgam};
+  if constexpr (std::is_same_v<S, float>)
+    return Lv<S>{L.ncol, L.nx, L.fstride, S(1.0 / L.dx), L.h, L.ih, L.hx, L.hxx,
+                 L.fpc32, L.finv32, L.flo32, L.fgam32, L.f32, L.u32, L.o32};
+  else
+    return Lv<S>{L.ncol, L.nx, L.fstride, 1.0 / L.dx, L.h, L.ih, L.hx, L.hxx, L.fpc, L.finv, L.flo, L.fgam,
+                 L.f, L.u, L.o};
+}
+
+template <class S>
+DEV const S* coarse_inverse(const Problem& P) {
+  if constexpr (std::is_same_v<S, float>) return P.cinv32;
+  else return P.cinv;
 }
 
 // tile-local staging: column c (unwrapped) <-> slot c - base
@@ -383,50 +422,52 @@ struct Stage {
 
 // (M u)(c, j): U(cc, jj) returns the staged field at unwrapped column cc; CD(cc, q) the
 // staged column data q = 0 h, 1 1/h, 2 h_x, 3 h_xx of unwrapped column cc.
-template <class U, class CD>
-DEV double m_apply(const Problem& P, int nc, double rdx, int c, int j, U u, CD cd) {
+template <class S, class U, class CD>
+DEV S m_apply(const Problem& P, int nc, S rdx, int c, int j, U u, CD cd) {
   const int nz = P.nz;
-  const double rds = 1.0 / P.dsig;
+  const S rds = S(1.0 / P.dsig);
+  const S half = S(0.5), two = S(2), one = S(1), quarter = S(0.25);
   if (j == nz) return u(c, j);
   if (!P.periodic && (c == 0 || c == nc - 1)) {
     if (j == 0) return u(c, j);
     const int w = (c == 0) ? 1 : nc - 2;
-    const double s = cd(w, 2) * (1.0 - P.sig[j]) * cd(w, 1);
-    const double gx = (u(w + 1, j) - u(w - 1, j)) * 0.5 * rdx + s * (u(w, j + 1) - u(w, j - 1)) * 0.5 * rds;
+    const S s = cd(w, 2) * (one - S(P.sig[j])) * cd(w, 1);
+    const S gx = (u(w + 1, j) - u(w - 1, j)) * half * rdx + s * (u(w, j + 1) - u(w, j - 1)) * half * rds;
     return c == 0 ? -gx : gx;
   }
-  const double ih = cd(c, 1), hx = cd(c, 2);
+  const S ih = cd(c, 1), hx = cd(c, 2);
   if (j == 0) {
-    const double s1 = hx * ih;
-    const double dz = (u(c, 2) - u(c, 0)) * 0.5 * rds;
-    const double gx = (u(c + 1, 1) - u(c - 1, 1)) * 0.5 * rdx + s1 * dz;
+    const S s1 = hx * ih;
+    const S dz = (u(c, 2) - u(c, 0)) * half * rds;
+    const S gx = (u(c + 1, 1) - u(c - 1, 1)) * half * rdx + s1 * dz;
     return -hx * gx - dz * ih;
   }
-  const double oms = 1.0 - P.sig[j];
-  const double s = hx * oms * ih;
-  const double sxx = oms * cd(c, 3) * ih - 2.0 * oms * hx * hx * ih * ih;
-  const double uc = u(c, j);
-  const double dxx = (u(c + 1, j) - 2.0 * uc + u(c - 1, j)) * rdx * rdx;
-  const double dxz = (u(c + 1, j + 1) - u(c + 1, j - 1) - u(c - 1, j + 1) + u(c - 1, j - 1)) * 0.25 * rdx * rds;
-  const double dzz = (u(c, j + 1) - 2.0 * uc + u(c, j - 1)) * rds * rds;
-  const double dz = (u(c, j + 1) - u(c, j - 1)) * 0.5 * rds;
-  return dxx + 2.0 * s * dxz + (s * s + ih * ih) * dzz + sxx * dz;
+  const S oms = one - S(P.sig[j]);
+  const S s = hx * oms * ih;
+  const S sxx = oms * cd(c, 3) * ih - two * oms * hx * hx * ih * ih;
+  const S uc = u(c, j);
+  const S dxx = (u(c + 1, j) - two * uc + u(c - 1, j)) * rdx * rdx;
+  const S dxz = (u(c + 1, j + 1) - u(c + 1, j - 1) - u(c - 1, j + 1) + u(c - 1, j - 1)) * quarter * rdx * rds;
+  const S dzz = (u(c, j + 1) - two * uc + u(c, j - 1)) * rds * rds;
+  const S dz = (u(c, j + 1) - u(c, j - 1)) * half * rds;
+  return dxx + two * s * dxz + (s * s + ih * ih) * dzz + sxx * dz;
 }
 
 // Line solve of one column in place: r <- L^-1 r with L the same-column part of M. The bed
 // row (coupling levels 0 and 2) is combined with row 1 (factor gam) so the system is
 // tridiagonal; lo, pc, inv are the precomputed sub-diagonal, elimination ratios and inverse
 // pivots (free-surface row: identity). Level stride rs for r, fs for the factors.
-DEV void line_solve(int nz, double gam, double* __restrict__ r, int rs, const double* __restrict__ lo,
-                    const double* __restrict__ pc, const double* __restrict__ inv, int fs) {
-  double pd = (r[0] - gam * r[rs]) * inv[0];
+template <class S>
+DEV void line_solve(int nz, S gam, S* __restrict__ r, int rs, const S* __restrict__ lo, const S* __restrict__ pc,
+                    const S* __restrict__ inv, int fs) {
+  S pd = (r[0] - gam * r[rs]) * inv[0];
   r[0] = pd;
 #pragma unroll 4
   for (int j = 1; j < nz; ++j) {
     pd = (r[j * rs] - lo[j * fs] * pd) * inv[j * fs];
     r[j * rs] = pd;
   }
-  double d = r[nz * rs];
+  S d = r[nz * rs];
 #pragma unroll 4
   for (int j = nz - 1; j >= 0; --j) {
     d = r[j * rs] - pc[j * fs] * d;
@@ -435,12 +476,14 @@ DEV void line_solve(int nz, double gam, double* __restrict__ r, int rs, const do
 }
 
 // coarse value interpolated to fine column c (linear in x), level j
-DEV double prolong_at(const Problem& P, int ncf, int ncc, const double* e, int c, int j) {
-  const double* ec = e + (size_t)j * ncc;
-  if (P.periodic) return (c & 1) ? 0.5 * (ec[(c - 1) >> 1] + ec[wrapc((c + 1) >> 1, ncc)]) : ec[c >> 1];
+template <class S>
+DEV S prolong_at(const Problem& P, int ncf, int ncc, const S* e, int c, int j) {
+  const S* ec = e + (size_t)j * ncc;
+  const S half = S(0.5);
+  if (P.periodic) return (c & 1) ? half * (ec[(c - 1) >> 1] + ec[wrapc((c + 1) >> 1, ncc)]) : ec[c >> 1];
   if (c == 0 || c == ncf - 1) return ec[c == 0 ? 0 : ncc - 1];
   const int p = c - 1;
-  return (p & 1) ? 0.5 * (ec[((p - 1) >> 1) + 1] + ec[((p + 1) >> 1) + 1]) : ec[(p >> 1) + 1];
+  return (p & 1) ? half * (ec[((p - 1) >> 1) + 1] + ec[((p + 1) >> 1) + 1]) : ec[(p >> 1) + 1];
 }
 
 DEV int ptiles(int nc) { return (nc + TM - 1) / TM; }
@@ -451,69 +494,48 @@ DEV int coarse_centre(const Problem& P, int C, int ncc, int ncf) {
   return 2 * C - 1;
 }
 
-// Stage column data (h, 1/h, h_x, h_xx) of the columns [st.base, st.base + width).
-DEV void stage_coldata(const Lv& L, const Stage& st, int width, double* scd) {
-  staged<4>(4 * width, [&](int i) {
-    const int q = i / width, lc = i - q * width;
-    const int c = st.base + lc;
-    if (!st.has(c)) return 1.0;
-    const int cg = st.col(c);
-    const double* src = q == 0 ? L.h : (q == 1 ? L.ih : (q == 2 ? L.hx : L.hxx));
-    return src[cg];
-  }, [&](int i, double v) { scd[i] = v; });
+// column data q (0 h, 1 1/h, 2 h_x, 3 h_xx) of global column cg, rounded to S
+template <class S>
+DEV S coldata(const Lv<S>& L, int q, int cg) {
+  const double* src = q == 0 ? L.h : (q == 1 ? L.ih : (q == 2 ? L.hx : L.hxx));
+  return S(src[cg]);
 }
 
-// Stage the line-solve factors lo, pc, inv (width x nl each, level-major) and gam (width)
-// of the columns [c0f, c0f + width).
-DEV void stage_factors(const Problem& P, const Lv& L, const Stage& st, int c0f, int width, double* sfac, double* sgam) {
-  const int nl = P.nl;
-  const int per = nl * width;
-  staged<8>(3 * per, [&](int i) {
-    const int q = i / per, r = i - q * per;
-    const int j = r / width, lc = r - j * width;
-    const int c = c0f + lc;
-    if (!st.has(c)) return q == 2 ? 1.0 : 0.0;
-    const int cg = L.fstride ? st.col(c) : 0;
-    const double* src = q == 0 ? L.flo : (q == 1 ? L.fpc : L.finv);
-    return src[(size_t)j * (L.fstride ? L.fstride : 1) + cg];
-  }, [&](int i, double v) { sfac[i] = v; });
-  for (int lc = threadIdx.x; lc < width; lc += BLOCK) {
-    const int c = c0f + lc;
-    sgam[lc] = st.has(c) ? L.fgam[L.fstride ? st.col(c) : 0] : 0.0;
-  }
+// line-solve factor qq (0 lo, 1 pc, 2 inv) at level j of global column cg
+template <class S>
+DEV S factor(const Lv<S>& L, int qq, int j, int cg) {
+  const S* src = qq == 0 ? L.flo : (qq == 1 ? L.fpc : L.finv);
+  return src[(size_t)j * (L.fstride ? L.fstride : 1) + (L.fstride ? cg : 0)];
 }
 
 // o = u + omega L^-1 (f - M u) on level l, u = (uin or 0) + (e ? P e : 0) formed on load.
 // Residuals are formed by all threads in LDS, then one thread per column eliminates.
-DEV void phase_sweep(const Problem& P, Cl& cl, int l, const double* f, const double* uin, const double* e,
-                     double* o, double* lds) {
-  const Lv L = level_view(P, l);
+template <class S>
+DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, const S* e, S* o, S* lds) {
+  const Lv<S> L = level_view<S>(P, l);
   const int nc = L.nc, nl = P.nl, nz = P.nz;
   const int ncc = e ? P.lev[l + 1].ncol : 0;
   constexpr int LW = TM + 2;
-  double* su = lds;                 // LW x nl
-  double* sr = su + LW * nl;        // TM x nl: f, then the residual, then the correction
-  double* scd = sr + TM * nl;       // 4 x LW
-  double* sfac = scd + 4 * LW;      // 3 x TM x nl
-  double* sgam = sfac + 3 * TM * nl;  // TM
+  S* su = lds;                 // LW x nl
+  S* sr = su + LW * nl;        // TM x nl: f, then the residual, then the correction
+  S* scd = sr + TM * nl;       // 4 x LW
+  S* sfac = scd + 4 * LW;      // 3 x TM x nl
+  S* sgam = sfac + 3 * TM * nl;  // TM
   const bool zero = !uin && !e;
   for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
     const int c0 = t * TM, w = min(TM, nc - c0);
     const Stage st{c0 - 1, w + 2, nc, P.periodic};
     const int wu = zero ? 0 : w + 2;
     const int cnt[5] = {wu * nl, w * nl, 4 * wu, 3 * nl * w, w};
-    staged_segments<16>(cnt, [&](int q, int k) -> double {
+    staged_segments<16>(cnt, [&](int q, int k) -> S {
       if (q == 0 || q == 2) {  // u with the prolongated correction, column data
         const int width = wu;
         const int j = k / width, lc = k - j * width;
         const int c = c0 - 1 + lc;
-        if (!st.has(c)) return q == 2 ? 1.0 : 0.0;
+        if (!st.has(c)) return q == 2 ? S(1) : S(0);
         const int cg = st.col(c);
-        if (q == 2) {
-          const double* src = j == 0 ? L.h : (j == 1 ? L.ih : (j == 2 ? L.hx : L.hxx));
-          return src[cg];
-        }
-        double v = uin ? uin[(size_t)j * nc + cg] : 0.0;
+        if (q == 2) return coldata(L, j, cg);
+        S v = uin ? uin[(size_t)j * nc + cg] : S(0);
         if (e) v += prolong_at(P, nc, ncc, e, cg, j);
         return v;
       }
@@ -525,12 +547,10 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const double* f, const dou
         const int per = nl * w;
         const int qq = k / per, r = k - qq * per;
         const int j = r / w, lc = r - j * w;
-        const int cg = L.fstride ? c0 + lc : 0;
-        const double* src = qq == 0 ? L.flo : (qq == 1 ? L.fpc : L.finv);
-        return src[(size_t)j * (L.fstride ? L.fstride : 1) + cg];
+        return factor(L, qq, j, c0 + lc);
       }
       return L.fgam[L.fstride ? c0 + k : 0];
-    }, [&](int q, int k, double v) {
+    }, [&](int q, int k, S v) {
       if (q == 0) { const int j = k / wu, lc = k - j * wu; su[j * LW + lc] = v; }
       else if (q == 1) { const int j = k / w, lc = k - j * w; sr[j * TM + lc] = v; }
       else if (q == 2) { const int j = k / wu, lc = k - j * wu; scd[j * LW + lc] = v; }
@@ -547,19 +567,19 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const double* f, const dou
       auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
       for (int i = threadIdx.x; i < TM * nl; i += BLOCK) {
         const int j = i / TM, lc = i - j * TM;
-        if (lc < w) sr[i] -= m_apply(P, nc, L.rdx, c0 + lc, j, U, CD);
+        if (lc < w) sr[i] -= m_apply<S>(P, nc, L.rdx, c0 + lc, j, U, CD);
       }
       __syncthreads();
     }
     if (threadIdx.x < w) {
       const int lc = threadIdx.x;
-      line_solve(nz, sgam[lc], sr + lc, TM, sfac + lc, sfac + TM * nl + lc, sfac + 2 * TM * nl + lc, TM);
+      line_solve<S>(nz, sgam[lc], sr + lc, TM, sfac + lc, sfac + TM * nl + lc, sfac + 2 * TM * nl + lc, TM);
     }
     __syncthreads();
-    const double om = P.omega;
+    const S om = S(P.omega);
     for (int i = threadIdx.x; i < TM * nl; i += BLOCK) {
       const int j = i / TM, lc = i - j * TM;
-      if (lc < w) o[(size_t)j * nc + c0 + lc] = (zero ? 0.0 : su[j * LW + lc + 1]) + om * sr[i];
+      if (lc < w) o[(size_t)j * nc + c0 + lc] = (zero ? S(0) : su[j * LW + lc + 1]) + om * sr[i];
     }
     __syncthreads();
   }
@@ -572,60 +592,59 @@ DEV void coarse_range(const Problem& P, int c0, int w, int nc, int ncc, int& Cfi
 }
 
 // full weighting of the residual R(cc) around the centre of coarse column C
-template <class RR>
-DEV double restrict_at(const Problem& P, int C, int ncc, int nxc, int nc, RR Rr) {
+template <class S, class RR>
+DEV S restrict_at(const Problem& P, int C, int ncc, int nxc, int nc, RR Rr) {
   const int cf = coarse_centre(P, C, ncc, nc);
-  if (P.periodic) return 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
+  const S half = S(0.5), quarter = S(0.25);
+  if (P.periodic) return quarter * Rr(cf - 1) + half * Rr(cf) + quarter * Rr(cf + 1);
   if (C == 0 || C == ncc - 1) return Rr(cf);
-  if (C == 1) return 0.5 * Rr(1) + 0.5 * Rr(2);
-  if (C == nxc) return 0.5 * Rr(cf) + 0.5 * Rr(cf - 1);
-  return 0.25 * Rr(cf - 1) + 0.5 * Rr(cf) + 0.25 * Rr(cf + 1);
+  if (C == 1) return half * Rr(1) + half * Rr(2);
+  if (C == nxc) return half * Rr(cf) + half * Rr(cf - 1);
+  return quarter * Rr(cf - 1) + half * Rr(cf) + quarter * Rr(cf + 1);
 }
 
 // Pre-smoothing from zero, residual and restriction in one pass (nu1 = 1):
 // u = omega L^-1 f on the tile plus a 2-column halo, u written for the tile's columns,
 // fc(C) = full weighting of f - M u at the fine columns around C's centre.
-DEV void phase_down(const Problem& P, Cl& cl, int l, const double* f, double* u, double* fc, double* lds) {
-  const Lv L = level_view(P, l);
+template <class S>
+DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S* lds) {
+  const Lv<S> L = level_view<S>(P, l);
   const int nc = L.nc, nl = P.nl, nz = P.nz;
   const int ncc = P.lev[l + 1].ncol, nxc = P.lev[l + 1].nx;
   constexpr int LW = TM + 4;
-  double* sf = lds;                 // LW x nl
-  double* su = sf + LW * nl;        // LW x nl
-  double* scd = su + LW * nl;       // 4 x LW
-  double* sfac = scd + 4 * LW;      // 3 x LW x nl
-  double* sgam = sfac + 3 * LW * nl;  // LW
+  S* sf = lds;                 // LW x nl
+  S* su = sf + LW * nl;        // LW x nl
+  S* scd = su + LW * nl;       // 4 x LW
+  S* sfac = scd + 4 * LW;      // 3 x LW x nl
+  S* sgam = sfac + 3 * LW * nl;  // LW
   for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
     const int c0 = t * TM, w = min(TM, nc - c0);
     const Stage st{c0 - 2, w + 4, nc, P.periodic};
     const int ww = w + 4;
     const int cnt[4] = {ww * nl, 4 * ww, 3 * nl * ww, ww};
-    staged_segments<16>(cnt, [&](int q, int k) -> double {
+    staged_segments<16>(cnt, [&](int q, int k) -> S {
       if (q == 0) {
         const int j = k / ww, lc = k - j * ww;
         const int c = c0 - 2 + lc;
-        return st.has(c) ? f[(size_t)j * nc + st.col(c)] : 0.0;
+        return st.has(c) ? f[(size_t)j * nc + st.col(c)] : S(0);
       }
       if (q == 1) {
         const int j = k / ww, lc = k - j * ww;
         const int c = c0 - 2 + lc;
-        if (!st.has(c)) return 1.0;
-        const double* src = j == 0 ? L.h : (j == 1 ? L.ih : (j == 2 ? L.hx : L.hxx));
-        return src[st.col(c)];
+        if (!st.has(c)) return S(1);
+        return coldata(L, j, st.col(c));
       }
       if (q == 2) {
         const int per = nl * ww;
         const int qq = k / per, r = k - qq * per;
         const int j = r / ww, lc = r - j * ww;
         const int c = c0 - 2 + lc;
-        if (!st.has(c)) return qq == 2 ? 1.0 : 0.0;
-        const int cg = L.fstride ? st.col(c) : 0;
-        const double* src = qq == 0 ? L.flo : (qq == 1 ? L.fpc : L.finv);
-        return src[(size_t)j * (L.fstride ? L.fstride : 1) + cg];
+        if (!st.has(c)) return qq == 2 ? S(1) : S(0);
+        return factor(L, qq, j, st.col(c));
       }
       const int c = c0 - 2 + k;
-      return st.has(c) ? L.fgam[L.fstride ? st.col(c) : 0] : 0.0;
-    }, [&](int q, int k, double v) {
+      return st.has(c) ? L.fgam[L.fstride ? st.col(c) : 0] : S(0);
+    }, [&](int q, int k, S v) {
       if (q == 0) { const int j = k / ww, lc = k - j * ww; sf[j * LW + lc] = v; su[j * LW + lc] = v; }
       else if (q == 1) { const int j = k / ww, lc = k - j * ww; scd[j * LW + lc] = v; }
       else if (q == 2) {
@@ -638,10 +657,10 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const double* f, double* u,
     __syncthreads();
     if (threadIdx.x < w + 4 && st.has(c0 - 2 + (int)threadIdx.x)) {
       const int lc = threadIdx.x;
-      line_solve(nz, sgam[lc], su + lc, LW, sfac + lc, sfac + LW * nl + lc, sfac + 2 * LW * nl + lc, LW);
+      line_solve<S>(nz, sgam[lc], su + lc, LW, sfac + lc, sfac + LW * nl + lc, sfac + 2 * LW * nl + lc, LW);
     }
     __syncthreads();
-    const double om = P.omega;
+    const S om = S(P.omega);
     for (int i = threadIdx.x; i < ww * nl; i += BLOCK) {
       const int j = i / ww, lc = i - j * ww;
       su[j * LW + lc] *= om;
@@ -659,37 +678,38 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const double* f, double* u,
     const int ncw = Clast - Cfirst + 1;
     for (int i = threadIdx.x; i < ncw * nl; i += BLOCK) {
       const int j = i / ncw, C = Cfirst + i - j * ncw;
-      auto Rr = [&](int cc) { return F(cc, j) - m_apply(P, nc, L.rdx, cc, j, U, CD); };
-      fc[(size_t)j * ncc + C] = restrict_at(P, C, ncc, nxc, nc, Rr);
+      auto Rr = [&](int cc) { return F(cc, j) - m_apply<S>(P, nc, L.rdx, cc, j, U, CD); };
+      fc[(size_t)j * ncc + C] = restrict_at<S>(P, C, ncc, nxc, nc, Rr);
     }
     __syncthreads();
   }
 }
 
 // fc = full weighting of f - M u (used when nu1 != 1)
-DEV void phase_restrict(const Problem& P, Cl& cl, int l, const double* f, const double* u, double* fc,
-                        double* lds) {
-  const Lv L = level_view(P, l);
+template <class S>
+DEV void phase_restrict(const Problem& P, Cl& cl, int l, const S* f, const S* u, S* fc, S* lds) {
+  const Lv<S> L = level_view<S>(P, l);
   const int nc = L.nc, nl = P.nl;
   const int ncc = P.lev[l + 1].ncol, nxc = P.lev[l + 1].nx;
   constexpr int LW = TM + 4;
-  double* sf = lds;
-  double* su = sf + LW * nl;
-  double* scd = su + LW * nl;
+  S* sf = lds;
+  S* su = sf + LW * nl;
+  S* scd = su + LW * nl;
   for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
     const int c0 = t * TM, w = min(TM, nc - c0);
     const Stage st{c0 - 2, w + 4, nc, P.periodic};
-    staged<8>(LW * nl, [&](int i) {
-      const int j = i / LW, lc = i - j * LW;
+    const int cnt[3] = {LW * nl, LW * nl, 4 * LW};
+    staged_segments<8>(cnt, [&](int q, int k) -> S {
+      if (q == 2) {
+        const int qq = k / LW, lc = k - qq * LW;
+        const int c = c0 - 2 + lc;
+        return st.has(c) ? coldata(L, qq, st.col(c)) : S(1);
+      }
+      const int j = k / LW, lc = k - j * LW;
       const int c = c0 - 2 + lc;
-      return (lc < w + 4 && st.has(c)) ? f[(size_t)j * nc + st.col(c)] : 0.0;
-    }, [&](int i, double v) { sf[i] = v; });
-    staged<8>(LW * nl, [&](int i) {
-      const int j = i / LW, lc = i - j * LW;
-      const int c = c0 - 2 + lc;
-      return (lc < w + 4 && st.has(c)) ? u[(size_t)j * nc + st.col(c)] : 0.0;
-    }, [&](int i, double v) { su[i] = v; });
-    stage_coldata(L, st, LW, scd);
+      const S* src = q == 0 ? f : u;
+      return (lc < w + 4 && st.has(c)) ? src[(size_t)j * nc + st.col(c)] : S(0);
+    }, [&](int q, int k, S v) { (q == 0 ? sf : (q == 1 ? su : scd))[k] = v; });
     __syncthreads();
     auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
     auto F = [&](int cc, int jj) { return sf[jj * LW + st.slot(cc)]; };
@@ -699,15 +719,16 @@ DEV void phase_restrict(const Problem& P, Cl& cl, int l, const double* f, const 
     const int ncw = Clast - Cfirst + 1;
     for (int i = threadIdx.x; i < ncw * nl; i += BLOCK) {
       const int j = i / ncw, C = Cfirst + i - j * ncw;
-      auto Rr = [&](int cc) { return F(cc, j) - m_apply(P, nc, L.rdx, cc, j, U, CD); };
-      fc[(size_t)j * ncc + C] = restrict_at(P, C, ncc, nxc, nc, Rr);
+      auto Rr = [&](int cc) { return F(cc, j) - m_apply<S>(P, nc, L.rdx, cc, j, U, CD); };
+      fc[(size_t)j * ncc + C] = restrict_at<S>(P, C, ncc, nxc, nc, Rr);
     }
     __syncthreads();
   }
 }
 
 // u += P e on level l
-DEV void phase_prolong(const Problem& P, Cl& cl, int l, const double* e, double* u) {
+template <class S>
+DEV void phase_prolong(const Problem& P, Cl& cl, int l, const S* e, S* u) {
   const int nc = P.lev[l].ncol, ncc = P.lev[l + 1].ncol;
   const int total = nc * P.nl;
   for (int i = cl.rank * BLOCK + threadIdx.x; i < total; i += cl.G * BLOCK) {
@@ -716,15 +737,17 @@ DEV void phase_prolong(const Problem& P, Cl& cl, int l, const double* e, double*
   }
 }
 
-DEV void phase_coarse(const Problem& P, Cl& cl, const double* f, double* o) {
+// o = M_c^-1 f on the coarsest grid: thread per row of the stored (transposed) inverse
+template <class S>
+DEV void phase_coarse(const Problem& P, Cl& cl, const S* f, S* o) {
   const int cn = P.cn;
-  const double* ci = P.cinv;
+  const S* ci = coarse_inverse<S>(P);
   for (int i = cl.rank * BLOCK + threadIdx.x; i < cn; i += cl.G * BLOCK) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    S s0 = S(0), s1 = S(0), s2 = S(0), s3 = S(0);
     int j = 0;
     for (; j + 3 < cn; j += 4) {
-      const double a0 = ci[(size_t)j * cn + i], a1 = ci[(size_t)(j + 1) * cn + i];
-      const double a2 = ci[(size_t)(j + 2) * cn + i], a3 = ci[(size_t)(j + 3) * cn + i];
+      const S a0 = ci[(size_t)j * cn + i], a1 = ci[(size_t)(j + 1) * cn + i];
+      const S a2 = ci[(size_t)(j + 2) * cn + i], a3 = ci[(size_t)(j + 3) * cn + i];
       s0 += a0 * f[j]; s1 += a1 * f[j + 1]; s2 += a2 * f[j + 2]; s3 += a3 * f[j + 3];
     }
     for (; j < cn; ++j) s0 += ci[(size_t)j * cn + i] * f[j];
@@ -732,22 +755,24 @@ DEV void phase_coarse(const Problem& P, Cl& cl, const double* f, double* o) {
   }
 }
 
-DEV void phase_zero(const Problem& P, Cl& cl, double* v, int len) {
-  for (int i = cl.rank * BLOCK + threadIdx.x; i < len; i += cl.G * BLOCK) v[i] = 0.0;
+template <class S>
+DEV void phase_zero(const Problem& P, Cl& cl, S* v, int len) {
+  for (int i = cl.rank * BLOCK + threadIdx.x; i < len; i += cl.G * BLOCK) v[i] = S(0);
 }
 
-DEV void phase_copy(const Problem& P, Cl& cl, const double* src, double* dst, int len) {
-  for (int i = cl.rank * BLOCK + threadIdx.x; i < len; i += cl.G * BLOCK) dst[i] = src[i];
+template <class S, class D>
+DEV void phase_copy(const Problem& P, Cl& cl, const S* src, D* dst, int len) {
+  for (int i = cl.rank * BLOCK + threadIdx.x; i < len; i += cl.G * BLOCK) dst[i] = D(src[i]);
 }
 
-// per-phase wall-clock accounting (workgroup 0, thread 0), enabled when a.prof != nullptr
+// per-phase wall-clock accounting (rank-0 workgroup, thread 0), enabled with a profile buffer
 struct PhaseClock {
   unsigned long long acc[NPHASE];
   unsigned long long* detail;  // NPROF counters or nullptr
   unsigned long long last, start;
   bool on;
-  DEV void begin(bool enable, unsigned long long* det = nullptr) {
-    on = enable && blockIdx.x == 0 && threadIdx.x == 0;
+  DEV void begin(bool enable, int rank, unsigned long long* det = nullptr) {
+    on = enable && rank == 0 && threadIdx.x == 0;
     detail = on ? det : nullptr;
     for (int i = 0; i < NPHASE; ++i) acc[i] = 0;
     last = start = on ? wall_clock64() : 0;
@@ -774,81 +799,88 @@ struct PhaseClock {
 };
 
 // one V-cycle level pair on the way down / up (cluster or single-workgroup view)
-DEV void mg_down(const Problem& P, Cl& cl, int l, const double* v, double* lds) {
-  const double* f = l == 0 ? v : P.lev[l].f;
-  double* A = P.lev[l].u;
-  double* B = P.lev[l].o;
+template <class S>
+DEV void mg_down(const Problem& P, Cl& cl, int l, const S* v, S* lds) {
+  const Lv<S> L = level_view<S>(P, l);
+  const Lv<S> Lc = level_view<S>(P, l + 1);
+  const S* f = l == 0 ? v : L.f;
+  S* A = L.u;
+  S* B = L.o;
   if (P.nu1 == 1) {
-    phase_down(P, cl, l, f, A, P.lev[l + 1].f, lds);
+    phase_down<S>(P, cl, l, f, A, Lc.f, lds);
     csync(cl);
     return;
   }
-  const double* prev = nullptr;
-  double* dst = A;
+  const S* prev = nullptr;
+  S* dst = A;
   if (P.nu1 == 0) {
-    phase_zero(P, cl, A, P.lev[l].ncol * P.nl);
+    phase_zero<S>(P, cl, A, L.nc * P.nl);
     csync(cl);
   }
   for (int s = 0; s < P.nu1; ++s) {
     dst = (prev == A) ? B : A;
-    phase_sweep(P, cl, l, f, prev, nullptr, dst, lds);
+    phase_sweep<S>(P, cl, l, f, prev, nullptr, dst, lds);
     csync(cl);
     prev = dst;
   }
   if (dst != A) {
-    phase_copy(P, cl, dst, A, P.lev[l].ncol * P.nl);
+    phase_copy(P, cl, (const S*)dst, A, L.nc * P.nl);
     csync(cl);
   }
-  phase_restrict(P, cl, l, f, A, P.lev[l + 1].f, lds);
+  phase_restrict<S>(P, cl, l, f, A, Lc.f, lds);
   csync(cl);
 }
 
 // returns the buffer holding level l's output; z is level 0's destination
-DEV const double* mg_up(const Problem& P, Cl& cl, int l, const double* v, const double* e, double* z, double* lds) {
-  const double* f = l == 0 ? v : P.lev[l].f;
-  double* A = P.lev[l].u;
-  double* B = P.lev[l].o;
-  double* out = (l == 0) ? z : B;
+template <class S>
+DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z, S* lds) {
+  const Lv<S> L = level_view<S>(P, l);
+  const S* f = l == 0 ? v : L.f;
+  S* A = L.u;
+  S* B = L.o;
+  S* out = (l == 0) ? z : B;
   if (P.nu2 == 0) {
-    phase_prolong(P, cl, l, e, A);
+    phase_prolong<S>(P, cl, l, e, A);
     csync(cl);
     if (l == 0) {
-      phase_copy(P, cl, A, z, P.n);
+      phase_copy(P, cl, (const S*)A, z, P.n);
       csync(cl);
       return z;
     }
     return A;
   }
-  double* dst = (P.nu2 == 1) ? out : B;
-  phase_sweep(P, cl, l, f, A, e, dst, lds);  // first post-sweep, correction added on load
+  S* dst = (P.nu2 == 1) ? out : B;
+  phase_sweep<S>(P, cl, l, f, A, e, dst, lds);  // first post-sweep, correction added on load
   csync(cl);
-  const double* prev = dst;
+  const S* prev = dst;
   for (int s = 1; s < P.nu2; ++s) {
-    double* nd = (s == P.nu2 - 1) ? out : ((prev == B) ? A : B);
-    phase_sweep(P, cl, l, f, prev, nullptr, nd, lds);
+    S* nd = (s == P.nu2 - 1) ? out : ((prev == B) ? A : B);
+    phase_sweep<S>(P, cl, l, f, prev, nullptr, nd, lds);
     csync(cl);
     prev = nd;
   }
   return out;
 }
 
-// z = M^-1 v. v and z are level-0 vectors distinct from each other and from the level-0
-// scratch (lev[0].u, lev[0].o). Levels from P.tail on (at most two tiles wide) are run by
-// workgroup 0 alone with workgroup barriers only. Ends with a cluster barrier.
-DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* lds, PhaseClock* ck = nullptr) {
+// z = M^-1 v in precision S. v and z are level-0 vectors distinct from each other and from
+// the level-0 scratch (u, o of level 0). Levels from P.tail on (at most one tile wide) are
+// run by the rank-0 workgroup alone with workgroup barriers only. Ends with a cluster barrier.
+template <class S>
+DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock* ck = nullptr) {
   const int n = P.n;
   if (P.pc == SA_PC_NONE) {
     phase_copy(P, cl, v, z, n);
     csync(cl);
     return;
   }
-  double* A0 = P.lev[0].u;
-  double* B0 = P.lev[0].o;
+  const Lv<S> L0 = level_view<S>(P, 0);
+  S* A0 = L0.u;
+  S* B0 = L0.o;
   if (P.pc == SA_PC_LINE) {  // nu1 sweeps from zero, the last one writes z
-    const double* prev = nullptr;
+    const S* prev = nullptr;
     for (int s = 0; s < P.nu1; ++s) {
-      double* dst = (s == P.nu1 - 1) ? z : ((prev == A0) ? B0 : A0);
-      phase_sweep(P, cl, 0, v, prev, nullptr, dst, lds);
+      S* dst = (s == P.nu1 - 1) ? z : ((prev == A0) ? B0 : A0);
+      phase_sweep<S>(P, cl, 0, v, prev, nullptr, dst, lds);
       csync(cl);
       prev = dst;
     }
@@ -856,51 +888,55 @@ DEV void precond(const Problem& P, Cl& cl, const double* v, double* z, double* l
   }
   const int L = P.nlev;
   if (L == 1) {
-    phase_coarse(P, cl, v, z);
+    phase_coarse<S>(P, cl, v, z);
     csync(cl);
     return;
   }
-  // levels [lt, L-1) are one tile wide: workgroup 0 runs their passes alone (workgroup
-  // barriers only); the coarsest dense solve is shared by the whole cluster
+  // levels [lt, L-1) are one tile wide: the rank-0 workgroup runs their passes alone
+  // (workgroup barriers only); the coarsest dense solve is shared by the whole cluster
   const int lt = (cl.G > 1 && P.tail < L - 1) ? P.tail : L - 1;
   auto tk = [&](int slot) { if (ck) ck->dtick(slot); };
-  for (int l = 0; l < lt; ++l) { mg_down(P, cl, l, v, lds); tk(1 + 2 * l); }
+  for (int l = 0; l < lt; ++l) { mg_down<S>(P, cl, l, v, lds); tk(1 + 2 * l); }
   Cl solo{0, 1, cl.bar, cl.flags, cl.partials, cl.pbuf};
   if (lt < L - 1) {
     if (cl.rank == 0)
-      for (int l = lt; l < L - 1; ++l) { mg_down(P, solo, l, v, lds); tk(1 + 2 * l); }
+      for (int l = lt; l < L - 1; ++l) { mg_down<S>(P, solo, l, v, lds); tk(1 + 2 * l); }
     csync(cl);
     tk(2 * MAXLEV);
   }
-  phase_coarse(P, cl, P.lev[L - 1].f, P.lev[L - 1].o);
+  const Lv<S> Lc = level_view<S>(P, L - 1);
+  phase_coarse<S>(P, cl, Lc.f, Lc.o);
   csync(cl);
   tk(0);
-  const double* e = P.lev[L - 1].o;
+  const S* e = Lc.o;
   if (lt < L - 1) {
     if (cl.rank == 0)
-      for (int l = L - 2; l >= lt; --l) { e = mg_up(P, solo, l, v, e, z, lds); tk(2 + 2 * l); }
+      for (int l = L - 2; l >= lt; --l) { e = mg_up<S>(P, solo, l, v, e, z, lds); tk(2 + 2 * l); }
     csync(cl);
     tk(2 * MAXLEV);
     // every workgroup knows which buffer holds the tail's output
-    e = (lt == 0) ? z : (P.nu2 == 0 ? P.lev[lt].u : P.lev[lt].o);
+    const Lv<S> Lt = level_view<S>(P, lt);
+    e = (lt == 0) ? z : (P.nu2 == 0 ? Lt.u : Lt.o);
     if (lt == 0) return;
   }
-  for (int l = lt - 1; l >= 0; --l) { e = mg_up(P, cl, l, v, e, z, lds); tk(2 + 2 * l); }
+  for (int l = lt - 1; l >= 0; --l) { e = mg_up<S>(P, cl, l, v, e, z, lds); tk(2 + 2 * l); }
 }
 
 // ------------------------------------------------------------------------------------------
 // Arnoldi pieces. V holds raw (unnormalised) basis vectors; vs[i] scales V_i to unit norm.
 
 // red[i] = vs[i] * (V_i . w), i < nv; red[nv] = ||w||^2 if with_norm. Each thread streams its
-// elements of one vector at a time, four loads in flight per accumulator set.
-DEV void phase_dots(const Problem& P, Cl& cl, const double* V, const double* vs, int nv, const double* w,
+// elements of one vector at a time, four loads in flight per accumulator set. V and w are
+// stored in S; products and sums are FP64.
+template <class S>
+DEV void phase_dots(const Problem& P, Cl& cl, const S* V, const double* vs, int nv, const S* w,
                     bool with_norm, double* wsum, double* red) {
   const int n = P.n;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int stride = cl.G * BLOCK;
   const int nred = nv + (with_norm ? 1 : 0);
   for (int i = 0; i < nred; ++i) {
-    const double* a = (i < nv) ? V + (size_t)i * n : w;
+    const S* a = (i < nv) ? V + (size_t)i * n : w;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int e = cl.rank * BLOCK + threadIdx.x;
     for (; e + 3 * stride < n; e += 4 * stride) {
@@ -908,7 +944,7 @@ DEV void phase_dots(const Problem& P, Cl& cl, const double* V, const double* vs,
       const double w0 = w[e], w1 = w[e + stride], w2 = w[e + 2 * stride], w3 = w[e + 3 * stride];
       s0 += a0 * w0; s1 += a1 * w1; s2 += a2 * w2; s3 += a3 * w3;
     }
-    for (; e < n; e += stride) s0 += a[e] * w[e];
+    for (; e < n; e += stride) s0 += double(a[e]) * double(w[e]);
     double sum = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) wsum[i * 4 + wave] = sum;
   }
@@ -922,8 +958,9 @@ DEV void phase_dots(const Problem& P, Cl& cl, const double* V, const double* vs,
 
 // w -= sum_i h[i] vs[i] V_i (in place); then red[i] = vs[i] (V_i . w) for i < nv when dots,
 // or red[0] = ||w||^2 when !dots. Basis loads go in groups of four.
-DEV void phase_update(const Problem& P, Cl& cl, const double* V, const double* vs, const double* h, int nv,
-                      double* w, bool dots, double* wsum, double* red) {
+template <class S>
+DEV void phase_update(const Problem& P, Cl& cl, const S* V, const double* vs, const double* h, int nv,
+                      S* w, bool dots, double* wsum, double* red) {
   const int n = P.n;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int stride = cl.G * BLOCK;
@@ -936,7 +973,7 @@ DEV void phase_update(const Problem& P, Cl& cl, const double* V, const double* v
     const int e = base + lane;
     const bool ok = e < n;
     const size_t ec = ok ? (size_t)e : 0;
-    double we = ok ? w[e] : 0.0;
+    double we = ok ? double(w[e]) : 0.0;
     int i = 0;
     for (; i + 3 < nv; i += 4) {
       const double v0 = V[(size_t)i * n + ec], v1 = V[(size_t)(i + 1) * n + ec];
@@ -946,17 +983,17 @@ DEV void phase_update(const Problem& P, Cl& cl, const double* V, const double* v
       we -= v2 * (h[i + 2] * vs[i + 2]);
       we -= v3 * (h[i + 3] * vs[i + 3]);
     }
-    for (; i < nv; ++i) we -= V[(size_t)i * n + ec] * (h[i] * vs[i]);
-    if (!ok) we = 0.0;
-    if (ok) w[e] = we;
+    for (; i < nv; ++i) we -= double(V[(size_t)i * n + ec]) * (h[i] * vs[i]);
+    const S ws = ok ? S(we) : S(0);
+    if (ok) w[e] = ws;
     if (dots) {
       for (int q = 0; q < nv; ++q) {
-        double p = V[(size_t)q * n + ec] * we;
+        double p = double(V[(size_t)q * n + ec]) * double(ws);
         p = wave_sum(p);
         if (lane == 0) wsum[q * 4 + wave] += p;
       }
     } else {
-      nrm += we * we;
+      nrm += double(ws) * double(ws);
     }
   }
   __syncthreads();
@@ -969,8 +1006,9 @@ DEV void phase_update(const Problem& P, Cl& cl, const double* V, const double* v
   }
 }
 
-// dst = src + sum_i y[i] vs[i] V_i
-DEV void phase_combine(const Problem& P, Cl& cl, const double* V, const double* vs, const double* y, int nv,
+// dst = src + sum_i y[i] vs[i] V_i (FP64 result, basis stored in S)
+template <class S>
+DEV void phase_combine(const Problem& P, Cl& cl, const S* V, const double* vs, const double* y, int nv,
                        const double* src, double* dst) {
   const int n = P.n;
   for (int e = cl.rank * BLOCK + threadIdx.x; e < n; e += cl.G * BLOCK) {
@@ -981,7 +1019,7 @@ DEV void phase_combine(const Problem& P, Cl& cl, const double* V, const double* 
       const double v2 = V[(size_t)(i + 2) * n + e], v3 = V[(size_t)(i + 3) * n + e];
       v += v0 * (y[i] * vs[i]) + v1 * (y[i + 1] * vs[i + 1]) + v2 * (y[i + 2] * vs[i + 2]) + v3 * (y[i + 3] * vs[i + 3]);
     }
-    for (; i < nv; ++i) v += V[(size_t)i * n + e] * (y[i] * vs[i]);
+    for (; i < nv; ++i) v += double(V[(size_t)i * n + e]) * (y[i] * vs[i]);
     dst[e] = v;
   }
 }
@@ -1125,7 +1163,7 @@ DEV void phase_block_gram(const Problem& P, Cl& cl, const SolveArgs& a, const do
         return v;
       };
       double* wcol = sW + (size_t)col * W * nl;
-      tile_operator<W>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int, double v) {
+      tile_operator<double, W>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int, double v) {
         wcol[lj * W + lc] = v;
       });
     }
@@ -1344,23 +1382,17 @@ DEV void back_substitute(const Smem& S, int m, int jj) {
   __syncthreads();
 }
 
+// Geometry of both stages, the initial guess and r0 = b - A x0 (shared by both precisions).
+// Fills info (rank, relres0) and returns whether the solve is already finished.
 template <bool SKETCH>
-DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a) {
-  const Problem& P = *PP;
-  extern __shared__ double smem[];
-  const int m = P.m;
-  Smem S = carve(smem, m);
-  Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
+DEV bool solve_start(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, PhaseClock& clk,
+                     sa_solve_info& info, double& nb, double& rn) {
   const int tid = threadIdx.x;
   const size_t n = P.n;
-
-  PhaseClock clk;
-  clk.begin(a.prof != nullptr, a.prof);
   phase_geometry(P, cl, a.eta_p, a.eta_c);
   csync(cl);
   clk.tick(PH_GEOM);
 
-  // ---------------- initial guess
   const double* Yo = P.Y[a.ycur];
   double* Yn = P.Y[a.ycur ^ 1];
   int rank = 0;
@@ -1383,113 +1415,132 @@ DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a) {
   csync(cl);
   clk.tick(PH_GUESS);
 
-  // ---------------- r0 = b - A x0
   phase_operator(P, cl, P.x, 1.0, P.r, a.b, S.big, S.red, 0);
   cluster_sum(cl, S.red, 2);
   clk.tick(PH_OPER);
-  const double nb = sqrt(S.red[1]);
-  double rn = sqrt(S.red[0]);
-  sa_solve_info info;
+  nb = sqrt(S.red[1]);
+  rn = sqrt(S.red[0]);
   info.iters = 0; info.restarts = 0; info.refinements = 0; info.status = SA_OK; info.rank = rank; info.checks = 0;
   info.relres0 = nb > 0.0 ? rn / nb : 0.0;
   info.relres = info.relres0;
+  if (!(nb > 0.0)) {
+    if (!(nb == 0.0)) atomicOr(P.flags + FLAG_NONFINITE, 1);
+    for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) P.x[e] = 0.0;
+    info.relres0 = info.relres = 0.0;
+    return true;
+  }
+  if (!isfinite(rn)) {
+    atomicOr(P.flags + FLAG_NONFINITE, 1);
+    return true;
+  }
+  return rn <= a.rtol * nb;
+}
+
+// Givens rotation of Hessenberg column j (h2 = second CGS pass added here), new g, basis scale
+DEV void givens_step(const Smem& S, int m, int j, double hn) {
+  if (threadIdx.x == 0) {
+    double* col = S.H + j * (m + 1);
+    for (int i = 0; i <= j; ++i) col[i] += S.y[i];
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t0 = S.cs[i] * col[i] + S.sn[i] * col[i + 1];
+      col[i + 1] = -S.sn[i] * col[i] + S.cs[i] * col[i + 1];
+      col[i] = t0;
+    }
+    const double den = hypot(col[j], col[j + 1]);
+    S.cs[j] = col[j] / den;
+    S.sn[j] = col[j + 1] / den;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    S.g[j + 1] = -S.sn[j] * S.g[j];
+    S.g[j] = S.cs[j] * S.g[j];
+    S.vs[j + 1] = 1.0 / hn;
+  }
+  __syncthreads();
+}
+
+// One Arnoldi step j in precision T: w = M^-1 A (vs_j V_j), CGS2 against V_0..V_j, Givens.
+// Returns ||w|| after orthogonalisation; w0 receives ||w|| before it.
+template <class T>
+DEV double arnoldi_step(const Problem& P, Cl& cl, const Smem& S, PhaseClock& clk, T* V, T* t, int j,
+                        double& w0) {
+  const size_t n = P.n;
+  const int m = P.m, tid = threadIdx.x;
+  T* wv = V + (size_t)(j + 1) * n;
+  T* lds = (T*)S.big;
+  clk.tick(PH_OTHER);
+  if constexpr (std::is_same_v<T, double>) phase_operator(P, cl, V + (size_t)j * n, S.vs[j], t, nullptr, S.big, S.red, 0);
+  else phase_operator_s<T>(P, cl, V + (size_t)j * n, T(S.vs[j]), t, lds);
+  csync(cl);
+  clk.tick(PH_OPER);
+  precond<T>(P, cl, t, wv, lds, &clk);
+  clk.tick(PH_PREC);
+  // CGS2: h1 = V^T w (and ||w||), w -= V h1, h2 = V^T w, w -= V h2
+  phase_dots<T>(P, cl, V, S.vs, j + 1, wv, true, S.wsum, S.red);
+  cluster_sum(cl, S.red, j + 2);
+  w0 = sqrt(S.red[j + 1]);
+  if (tid < j + 1) S.H[j * (m + 1) + tid] = S.red[tid];
+  __syncthreads();
+  phase_update<T>(P, cl, V, S.vs, S.H + j * (m + 1), j + 1, wv, true, S.wsum, S.red);
+  cluster_sum(cl, S.red, j + 1);
+  if (tid < j + 1) S.y[tid] = S.red[tid];  // h2 (y is free here)
+  __syncthreads();
+  phase_update<T>(P, cl, V, S.vs, S.y, j + 1, wv, false, S.wsum, S.red);
+  cluster_sum(cl, S.red, 1);
+  clk.tick(PH_ORTH);
+  const double hn = sqrt(S.red[0]);
+  givens_step(S, m, j, hn);
+  return hn;
+}
+
+// ||v||^2 summed over the cluster into red[0]
+template <class T>
+DEV double cluster_norm(const Problem& P, Cl& cl, const Smem& S, const T* v) {
+  const size_t n = P.n;
+  block_sum_to([&] {
+    double s = 0.0;
+    for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK) s += double(v[e]) * double(v[e]);
+    return s;
+  }(), S.wsum, S.red, 0);
+  cluster_sum(cl, S.red, 1);
+  return sqrt(S.red[0]);
+}
+
+// FP64 restarted GMRES from P.x with residual P.r (left-preconditioned, CGS2, decisions on the
+// true residual).
+DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, PhaseClock& clk,
+                 sa_solve_info& info, double nb, double rn) {
+  const int m = P.m;
   const double rtol = a.rtol;
   bool done = false;
   double* x = P.x;
   double* xc = P.xc;
   double* r = P.r;
   double* rc = P.rc;
-  if (!(nb > 0.0)) {
-    if (!(nb == 0.0)) atomicOr(P.flags + FLAG_NONFINITE, 1);
-    for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) x[e] = 0.0;
-    info.relres0 = info.relres = 0.0;
-    done = true;
-  } else if (!isfinite(rn)) {
-    atomicOr(P.flags + FLAG_NONFINITE, 1);
-    done = true;
-  } else if (rn <= rtol * nb) {
-    done = true;
-  }
-  double trigger = 0.0;
-  if (!done) {
-    // trigger of the true-residual check: rtol ||M^-1 b||
-    precond(P, cl, a.b, P.t, S.big, &clk);
-    clk.tick(PH_PREC);
-    block_sum_to([&] {
-      double s = 0.0;
-      for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) s += P.t[e] * P.t[e];
-      return s;
-    }(), S.wsum, S.red, 0);
-    cluster_sum(cl, S.red, 1);
-    trigger = rtol * sqrt(S.red[0]);
-  }
-  // ---------------- restarted GMRES
+  // trigger of the true-residual check: rtol ||M^-1 b||
+  precond<double>(P, cl, a.b, P.t, S.big, &clk);
+  clk.tick(PH_PREC);
+  double trigger = rtol * cluster_norm(P, cl, S, (const double*)P.t);
   while (!done && !aborted(cl)) {
     double* V = P.V;
     clk.tick(PH_OTHER);
-    precond(P, cl, r, V, S.big, &clk);
+    precond<double>(P, cl, r, V, S.big, &clk);
     clk.tick(PH_PREC);
-    block_sum_to([&] {
-      double s = 0.0;
-      for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) s += V[e] * V[e];
-      return s;
-    }(), S.wsum, S.red, 0);
-    cluster_sum(cl, S.red, 1);
-    const double beta = sqrt(S.red[0]);
-    if (tid == 0) {
+    const double beta = cluster_norm(P, cl, S, (const double*)V);
+    if (threadIdx.x == 0) {
       S.vs[0] = 1.0 / beta;
       S.g[0] = beta;
     }
     __syncthreads();
     bool restart_now = false;
-    int jend = m;
     for (int j = 0; j < m && !aborted(cl); ++j) {
       info.iters += 1;
-      double* wv = V + (size_t)(j + 1) * n;
-      clk.tick(PH_OTHER);
-      phase_operator(P, cl, V + (size_t)j * n, S.vs[j], P.t, nullptr, S.big, S.red, 0);
-      csync(cl);
-      clk.tick(PH_OPER);
-      precond(P, cl, P.t, wv, S.big, &clk);
-      clk.tick(PH_PREC);
-      // CGS2: h1 = V^T w (and ||w||), w -= V h1, h2 = V^T w, w -= V h2
-      phase_dots(P, cl, V, S.vs, j + 1, wv, true, S.wsum, S.red);
-      cluster_sum(cl, S.red, j + 2);
-      const double w0 = sqrt(S.red[j + 1]);
-      if (tid < j + 1) S.H[j * (m + 1) + tid] = S.red[tid];
-      __syncthreads();
-      phase_update(P, cl, V, S.vs, S.H + j * (m + 1), j + 1, wv, true, S.wsum, S.red);
-      cluster_sum(cl, S.red, j + 1);
-      if (tid < j + 1) S.y[tid] = S.red[tid];  // h2 (y is free here)
-      __syncthreads();
-      phase_update(P, cl, V, S.vs, S.y, j + 1, wv, false, S.wsum, S.red);
-      cluster_sum(cl, S.red, 1);
-      clk.tick(PH_ORTH);
-      const double hn = sqrt(S.red[0]);
-      // Givens rotations (identical in every workgroup)
-      if (tid == 0) {
-        double* col = S.H + j * (m + 1);
-        for (int i = 0; i <= j; ++i) col[i] += S.y[i];
-        col[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-          const double t0 = S.cs[i] * col[i] + S.sn[i] * col[i + 1];
-          col[i + 1] = -S.sn[i] * col[i] + S.cs[i] * col[i + 1];
-          col[i] = t0;
-        }
-        const double den = hypot(col[j], col[j + 1]);
-        S.cs[j] = col[j] / den;
-        S.sn[j] = col[j + 1] / den;
-        col[j] = den;
-        col[j + 1] = 0.0;
-        S.g[j + 1] = -S.sn[j] * S.g[j];
-        S.g[j] = S.cs[j] * S.g[j];
-        S.vs[j + 1] = 1.0 / hn;
-      }
-      __syncthreads();
+      double w0;
+      const double hn = arnoldi_step<double>(P, cl, S, clk, V, P.t, j, w0);
       const bool breakdown = hn <= 1e-14 * w0;
       if (breakdown || fabs(S.g[j + 1]) <= trigger) {
         back_substitute(S, m, j + 1);
-        phase_combine(P, cl, V, S.vs, S.y, j + 1, x, xc);
+        phase_combine<double>(P, cl, V, S.vs, S.y, j + 1, x, xc);
         csync(cl);
         clk.tick(PH_OTHER);
         phase_operator(P, cl, xc, 1.0, rc, a.b, S.big, S.red, 0);
@@ -1516,8 +1567,8 @@ DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a) {
     }
     if (done) break;
     if (!restart_now) {
-      back_substitute(S, m, jend);
-      phase_combine(P, cl, V, S.vs, S.y, jend, x, x);
+      back_substitute(S, m, m);
+      phase_combine<double>(P, cl, V, S.vs, S.y, m, x, x);
       csync(cl);
       clk.tick(PH_OTHER);
       phase_operator(P, cl, x, 1.0, r, a.b, S.big, S.red, 0);
@@ -1538,10 +1589,135 @@ DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a) {
   // the solution must end in P.x (the next solve's previous solution)
   if (x != P.x) {
     csync(cl);
-    phase_copy(P, cl, x, P.x, P.n);
+    phase_copy(P, cl, (const double*)x, P.x, P.n);
+  }
+}
+
+// Mixed precision: FP64 iterative refinement around FP32 GMRES cycles on A d = r / ||r||.
+// Operator, V-cycle and basis are FP32; Gram-Schmidt sums, Hessenberg and Givens are FP64.
+// Candidates x + ||r|| V y are checked on the FP64 residual b - A x with the trigger rule of
+// the FP64 path (first at rtol ||M^-1 b||, lowered after a failed check); when the cycle
+// reaches FP32 resolution (estimate down by rtol_inner, or h_{j+1,j} <= 1e-7 ||w||) the
+// checked candidate becomes the new x and the next correction starts from its residual.
+DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, PhaseClock& clk,
+                  sa_solve_info& info, double nb, double rn) {
+  const int m = P.m;
+  const size_t n = P.n;
+  const double rtol = a.rtol;
+  float* V = P.V32;
+  float* r32 = P.r32;
+  float* lds = (float*)S.big;
+  double* x = P.x;
+  double* xc = P.xc;
+  double* r = P.r;
+  double* rc = P.rc;
+  // trigger: rtol ||b|| ||M^-1 fl32(b / ||b||)||
+  {
+    const double sb = 1.0 / nb;
+    for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK)
+      r32[e] = float(a.b[e] * sb);
+    csync(cl);
+    precond<float>(P, cl, r32, P.t32, lds, &clk);
+    clk.tick(PH_PREC);
+  }
+  double trigger = rtol * nb * cluster_norm(P, cl, S, (const float*)P.t32);
+  bool converged = false;
+  while (!aborted(cl)) {
+    if (info.refinements >= P.max_refine) {
+      info.status = SA_NOCONV;
+      break;
+    }
+    info.refinements += 1;
+    const double sc = 1.0 / rn;
+    for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK)
+      r32[e] = float(r[e] * sc);
+    csync(cl);
+    clk.tick(PH_OTHER);
+    precond<float>(P, cl, r32, V, lds, &clk);
+    clk.tick(PH_PREC);
+    const double beta = cluster_norm(P, cl, S, (const float*)V);
+    if (threadIdx.x == 0) {
+      S.vs[0] = 1.0 / beta;
+      S.g[0] = beta;
+    }
+    __syncthreads();
+    bool restarted = false;
+    for (int j = 0; j < m && !aborted(cl); ++j) {
+      info.iters += 1;
+      double w0;
+      const double hn = arnoldi_step<float>(P, cl, S, clk, V, P.t32, j, w0);
+      const double est = rn * fabs(S.g[j + 1]);
+      const bool floor = hn <= 1e-7 * w0 || fabs(S.g[j + 1]) <= P.rtol_inner * beta;
+      if (floor || est <= trigger) {
+        back_substitute(S, m, j + 1);
+        if (threadIdx.x <= j) S.y[threadIdx.x] *= rn;
+        __syncthreads();
+        phase_combine<float>(P, cl, V, S.vs, S.y, j + 1, x, xc);
+        csync(cl);
+        clk.tick(PH_OTHER);
+        phase_operator(P, cl, xc, 1.0, rc, a.b, S.big, S.red, 0);
+        cluster_sum(cl, S.red, 2);
+        clk.tick(PH_OPER);
+        const double rcn = sqrt(S.red[0]);
+        info.checks += 1;
+        if (!isfinite(rcn)) {
+          atomicOr(P.flags + FLAG_NONFINITE, 1);
+          converged = true;  // leave with the flag set
+          break;
+        }
+        if (rcn <= rtol * nb || floor) {
+          double* t = x; x = xc; xc = t;
+          t = r; r = rc; rc = t;
+          rn = rcn;
+          converged = rcn <= rtol * nb;
+          restarted = !converged;
+          break;
+        }
+        trigger = est * rtol * nb / rcn;
+      }
+    }
+    if (!converged && !restarted) {
+      back_substitute(S, m, m);
+      if (threadIdx.x < m) S.y[threadIdx.x] *= rn;
+      __syncthreads();
+      phase_combine<float>(P, cl, V, S.vs, S.y, m, x, x);
+      csync(cl);
+      clk.tick(PH_OTHER);
+      phase_operator(P, cl, x, 1.0, r, a.b, S.big, S.red, 0);
+      cluster_sum(cl, S.red, 2);
+      clk.tick(PH_OPER);
+      rn = sqrt(S.red[0]);
+      if (!isfinite(rn)) { atomicOr(P.flags + FLAG_NONFINITE, 1); converged = true; }
+      else converged = rn <= rtol * nb;
+    }
+    info.relres = rn / nb;
+    if (converged) break;
+  }
+  if (x != P.x) {
+    csync(cl);
+    phase_copy(P, cl, (const double*)x, P.x, P.n);
+  }
+}
+
+// One solve of the problem by the cluster workgroup `rank`: guess, then FP64 GMRES or FP32
+// refinement, then the report into the log.
+template <bool SKETCH>
+DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a, int rank) {
+  const Problem& P = *PP;
+  extern __shared__ double smem[];
+  Smem S = carve(smem, P.m);
+  Cl cl{rank, P.G, P.bar, P.flags, P.partials, 0};
+  PhaseClock clk;
+  clk.begin(a.prof != nullptr, rank, a.prof);
+  sa_solve_info info;
+  double nb = 0.0, rn = 0.0;
+  const bool done = solve_start<SKETCH>(P, cl, a, S, clk, info, nb, rn);
+  if (!done) {
+    if (P.precision == SA_FP32_IR) refine32(P, cl, a, S, clk, info, nb, rn);
+    else gmres64(P, cl, a, S, clk, info, nb, rn);
   }
   clk.tick(PH_OTHER);
-  if (cl.rank == 0 && tid == 0) {
+  if (cl.rank == 0 && threadIdx.x == 0) {
     if (aborted(cl)) info.status = SA_EDEVICE;
     P.log[a.log_slot] = info;
   }
@@ -1550,12 +1726,12 @@ DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a) {
 
 // one solve with the EWMA-sketch guess (push of the previous solution, Alg. 2 guess)
 extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Problem* __restrict__ PP, SolveArgs a) {
-  solve_body<true>(PP, a);
+  solve_body<true>(PP, a, (int)blockIdx.x);
 }
 
 // one solve from a zero or previous-solution guess (no sketch)
 extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_plain_kernel(const Problem* __restrict__ PP, SolveArgs a) {
-  solve_body<false>(PP, a);
+  solve_body<false>(PP, a, (int)blockIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1576,6 +1752,15 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_operator_kernel(const Pro
   phase_operator(P, cl, x, 1.0, y, nullptr, smem, smem, 0);
 }
 
+// y = A x with FP32 input, output and arithmetic (the inner operator of the refinement path)
+extern "C" __global__ void __launch_bounds__(BLOCK) sa_operator32_kernel(const Problem* __restrict__ PP,
+                                                                         const float* x, float* y) {
+  const Problem& P = *PP;
+  extern __shared__ double smem[];
+  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
+  phase_operator_s<float>(P, cl, x, 1.0f, y, (float*)smem);
+}
+
 extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond_kernel(const Problem* __restrict__ PP,
                                                                       const double* v, double* z,
                                                                       unsigned long long* prof) {
@@ -1583,9 +1768,18 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond_kernel(const Prob
   extern __shared__ double smem[];
   Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
   PhaseClock clk;
-  clk.begin(prof != nullptr, prof);
-  precond(P, cl, v, z, smem, &clk);
+  clk.begin(prof != nullptr, cl.rank, prof);
+  precond<double>(P, cl, v, z, smem, &clk);
   clk.flush(prof);
+}
+
+// z = M^-1 v in FP32 (the inner preconditioner of the refinement path)
+extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond32_kernel(const Problem* __restrict__ PP,
+                                                                        const float* v, float* z) {
+  const Problem& P = *PP;
+  extern __shared__ double smem[];
+  Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
+  precond<float>(P, cl, v, z, (float*)smem, nullptr);
 }
 
 extern "C" __global__ void __launch_bounds__(BLOCK) sa_push_kernel(const Problem* __restrict__ PP, SolveArgs a) {

@@ -69,3 +69,12 @@ def test_ctypes_struct_layout(binding):
     assert binding.SaGrid.length.offset == 16
     assert ctypes.sizeof(binding.SaSolveInfo) == 6 * 4 + 2 * 8
     assert binding.SaOptions.rtol.offset == 8
+
+
+def test_refinement_option_errors_need_no_gpu(binding):
+    for bad in (dict(rtol_inner=0.0), dict(rtol_inner=1.5), dict(max_refine=0)):
+        with pytest.raises(binding.SawaveError) as e:
+            binding.Problem(65, 9, "periodic", 1.0, np.ones(64), precision="fp32_ir", **bad)
+        assert e.value.code == -1, bad
+    with pytest.raises(binding.SawaveError):
+        binding.Problem(65, 9, "periodic", 1.0, np.ones(64), precision=7)
