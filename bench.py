@@ -36,6 +36,11 @@ def parse():
     ap.add_argument("--cluster", type=int, default=0, help="workgroups per solve (0 = size rule)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-solves", type=int, default=30)
+    ap.add_argument("--serve-sims", type=int, default=256, help="serving: simulations")
+    ap.add_argument("--serve-systems", type=int, default=10, help="serving: systems per simulation")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="serving: offered solves/s (open loop)")
+    ap.add_argument("--serve-baseline-stride", type=int, default=8,
+                    help="serving: the one-at-a-time FP64 baseline solves every k-th simulation")
     return ap.parse_args()
 
 
@@ -166,6 +171,132 @@ def cpu_baseline(w, nsolves):
                        f"{np.mean(its):.2f} iterations/solve, one thread")
 
 
+def run_serving(args):
+    """Continuous batching of the serving mix (independent simulations of different sizes).
+
+    Inputs (surfaces and b = A p* of every system) are formed by the library's operator and
+    resident in HBM first. Three runs on fresh simulations: saturation (every request queued
+    at t = 0, FIFO per simulation), open loop (Poisson arrivals at --serve-rate, round robin
+    over the simulations), both FP32-inner refinement with the EWMA guess through the server;
+    and the one-at-a-time FP64 cold-start path (sa_solve, no sketch) on every k-th simulation.
+    All at relative residual 1e-8 checked on the FP64 residual.
+    """
+    import torch
+    from paper_2511_18071_amd import binding as B
+    from paper_2511_18071_amd import workload as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sims = W.serving_mix(args.serve_sims, seed=5, nsys=args.serve_systems)
+    nsys = args.serve_systems
+    t_setup = time.perf_counter()
+    inputs = []
+    with B.Server(stream=stream) as gen:
+        for w in sims:
+            sid = gen.open(w, precond="none", guess="cold", cluster=1)
+            eta = torch.empty((nsys, 2, w.nphys), dtype=torch.float64, device=dev)
+            bs = torch.empty((nsys, w.n), dtype=torch.float64, device=dev)
+            for s in range(nsys):
+                ep, ec, ps = w.system(s)
+                eta[s, 0].copy_(torch.from_numpy(ep))
+                eta[s, 1].copy_(torch.from_numpy(ec))
+                gen.apply_operator(sid, eta[s, 0], eta[s, 1], torch.from_numpy(ps).to(dev), bs[s])
+            gen.close_sim(sid)
+            inputs.append((eta, bs))
+    torch.cuda.synchronize()
+    total_unknowns = sum(w.n for w in sims)
+    nreq = len(sims) * nsys
+    # request j: simulation j mod nsims, its (j // nsims)-th system (round robin, FIFO per sim)
+    order = [(j % len(sims), j // len(sims)) for j in range(nreq)]
+
+    def serve(arrivals):
+        srv = B.Server(stream=stream)
+        ids = [srv.open(w, precision="fp32_ir") for w in sims]
+        if any(i is None for i in ids):
+            raise RuntimeError("serving mix does not fit the HBM budget")
+        torch.cuda.synchronize()
+        lat, infos = [], []
+        k = 0
+        t0 = time.perf_counter()
+        while k < nreq or srv.outstanding > 0:
+            now = time.perf_counter() - t0
+            while k < nreq and arrivals[k] <= now:
+                i, s = order[k]
+                eta, bs = inputs[i]
+                srv.submit(ids[i], eta[s, 0], eta[s, 1], bs[s])
+                k += 1
+            wait = k >= nreq or (arrivals[k] - (time.perf_counter() - t0)) > 0.002
+            for c in srv.poll(wait=wait and srv.outstanding > 0):
+                lat.append(c.t_done_ms - c.t_submit_ms)
+                infos.append(c.info)
+        wall = time.perf_counter() - t0
+        bytes_used = srv.bytes_used
+        srv.close()
+        return dict(wall=wall, lat=np.array(lat), infos=infos, bytes=bytes_used)
+
+    sat = serve(np.zeros(nreq))
+    rng = np.random.default_rng(5)
+    arr = np.cumsum(rng.exponential(1.0 / args.serve_rate, nreq))
+    ol = serve(arr)
+    # one-at-a-time FP64 cold start (sa_solve) on every k-th simulation
+    base_lat, base_its, base_bad = [], [], 0
+    for i in range(0, len(sims), args.serve_baseline_stride):
+        w = sims[i]
+        eta, bs = inputs[i]
+        p = B.Problem.from_workload(w, stream=stream, cluster=default_cluster(w), guess="cold")
+        for s in range(nsys):
+            p.set_surface(eta[s, 0], eta[s, 1])
+            p.push_rhs(bs[s])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = p.solve()
+            base_lat.append(1e3 * (time.perf_counter() - t))
+            base_its.append(info.iters)
+            base_bad += info.status != 0 or info.relres > w.rtol
+        p.close()
+    base_rate = len(base_lat) / (1e-3 * sum(base_lat))
+
+    def stats(r):
+        its = np.array([i.iters for i in r["infos"]])
+        bad = sum(1 for i in r["infos"] if i.status != 0 or i.relres > 1e-8)
+        return dict(solves_per_s=round(nreq / r["wall"], 2), wall_s=round(r["wall"], 3),
+                    p50_ms=round(float(np.percentile(r["lat"], 50)), 3),
+                    p99_ms=round(float(np.percentile(r["lat"], 99)), 3),
+                    iters_per_solve=round(float(its.mean()), 3),
+                    refinements_per_solve=round(float(np.mean([i.refinements for i in r["infos"]])), 3),
+                    max_relres=float(max(i.relres for i in r["infos"])), failed_solves=bad)
+
+    s_sat, s_ol = stats(sat), stats(ol)
+    out = {
+        "metric": "serving solves/s at saturation @relres 1e-8, p50/p99 solve latency (open loop)",
+        "value": s_sat["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": nreq,
+        "warmup": 0,
+        "ms_per_step": round(1e3 * sat["wall"] / nreq, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving_mix({len(sims)} simulations x {nsys} systems, seed 5)",
+                   "unknowns_total": total_unknowns, "precision": "fp32 inner GMRES, fp64 refinement",
+                   "guess": "EWMA", "hbm_bytes_resident": sat["bytes"]},
+        "saturation": s_sat,
+        "open_loop": dict(offered_solves_per_s=args.serve_rate, **s_ol),
+        "baseline_one_at_a_time_fp64_cold": {
+            "solves_per_s": round(base_rate, 2), "solves": len(base_lat),
+            "sample": f"every {args.serve_baseline_stride}th simulation, all its systems",
+            "p50_ms": round(float(np.percentile(base_lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(base_lat, 99)), 3),
+            "iters_per_solve": round(float(np.mean(base_its)), 3), "failed_solves": base_bad},
+        "speedup_vs_baseline": round(s_sat["solves_per_s"] / base_rate, 2),
+        "setup_s": round(time.perf_counter() - t_setup, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -174,6 +305,9 @@ def main():
         sys.exit(2)
     from paper_2511_18071_amd import workload as W
 
+    if args.workload == "serving":
+        run_serving(args)
+        return
     w = W.get(args.workload)
     ewma, plain, G = run_gpu(args, w)
     nsol = 5 * args.steps

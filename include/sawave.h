@@ -55,7 +55,8 @@ enum {
   SA_ENONFINITE = -3,/* NaN/Inf in the right-hand side or during the solve               */
   SA_EOOM = -4,      /* device allocation failed                                         */
   SA_EDEVICE = -5,   /* HIP runtime error or device-side fault flag; problem unusable     */
-  SA_ENOTBUILT = -6  /* no usable gfx950 device                                          */
+  SA_ENOTBUILT = -6, /* no usable gfx950 device                                          */
+  SA_EBUSY = -7      /* server: HBM budget exhausted, or the simulation still has work     */
 };
 
 enum { SA_PERIODIC = 0, SA_WALLS = 1 };
@@ -170,6 +171,10 @@ int sa_get_sketch(sa_problem* p, double* y, int32_t mem);
 /* Number of solutions stored in the sketch so far. */
 int64_t sa_sketch_count(const sa_problem* p);
 
+/* Bytes of device memory sa_create would allocate for these arguments (no device needed);
+ * validates the arguments like sa_create. */
+int sa_problem_footprint(const sa_grid* grid, const double* h, const sa_options* opt, int64_t* bytes);
+
 /* Device time spent in each phase of the solves run so far with opt.profile = 1, in
  * milliseconds of the device's constant-rate clock, measured by the first workgroup:
  * out[0] geometry, [1] sketch guess (block operator, Gram, x0), [2] k x k solve,
@@ -178,6 +183,59 @@ int64_t sa_sketch_count(const sa_problem* p);
  * solve, [9 + 2 l] down pass and [10 + 2 l] up pass of level l (l < 24), [56] the wait of
  * the other workgroups for the single-workgroup coarse tail. n = entries wanted (<= 57). */
 int sa_get_phase_times(sa_problem* p, double* out, int32_t n);
+
+/* ---- continuous-batching server ---------------------------------------------------------
+ * Many independent simulations (each an sa_problem with its own sketch and hierarchy) on one
+ * GPU. Simulations are admitted when their device arena fits the HBM budget; requests (the
+ * surfaces and right-hand side of a simulation's next system) queue per simulation, first in
+ * first out; a tick runs the oldest request of as many simulations as fit into one launch,
+ * one workgroup cluster per request; up to max_inflight ticks are queued on the stream, so
+ * requests arriving while a tick runs join the next one. A solve in a tick computes exactly
+ * what sa_solve computes for that simulation. Not thread-safe: one host thread drives it. */
+typedef struct sa_server sa_server;
+
+typedef struct {
+  int64_t hbm_budget;             /* device bytes the simulations may hold; 0 = 90% of free */
+  int32_t max_inflight;           /* launched, unfinished ticks (1..4), default 2            */
+  int32_t max_batch;              /* solves per tick, 0 = as many as are co-resident          */
+  int32_t unknowns_per_workgroup; /* cluster size of simulations opened with cluster = 0:    */
+                                  /* ceil(n / this), 1..16, default 40000                    */
+  int32_t reserved;
+} sa_server_options;
+
+typedef struct {
+  uint64_t ticket;                /* from sa_server_submit                                    */
+  int32_t sim;
+  int32_t reserved;
+  sa_solve_info info;             /* as sa_solve reports it; status < 0 for SA_EGEOM etc.    */
+  double t_submit_ms;             /* server clock: ms since sa_server_create                  */
+  double t_launch_ms;             /* when its tick was enqueued                               */
+  double t_done_ms;               /* when its tick finished on the device                     */
+} sa_completion;
+
+void sa_server_default_options(sa_server_options* opt);
+int sa_server_create(const sa_server_options* opt, void* hip_stream, sa_server** out);
+/* Waits for all work, destroys every open simulation. */
+void sa_server_destroy(sa_server* s);
+/* Admit a simulation (arguments as sa_create; opt->cluster = 0 picks the cluster size from
+ * its size). SA_EBUSY (nothing allocated) when its arena would exceed the HBM budget. */
+int sa_server_open(sa_server* s, const sa_grid* grid, const double* h, const sa_options* opt, int32_t* sim);
+/* Free a simulation without queued or running requests (else SA_EBUSY). */
+int sa_server_close(sa_server* s, int32_t sim);
+/* Queue the next system of `sim`. Host inputs (eta: nphys values each, b: n values) are copied
+ * before return; device inputs must stay valid until the request completes. */
+int sa_server_submit(sa_server* s, int32_t sim, const double* eta_prev, const double* eta_cur, const double* b,
+                     int32_t mem, uint64_t* ticket);
+/* Harvest finished ticks, launch new ones from the queues, return up to `max` completions
+ * (oldest tick first). wait != 0: block until at least one completion is available when
+ * work is outstanding. */
+int sa_server_poll(sa_server* s, sa_completion* out, int32_t max, int32_t* n_out, int32_t wait);
+/* Requests queued, running or completed but not yet returned by sa_server_poll. */
+int64_t sa_server_outstanding(const sa_server* s);
+/* Device bytes held by the open simulations. */
+int64_t sa_server_bytes_used(const sa_server* s);
+/* The problem of an open simulation (for sa_get_solution, sa_read_log; no sa_solve on it). */
+sa_problem* sa_server_problem(sa_server* s, int32_t sim);
 
 /* Thread-local message of the last hard error ("" if none). */
 const char* sa_last_error(void);

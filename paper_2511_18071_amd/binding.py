@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsawave.so")
 
 SA_OK, SA_NOCONV = 0, 1
+SA_EBUSY = -7
 SA_PERIODIC, SA_WALLS = 0, 1
 SA_PC = {"none": 0, "line": 1, "mg": 2}
 SA_GUESS = {"cold": 0, "previous": 1, "ewma": 2}
@@ -47,6 +48,16 @@ class SaSolveInfo(C.Structure):
     ]
 
 
+class SaServerOptions(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
+                ("unknowns_per_workgroup", C.c_int32), ("reserved", C.c_int32)]
+
+
+class SaCompletion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("sim", C.c_int32), ("reserved", C.c_int32), ("info", SaSolveInfo),
+                ("t_submit_ms", C.c_double), ("t_launch_ms", C.c_double), ("t_done_ms", C.c_double)]
+
+
 @dataclass
 class SolveInfo:
     iters: int
@@ -67,6 +78,24 @@ class SawaveError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"sawave error {code}: {msg}")
         self.code = code
+
+
+def _torch_first():
+    """Let PyTorch bring up its HIP runtime before this library does.
+
+    The PyTorch-ROCm wheel ships its own HIP and HSA runtimes beside the system ROCm ones this
+    library links; both can serve one process (device pointers are shared), but PyTorch finds no
+    device when it initialises after the system runtime has. Nothing happens without torch or
+    without a GPU."""
+    try:
+        import torch
+    except Exception:
+        return
+    try:
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:
+        pass
 
 
 def _load():
@@ -96,6 +125,17 @@ def _load():
         "sa_last_error": (C.c_char_p, []),
         "sa_build_info": (C.c_char_p, []),
         "sa_get_phase_times": (C.c_int, [P, D, C.c_int32]),
+        "sa_problem_footprint": (C.c_int, [C.POINTER(SaGrid), D, C.POINTER(SaOptions), C.POINTER(C.c_int64)]),
+        "sa_server_default_options": (None, [C.POINTER(SaServerOptions)]),
+        "sa_server_create": (C.c_int, [C.POINTER(SaServerOptions), P, C.POINTER(P)]),
+        "sa_server_destroy": (None, [P]),
+        "sa_server_open": (C.c_int, [P, C.POINTER(SaGrid), D, C.POINTER(SaOptions), C.POINTER(C.c_int32)]),
+        "sa_server_close": (C.c_int, [P, C.c_int32]),
+        "sa_server_submit": (C.c_int, [P, C.c_int32, P, P, P, C.c_int32, C.POINTER(C.c_uint64)]),
+        "sa_server_poll": (C.c_int, [P, C.POINTER(SaCompletion), C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
+        "sa_server_outstanding": (C.c_int64, [P]),
+        "sa_server_bytes_used": (C.c_int64, [P]),
+        "sa_server_problem": (P, [P, C.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -104,6 +144,7 @@ def _load():
     return lib
 
 
+_torch_first()
 lib = _load()
 
 
@@ -159,19 +200,41 @@ def _stream_handle(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+def make_options(**opts) -> SaOptions:
+    """sa_options from keyword arguments (names of include/sawave.h; enum values by name)."""
+    o = default_options()
+    for key, val in opts.items():
+        names = {"precond": SA_PC, "guess": SA_GUESS, "precision": SA_PRECISION}.get(key)
+        if names is not None and isinstance(val, str):
+            val = names[val]
+        if not hasattr(o, key):
+            raise KeyError(key)
+        setattr(o, key, val)
+    return o
+
+
+def workload_args(w, **overrides):
+    """(grid, depth, options) of a synthetic workload."""
+    kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, k=w.k, r=w.r, seed=w.seed)
+    kw.update(overrides)
+    grid = SaGrid(w.nx, w.nz, SA_PERIODIC if w.bc == "periodic" else SA_WALLS, float(w.length))
+    return grid, np.ascontiguousarray(w.depth(), dtype=np.float64), make_options(**kw)
+
+
+def footprint(w, **overrides) -> int:
+    """Device bytes a problem of workload w would allocate."""
+    grid, h, o = workload_args(w, **overrides)
+    out = C.c_int64(0)
+    _check(lib.sa_problem_footprint(C.byref(grid), h.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o), C.byref(out)))
+    return int(out.value)
+
+
 class Problem:
     """One simulation's sequence of systems on the GPU (see include/sawave.h)."""
 
     def __init__(self, nx: int, nz: int, bc: str, length: float, h, stream=None, **opts):
         self.grid = SaGrid(nx, nz, SA_PERIODIC if bc == "periodic" else SA_WALLS, float(length))
-        o = default_options()
-        for key, val in opts.items():
-            names = {"precond": SA_PC, "guess": SA_GUESS, "precision": SA_PRECISION}.get(key)
-            if names is not None and isinstance(val, str):
-                val = names[val]
-            if not hasattr(o, key):
-                raise KeyError(key)
-            setattr(o, key, val)
+        o = make_options(**opts)
         self.options = o
         hh = np.ascontiguousarray(h, dtype=np.float64)
         self._stream = _stream_handle(stream)
@@ -297,3 +360,124 @@ class Problem:
     @property
     def sketch_count(self) -> int:
         return int(lib.sa_sketch_count(self._h))
+
+
+@dataclass
+class Completion:
+    ticket: int
+    sim: int
+    info: SolveInfo
+    t_submit_ms: float
+    t_launch_ms: float
+    t_done_ms: float
+
+
+class Server:
+    """Continuous-batching server of independent simulations (sa_server_* in include/sawave.h)."""
+
+    def __init__(self, stream=None, **opts):
+        o = SaServerOptions()
+        lib.sa_server_default_options(C.byref(o))
+        for key, val in opts.items():
+            if not hasattr(o, key):
+                raise KeyError(key)
+            setattr(o, key, val)
+        self.options = o
+        self._stream = _stream_handle(stream)
+        h = C.c_void_p()
+        _check(lib.sa_server_create(C.byref(o), self._stream, C.byref(h)))
+        self._h = h
+        self._keep = {}
+        self._sims = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sa_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def open(self, w, **overrides) -> int | None:
+        """Admit workload w; None when its arena does not fit the HBM budget now."""
+        grid, h, o = workload_args(w, **overrides)
+        sid = C.c_int32(-1)
+        code = lib.sa_server_open(self._h, C.byref(grid), h.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o),
+                                  C.byref(sid))
+        if code == SA_EBUSY:
+            return None
+        _check(code)
+        self._sims[sid.value] = (w.n, w.nx - 1 if w.bc == "periodic" else w.nx)
+        return sid.value
+
+    def close_sim(self, sim: int):
+        _check(lib.sa_server_close(self._h, sim))
+        self._sims.pop(sim, None)
+
+    def submit(self, sim: int, eta_prev, eta_cur, b) -> int:
+        n, nphys = self._sims[sim]
+        pa, ma, ka = _ptr(eta_prev, nphys)
+        pb, mb, kb = _ptr(eta_cur, nphys)
+        pr, mr, kr = _ptr(b, n)
+        if not (ma == mb == mr):
+            raise ValueError("all inputs must live in the same memory")
+        t = C.c_uint64(0)
+        _check(lib.sa_server_submit(self._h, sim, pa, pb, pr, ma, C.byref(t)))
+        if ma == SA_MEM_DEVICE:
+            self._keep[t.value] = (ka, kb, kr)  # device inputs stay alive until completion
+        return t.value
+
+    def poll(self, wait: bool = False, max_entries: int = 1024) -> list:
+        buf = (SaCompletion * max_entries)()
+        cnt = C.c_int32(0)
+        _check(lib.sa_server_poll(self._h, buf, max_entries, C.byref(cnt), 1 if wait else 0))
+        out = []
+        for i in range(cnt.value):
+            c = buf[i]
+            self._keep.pop(c.ticket, None)
+            out.append(Completion(c.ticket, c.sim, SolveInfo.of(c.info), c.t_submit_ms, c.t_launch_ms, c.t_done_ms))
+        return out
+
+    @property
+    def outstanding(self) -> int:
+        return int(lib.sa_server_outstanding(self._h))
+
+    @property
+    def bytes_used(self) -> int:
+        return int(lib.sa_server_bytes_used(self._h))
+
+    def apply_operator(self, sim: int, eta_prev, eta_cur, x, out):
+        """out = A(eta_prev, eta_cur) x with simulation `sim`'s operator (before it has work)."""
+        n, nphys = self._sims[sim]
+        p = lib.sa_server_problem(self._h, sim)
+        if not p:
+            raise SawaveError(-1, f"no simulation {sim}")
+        pa, ma, _ = _ptr(eta_prev, nphys)
+        pb, mb, _ = _ptr(eta_cur, nphys)
+        px, mx, _ = _ptr(x, n)
+        py, my, _ = _ptr(out, n)
+        if not (ma == mb == mx == my):
+            raise ValueError("all arrays must live in the same memory")
+        _check(lib.sa_set_surface(p, pa, pb, ma))
+        _check(lib.sa_apply_operator(p, px, py, mx))
+        return out
+
+    def solution(self, sim: int, out=None):
+        n, _ = self._sims[sim]
+        p = lib.sa_server_problem(self._h, sim)
+        if not p:
+            raise SawaveError(-1, f"no simulation {sim}")
+        if out is None:
+            out = np.zeros(n)
+        ptr, m, _ = _ptr(out, n)
+        _check(lib.sa_get_solution(p, ptr, m))
+        return out

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsawave.so")
-SOURCES = ["solver.hip", "api.hip", "setup.cpp"]
+SOURCES = ["solve64.hip", "solve32.hip", "api.hip", "server.hip", "setup.cpp"]
 ARCH = "gfx950"
 
 
@@ -30,6 +30,7 @@ def build(verbose: bool = False) -> str:
     build_dir = os.path.join(ROOT, "_build")
     os.makedirs(build_dir, exist_ok=True)
     objs = []
+    cmds = []
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
     for src in SOURCES:
         path = os.path.join(CSRC, src)
@@ -41,8 +42,13 @@ def build(verbose: bool = False) -> str:
             cmd = [hipcc(), *common, "-x", "c++", "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    # the kernel translation units are large: compile them side by side
+    procs = [subprocess.Popen(c) for c in cmds]
+    codes = [p.wait() for p in procs]
+    if any(codes):
+        raise subprocess.CalledProcessError(next(c for c in codes if c), "hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:

@@ -1,33 +1,26 @@
 // C ABI of the solver library (declared in include/sawave.h): problem set-up, buffer
 // ownership, kernel launches and the per-solve report log.
-#include <hip/hip_runtime.h>
-#include <math.h>
-#include <stdarg.h>
-#include <stdio.h>
-#include <string.h>
-
-#include <string>
-#include <vector>
-
-#include "internal.h"
-
-namespace sa {
-extern "C" __global__ void sa_solve_kernel(const Problem*, SolveArgs);
-extern "C" __global__ void sa_solve_plain_kernel(const Problem*, SolveArgs);
-extern "C" __global__ void sa_geometry_kernel(const Problem*, const double*, const double*);
-extern "C" __global__ void sa_operator_kernel(const Problem*, const double*, double*);
-extern "C" __global__ void sa_precond_kernel(const Problem*, const double*, double*, unsigned long long*);
-extern "C" __global__ void sa_push_kernel(const Problem*, SolveArgs);
-extern "C" __global__ void sa_operator32_kernel(const Problem*, const float*, float*);
-extern "C" __global__ void sa_precond32_kernel(const Problem*, const float*, float*);
-}  // namespace sa
+#include "host.h"
 
 using namespace sa;
 
 static thread_local std::string g_err;
 
-static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-static int fail(int code, const char* fmt, ...) {
+static size_t g_solve_lds = 0;  // dynamic-LDS limit set on the solve kernel so far
+
+const void* sa_solve_fn(int precision) {
+  return precision == SA_FP32_IR ? (const void*)sa_solve_ir_kernel : (const void*)sa_solve_kernel;
+}
+
+int sa_reserve_solve_lds(size_t bytes) {
+  if (bytes <= g_solve_lds) return SA_OK;
+  HIPCHK(hipFuncSetAttribute(sa_solve_fn(SA_FP64), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  HIPCHK(hipFuncSetAttribute(sa_solve_fn(SA_FP32_IR), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  g_solve_lds = bytes;
+  return SA_OK;
+}
+
+int sa_fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -36,39 +29,6 @@ static int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
-
-#define HIPCHK(expr)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess) return fail(SA_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-struct sa_problem {
-  sa_grid grid;
-  sa_options opt;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  int ncol = 0, nl = 0, n = 0, nphys = 0;
-  Problem hp{};                  // host copy of the device descriptor
-  Problem* dp = nullptr;         // device descriptor
-  char* arena = nullptr;         // one device allocation holding every buffer
-  size_t arena_bytes = 0;
-  double* b_own = nullptr;       // internal right-hand side (host pushes)
-  double* eta_own = nullptr;     // 2 x nphys internal surfaces (host pushes)
-  const double* b = nullptr;     // current right-hand side (device)
-  const double* eta_p = nullptr;
-  const double* eta_c = nullptr;
-  size_t lds_solve = 0, lds_op = 0, lds_pc = 0;
-  int G = 1;
-  int ycur = 0;
-  int64_t pushes = 0, solves = 0;
-  bool unpushed = false;         // the last solution is not in the sketch yet
-  bool have_solution = false;
-  int64_t log_pos = 0, log_read = 0;
-  bool broken = false;
-  unsigned long long* prof = nullptr;  // NPHASE device counters (opt.profile)
-  double clock_khz = 100000.0;
-};
 
 extern "C" void sa_default_options(sa_options* o) {
   memset(o, 0, sizeof *o);
@@ -104,7 +64,7 @@ extern "C" const char* sa_build_info(void) {
 }
 
 extern "C" int sa_sketch_draws(uint64_t seed, int64_t index, int32_t k, double* out) {
-  if (!out || k < 1 || k > 64 || index < 0) return fail(SA_EARG, "sa_sketch_draws: bad arguments");
+  if (!out || k < 1 || k > 64 || index < 0) return sa_fail(SA_EARG, "sa_sketch_draws: bad arguments");
   splitmix_gaussians(seed, index, k, out);
   return SA_OK;
 }
@@ -231,46 +191,49 @@ static int tiles_host(int ncol, int periodic, int tw) {
 
 // ---------------------------------------------------------------------------------------
 
-extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options* optin, void* hip_stream,
-                         sa_problem** out) {
-  if (!grid || !h || !out) return fail(SA_EARG, "sa_create: null argument");
-  *out = nullptr;
+// Builds a problem; with bytes_only set it validates, sizes the device arena, stores its size
+// there and returns without touching the device.
+static int create_impl(const sa_grid* grid, const double* h, const sa_options* optin, void* hip_stream,
+                       sa_problem** out, int64_t* bytes_only) {
+  if (!grid || !h || (!out && !bytes_only)) return sa_fail(SA_EARG, "sa_create: null argument");
+  if (out) *out = nullptr;
   sa_options opt;
   if (optin) opt = *optin; else sa_default_options(&opt);
   const int periodic = grid->bc == SA_PERIODIC;
-  if (grid->bc != SA_PERIODIC && grid->bc != SA_WALLS) return fail(SA_EARG, "sa_create: bc must be SA_PERIODIC or SA_WALLS");
-  if (grid->nz < 6 || grid->nz + 1 > NLMAX) return fail(SA_EARG, "sa_create: nz must be in [6, %d]", NLMAX - 1);
+  if (grid->bc != SA_PERIODIC && grid->bc != SA_WALLS) return sa_fail(SA_EARG, "sa_create: bc must be SA_PERIODIC or SA_WALLS");
+  if (grid->nz < 6 || grid->nz + 1 > NLMAX) return sa_fail(SA_EARG, "sa_create: nz must be in [6, %d]", NLMAX - 1);
   const int ncol = periodic ? grid->nx - 1 : grid->nx + 2;
   if ((periodic && ncol < 8) || (!periodic && grid->nx < 7))
-    return fail(SA_EARG, "sa_create: nx too small for seven-point stencils");
-  if (!(grid->length > 0.0) || !isfinite(grid->length)) return fail(SA_EARG, "sa_create: length must be positive");
-  if (opt.restart < 1 || opt.restart > MMAX) return fail(SA_EARG, "sa_create: restart must be in [1, %d]", MMAX);
-  if (opt.max_restarts < 0) return fail(SA_EARG, "sa_create: max_restarts < 0");
-  if (!(opt.rtol >= 0.0)) return fail(SA_EARG, "sa_create: rtol must be >= 0");
-  if (opt.precond < SA_PC_NONE || opt.precond > SA_PC_MG) return fail(SA_EARG, "sa_create: unknown precond");
-  if (opt.nu1 < 0 || opt.nu2 < 0 || opt.nu1 > 8 || opt.nu2 > 8) return fail(SA_EARG, "sa_create: sweeps in [0, 8]");
-  if (opt.precond == SA_PC_LINE && opt.nu1 < 1) return fail(SA_EARG, "sa_create: line preconditioner needs nu1 >= 1");
-  if (opt.guess < SA_GUESS_COLD || opt.guess > SA_GUESS_EWMA) return fail(SA_EARG, "sa_create: unknown guess mode");
-  if (opt.k < 1 || opt.k > KMAX) return fail(SA_EARG, "sa_create: k must be in [1, %d]", KMAX);
-  if (!(opt.r >= 0.0 && opt.r <= 1.0)) return fail(SA_EARG, "sa_create: r must be in [0, 1]");
-  if (opt.precision != SA_FP64 && opt.precision != SA_FP32_IR) return fail(SA_EARG, "sa_create: unknown precision");
+    return sa_fail(SA_EARG, "sa_create: nx too small for seven-point stencils");
+  if (!(grid->length > 0.0) || !isfinite(grid->length)) return sa_fail(SA_EARG, "sa_create: length must be positive");
+  if (opt.restart < 1 || opt.restart > MMAX) return sa_fail(SA_EARG, "sa_create: restart must be in [1, %d]", MMAX);
+  if (opt.max_restarts < 0) return sa_fail(SA_EARG, "sa_create: max_restarts < 0");
+  if (!(opt.rtol >= 0.0)) return sa_fail(SA_EARG, "sa_create: rtol must be >= 0");
+  if (opt.precond < SA_PC_NONE || opt.precond > SA_PC_MG) return sa_fail(SA_EARG, "sa_create: unknown precond");
+  if (opt.nu1 < 0 || opt.nu2 < 0 || opt.nu1 > 8 || opt.nu2 > 8) return sa_fail(SA_EARG, "sa_create: sweeps in [0, 8]");
+  if (opt.precond == SA_PC_LINE && opt.nu1 < 1) return sa_fail(SA_EARG, "sa_create: line preconditioner needs nu1 >= 1");
+  if (opt.guess < SA_GUESS_COLD || opt.guess > SA_GUESS_EWMA) return sa_fail(SA_EARG, "sa_create: unknown guess mode");
+  if (opt.k < 1 || opt.k > KMAX) return sa_fail(SA_EARG, "sa_create: k must be in [1, %d]", KMAX);
+  if (!(opt.r >= 0.0 && opt.r <= 1.0)) return sa_fail(SA_EARG, "sa_create: r must be in [0, 1]");
+  if (opt.precision != SA_FP64 && opt.precision != SA_FP32_IR) return sa_fail(SA_EARG, "sa_create: unknown precision");
   if (opt.precision == SA_FP32_IR && !(opt.rtol_inner > 0.0 && opt.rtol_inner < 1.0))
-    return fail(SA_EARG, "sa_create: rtol_inner must be in (0, 1)");
-  if (opt.precision == SA_FP32_IR && opt.max_refine < 1) return fail(SA_EARG, "sa_create: max_refine >= 1");
-  if (opt.max_levels < 1) return fail(SA_EARG, "sa_create: max_levels >= 1");
-  if (opt.coarse_max < 1 || opt.coarse_max > COARSE_MAX) return fail(SA_EARG, "sa_create: coarse_max in [1, %d]", COARSE_MAX);
+    return sa_fail(SA_EARG, "sa_create: rtol_inner must be in (0, 1)");
+  if (opt.precision == SA_FP32_IR && opt.max_refine < 1) return sa_fail(SA_EARG, "sa_create: max_refine >= 1");
+  if (opt.max_levels < 1) return sa_fail(SA_EARG, "sa_create: max_levels >= 1");
+  if (opt.coarse_max < 1 || opt.coarse_max > COARSE_MAX) return sa_fail(SA_EARG, "sa_create: coarse_max in [1, %d]", COARSE_MAX);
   const int nphys = periodic ? grid->nx - 1 : grid->nx;
   for (int i = 0; i < nphys; ++i)
-    if (!(h[i] > 0.0) || !isfinite(h[i])) return fail(SA_EGEOM, "sa_create: depth must be positive and finite");
+    if (!(h[i] > 0.0) || !isfinite(h[i])) return sa_fail(SA_EGEOM, "sa_create: depth must be positive and finite");
 
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(SA_ENOTBUILT, "sa_create: no HIP device");
+  if (!bytes_only && (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1))
+    return sa_fail(SA_ENOTBUILT, "sa_create: no HIP device");
 
   sa_problem* p = new sa_problem();
   p->grid = *grid;
   p->opt = opt;
   p->stream = (hipStream_t)hip_stream;
-  hipGetDevice(&p->device);
+  if (!bytes_only) (void)hipGetDevice(&p->device);
   p->ncol = ncol;
   p->nl = grid->nz + 1;
   p->n = ncol * p->nl;
@@ -343,26 +306,24 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
     L.fstride = uniform ? 0 : L.ncol;
   }
   std::vector<double> cinv;
+  size_t cinv_n = 0;
   if (opt.precond == SA_PC_MG) {
     if (cn > COARSE_MAX) {
       delete p;
-      return fail(SA_EARG, "sa_create: coarsest grid has %d unknowns (> %d); allow more levels", cn, COARSE_MAX);
+      return sa_fail(SA_EARG, "sa_create: coarsest grid has %d unknowns (> %d); allow more levels", cn, COARSE_MAX);
     }
-    cinv.resize((size_t)cn * cn);
-    const HL& L = levs.back();
-    if (dense_still_water_inverse(L.ncol, L.nx, nl, periodic, L.dx, dsig, L.h.data(), L.hx.data(), L.hxx.data(),
-                                  cinv.data()) != 0) {
-      delete p;
-      return fail(SA_EARG, "sa_create: singular coarsest operator");
-    }
+    cinv_n = (size_t)cn * cn;
   }
 
   // ---- cluster size and LDS
   const int m = opt.restart, k = opt.k;
   int G = opt.cluster;
   if (G <= 0) G = 1;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) { delete p; return fail(SA_EDEVICE, "hipGetDeviceProperties failed"); }
+  hipDeviceProp_t prop{};
+  if (!bytes_only && hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
+    delete p;
+    return sa_fail(SA_EDEVICE, "hipGetDeviceProperties failed");
+  }
   const size_t head = (size_t)PSTRIDE + 4 * (MMAX + 2) + (size_t)(m + 1) * m + 2 * m + 2 * (m + 1) + m + KMAX +
                       4 * KMAX * KMAX + 8;
   const int TWMh = TX + 3, TWGMh = TXG + 3;
@@ -378,17 +339,20 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
   p->lds_solve = (head + big) * sizeof(double);
   p->lds_op = need_op * sizeof(double);
   p->lds_pc = need_pc * sizeof(double);
-  if (p->lds_solve > (size_t)prop.sharedMemPerBlock && p->lds_solve > 160 * 1024) {
+  if (p->lds_solve > 160 * 1024 && (bytes_only || p->lds_solve > (size_t)prop.sharedMemPerBlock)) {
     delete p;
-    return fail(SA_EARG, "sa_create: %zu bytes of LDS needed (nz, k or restart too large)", p->lds_solve);
+    return sa_fail(SA_EARG, "sa_create: %zu bytes of LDS needed (nz, k or restart too large)", p->lds_solve);
   }
-  if (G > 1) {
+  if (!bytes_only && sa_reserve_solve_lds(p->lds_solve) != SA_OK) {
+    delete p;
+    return SA_EDEVICE;
+  }
+  if (G > 1 && !bytes_only) {
     int per_cu = 0;
-    (void)hipFuncSetAttribute((const void*)sa_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)sa_solve_kernel, BLOCK, p->lds_solve) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sa_solve_fn(opt.precision), BLOCK, p->lds_solve) != hipSuccess ||
         per_cu < 1 || G > per_cu * prop.multiProcessorCount) {
       delete p;
-      return fail(SA_EARG, "sa_create: cluster of %d workgroups cannot be co-resident", G);
+      return sa_fail(SA_EARG, "sa_create: cluster of %d workgroups cannot be co-resident", G);
     }
   }
   p->G = G;
@@ -417,8 +381,8 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
       o_lf32[l] = take(nlv * 4); o_lu32[l] = take(nlv * 4); o_lo32[l] = take(nlv * 4);
     }
   }
-  const size_t o_cinv = take(cinv.size() * 8 + 8);
-  const size_t o_cinv32 = ir ? take(cinv.size() * 4 + 8) : 0;
+  const size_t o_cinv = take(cinv_n * 8 + 8);
+  const size_t o_cinv32 = ir ? take(cinv_n * 4 + 8) : 0;
   const size_t o_V32 = ir ? take((size_t)(m + 1) * n * 4) : 0, o_t32 = ir ? take((size_t)n * 4) : 0,
                o_r32 = ir ? take((size_t)n * 4) : 0;
   const size_t o_x = take((size_t)n * 8), o_xc = take((size_t)n * 8), o_r = take((size_t)n * 8),
@@ -429,9 +393,23 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
                o_log = take(LOGCAP * sizeof(sa_solve_info)), o_b = take((size_t)n * 8), o_eta = take(2 * (size_t)nphys * 8),
                o_prob = take(sizeof(Problem)), o_prof = take(NPROF * 8);
   p->arena_bytes = off;
+  if (bytes_only) {
+    *bytes_only = (int64_t)off;
+    delete p;
+    return SA_OK;
+  }
+  if (cinv_n) {
+    cinv.resize(cinv_n);
+    const HL& L = levs.back();
+    if (dense_still_water_inverse(L.ncol, L.nx, nl, periodic, L.dx, dsig, L.h.data(), L.hx.data(), L.hxx.data(),
+                                  cinv.data()) != 0) {
+      delete p;
+      return sa_fail(SA_EARG, "sa_create: singular coarsest operator");
+    }
+  }
   if (hipMalloc((void**)&p->arena, off) != hipSuccess) {
     delete p;
-    return fail(SA_EOOM, "sa_create: cannot allocate %zu bytes of device memory", off);
+    return sa_fail(SA_EOOM, "sa_create: cannot allocate %zu bytes of device memory", off);
   }
   char* A = p->arena;
   auto up = [&](size_t o, const void* src, size_t bytes) {
@@ -516,25 +494,43 @@ extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options*
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) == hipSuccess && khz > 0) p->clock_khz = khz;
   }
   if (e == hipSuccess) e = up(o_prob, &P, sizeof(Problem));
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_solve_plain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_solve);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_operator_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_op);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_precond_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_pc);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_operator32_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_op);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)sa_precond32_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_pc);
   if (e != hipSuccess) {
-    hipFree(p->arena);
+    (void)hipFree(p->arena);
     delete p;
-    return fail(SA_EDEVICE, "sa_create: %s", hipGetErrorString(e));
+    return sa_fail(SA_EDEVICE, "sa_create: %s", hipGetErrorString(e));
   }
   *out = p;
   return SA_OK;
 }
 
+extern "C" int sa_create(const sa_grid* grid, const double* h, const sa_options* opt, void* hip_stream,
+                         sa_problem** out) {
+  if (!out) return sa_fail(SA_EARG, "sa_create: null argument");
+  return create_impl(grid, h, opt, hip_stream, out, nullptr);
+}
+
+int64_t sa_problem_bytes(const sa_grid* grid, const double* h, const sa_options* opt) {
+  int64_t bytes = 0;
+  const int rc = create_impl(grid, h, opt, nullptr, nullptr, &bytes);
+  return rc < 0 ? rc : bytes;
+}
+
+extern "C" int sa_problem_footprint(const sa_grid* grid, const double* h, const sa_options* opt, int64_t* bytes) {
+  if (!bytes) return sa_fail(SA_EARG, "sa_problem_footprint: null argument");
+  const int64_t b = sa_problem_bytes(grid, h, opt);
+  if (b < 0) return (int)b;
+  *bytes = b;
+  return SA_OK;
+}
+
 extern "C" void sa_destroy(sa_problem* p) {
   if (!p) return;
-  if (p->stream) hipStreamSynchronize(p->stream); else hipDeviceSynchronize();
-  hipFree(p->arena);
+  if (p->stream) (void)hipStreamSynchronize(p->stream); else (void)hipDeviceSynchronize();
+  (void)hipFree(p->arena);
   delete p;
 }
 
@@ -542,17 +538,17 @@ extern "C" int64_t sa_size(const sa_problem* p) { return p ? p->n : -1; }
 extern "C" int32_t sa_ncol(const sa_problem* p) { return p ? p->ncol : -1; }
 extern "C" int64_t sa_sketch_count(const sa_problem* p) { return p ? p->pushes + (p->unpushed ? 1 : 0) : -1; }
 
-static int check_flags(sa_problem* p) {
+int sa_check_flags(sa_problem* p) {
   int f[NFLAGS];
   HIPCHK(hipMemcpyAsync(f, p->hp.flags, sizeof f, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   if (f[FLAG_ABORT]) {
     p->broken = true;
-    return fail(SA_EDEVICE, "device barrier timed out; problem unusable");
+    return sa_fail(SA_EDEVICE, "device barrier timed out; problem unusable");
   }
   int code = SA_OK;
-  if (f[FLAG_GEOM]) code = fail(SA_EGEOM, "h + eta <= 0 or non-finite surface");
-  else if (f[FLAG_NONFINITE]) code = fail(SA_ENONFINITE, "non-finite value in the right-hand side or solve");
+  if (f[FLAG_GEOM]) code = sa_fail(SA_EGEOM, "h + eta <= 0 or non-finite surface");
+  else if (f[FLAG_NONFINITE]) code = sa_fail(SA_ENONFINITE, "non-finite value in the right-hand side or solve");
   if (code != SA_OK) {
     int z[NFLAGS] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(p->hp.flags, z, sizeof z, hipMemcpyHostToDevice, p->stream));
@@ -562,12 +558,12 @@ static int check_flags(sa_problem* p) {
 }
 
 extern "C" int sa_set_surface(sa_problem* p, const double* eta_prev, const double* eta_cur, int32_t mem) {
-  if (!p || !eta_prev || !eta_cur) return fail(SA_EARG, "sa_set_surface: null argument");
-  if (p->broken) return fail(SA_EDEVICE, "problem unusable after a device error");
+  if (!p || !eta_prev || !eta_cur) return sa_fail(SA_EARG, "sa_set_surface: null argument");
+  if (p->broken) return sa_fail(SA_EDEVICE, "problem unusable after a device error");
   if (mem == SA_MEM_HOST) {
     for (int i = 0; i < p->nphys; ++i) {
       const double hp = eta_prev[i], hc = eta_cur[i];
-      if (!isfinite(hp) || !isfinite(hc)) return fail(SA_EGEOM, "sa_set_surface: non-finite surface");
+      if (!isfinite(hp) || !isfinite(hc)) return sa_fail(SA_EGEOM, "sa_set_surface: non-finite surface");
     }
     HIPCHK(hipMemcpyAsync(p->eta_own, eta_prev, p->nphys * 8, hipMemcpyHostToDevice, p->stream));
     HIPCHK(hipMemcpyAsync(p->eta_own + p->nphys, eta_cur, p->nphys * 8, hipMemcpyHostToDevice, p->stream));
@@ -578,14 +574,14 @@ extern "C" int sa_set_surface(sa_problem* p, const double* eta_prev, const doubl
     p->eta_p = eta_prev;
     p->eta_c = eta_cur;
   } else {
-    return fail(SA_EARG, "sa_set_surface: bad mem");
+    return sa_fail(SA_EARG, "sa_set_surface: bad mem");
   }
   return SA_OK;
 }
 
 extern "C" int sa_push_rhs(sa_problem* p, const double* b, int32_t mem) {
-  if (!p || !b) return fail(SA_EARG, "sa_push_rhs: null argument");
-  if (p->broken) return fail(SA_EDEVICE, "problem unusable after a device error");
+  if (!p || !b) return sa_fail(SA_EARG, "sa_push_rhs: null argument");
+  if (p->broken) return sa_fail(SA_EDEVICE, "problem unusable after a device error");
   if (mem == SA_MEM_HOST) {
     HIPCHK(hipMemcpyAsync(p->b_own, b, (size_t)p->n * 8, hipMemcpyHostToDevice, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
@@ -593,7 +589,7 @@ extern "C" int sa_push_rhs(sa_problem* p, const double* b, int32_t mem) {
   } else if (mem == SA_MEM_DEVICE) {
     p->b = b;
   } else {
-    return fail(SA_EARG, "sa_push_rhs: bad mem");
+    return sa_fail(SA_EARG, "sa_push_rhs: bad mem");
   }
   return SA_OK;
 }
@@ -616,10 +612,7 @@ static hipError_t launch_cluster(sa_problem* p, const void* fn, void** args, siz
   return hipLaunchCooperativeKernel(fn, dim3(p->G), dim3(BLOCK), args, (unsigned)lds, p->stream);
 }
 
-extern "C" int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags) {
-  if (!p) return fail(SA_EARG, "sa_solve: null problem");
-  if (p->broken) return fail(SA_EDEVICE, "problem unusable after a device error");
-  if (!p->b || !p->eta_p || !p->eta_c) return fail(SA_EARG, "sa_solve: set the surfaces and the right-hand side first");
+SolveArgs sa_prepare_solve(sa_problem* p, bool* ewma_out) {
   SolveArgs a = base_args(p);
   const sa_options& o = p->opt;
   const bool ewma = o.guess == SA_GUESS_EWMA;
@@ -629,20 +622,40 @@ extern "C" int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags) {
   a.sketch_guess = ewma && pushes_after > 0 && p->solves >= o.n_init;
   a.prev_guess = p->have_solution && (o.guess == SA_GUESS_PREVIOUS || (ewma && !a.sketch_guess));
   a.log_slot = (int)(p->log_pos % LOGCAP);
-  void* args[] = {(void*)&p->dp, (void*)&a};
-  const void* fn = ewma ? (const void*)sa_solve_kernel : (const void*)sa_solve_plain_kernel;
-  HIPCHK(launch_cluster(p, fn, args, p->lds_solve));
+  *ewma_out = ewma;
+  return a;
+}
+
+void sa_commit_solve(sa_problem* p, const SolveArgs& a) {
   if (a.push) {
     p->ycur ^= 1;
     p->pushes += 1;
   }
-  p->unpushed = ewma;
+  p->unpushed = p->opt.guess == SA_GUESS_EWMA;
   p->have_solution = true;
   p->solves += 1;
   p->log_pos += 1;
+}
+
+extern "C" int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags) {
+  if (!p) return sa_fail(SA_EARG, "sa_solve: null problem");
+  if (p->broken) return sa_fail(SA_EDEVICE, "problem unusable after a device error");
+  if (!p->b || !p->eta_p || !p->eta_c) return sa_fail(SA_EARG, "sa_solve: set the surfaces and the right-hand side first");
+  bool ewma = false;
+  SolveArgs a = sa_prepare_solve(p, &ewma);
+  BatchItem one;
+  one.P = p->dp;
+  one.first = 0;
+  one.sketch = ewma ? 1 : 0;
+  one.a = a;
+  const BatchItem* none = nullptr;
+  int zero = 0;
+  void* args[] = {(void*)&none, (void*)&zero, (void*)&one};
+  HIPCHK(launch_cluster(p, sa_solve_fn(p->opt.precision), args, p->lds_solve));
+  sa_commit_solve(p, a);
   if (flags & SA_ASYNC) return SA_OK;
   HIPCHK(hipStreamSynchronize(p->stream));
-  int code = check_flags(p);
+  int code = sa_check_flags(p);
   sa_solve_info rep;
   HIPCHK(hipMemcpy(&rep, p->hp.log + a.log_slot, sizeof rep, hipMemcpyDeviceToHost));
   p->log_read = p->log_pos;
@@ -650,15 +663,15 @@ extern "C" int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags) {
   if (code != SA_OK) return code;
   if (rep.status == SA_EDEVICE) {
     p->broken = true;
-    return fail(SA_EDEVICE, "device barrier timed out");
+    return sa_fail(SA_EDEVICE, "device barrier timed out");
   }
   return rep.status;
 }
 
 extern "C" int sa_read_log(sa_problem* p, sa_solve_info* out, int32_t max, int32_t* n_out) {
-  if (!p || !n_out || (max > 0 && !out)) return fail(SA_EARG, "sa_read_log: bad arguments");
+  if (!p || !n_out || (max > 0 && !out)) return sa_fail(SA_EARG, "sa_read_log: bad arguments");
   HIPCHK(hipStreamSynchronize(p->stream));
-  int code = check_flags(p);
+  int code = sa_check_flags(p);
   int64_t avail = p->log_pos - p->log_read;
   if (avail > LOGCAP) {
     p->log_read = p->log_pos - LOGCAP;
@@ -680,7 +693,7 @@ static hipMemcpyKind kind_from(int32_t mem, bool to_device) {
 }
 
 extern "C" int sa_get_solution(sa_problem* p, double* x, int32_t mem) {
-  if (!p || !x || (mem != SA_MEM_HOST && mem != SA_MEM_DEVICE)) return fail(SA_EARG, "sa_get_solution: bad arguments");
+  if (!p || !x || (mem != SA_MEM_HOST && mem != SA_MEM_DEVICE)) return sa_fail(SA_EARG, "sa_get_solution: bad arguments");
   HIPCHK(hipMemcpyAsync(x, p->hp.x, (size_t)p->n * 8, kind_from(mem, false), p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return SA_OK;
@@ -689,15 +702,15 @@ extern "C" int sa_get_solution(sa_problem* p, double* x, int32_t mem) {
 // copy an input into a device scratch vector when it lives on the host
 static int stage_in(sa_problem* p, const double* src, int32_t mem, double* scratch, const double** dev) {
   if (mem == SA_MEM_DEVICE) { *dev = src; return SA_OK; }
-  if (mem != SA_MEM_HOST) return fail(SA_EARG, "bad mem");
+  if (mem != SA_MEM_HOST) return sa_fail(SA_EARG, "bad mem");
   HIPCHK(hipMemcpyAsync(scratch, src, (size_t)p->n * 8, hipMemcpyHostToDevice, p->stream));
   *dev = scratch;
   return SA_OK;
 }
 
 extern "C" int sa_apply_operator(sa_problem* p, const double* x, double* y, int32_t mem) {
-  if (!p || !x || !y) return fail(SA_EARG, "sa_apply_operator: null argument");
-  if (!p->eta_p || !p->eta_c) return fail(SA_EARG, "sa_apply_operator: set the surfaces first");
+  if (!p || !x || !y) return sa_fail(SA_EARG, "sa_apply_operator: null argument");
+  if (!p->eta_p || !p->eta_c) return sa_fail(SA_EARG, "sa_apply_operator: set the surfaces first");
   const double* xd;
   int rc = stage_in(p, x, mem, p->hp.xc, &xd);
   if (rc) return rc;
@@ -710,11 +723,11 @@ extern "C" int sa_apply_operator(sa_problem* p, const double* x, double* y, int3
   HIPCHK(hipGetLastError());
   if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 8, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
-  return check_flags(p);
+  return sa_check_flags(p);
 }
 
 extern "C" int sa_apply_precond(sa_problem* p, const double* x, double* y, int32_t mem) {
-  if (!p || !x || !y) return fail(SA_EARG, "sa_apply_precond: null argument");
+  if (!p || !x || !y) return sa_fail(SA_EARG, "sa_apply_precond: null argument");
   const double* xd;
   int rc = stage_in(p, x, mem, p->hp.xc, &xd);
   if (rc) return rc;
@@ -723,16 +736,16 @@ extern "C" int sa_apply_precond(sa_problem* p, const double* x, double* y, int32
   HIPCHK(launch_cluster(p, (const void*)sa_precond_kernel, args, p->lds_pc));
   if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 8, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
-  return check_flags(p);
+  return sa_check_flags(p);
 }
 
 // FP32 inner kernels of the refinement path, for tests: host arrays are staged through the
 // problem's FP32 work vectors.
 static int fp32_io(sa_problem* p, const float* x, float* y, int32_t mem, const char* who, const float** xd, float** yd) {
-  if (!p || !x || !y) return fail(SA_EARG, "%s: null argument", who);
-  if (p->opt.precision != SA_FP32_IR) return fail(SA_EARG, "%s: problem created without SA_FP32_IR", who);
+  if (!p || !x || !y) return sa_fail(SA_EARG, "%s: null argument", who);
+  if (p->opt.precision != SA_FP32_IR) return sa_fail(SA_EARG, "%s: problem created without SA_FP32_IR", who);
   if (mem == SA_MEM_DEVICE) { *xd = x; *yd = y; return SA_OK; }
-  if (mem != SA_MEM_HOST) return fail(SA_EARG, "%s: bad mem", who);
+  if (mem != SA_MEM_HOST) return sa_fail(SA_EARG, "%s: bad mem", who);
   HIPCHK(hipMemcpyAsync(p->hp.r32, x, (size_t)p->n * 4, hipMemcpyHostToDevice, p->stream));
   *xd = p->hp.r32;
   *yd = p->hp.t32;
@@ -744,7 +757,7 @@ extern "C" int sa_apply_operator_f32(sa_problem* p, const float* x, float* y, in
   float* yd;
   int rc = fp32_io(p, x, y, mem, "sa_apply_operator_f32", &xd, &yd);
   if (rc) return rc;
-  if (!p->eta_p || !p->eta_c) return fail(SA_EARG, "sa_apply_operator_f32: set the surfaces first");
+  if (!p->eta_p || !p->eta_c) return sa_fail(SA_EARG, "sa_apply_operator_f32: set the surfaces first");
   const int gb = (p->ncol + BLOCK - 1) / BLOCK;
   hipLaunchKernelGGL(sa_geometry_kernel, dim3(gb), dim3(BLOCK), 0, p->stream, p->dp, p->eta_p, p->eta_c);
   HIPCHK(hipGetLastError());
@@ -753,7 +766,7 @@ extern "C" int sa_apply_operator_f32(sa_problem* p, const float* x, float* y, in
   HIPCHK(hipGetLastError());
   if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 4, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
-  return check_flags(p);
+  return sa_check_flags(p);
 }
 
 extern "C" int sa_apply_precond_f32(sa_problem* p, const float* x, float* y, int32_t mem) {
@@ -765,7 +778,7 @@ extern "C" int sa_apply_precond_f32(sa_problem* p, const float* x, float* y, int
   HIPCHK(launch_cluster(p, (const void*)sa_precond32_kernel, args, p->lds_pc));
   if (mem == SA_MEM_HOST) HIPCHK(hipMemcpyAsync(y, yd, (size_t)p->n * 4, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
-  return check_flags(p);
+  return sa_check_flags(p);
 }
 
 // store a solution that is still waiting for the next solve's fused push
@@ -784,8 +797,8 @@ static int flush_push(sa_problem* p) {
 }
 
 extern "C" int sa_get_sketch(sa_problem* p, double* y, int32_t mem) {
-  if (!p || !y || (mem != SA_MEM_HOST && mem != SA_MEM_DEVICE)) return fail(SA_EARG, "sa_get_sketch: bad arguments");
-  if (p->opt.guess != SA_GUESS_EWMA) return fail(SA_EARG, "sa_get_sketch: no sketch in this guess mode");
+  if (!p || !y || (mem != SA_MEM_HOST && mem != SA_MEM_DEVICE)) return sa_fail(SA_EARG, "sa_get_sketch: bad arguments");
+  if (p->opt.guess != SA_GUESS_EWMA) return sa_fail(SA_EARG, "sa_get_sketch: no sketch in this guess mode");
   int rc = flush_push(p);
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(y, p->hp.Y[p->ycur], (size_t)p->n * p->opt.k * 8, kind_from(mem, false), p->stream));
@@ -794,8 +807,8 @@ extern "C" int sa_get_sketch(sa_problem* p, double* y, int32_t mem) {
 }
 
 extern "C" int sa_get_phase_times(sa_problem* p, double* out, int32_t n) {
-  if (!p || !out || n < 1 || n > NPROF) return fail(SA_EARG, "sa_get_phase_times: bad arguments");
-  if (!p->prof) return fail(SA_EARG, "sa_get_phase_times: problem created without profile = 1");
+  if (!p || !out || n < 1 || n > NPROF) return sa_fail(SA_EARG, "sa_get_phase_times: bad arguments");
+  if (!p->prof) return sa_fail(SA_EARG, "sa_get_phase_times: problem created without profile = 1");
   unsigned long long t[NPROF];
   HIPCHK(hipMemcpyAsync(t, p->prof, sizeof t, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));

@@ -1,4 +1,5 @@
-// gfx950 kernels of the subspace-accelerated sigma-transformed Poisson solver.
+// Device code of the subspace-accelerated sigma-transformed Poisson solver for gfx950, shared
+// by the kernel translation units (solve64.hip: FP64 path, solve32.hip: FP32 refinement path).
 //
 // One solve (guess + restarted GMRES) is one persistent launch: a cluster of G workgroups
 // owns the problem, walks through the phases below in order, and meets at a cluster barrier
@@ -21,11 +22,15 @@
 
 #include <type_traits>
 
+#pragma once
 #include "internal.h"
 
 namespace sa {
 
 #define DEV __device__ __forceinline__
+
+// dynamic LDS of every kernel (size given at launch)
+extern __shared__ double dyn_lds[];
 
 constexpr long SPIN_LIMIT = 1L << 25;
 constexpr int TWM = TX + 3;   // widest operator tile (a last wall tile absorbs up to 3 columns)
@@ -1384,7 +1389,6 @@ DEV void back_substitute(const Smem& S, int m, int jj) {
 
 // Geometry of both stages, the initial guess and r0 = b - A x0 (shared by both precisions).
 // Fills info (rank, relres0) and returns whether the solve is already finished.
-template <bool SKETCH>
 DEV bool solve_start(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, PhaseClock& clk,
                      sa_solve_info& info, double& nb, double& rn) {
   const int tid = threadIdx.x;
@@ -1396,7 +1400,7 @@ DEV bool solve_start(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S
   const double* Yo = P.Y[a.ycur];
   double* Yn = P.Y[a.ycur ^ 1];
   int rank = 0;
-  if (SKETCH && a.sketch_guess) {
+  if (a.sketch_guess) {
     phase_block_gram(P, cl, a, Yo, Yn, S.big, S.red);
     const int nv = P.k * (P.k + 1) / 2 + P.k;
     cluster_sum_dd(cl, S.red, nv);
@@ -1406,7 +1410,7 @@ DEV bool solve_start(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S
     clk.tick(PH_SMALL);
     phase_sketch_combine(P, cl, a.push ? Yn : Yo, S.z);
   } else {
-    if (SKETCH && a.push) phase_push(P, cl, a, Yo, Yn);
+    if (a.push) phase_push(P, cl, a, Yo, Yn);
     if (!a.prev_guess) {
       csync(cl);
       for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) P.x[e] = 0.0;
@@ -1459,23 +1463,14 @@ DEV void givens_step(const Smem& S, int m, int j, double hn) {
   __syncthreads();
 }
 
-// One Arnoldi step j in precision T: w = M^-1 A (vs_j V_j), CGS2 against V_0..V_j, Givens.
-// Returns ||w|| after orthogonalisation; w0 receives ||w|| before it.
+// CGS2 of the new Arnoldi vector w = V_{j+1} against V_0..V_j (h1 = V^T w with ||w||, w -= V h1,
+// h2 = V^T w, w -= V h2), then the Givens rotation of Hessenberg column j. Returns ||w|| after
+// orthogonalisation; w0 receives ||w|| before it.
 template <class T>
-DEV double arnoldi_step(const Problem& P, Cl& cl, const Smem& S, PhaseClock& clk, T* V, T* t, int j,
-                        double& w0) {
+DEV double cgs2_givens(const Problem& P, Cl& cl, const Smem& S, PhaseClock& clk, T* V, int j, double& w0) {
   const size_t n = P.n;
   const int m = P.m, tid = threadIdx.x;
   T* wv = V + (size_t)(j + 1) * n;
-  T* lds = (T*)S.big;
-  clk.tick(PH_OTHER);
-  if constexpr (std::is_same_v<T, double>) phase_operator(P, cl, V + (size_t)j * n, S.vs[j], t, nullptr, S.big, S.red, 0);
-  else phase_operator_s<T>(P, cl, V + (size_t)j * n, T(S.vs[j]), t, lds);
-  csync(cl);
-  clk.tick(PH_OPER);
-  precond<T>(P, cl, t, wv, lds, &clk);
-  clk.tick(PH_PREC);
-  // CGS2: h1 = V^T w (and ||w||), w -= V h1, h2 = V^T w, w -= V h2
   phase_dots<T>(P, cl, V, S.vs, j + 1, wv, true, S.wsum, S.red);
   cluster_sum(cl, S.red, j + 2);
   w0 = sqrt(S.red[j + 1]);
@@ -1506,67 +1501,89 @@ DEV double cluster_norm(const Problem& P, Cl& cl, const Smem& S, const T* v) {
   return sqrt(S.red[0]);
 }
 
+// Stages of a Krylov solve. Every preconditioner application of a solve goes through one call
+// site (the V-cycle is by far the largest piece of code): the stage says what it is applied to.
+enum { ST_TRIGGER = 0, ST_START = 1, ST_STEP = 2 };
+
 // FP64 restarted GMRES from P.x with residual P.r (left-preconditioned, CGS2, decisions on the
-// true residual).
+// true residual): the check trigger starts at rtol ||M^-1 b||; a candidate x + V y is checked
+// on b - A x when the Arnoldi estimate reaches it, the trigger is lowered after a failed check;
+// lucky breakdown restarts from the checked candidate.
 DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, PhaseClock& clk,
                  sa_solve_info& info, double nb, double rn) {
-  const int m = P.m;
+  const int m = P.m, tid = threadIdx.x;
+  const size_t n = P.n;
   const double rtol = a.rtol;
-  bool done = false;
   double* x = P.x;
   double* xc = P.xc;
   double* r = P.r;
   double* rc = P.rc;
-  // trigger of the true-residual check: rtol ||M^-1 b||
-  precond<double>(P, cl, a.b, P.t, S.big, &clk);
-  clk.tick(PH_PREC);
-  double trigger = rtol * cluster_norm(P, cl, S, (const double*)P.t);
-  while (!done && !aborted(cl)) {
-    double* V = P.V;
+  double* V = P.V;
+  double trigger = 0.0;
+  int stage = ST_TRIGGER, j = 0;
+  while (!aborted(cl)) {
+    const double* src = a.b;
+    double* dst = P.t;
     clk.tick(PH_OTHER);
-    precond<double>(P, cl, r, V, S.big, &clk);
-    clk.tick(PH_PREC);
-    const double beta = cluster_norm(P, cl, S, (const double*)V);
-    if (threadIdx.x == 0) {
-      S.vs[0] = 1.0 / beta;
-      S.g[0] = beta;
-    }
-    __syncthreads();
-    bool restart_now = false;
-    for (int j = 0; j < m && !aborted(cl); ++j) {
+    if (stage == ST_START) {
+      src = r;
+      dst = V;
+    } else if (stage == ST_STEP) {
       info.iters += 1;
-      double w0;
-      const double hn = arnoldi_step<double>(P, cl, S, clk, V, P.t, j, w0);
-      const bool breakdown = hn <= 1e-14 * w0;
-      if (breakdown || fabs(S.g[j + 1]) <= trigger) {
-        back_substitute(S, m, j + 1);
-        phase_combine<double>(P, cl, V, S.vs, S.y, j + 1, x, xc);
-        csync(cl);
-        clk.tick(PH_OTHER);
-        phase_operator(P, cl, xc, 1.0, rc, a.b, S.big, S.red, 0);
-        cluster_sum(cl, S.red, 2);
-        clk.tick(PH_OPER);
-        const double rcn = sqrt(S.red[0]);
-        info.checks += 1;
-        if (rcn <= rtol * nb) {
-          double* t = x; x = xc; xc = t;
-          info.relres = rcn / nb;
-          done = true;
-          break;
-        }
-        if (breakdown || !isfinite(rcn)) {
-          double* t = x; x = xc; xc = t;
-          t = r; r = rc; rc = t;
-          rn = rcn;
-          restart_now = true;
-          if (!isfinite(rcn)) { atomicOr(P.flags + FLAG_NONFINITE, 1); done = true; }
-          break;
-        }
+      phase_operator(P, cl, V + (size_t)j * n, S.vs[j], P.t, nullptr, S.big, S.red, 0);
+      csync(cl);
+      clk.tick(PH_OPER);
+      src = P.t;
+      dst = V + (size_t)(j + 1) * n;
+    }
+    precond<double>(P, cl, src, dst, S.big, &clk);
+    clk.tick(PH_PREC);
+    if (stage == ST_TRIGGER) {
+      trigger = rtol * cluster_norm(P, cl, S, (const double*)P.t);
+      stage = ST_START;
+      continue;
+    }
+    if (stage == ST_START) {
+      const double beta = cluster_norm(P, cl, S, (const double*)V);
+      if (tid == 0) {
+        S.vs[0] = 1.0 / beta;
+        S.g[0] = beta;
+      }
+      __syncthreads();
+      j = 0;
+      stage = ST_STEP;
+      continue;
+    }
+    double w0;
+    const double hn = cgs2_givens<double>(P, cl, S, clk, V, j, w0);
+    const bool breakdown = hn <= 1e-14 * w0;
+    bool end_cycle = false;
+    if (breakdown || fabs(S.g[j + 1]) <= trigger) {
+      back_substitute(S, m, j + 1);
+      phase_combine<double>(P, cl, V, S.vs, S.y, j + 1, x, xc);
+      csync(cl);
+      clk.tick(PH_OTHER);
+      phase_operator(P, cl, xc, 1.0, rc, a.b, S.big, S.red, 0);
+      cluster_sum(cl, S.red, 2);
+      clk.tick(PH_OPER);
+      const double rcn = sqrt(S.red[0]);
+      info.checks += 1;
+      if (rcn <= rtol * nb) {
+        double* t = x; x = xc; xc = t;
+        info.relres = rcn / nb;
+        break;
+      }
+      if (breakdown || !isfinite(rcn)) {
+        double* t = x; x = xc; xc = t;
+        t = r; r = rc; rc = t;
+        rn = rcn;
+        if (!isfinite(rcn)) { atomicOr(P.flags + FLAG_NONFINITE, 1); break; }
+        end_cycle = true;
+      } else {
         trigger = fabs(S.g[j + 1]) * rtol * nb / rcn;
       }
     }
-    if (done) break;
-    if (!restart_now) {
+    if (!end_cycle && j + 1 == m) {  // cycle complete: x += V y, true residual
       back_substitute(S, m, m);
       phase_combine<double>(P, cl, V, S.vs, S.y, m, x, x);
       csync(cl);
@@ -1578,13 +1595,19 @@ DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, Ph
       info.relres = rn / nb;
       if (rn <= rtol * nb) break;
       if (!isfinite(rn)) { atomicOr(P.flags + FLAG_NONFINITE, 1); break; }
+      end_cycle = true;
     }
-    info.relres = rn / nb;
-    info.restarts += 1;
-    if (info.restarts > P.max_restarts) {
-      info.status = SA_NOCONV;
-      break;
+    if (end_cycle) {  // restart from (x, r)
+      info.relres = rn / nb;
+      info.restarts += 1;
+      if (info.restarts > P.max_restarts) {
+        info.status = SA_NOCONV;
+        break;
+      }
+      stage = ST_START;
+      continue;
     }
+    j += 1;
   }
   // the solution must end in P.x (the next solve's previous solution)
   if (x != P.x) {
@@ -1596,12 +1619,13 @@ DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, Ph
 // Mixed precision: FP64 iterative refinement around FP32 GMRES cycles on A d = r / ||r||.
 // Operator, V-cycle and basis are FP32; Gram-Schmidt sums, Hessenberg and Givens are FP64.
 // Candidates x + ||r|| V y are checked on the FP64 residual b - A x with the trigger rule of
-// the FP64 path (first at rtol ||M^-1 b||, lowered after a failed check); when the cycle
-// reaches FP32 resolution (estimate down by rtol_inner, or h_{j+1,j} <= 1e-7 ||w||) the
-// checked candidate becomes the new x and the next correction starts from its residual.
+// the FP64 path (first at rtol ||b|| ||M^-1 fl32(b / ||b||)||, lowered after a failed check);
+// when the cycle reaches FP32 resolution (estimate down by rtol_inner, or h_{j+1,j} <=
+// 1e-7 ||w||) the checked candidate becomes the new x and the next correction starts from its
+// residual; a complete cycle adds its correction and starts the next one.
 DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, PhaseClock& clk,
                   sa_solve_info& info, double nb, double rn) {
-  const int m = P.m;
+  const int m = P.m, tid = threadIdx.x;
   const size_t n = P.n;
   const double rtol = a.rtol;
   float* V = P.V32;
@@ -1611,74 +1635,86 @@ DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, P
   double* xc = P.xc;
   double* r = P.r;
   double* rc = P.rc;
-  // trigger: rtol ||b|| ||M^-1 fl32(b / ||b||)||
-  {
-    const double sb = 1.0 / nb;
-    for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK)
-      r32[e] = float(a.b[e] * sb);
-    csync(cl);
-    precond<float>(P, cl, r32, P.t32, lds, &clk);
-    clk.tick(PH_PREC);
-  }
-  double trigger = rtol * nb * cluster_norm(P, cl, S, (const float*)P.t32);
-  bool converged = false;
+  double trigger = 0.0, beta = 0.0;
+  int stage = ST_TRIGGER, j = 0;
   while (!aborted(cl)) {
-    if (info.refinements >= P.max_refine) {
-      info.status = SA_NOCONV;
-      break;
-    }
-    info.refinements += 1;
-    const double sc = 1.0 / rn;
-    for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK)
-      r32[e] = float(r[e] * sc);
-    csync(cl);
+    const float* src = r32;
+    float* dst = P.t32;
     clk.tick(PH_OTHER);
-    precond<float>(P, cl, r32, V, lds, &clk);
-    clk.tick(PH_PREC);
-    const double beta = cluster_norm(P, cl, S, (const float*)V);
-    if (threadIdx.x == 0) {
-      S.vs[0] = 1.0 / beta;
-      S.g[0] = beta;
-    }
-    __syncthreads();
-    bool restarted = false;
-    for (int j = 0; j < m && !aborted(cl); ++j) {
+    if (stage != ST_STEP) {  // fl32(b / ||b||) or fl32(r / ||r||)
+      if (stage == ST_START) {
+        if (info.refinements >= P.max_refine) {
+          info.status = SA_NOCONV;
+          break;
+        }
+        info.refinements += 1;
+        dst = V;
+      }
+      const double* v = stage == ST_TRIGGER ? a.b : r;
+      const double sc = 1.0 / (stage == ST_TRIGGER ? nb : rn);
+      for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) r32[e] = float(v[e] * sc);
+      csync(cl);
+    } else {
       info.iters += 1;
-      double w0;
-      const double hn = arnoldi_step<float>(P, cl, S, clk, V, P.t32, j, w0);
-      const double est = rn * fabs(S.g[j + 1]);
-      const bool floor = hn <= 1e-7 * w0 || fabs(S.g[j + 1]) <= P.rtol_inner * beta;
-      if (floor || est <= trigger) {
-        back_substitute(S, m, j + 1);
-        if (threadIdx.x <= j) S.y[threadIdx.x] *= rn;
-        __syncthreads();
-        phase_combine<float>(P, cl, V, S.vs, S.y, j + 1, x, xc);
-        csync(cl);
-        clk.tick(PH_OTHER);
-        phase_operator(P, cl, xc, 1.0, rc, a.b, S.big, S.red, 0);
-        cluster_sum(cl, S.red, 2);
-        clk.tick(PH_OPER);
-        const double rcn = sqrt(S.red[0]);
-        info.checks += 1;
-        if (!isfinite(rcn)) {
-          atomicOr(P.flags + FLAG_NONFINITE, 1);
-          converged = true;  // leave with the flag set
-          break;
-        }
-        if (rcn <= rtol * nb || floor) {
-          double* t = x; x = xc; xc = t;
-          t = r; r = rc; rc = t;
-          rn = rcn;
-          converged = rcn <= rtol * nb;
-          restarted = !converged;
-          break;
-        }
+      phase_operator_s<float>(P, cl, V + (size_t)j * n, float(S.vs[j]), P.t32, lds);
+      csync(cl);
+      clk.tick(PH_OPER);
+      src = P.t32;
+      dst = V + (size_t)(j + 1) * n;
+    }
+    precond<float>(P, cl, src, dst, lds, &clk);
+    clk.tick(PH_PREC);
+    if (stage == ST_TRIGGER) {
+      trigger = rtol * nb * cluster_norm(P, cl, S, (const float*)P.t32);
+      stage = ST_START;
+      continue;
+    }
+    if (stage == ST_START) {
+      beta = cluster_norm(P, cl, S, (const float*)V);
+      if (tid == 0) {
+        S.vs[0] = 1.0 / beta;
+        S.g[0] = beta;
+      }
+      __syncthreads();
+      j = 0;
+      stage = ST_STEP;
+      continue;
+    }
+    double w0;
+    const double hn = cgs2_givens<float>(P, cl, S, clk, V, j, w0);
+    const double est = rn * fabs(S.g[j + 1]);
+    const bool floor = hn <= 1e-7 * w0 || fabs(S.g[j + 1]) <= P.rtol_inner * beta;
+    bool next = false;
+    if (floor || est <= trigger) {
+      back_substitute(S, m, j + 1);
+      if (tid <= j) S.y[tid] *= rn;
+      __syncthreads();
+      phase_combine<float>(P, cl, V, S.vs, S.y, j + 1, x, xc);
+      csync(cl);
+      clk.tick(PH_OTHER);
+      phase_operator(P, cl, xc, 1.0, rc, a.b, S.big, S.red, 0);
+      cluster_sum(cl, S.red, 2);
+      clk.tick(PH_OPER);
+      const double rcn = sqrt(S.red[0]);
+      info.checks += 1;
+      if (!isfinite(rcn)) {
+        atomicOr(P.flags + FLAG_NONFINITE, 1);
+        break;
+      }
+      if (rcn <= rtol * nb || floor) {
+        double* t = x; x = xc; xc = t;
+        t = r; r = rc; rc = t;
+        rn = rcn;
+        info.relres = rn / nb;
+        if (rcn <= rtol * nb) break;
+        next = true;
+      } else {
         trigger = est * rtol * nb / rcn;
       }
     }
-    if (!converged && !restarted) {
+    if (!next && j + 1 == m) {  // cycle complete: x += ||r|| V y, true residual
       back_substitute(S, m, m);
-      if (threadIdx.x < m) S.y[threadIdx.x] *= rn;
+      if (tid < m) S.y[tid] *= rn;
       __syncthreads();
       phase_combine<float>(P, cl, V, S.vs, S.y, m, x, x);
       csync(cl);
@@ -1687,11 +1723,16 @@ DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, P
       cluster_sum(cl, S.red, 2);
       clk.tick(PH_OPER);
       rn = sqrt(S.red[0]);
-      if (!isfinite(rn)) { atomicOr(P.flags + FLAG_NONFINITE, 1); converged = true; }
-      else converged = rn <= rtol * nb;
+      info.relres = rn / nb;
+      if (!isfinite(rn)) { atomicOr(P.flags + FLAG_NONFINITE, 1); break; }
+      if (rn <= rtol * nb) break;
+      next = true;
     }
-    info.relres = rn / nb;
-    if (converged) break;
+    if (next) {
+      stage = ST_START;
+      continue;
+    }
+    j += 1;
   }
   if (x != P.x) {
     csync(cl);
@@ -1699,93 +1740,60 @@ DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, P
   }
 }
 
-// One solve of the problem by the cluster workgroup `rank`: guess, then FP64 GMRES or FP32
-// refinement, then the report into the log.
-template <bool SKETCH>
+// One solve of the problem by the cluster workgroup `rank`: guess, then FP64 GMRES (PREC =
+// SA_FP64) or FP32 refinement (PREC = SA_FP32_IR), then the report into the log.
+template <int PREC>
 DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a, int rank) {
   const Problem& P = *PP;
-  extern __shared__ double smem[];
+  double* smem = dyn_lds;
   Smem S = carve(smem, P.m);
   Cl cl{rank, P.G, P.bar, P.flags, P.partials, 0};
   PhaseClock clk;
   clk.begin(a.prof != nullptr, rank, a.prof);
   sa_solve_info info;
   double nb = 0.0, rn = 0.0;
-  const bool done = solve_start<SKETCH>(P, cl, a, S, clk, info, nb, rn);
+  const bool done = solve_start(P, cl, a, S, clk, info, nb, rn);
   if (!done) {
-    if (P.precision == SA_FP32_IR) refine32(P, cl, a, S, clk, info, nb, rn);
+    if constexpr (PREC == SA_FP32_IR) refine32(P, cl, a, S, clk, info, nb, rn);
     else gmres64(P, cl, a, S, clk, info, nb, rn);
   }
   clk.tick(PH_OTHER);
   if (cl.rank == 0 && threadIdx.x == 0) {
     if (aborted(cl)) info.status = SA_EDEVICE;
     P.log[a.log_slot] = info;
+    if (a.out) {  // batched solve: fold and clear the problem's error flags
+      if (info.status == SA_OK || info.status == SA_NOCONV) {
+        if (atomicExch(P.flags + FLAG_GEOM, 0)) info.status = SA_EGEOM;
+        if (atomicExch(P.flags + FLAG_NONFINITE, 0) && info.status != SA_EGEOM) info.status = SA_ENONFINITE;
+      }
+      *a.out = info;
+    }
   }
   clk.flush(a.prof);
 }
 
-// one solve with the EWMA-sketch guess (push of the previous solution, Alg. 2 guess)
-extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const Problem* __restrict__ PP, SolveArgs a) {
-  solve_body<true>(PP, a, (int)blockIdx.x);
-}
-
-// one solve from a zero or previous-solution guess (no sketch)
-extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_plain_kernel(const Problem* __restrict__ PP, SolveArgs a) {
-  solve_body<false>(PP, a, (int)blockIdx.x);
-}
-
-// ------------------------------------------------------------------------------------------
-// standalone entry kernels (operator and preconditioner applications, sketch push)
-
-extern "C" __global__ void __launch_bounds__(BLOCK) sa_geometry_kernel(const Problem* __restrict__ PP,
-                                                                       const double* eta_p, const double* eta_c) {
-  const Problem& P = *PP;
-  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
-  phase_geometry(P, cl, eta_p, eta_c);
-}
-
-extern "C" __global__ void __launch_bounds__(BLOCK) sa_operator_kernel(const Problem* __restrict__ PP,
-                                                                       const double* x, double* y) {
-  const Problem& P = *PP;
-  extern __shared__ double smem[];
-  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
-  phase_operator(P, cl, x, 1.0, y, nullptr, smem, smem, 0);
-}
-
-// y = A x with FP32 input, output and arithmetic (the inner operator of the refinement path)
-extern "C" __global__ void __launch_bounds__(BLOCK) sa_operator32_kernel(const Problem* __restrict__ PP,
-                                                                         const float* x, float* y) {
-  const Problem& P = *PP;
-  extern __shared__ double smem[];
-  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
-  phase_operator_s<float>(P, cl, x, 1.0f, y, (float*)smem);
-}
-
-extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond_kernel(const Problem* __restrict__ PP,
-                                                                      const double* v, double* z,
-                                                                      unsigned long long* prof) {
-  const Problem& P = *PP;
-  extern __shared__ double smem[];
-  Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
-  PhaseClock clk;
-  clk.begin(prof != nullptr, cl.rank, prof);
-  precond<double>(P, cl, v, z, smem, &clk);
-  clk.flush(prof);
-}
-
-// z = M^-1 v in FP32 (the inner preconditioner of the refinement path)
-extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond32_kernel(const Problem* __restrict__ PP,
-                                                                        const float* v, float* z) {
-  const Problem& P = *PP;
-  extern __shared__ double smem[];
-  Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
-  precond<float>(P, cl, v, z, (float*)smem, nullptr);
-}
-
-extern "C" __global__ void __launch_bounds__(BLOCK) sa_push_kernel(const Problem* __restrict__ PP, SolveArgs a) {
-  const Problem& P = *PP;
-  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
-  phase_push(P, cl, a, P.Y[a.ycur], P.Y[a.ycur ^ 1]);
+// Entry of the solve kernels. With nitems = 0 the grid solves the single problem of `one`
+// (sa_solve); otherwise its workgroups are split into consecutive clusters, item i owning
+// [first_i, first_i + G_i), and every cluster solves its own problem (the server's batched
+// launch). Each problem has its own barrier words, partial sums and log, so clusters never
+// interact. One entry serves every guess mode: without a sketch no push or sketch guess is
+// requested.
+template <int PREC>
+DEV void solve_entry(const BatchItem* __restrict__ items, int nitems, const BatchItem& one) {
+  if (nitems <= 0) {
+    solve_body<PREC>(one.P, one.a, (int)blockIdx.x);
+    return;
+  }
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchItem& it = items[lo];
+  const int rank = (int)blockIdx.x - it.first;
+  if (rank < 0 || rank >= it.P->G) return;  // padding workgroups of the launch
+  solve_body<PREC>(it.P, it.a, rank);
 }
 
 }  // namespace sa

@@ -92,6 +92,16 @@ struct SolveArgs {
   double rtol;
   double om[KMAX];   // sketch draws of the stored solution
   unsigned long long* prof;  // NPHASE accumulated wall-clock ticks, or nullptr
+  sa_solve_info* out;        // a second copy of the report with the problem's flags folded
+                             // into its status (batched solves), or nullptr
+};
+
+// One solve of a batched launch: the workgroups [first, first + P->G) of the grid run it.
+struct BatchItem {
+  const Problem* P;
+  int first;
+  int sketch;   // the sketch variant of the solve (EWMA guess mode)
+  SolveArgs a;
 };
 
 // phase-time categories of the solve kernel (sa_get_phase_times)

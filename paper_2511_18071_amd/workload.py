@@ -259,13 +259,17 @@ def _bar(name, nx, nz, seed, nsys, restart, k, r, scale=1.0, a0=0.01, dtau=0.025
 def serving_mix(nsims: int = 256, seed: int = 5, nsys: int = 50, nx_range=(257, 8193),
                 nz_choices=(9, 17, 33)) -> list[Workload]:
     """Independent simulations of different sizes for the continuous-batching server:
-    nx uniform in nx_range rounded to 64 q + 1, nz from nz_choices, flat (periodic) or
-    submerged-bar (walls, bar scaled to the domain) bathymetry, H/L uniform in [0.01, 0.08],
-    history rank uniform in 8..16, forgetting factor 0.9."""
+    nx uniform in nx_range, moved to the nearest 64 q + 1 with q = 2^a b, b in {1, 3, 5, 7}
+    (grids that halve down to a few columns, so the still-water V-cycle reaches a small
+    coarsest grid), nz from nz_choices, flat (periodic) or submerged-bar (walls, bar scaled to
+    the domain) bathymetry, H/L uniform in [0.01, 0.08], history rank uniform in 8..16,
+    forgetting factor 0.9."""
     rng = np.random.default_rng(seed)
+    qs = sorted({(2 ** a) * b for a in range(12) for b in (1, 3, 5, 7)})
     sims = []
     for i in range(nsims):
-        q = int(rng.integers((nx_range[0] - 1) // 64, (nx_range[1] - 1) // 64 + 1))
+        nx_u = float(rng.uniform(nx_range[0], nx_range[1]))
+        q = min(qs, key=lambda v: (abs(64 * v + 1 - nx_u), v))
         nx = 64 * q + 1
         nz = int(rng.choice(nz_choices))
         k = int(rng.integers(8, 17))

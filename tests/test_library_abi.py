@@ -78,3 +78,25 @@ def test_refinement_option_errors_need_no_gpu(binding):
         assert e.value.code == -1, bad
     with pytest.raises(binding.SawaveError):
         binding.Problem(65, 9, "periodic", 1.0, np.ones(64), precision=7)
+
+
+def test_footprint_needs_no_gpu(binding):
+    from paper_2511_18071_amd import workload as W
+    w = W.get("bar_513x17")
+    f64 = binding.footprint(w)
+    f32 = binding.footprint(w, precision="fp32_ir")
+    cold = binding.footprint(w, guess="cold")
+    n = w.n
+    # at least the Krylov basis (m + 1 vectors) and the two sketch buffers
+    assert f64 >= 8 * n * (w.restart + 1 + 2 * w.k)
+    assert f32 >= f64 + 4 * n * (w.restart + 1)   # plus the FP32 basis
+    assert cold <= f64 - 8 * n * 2 * w.k + 4096   # no sketch
+    with pytest.raises(binding.SawaveError):
+        binding.footprint(w, k=99)
+
+
+def test_server_option_errors_need_no_gpu(binding):
+    for bad in (dict(max_inflight=0), dict(max_inflight=9), dict(max_batch=-1), dict(unknowns_per_workgroup=0)):
+        with pytest.raises(binding.SawaveError) as e:
+            binding.Server(**bad)
+        assert e.value.code == -1, bad
