@@ -190,9 +190,13 @@ def run_serving(args):
     sims = W.serving_mix(args.serve_sims, seed=5, nsys=args.serve_systems)
     nsys = args.serve_systems
     t_setup = time.perf_counter()
+    say = lambda *a: print(*a, file=sys.stderr, flush=True)  # progress (the JSON line goes to stdout)
+    say(f"serving: {len(sims)} simulations x {nsys} systems, {sum(w.n for w in sims)} unknowns")
     inputs = []
     with B.Server(stream=stream) as gen:
-        for w in sims:
+        for i, w in enumerate(sims):
+            if i % 32 == 0:
+                say(f"  inputs of simulation {i} ({time.perf_counter() - t_setup:.0f} s)")
             sid = gen.open(w, precond="none", guess="cold", cluster=1)
             eta = torch.empty((nsys, 2, w.nphys), dtype=torch.float64, device=dev)
             bs = torch.empty((nsys, w.n), dtype=torch.float64, device=dev)
@@ -209,7 +213,8 @@ def run_serving(args):
     # request j: simulation j mod nsims, its (j // nsims)-th system (round robin, FIFO per sim)
     order = [(j % len(sims), j // len(sims)) for j in range(nreq)]
 
-    def serve(arrivals):
+    def serve(arrivals, label):
+        say(f"  {label}: opening {len(sims)} simulations ({time.perf_counter() - t_setup:.0f} s)")
         srv = B.Server(stream=stream)
         ids = [srv.open(w, precision="fp32_ir") for w in sims]
         if any(i is None for i in ids):
@@ -217,8 +222,13 @@ def run_serving(args):
         torch.cuda.synchronize()
         lat, infos = [], []
         k = 0
+        say(f"  {label}: serving {nreq} requests")
         t0 = time.perf_counter()
+        t_say = t0
         while k < nreq or srv.outstanding > 0:
+            if time.perf_counter() - t_say > 10.0:
+                t_say = time.perf_counter()
+                say(f"    {len(lat)} of {nreq} done, {t_say - t0:.0f} s")
             now = time.perf_counter() - t0
             while k < nreq and arrivals[k] <= now:
                 i, s = order[k]
@@ -234,10 +244,11 @@ def run_serving(args):
         srv.close()
         return dict(wall=wall, lat=np.array(lat), infos=infos, bytes=bytes_used)
 
-    sat = serve(np.zeros(nreq))
+    sat = serve(np.zeros(nreq), "saturation")
     rng = np.random.default_rng(5)
     arr = np.cumsum(rng.exponential(1.0 / args.serve_rate, nreq))
-    ol = serve(arr)
+    ol = serve(arr, "open loop")
+    say(f"  baseline: one-at-a-time FP64 cold start ({time.perf_counter() - t_setup:.0f} s)")
     # one-at-a-time FP64 cold start (sa_solve) on every k-th simulation
     base_lat, base_its, base_bad = [], [], 0
     for i in range(0, len(sims), args.serve_baseline_stride):

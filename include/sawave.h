@@ -96,7 +96,7 @@ typedef struct {
   double rtol_inner;    /* FP32 resolution: a cycle whose Arnoldi estimate has fallen to    */
                         /* this fraction of its start hands its checked candidate to the    */
                         /* next correction (SA_FP32_IR), default 1e-5                       */
-  int32_t max_refine;   /* refinement steps cap (SA_FP32_IR), default 20; SA_NOCONV after  */
+  int32_t max_refine;   /* FP32 cycles cap (SA_FP32_IR), default 200; SA_NOCONV after      */
   int32_t cluster;      /* workgroups cooperating on one solve; 0 = chosen from the size  */
   int32_t profile;      /* 1: accumulate per-phase device time (sa_get_phase_times), 0      */
   int32_t coarse_max;   /* MG: coarsening stops at the first grid with at most this many    */
@@ -196,7 +196,9 @@ typedef struct sa_server sa_server;
 
 typedef struct {
   int64_t hbm_budget;             /* device bytes the simulations may hold; 0 = 90% of free */
-  int32_t max_inflight;           /* launched, unfinished ticks (1..4), default 2            */
+  int32_t max_inflight;           /* ticks running at once, each on its own stream (1..4),   */
+                                  /* default 4; a tick gets capacity / max_inflight          */
+                                  /* workgroups (at least one simulation's cluster)          */
   int32_t max_batch;              /* solves per tick, 0 = as many as are co-resident          */
   int32_t unknowns_per_workgroup; /* cluster size of simulations opened with cluster = 0:    */
                                   /* ceil(n / this), 1..16, default 40000                    */
@@ -234,7 +236,8 @@ int sa_server_poll(sa_server* s, sa_completion* out, int32_t max, int32_t* n_out
 int64_t sa_server_outstanding(const sa_server* s);
 /* Device bytes held by the open simulations. */
 int64_t sa_server_bytes_used(const sa_server* s);
-/* The problem of an open simulation (for sa_get_solution, sa_read_log; no sa_solve on it). */
+/* The problem of an open simulation with no request running (for sa_get_solution,
+ * sa_read_log; no sa_solve on it); NULL while one of its requests is in a running tick. */
 sa_problem* sa_server_problem(sa_server* s, int32_t sim);
 
 /* Thread-local message of the last hard error ("" if none). */

@@ -41,7 +41,7 @@ class Options:
     tau_drop: float = TAU_DROP
     precision: str = "fp64"  # fp64 | fp32_ir
     rtol_inner: float = 1e-5
-    max_refine: int = 20
+    max_refine: int = 200
 
 
 @dataclass

@@ -48,7 +48,7 @@ extern "C" void sa_default_options(sa_options* o) {
   o->tau_drop = 1e-7;
   o->precision = SA_FP64;
   o->rtol_inner = 1e-5;
-  o->max_refine = 20;
+  o->max_refine = 200;
   o->cluster = 0;
   o->profile = 0;
   o->coarse_max = 700;

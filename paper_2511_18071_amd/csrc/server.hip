@@ -3,12 +3,20 @@
 // Each simulation is an ordinary problem (its own sketch, Krylov basis and hierarchy, all in
 // its own device arena) admitted when its arena fits the server's HBM budget. Requests (the
 // surfaces and right-hand side of a simulation's next system) queue per simulation, first in
-// first out. A tick takes the oldest request of as many simulations as fit into one launch
-// (round robin over the simulations, at most one request each), and runs them all in one
-// launch of the batch kernel: consecutive workgroup clusters, one per request, each running
-// the same solve as sa_solve. Up to max_inflight ticks are queued on the server's stream, so
-// requests that arrive while a tick runs join the next one without waiting for the GPU to
-// drain. Stream order keeps each simulation's solves in sequence.
+// first out. A tick takes the oldest request of idle simulations (round robin, at most one
+// request each, up to a workgroup budget) and runs them in one launch of the solve kernel:
+// consecutive workgroup clusters, one per request, each running the same solve as sa_solve.
+// Up to max_inflight ticks run at once, each on a stream of its own, so a long solve holds
+// back only its own tick: as soon as any tick ends, its simulations' next requests and newly
+// arrived ones form the next tick while the others keep running. A simulation is in at most
+// one tick at a time, which keeps its solves in sequence.
+//
+// Co-residency of the clusters: every tick gets at most capacity / max_inflight workgroups
+// (capacity = workgroups of the solve kernels the device holds at once), and a tick is only
+// launched after the one it replaces has finished, so all workgroups of all running ticks fit
+// on the device together and every cluster is resident as a whole. Ticks are therefore plain
+// launches that run concurrently (cooperative launches would be serialised); the cluster
+// barriers keep their bounded waits as a backstop.
 #include <chrono>
 #include <deque>
 
@@ -46,12 +54,14 @@ struct Entry {
 };
 
 struct Slot {
+  hipStream_t stream = nullptr;  // the slot's own stream
   BatchItem* h_items = nullptr;  // pinned
   BatchItem* d_items = nullptr;
   sa_solve_info* h_rep = nullptr;  // pinned
   sa_solve_info* d_rep = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
+  uint64_t seq = 0;  // launch order
   std::vector<Entry> entries;
 };
 
@@ -64,13 +74,14 @@ struct sa_server {
   int64_t used = 0;
   std::vector<Sim> sims;
   Slot slots[MAX_INFLIGHT];
-  std::deque<int> order;  // busy slots in launch order
-  int capacity = 0;       // co-resident workgroups of the batch kernel at lds_set
+  int capacity = 0;       // co-resident workgroups of the solve kernels at lds_set
   size_t lds_set = 0;
   int cus = 0;
   int rr = 0;
   uint64_t next_ticket = 1;
   int64_t queued = 0, inflight = 0;
+  int running = 0;        // busy slots
+  uint64_t launches = 0;
   std::deque<sa_completion> ready;
   std::chrono::steady_clock::time_point t0;
   hipEvent_t ev0 = nullptr;
@@ -80,7 +91,7 @@ struct sa_server {
 extern "C" void sa_server_default_options(sa_server_options* o) {
   memset(o, 0, sizeof *o);
   o->hbm_budget = 0;
-  o->max_inflight = 2;
+  o->max_inflight = 4;
   o->max_batch = 0;
   o->unknowns_per_workgroup = 40000;
 }
@@ -139,6 +150,7 @@ extern "C" int sa_server_create(const sa_server_options* optin, void* hip_stream
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_items, sizeof(BatchItem) * maxitems);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_rep, sizeof(sa_solve_info) * maxitems);
     if (e == hipSuccess) e = hipEventCreate(&sl.done);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
   }
   if (e == hipSuccess) e = hipEventCreate(&s->ev0);
   if (e == hipSuccess) {
@@ -158,6 +170,8 @@ extern "C" int sa_server_create(const sa_server_options* optin, void* hip_stream
 extern "C" void sa_server_destroy(sa_server* s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream); else (void)hipDeviceSynchronize();
+  for (Slot& sl : s->slots)
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
   for (Sim& m : s->sims)
     if (m.p) sa_destroy(m.p);
   for (Slot& sl : s->slots) {
@@ -166,6 +180,7 @@ extern "C" void sa_server_destroy(sa_server* s) {
     if (sl.d_items) (void)hipFree(sl.d_items);
     if (sl.d_rep) (void)hipFree(sl.d_rep);
     if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   delete s;
@@ -176,12 +191,16 @@ extern "C" int sa_server_open(sa_server* s, const sa_grid* grid, const double* h
   if (!s || !grid || !h || !sim) return sa_fail(SA_EARG, "sa_server_open: null argument");
   sa_options opt;
   if (optin) opt = *optin; else sa_default_options(&opt);
+  const int budget = s->capacity / s->opt.max_inflight;
   if (opt.cluster <= 0) {
     const int ncol = grid->bc == SA_PERIODIC ? grid->nx - 1 : grid->nx + 2;
     const int64_t n = (int64_t)ncol * (grid->nz + 1);
     int64_t G = (n + s->opt.unknowns_per_workgroup - 1) / s->opt.unknowns_per_workgroup;
+    if (G > budget) G = budget;
     opt.cluster = (int)(G < 1 ? 1 : (G > 16 ? 16 : G));
   }
+  if (opt.cluster > budget)
+    return sa_fail(SA_EARG, "sa_server_open: cluster of %d workgroups exceeds a tick's %d", opt.cluster, budget);
   opt.profile = 0;
   const int64_t bytes = sa_problem_bytes(grid, h, &opt);
   if (bytes < 0) return (int)bytes;
@@ -192,7 +211,8 @@ extern "C" int sa_server_open(sa_server* s, const sa_grid* grid, const double* h
   int rc = sa_create(grid, h, &opt, (void*)s->stream, &p);
   if (rc < 0) return rc;
   rc = set_lds(s, p->lds_solve);
-  if (rc == SA_OK && p->G > s->capacity) rc = sa_fail(SA_EARG, "sa_server_open: cluster of %d workgroups too large", p->G);
+  if (rc == SA_OK && p->G > s->capacity / s->opt.max_inflight)
+    rc = sa_fail(SA_EARG, "sa_server_open: cluster of %d workgroups too large for this device", p->G);
   if (rc != SA_OK) {
     sa_destroy(p);
     return rc;
@@ -253,12 +273,19 @@ extern "C" int sa_server_submit(sa_server* s, int32_t id, const double* eta_prev
   return SA_OK;
 }
 
-// collect the reports of finished ticks (the oldest first); block on the oldest if `wait`
+// collect the reports of finished ticks; with `wait`, block on the oldest running tick first
 static int harvest(sa_server* s, bool wait) {
-  while (!s->order.empty()) {
-    Slot& sl = s->slots[s->order.front()];
-    hipError_t q = wait ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
-    if (q == hipErrorNotReady) return SA_OK;
+  if (wait) {
+    int oldest = -1;
+    for (int i = 0; i < MAX_INFLIGHT; ++i)
+      if (s->slots[i].busy && (oldest < 0 || s->slots[i].seq < s->slots[oldest].seq)) oldest = i;
+    if (oldest >= 0) HIPCHK(hipEventSynchronize(s->slots[oldest].done));
+  }
+  for (int si = 0; si < MAX_INFLIGHT; ++si) {
+    Slot& sl = s->slots[si];
+    if (!sl.busy) continue;
+    hipError_t q = hipEventQuery(sl.done);
+    if (q == hipErrorNotReady) continue;
     HIPCHK(q);
     float el = 0.0f;
     HIPCHK(hipEventElapsedTime(&el, s->ev0, sl.done));
@@ -281,18 +308,17 @@ static int harvest(sa_server* s, bool wait) {
     s->inflight -= (int64_t)sl.entries.size();
     sl.entries.clear();
     sl.busy = false;
-    s->order.pop_front();
-    wait = false;
+    s->running -= 1;
   }
   return SA_OK;
 }
 
 // launch one tick from the queued requests into a free slot; *launched = number of solves.
-// The tick's solves run in one launch per precision (FP64 group first, then FP32-refinement),
-// each launch at most `capacity` co-resident workgroups.
+// The tick's solves run in one launch per precision (FP64 group first, then FP32 refinement)
+// on the slot's stream, together at most capacity / max_inflight workgroups.
 static int launch_tick(sa_server* s, int* launched) {
   *launched = 0;
-  if (s->queued == 0 || (int)s->order.size() >= s->opt.max_inflight) return SA_OK;
+  if (s->queued == 0 || s->running >= s->opt.max_inflight) return SA_OK;
   int si = -1;
   for (int i = 0; i < s->opt.max_inflight; ++i)
     if (!s->slots[i].busy) { si = i; break; }
@@ -300,16 +326,19 @@ static int launch_tick(sa_server* s, int* launched) {
   Slot& sl = s->slots[si];
   const int nsim = (int)s->sims.size();
   const int maxb = s->opt.max_batch > 0 ? s->opt.max_batch : s->capacity;
-  // pick the requests: round robin from s->rr, at most one per simulation
+  // workgroups per tick: an equal share of the co-resident capacity per running tick (every
+  // open simulation's cluster fits it)
+  const int budget = s->capacity / s->opt.max_inflight;
+  // pick the requests: round robin from s->rr, at most one per idle simulation
   std::vector<int> picked[2];
   int blocks[2] = {0, 0};
   int total = 0, scanned = 0;
   for (; scanned < nsim && total < maxb; ++scanned) {
     const int id = (s->rr + scanned) % nsim;
     Sim& m = s->sims[id];
-    if (!m.p || m.queue.empty() || m.p->broken) continue;
+    if (!m.p || m.queue.empty() || m.p->broken || m.inflight > 0) continue;
     const int g = m.p->opt.precision == SA_FP32_IR ? 1 : 0;
-    if (blocks[g] + m.p->G > s->capacity) break;
+    if (blocks[0] + blocks[1] + m.p->G > budget) break;
     blocks[g] += m.p->G;
     picked[g].push_back(id);
     ++total;
@@ -319,7 +348,7 @@ static int launch_tick(sa_server* s, int* launched) {
   const double t_launch = now_ms(s->t0);
   int nitems = 0;
   int start[2] = {0, 0}, count[2] = {0, 0};
-  bool coop[2] = {false, false};
+
   for (int g = 0; g < 2; ++g) {
     start[g] = nitems;
     int first = 0;
@@ -329,8 +358,8 @@ static int launch_tick(sa_server* s, int* launched) {
       Request& r = m.queue.front();
       if (!r.host.empty()) {
         const int np = p->nphys;
-        HIPCHK(hipMemcpyAsync(p->eta_own, r.host.data(), (size_t)2 * np * 8, hipMemcpyHostToDevice, s->stream));
-        HIPCHK(hipMemcpyAsync(p->b_own, r.host.data() + 2 * np, (size_t)p->n * 8, hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(p->eta_own, r.host.data(), (size_t)2 * np * 8, hipMemcpyHostToDevice, sl.stream));
+        HIPCHK(hipMemcpyAsync(p->b_own, r.host.data() + 2 * np, (size_t)p->n * 8, hipMemcpyHostToDevice, sl.stream));
         p->eta_p = p->eta_own;
         p->eta_c = p->eta_own + np;
         p->b = p->b_own;
@@ -349,7 +378,6 @@ static int launch_tick(sa_server* s, int* launched) {
       it.a = a;
       sa_commit_solve(p, a);
       first += p->G;
-      coop[g] = coop[g] || p->G > 1;
       sl.entries.push_back(Entry{id, r.ticket, r.t_submit, t_launch, std::move(r.host)});
       m.queue.pop_front();
       m.inflight += 1;
@@ -358,7 +386,7 @@ static int launch_tick(sa_server* s, int* launched) {
     }
     count[g] = nitems - start[g];
   }
-  HIPCHK(hipMemcpyAsync(sl.d_items, sl.h_items, sizeof(BatchItem) * nitems, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(sl.d_items, sl.h_items, sizeof(BatchItem) * nitems, hipMemcpyHostToDevice, sl.stream));
   BatchItem unused;
   memset(&unused, 0, sizeof unused);
   for (int g = 0; g < 2; ++g) {
@@ -367,15 +395,13 @@ static int launch_tick(sa_server* s, int* launched) {
     int ni = count[g];
     void* args[] = {(void*)&items, (void*)&ni, (void*)&unused};
     const void* fn = sa_solve_fn(g ? SA_FP32_IR : SA_FP64);
-    if (coop[g])
-      HIPCHK(hipLaunchCooperativeKernel(fn, dim3(blocks[g]), dim3(BLOCK), args, (unsigned)s->lds_set, s->stream));
-    else
-      HIPCHK(hipLaunchKernel(fn, dim3(blocks[g]), dim3(BLOCK), args, s->lds_set, s->stream));
+    HIPCHK(hipLaunchKernel(fn, dim3(blocks[g]), dim3(BLOCK), args, s->lds_set, sl.stream));
   }
-  HIPCHK(hipMemcpyAsync(sl.h_rep, sl.d_rep, sizeof(sa_solve_info) * nitems, hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipEventRecord(sl.done, s->stream));
+  HIPCHK(hipMemcpyAsync(sl.h_rep, sl.d_rep, sizeof(sa_solve_info) * nitems, hipMemcpyDeviceToHost, sl.stream));
+  HIPCHK(hipEventRecord(sl.done, sl.stream));
   sl.busy = true;
-  s->order.push_back(si);
+  sl.seq = ++s->launches;
+  s->running += 1;
   s->inflight += nitems;
   *launched = nitems;
   return SA_OK;
@@ -392,7 +418,7 @@ extern "C" int sa_server_poll(sa_server* s, sa_completion* out, int32_t max, int
     if (rc) return rc;
     if (!launched) break;
   }
-  if (wait && s->ready.empty() && !s->order.empty()) {
+  if (wait && s->ready.empty() && s->running > 0) {
     rc = harvest(s, true);
     if (rc) return rc;
     for (;;) {  // refill the slot that just freed
@@ -420,5 +446,6 @@ extern "C" int64_t sa_server_bytes_used(const sa_server* s) { return s ? s->used
 extern "C" sa_problem* sa_server_problem(sa_server* s, int32_t id) {
   if (!s) return nullptr;
   Sim* m = sim_of(s, id);
-  return m ? m->p : nullptr;
+  // its device state may only be read once its last tick has been harvested
+  return (m && m->inflight == 0) ? m->p : nullptr;
 }

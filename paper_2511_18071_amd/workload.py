@@ -262,8 +262,8 @@ def serving_mix(nsims: int = 256, seed: int = 5, nsys: int = 50, nx_range=(257, 
     nx uniform in nx_range, moved to the nearest 64 q + 1 with q = 2^a b, b in {1, 3, 5, 7}
     (grids that halve down to a few columns, so the still-water V-cycle reaches a small
     coarsest grid), nz from nz_choices, flat (periodic) or submerged-bar (walls, bar scaled to
-    the domain) bathymetry, H/L uniform in [0.01, 0.08], history rank uniform in 8..16,
-    forgetting factor 0.9."""
+    the domain) bathymetry, H/L uniform in [0.01, 0.08] (periodic waves capped at 0.7 of the
+    breaking limit at their kh), history rank uniform in 8..16, forgetting factor 0.9."""
     rng = np.random.default_rng(seed)
     qs = sorted({(2 ** a) * b for a in range(12) for b in (1, 3, 5, 7)})
     sims = []
@@ -276,6 +276,8 @@ def serving_mix(nsims: int = 256, seed: int = 5, nsys: int = 50, nx_range=(257, 
         steep = float(rng.uniform(0.01, 0.08))
         if rng.uniform() < 0.5:
             kh = float(rng.uniform(0.5, 2.0))
+            # at most the steepest fraction of the breaking limit the paper runs (0.7, Sec. 5.1)
+            steep = min(steep, 0.7 * battjes_max_steepness(kh))
             w = _stream(f"serve{i:03d}", nx, nz, kh, max(1, (nx - 1) // 256), 4, steep,
                         seed * 1000 + i, nsys, 30, k, 0.9)
         else:
