@@ -324,11 +324,11 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     delete p;
     return sa_fail(SA_EDEVICE, "hipGetDeviceProperties failed");
   }
-  const size_t head = (size_t)PSTRIDE + 4 * (MMAX + 2) + (size_t)(m + 1) * m + 2 * m + 2 * (m + 1) + m + KMAX +
+  const size_t head = (size_t)PSTRIDE + NWAVE * (MMAX + 2) + (size_t)(m + 1) * m + 2 * m + 2 * (m + 1) + m + KMAX +
                       4 * KMAX * KMAX + 8;
   const int TWMh = TX + 3, TWGMh = TXG + 3;
   auto opcoef = [&](int W) { return (size_t)(49 + 9 * nl + 5 * (W + 6)); };
-  const size_t need_op = (size_t)(TWMh + 12 + 2 * (TWMh + 6)) * nl + opcoef(TWMh) + 4;
+  const size_t need_op = (size_t)(TWMh + 12 + 2 * (TWMh + 6)) * nl + opcoef(TWMh) + NWAVE;
   const size_t need_gram = opt.guess == SA_GUESS_EWMA
                                ? (size_t)(k * TWGMh + TWGMh + TWGMh + 12 + 2 * (TWGMh + 6)) * nl + opcoef(TWGMh) : 0;
   const int TMSh = 64 + 4;  // preconditioner tile with its 2-column halo
@@ -336,6 +336,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   size_t big = need_op;
   if (need_gram > big) big = need_gram;
   if (need_pc > big) big = need_pc;
+  if (big < 2 * (size_t)BLOCK) big = 2 * (size_t)BLOCK;  // the Gram pass combines per-thread partials
   p->lds_solve = (head + big) * sizeof(double);
   p->lds_op = need_op * sizeof(double);
   p->lds_pc = need_pc * sizeof(double);

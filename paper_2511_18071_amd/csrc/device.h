@@ -102,13 +102,25 @@ DEV void cluster_sum(Cl& cl, double* red, int nv) {
   __syncthreads();
 }
 
+// sum of the NWAVE per-wave values w[0..NWAVE) in a fixed pairwise order
+DEV double waves_sum(const double* w) {
+  double s[NWAVE];
+#pragma unroll
+  for (int i = 0; i < NWAVE; ++i) s[i] = w[i];
+#pragma unroll
+  for (int h = NWAVE / 2; h > 0; h >>= 1)
+#pragma unroll
+    for (int i = 0; i < h; ++i) s[i] = s[2 * i] + s[2 * i + 1];
+  return s[0];
+}
+
 // per-thread value v -> red[slot] = workgroup sum (fixed tree), all threads must call
-DEV void block_sum_to(double v, double* wsum /*LDS 4*/, double* red, int slot) {
+DEV void block_sum_to(double v, double* wsum /*LDS NWAVE*/, double* red, int slot) {
   v = wave_sum(v);
   const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) wsum[wave] = v;
   __syncthreads();
-  if (threadIdx.x == 0) red[slot] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+  if (threadIdx.x == 0) red[slot] = waves_sum(wsum);
   __syncthreads();
 }
 
@@ -951,11 +963,11 @@ DEV void phase_dots(const Problem& P, Cl& cl, const S* V, const double* vs, int 
     }
     for (; e < n; e += stride) s0 += double(a[e]) * double(w[e]);
     double sum = wave_sum((s0 + s1) + (s2 + s3));
-    if (lane == 0) wsum[i * 4 + wave] = sum;
+    if (lane == 0) wsum[i * NWAVE + wave] = sum;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nred; i += BLOCK) {
-    const double sm = (wsum[i * 4] + wsum[i * 4 + 1]) + (wsum[i * 4 + 2] + wsum[i * 4 + 3]);
+    const double sm = waves_sum(wsum + i * NWAVE);
     red[i] = (i < nv) ? vs[i] * sm : sm;
   }
   __syncthreads();
@@ -971,7 +983,7 @@ DEV void phase_update(const Problem& P, Cl& cl, const S* V, const double* vs, co
   const int stride = cl.G * BLOCK;
   double nrm = 0.0;
   if (dots)
-    for (int i = threadIdx.x; i < nv * 4; i += BLOCK) wsum[i] = 0.0;
+    for (int i = threadIdx.x; i < nv * NWAVE; i += BLOCK) wsum[i] = 0.0;
   __syncthreads();
   // each wave walks its own 64-element chunks so that per-chunk sums stay in one order
   for (int base = cl.rank * BLOCK + wave * 64; base < n; base += stride) {
@@ -995,7 +1007,7 @@ DEV void phase_update(const Problem& P, Cl& cl, const S* V, const double* vs, co
       for (int q = 0; q < nv; ++q) {
         double p = double(V[(size_t)q * n + ec]) * double(ws);
         p = wave_sum(p);
-        if (lane == 0) wsum[q * 4 + wave] += p;
+        if (lane == 0) wsum[q * NWAVE + wave] += p;
       }
     } else {
       nrm += double(ws) * double(ws);
@@ -1004,7 +1016,7 @@ DEV void phase_update(const Problem& P, Cl& cl, const S* V, const double* vs, co
   __syncthreads();
   if (dots) {
     for (int i = threadIdx.x; i < nv; i += BLOCK)
-      red[i] = vs[i] * ((wsum[i * 4] + wsum[i * 4 + 1]) + (wsum[i * 4 + 2] + wsum[i * 4 + 3]));
+      red[i] = vs[i] * waves_sum(wsum + i * NWAVE);
     __syncthreads();
   } else {
     block_sum_to(nrm, wsum, red, 0);
@@ -1347,7 +1359,7 @@ DEV void phase_sketch_combine(const Problem& P, Cl& cl, const double* Yn, const 
 // LDS layout of the solve kernel
 struct Smem {
   double* red;    // PSTRIDE
-  double* wsum;   // 4 * (MMAX + 2)
+  double* wsum;   // NWAVE * (MMAX + 2)
   double* H;      // (m+1) x m, column j at j*(m+1)
   double* cs;     // m
   double* sn;     // m
@@ -1363,7 +1375,7 @@ DEV Smem carve(double* s, int m) {
   Smem S;
   S.red = s;
   S.wsum = S.red + PSTRIDE;
-  S.H = S.wsum + 4 * (MMAX + 2);
+  S.H = S.wsum + NWAVE * (MMAX + 2);
   S.cs = S.H + (m + 1) * m;
   S.sn = S.cs + m;
   S.g = S.sn + m;

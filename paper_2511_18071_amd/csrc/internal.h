@@ -6,7 +6,8 @@
 
 namespace sa {
 
-constexpr int BLOCK = 256;        // threads per workgroup (4 wave64)
+constexpr int BLOCK = 512;        // threads per workgroup
+constexpr int NWAVE = BLOCK / 64; // wave64s per workgroup (a power of two)
 constexpr int KMAX = 16;          // largest sketch rank handled on the device
 constexpr int MMAX = 64;          // largest restart length
 constexpr int MAXLEV = 24;        // multigrid levels
