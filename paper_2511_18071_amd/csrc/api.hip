@@ -332,7 +332,8 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   const size_t need_gram = opt.guess == SA_GUESS_EWMA
                                ? (size_t)(k * TWGMh + TWGMh + TWGMh + 12 + 2 * (TWGMh + 6)) * nl + opcoef(TWGMh) : 0;
   const int TMSh = 64 + 4;  // preconditioner tile with its 2-column halo
-  const size_t need_pc = (size_t)5 * TMSh * nl + 5 * TMSh;
+  size_t need_pc = (size_t)5 * TMSh * nl + 5 * TMSh;
+  if (need_pc < (size_t)cn + BLOCK) need_pc = (size_t)cn + BLOCK;  // coarsest solve: f and partial sums
   size_t big = need_op;
   if (need_gram > big) big = need_gram;
   if (need_pc > big) big = need_pc;

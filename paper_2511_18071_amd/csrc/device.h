@@ -754,21 +754,60 @@ DEV void phase_prolong(const Problem& P, Cl& cl, int l, const S* e, S* u) {
   }
 }
 
-// o = M_c^-1 f on the coarsest grid: thread per row of the stored (transposed) inverse
+// o = M_c^-1 f on the coarsest grid with the stored (transposed) inverse. Each workgroup of
+// the cluster takes a contiguous slice of R rows; when R < BLOCK the slice's dot products are
+// split over Q = BLOCK / R threads per row (thread (q, r) takes j = q, q + Q, ...; consecutive
+// threads read consecutive rows of one column, coalesced), eight loads in flight per thread,
+// and the Q partial sums are added in LDS in a fixed order. f is staged in LDS first.
 template <class S>
-DEV void phase_coarse(const Problem& P, Cl& cl, const S* f, S* o) {
+DEV void phase_coarse(const Problem& P, Cl& cl, const S* f, S* o, S* lds) {
   const int cn = P.cn;
   const S* ci = coarse_inverse<S>(P);
-  for (int i = cl.rank * BLOCK + threadIdx.x; i < cn; i += cl.G * BLOCK) {
-    S s0 = S(0), s1 = S(0), s2 = S(0), s3 = S(0);
-    int j = 0;
-    for (; j + 3 < cn; j += 4) {
-      const S a0 = ci[(size_t)j * cn + i], a1 = ci[(size_t)(j + 1) * cn + i];
-      const S a2 = ci[(size_t)(j + 2) * cn + i], a3 = ci[(size_t)(j + 3) * cn + i];
-      s0 += a0 * f[j]; s1 += a1 * f[j + 1]; s2 += a2 * f[j + 2]; s3 += a3 * f[j + 3];
+  S* sf = lds;             // cn
+  S* part = lds + cn;      // BLOCK partial sums
+  for (int j = threadIdx.x; j < cn; j += BLOCK) sf[j] = f[j];
+  __syncthreads();
+  const int R = (cn + cl.G - 1) / cl.G;
+  const int r0 = cl.rank * R;
+  const int r1 = min(cn, r0 + R);
+  if (r0 >= r1) return;
+  const int rows = r1 - r0;
+  const int Q = rows < BLOCK ? BLOCK / rows : 1;
+  const int t = threadIdx.x;
+  const int q = t / rows, rl = t - q * rows;
+  for (int rb = 0; rb < rows; rb += BLOCK) {  // one pass unless the slice exceeds BLOCK rows
+    const int r = Q > 1 ? rl : rb + t;
+    const bool active = Q > 1 ? q < Q : r < rows;
+    S acc = S(0);
+    if (active) {
+      const size_t i = (size_t)(r0 + r);
+      S a[8];
+      int j = q;
+      for (; j + 7 * Q < cn; j += 8 * Q) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = ci[(size_t)(j + u * Q) * cn + i];
+        S s0 = S(0), s1 = S(0);
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          s0 += a[u] * sf[j + u * Q];
+          s1 += a[u + 1] * sf[j + (u + 1) * Q];
+        }
+        acc += s0 + s1;
+      }
+      for (; j < cn; j += Q) acc += ci[(size_t)j * cn + i] * sf[j];
     }
-    for (; j < cn; ++j) s0 += ci[(size_t)j * cn + i] * f[j];
-    o[i] = (s0 + s1) + (s2 + s3);
+    if (Q == 1) {
+      if (active) o[r0 + r] = acc;
+      continue;
+    }
+    part[t] = active ? acc : S(0);
+    __syncthreads();
+    if (t < rows) {
+      S sum = S(0);
+      for (int qq = 0; qq < Q; ++qq) sum += part[qq * rows + t];
+      o[r0 + t] = sum;
+    }
+    __syncthreads();
   }
 }
 
@@ -905,7 +944,7 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
   }
   const int L = P.nlev;
   if (L == 1) {
-    phase_coarse<S>(P, cl, v, z);
+    phase_coarse<S>(P, cl, v, z, lds);
     csync(cl);
     return;
   }
@@ -922,7 +961,7 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
     tk(2 * MAXLEV);
   }
   const Lv<S> Lc = level_view<S>(P, L - 1);
-  phase_coarse<S>(P, cl, Lc.f, Lc.o);
+  phase_coarse<S>(P, cl, Lc.f, Lc.o, lds);
   csync(cl);
   tk(0);
   const S* e = Lc.o;
