@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving: offered solves/s (open loop)")
     ap.add_argument("--serve-baseline-stride", type=int, default=8,
                     help="serving: the one-at-a-time FP64 baseline solves every k-th simulation")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes five times (the "
+                         "reference kernel that scales HBM counter readings)")
     return ap.parse_args()
 
 
@@ -308,8 +311,24 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_probe(nbytes: int):
+    """Five launches of a plain device copy of nbytes: FETCH_SIZE and WRITE_SIZE of these
+    dispatches against nbytes give the factor that turns the counters into bytes."""
+    import torch
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "launches": 5}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build measures the one-GPU path (asked for {args.gpus}).",
               file=sys.stderr)

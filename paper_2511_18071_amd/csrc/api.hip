@@ -333,7 +333,8 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
                                ? (size_t)(k * TWGMh + TWGMh + TWGMh + 12 + 2 * (TWGMh + 6)) * nl + opcoef(TWGMh) : 0;
   const int TMSh = 64 + 4;  // preconditioner tile with its 2-column halo
   size_t need_pc = (size_t)5 * TMSh * nl + 5 * TMSh;
-  if (need_pc < (size_t)cn + BLOCK) need_pc = (size_t)cn + BLOCK;  // coarsest solve: f and partial sums
+  if (opt.precond == SA_PC_MG && need_pc < (size_t)cn + BLOCK)
+    need_pc = (size_t)cn + BLOCK;  // coarsest solve: f and partial sums
   size_t big = need_op;
   if (need_gram > big) big = need_gram;
   if (need_pc > big) big = need_pc;
@@ -453,40 +454,40 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   Problem& P = p->hp;
   P.ncol = ncol; P.nl = nl; P.nz = grid->nz; P.n = n; P.nphys = nphys; P.periodic = periodic;
   P.dx = dx; P.dsig = dsig;
-  P.wsig = (const double*)(A + o_wsig); P.ssig = (const int*)(A + o_ssig); P.wchi = (const double*)(A + o_wchi);
-  P.sig = (const double*)(A + o_sig); P.h = (const double*)(A + o_h); P.hchi = (const double*)(A + o_hchi);
-  P.geo = (double*)(A + o_geo);
+  P.wsig = (decltype(P.wsig))(A + o_wsig); P.ssig = (decltype(P.ssig))(A + o_ssig); P.wchi = (decltype(P.wchi))(A + o_wchi);
+  P.sig = (decltype(P.sig))(A + o_sig); P.h = (decltype(P.h))(A + o_h); P.hchi = (decltype(P.hchi))(A + o_hchi);
+  P.geo = (decltype(P.geo))(A + o_geo);
   P.pc = opt.precond; P.nu1 = opt.nu1; P.nu2 = opt.nu2; P.nlev = nlev; P.omega = opt.omega; P.tail = tail;
   for (int l = 0; l < nlev; ++l) {
     Level& L = P.lev[l];
     L.ncol = levs[l].ncol; L.nx = levs[l].nx; L.dx = levs[l].dx;
-    L.h = (const double*)(A + o_lh[l]); L.hx = (const double*)(A + o_lhx[l]); L.hxx = (const double*)(A + o_lhxx[l]);
-    L.ih = (const double*)(A + o_lih[l]);
-    L.fpc = (const double*)(A + o_fpc[l]); L.finv = (const double*)(A + o_finv[l]);
-    L.fgam = (const double*)(A + o_fgam[l]); L.fstride = levs[l].fstride;
-    L.flo = (const double*)(A + o_flo[l]);
-    L.f = (double*)(A + o_lf[l]); L.u = (double*)(A + o_lu[l]); L.o = (double*)(A + o_lo[l]);
+    L.h = (decltype(L.h))(A + o_lh[l]); L.hx = (decltype(L.hx))(A + o_lhx[l]); L.hxx = (decltype(L.hxx))(A + o_lhxx[l]);
+    L.ih = (decltype(L.ih))(A + o_lih[l]);
+    L.fpc = (decltype(L.fpc))(A + o_fpc[l]); L.finv = (decltype(L.finv))(A + o_finv[l]);
+    L.fgam = (decltype(L.fgam))(A + o_fgam[l]); L.fstride = levs[l].fstride;
+    L.flo = (decltype(L.flo))(A + o_flo[l]);
+    L.f = (decltype(L.f))(A + o_lf[l]); L.u = (decltype(L.u))(A + o_lu[l]); L.o = (decltype(L.o))(A + o_lo[l]);
     if (ir) {
-      L.fpc32 = (const float*)(A + o_fpc32[l]); L.finv32 = (const float*)(A + o_finv32[l]);
-      L.flo32 = (const float*)(A + o_flo32[l]); L.fgam32 = (const float*)(A + o_fgam32[l]);
-      L.f32 = (float*)(A + o_lf32[l]); L.u32 = (float*)(A + o_lu32[l]); L.o32 = (float*)(A + o_lo32[l]);
+      L.fpc32 = (decltype(L.fpc32))(A + o_fpc32[l]); L.finv32 = (decltype(L.finv32))(A + o_finv32[l]);
+      L.flo32 = (decltype(L.flo32))(A + o_flo32[l]); L.fgam32 = (decltype(L.fgam32))(A + o_fgam32[l]);
+      L.f32 = (decltype(L.f32))(A + o_lf32[l]); L.u32 = (decltype(L.u32))(A + o_lu32[l]); L.o32 = (decltype(L.o32))(A + o_lo32[l]);
     } else {
       L.fpc32 = L.finv32 = L.flo32 = L.fgam32 = nullptr;
       L.f32 = L.u32 = L.o32 = nullptr;
     }
   }
-  P.cinv = (const double*)(A + o_cinv); P.cn = cn;
-  P.cinv32 = ir ? (const float*)(A + o_cinv32) : nullptr;
-  P.V32 = ir ? (float*)(A + o_V32) : nullptr;
-  P.t32 = ir ? (float*)(A + o_t32) : nullptr;
-  P.r32 = ir ? (float*)(A + o_r32) : nullptr;
+  P.cinv = (decltype(P.cinv))(A + o_cinv); P.cn = cn;
+  P.cinv32 = ir ? (decltype(P.cinv32))(A + o_cinv32) : nullptr;
+  P.V32 = ir ? (decltype(P.V32))(A + o_V32) : nullptr;
+  P.t32 = ir ? (decltype(P.t32))(A + o_t32) : nullptr;
+  P.r32 = ir ? (decltype(P.r32))(A + o_r32) : nullptr;
   P.precision = opt.precision; P.max_refine = opt.max_refine; P.rtol_inner = opt.rtol_inner;
-  P.x = (double*)(A + o_x); P.xc = (double*)(A + o_xc); P.r = (double*)(A + o_r); P.rc = (double*)(A + o_rc);
-  P.t = (double*)(A + o_t); P.V = (double*)(A + o_V);
-  P.Y[0] = (double*)(A + o_Y0); P.Y[1] = (double*)(A + o_Y1);
+  P.x = (decltype(P.x))(A + o_x); P.xc = (decltype(P.xc))(A + o_xc); P.r = (decltype(P.r))(A + o_r); P.rc = (decltype(P.rc))(A + o_rc);
+  P.t = (decltype(P.t))(A + o_t); P.V = (decltype(P.V))(A + o_V);
+  P.Y[0] = (std::remove_reference_t<decltype(P.Y[0])>)(A + o_Y0); P.Y[1] = (std::remove_reference_t<decltype(P.Y[1])>)(A + o_Y1);
   P.k = k; P.m = m; P.max_restarts = opt.max_restarts; P.tau_drop = opt.tau_drop;
-  P.partials = (double*)(A + o_part); P.bar = (unsigned*)(A + o_bar); P.flags = (int*)(A + o_flags);
-  P.log = (sa_solve_info*)(A + o_log); P.G = G;
+  P.partials = (decltype(P.partials))(A + o_part); P.bar = (decltype(P.bar))(A + o_bar); P.flags = (decltype(P.flags))(A + o_flags);
+  P.log = (decltype(P.log))(A + o_log); P.G = G;
   p->dp = (Problem*)(A + o_prob);
   p->b_own = (double*)(A + o_b);
   p->eta_own = (double*)(A + o_eta);
@@ -602,10 +603,10 @@ static SolveArgs base_args(sa_problem* p) {
   a.ycur = p->ycur;
   a.r = p->opt.r;
   a.rtol = p->opt.rtol;
-  a.b = p->b;
-  a.eta_p = p->eta_p;
-  a.eta_c = p->eta_c;
-  a.prof = p->prof;
+  a.b = (decltype(a.b))p->b;
+  a.eta_p = (decltype(a.eta_p))p->eta_p;
+  a.eta_c = (decltype(a.eta_c))p->eta_c;
+  a.prof = (decltype(a.prof))p->prof;
   return a;
 }
 
@@ -646,7 +647,7 @@ extern "C" int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags) {
   bool ewma = false;
   SolveArgs a = sa_prepare_solve(p, &ewma);
   BatchItem one;
-  one.P = p->dp;
+  one.P = (decltype(one.P))p->dp;
   one.first = 0;
   one.sketch = ewma ? 1 : 0;
   one.a = a;

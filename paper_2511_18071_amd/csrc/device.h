@@ -1831,20 +1831,22 @@ DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a, int rank
 // requested.
 template <int PREC>
 DEV void solve_entry(const BatchItem* __restrict__ items, int nitems, const BatchItem& one) {
-  if (nitems <= 0) {
-    solve_body<PREC>(one.P, one.a, (int)blockIdx.x);
-    return;
+  const Problem SA_GLOBAL* P = one.P;
+  const SolveArgs* a = &one.a;
+  int rank = (int)blockIdx.x;
+  if (nitems > 0) {
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].first <= (int)blockIdx.x) lo = mid;
+      else hi = mid - 1;
+    }
+    P = items[lo].P;
+    a = &items[lo].a;
+    rank = (int)blockIdx.x - items[lo].first;
+    if (rank < 0 || rank >= P->G) return;  // padding workgroups of the launch
   }
-  int lo = 0, hi = nitems - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].first <= (int)blockIdx.x) lo = mid;
-    else hi = mid - 1;
-  }
-  const BatchItem& it = items[lo];
-  const int rank = (int)blockIdx.x - it.first;
-  if (rank < 0 || rank >= it.P->G) return;  // padding workgroups of the launch
-  solve_body<PREC>(it.P, it.a, rank);
+  solve_body<PREC>(P, *a, rank);  // one call site: one inlined copy of the solve
 }
 
 }  // namespace sa

@@ -4,6 +4,15 @@
 
 #include "../../include/sawave.h"
 
+// Device memory pointers stored in the structures below. The device pass gives them the
+// global address space so that every load and store through them is a global (not flat)
+// access; the host pass sees plain pointers (set them with a cast to decltype(field)).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SA_GLOBAL __attribute__((address_space(1)))
+#else
+#define SA_GLOBAL
+#endif
+
 namespace sa {
 
 constexpr int BLOCK = 512;        // threads per workgroup
@@ -26,57 +35,71 @@ enum { FLAG_GEOM = 0, FLAG_NONFINITE = 1, FLAG_ABORT = 2, NFLAGS = 4 };
 struct Level {
   int ncol, nx;              // columns (ghosts included), physical points
   double dx;
-  const double* h;           // depth per column (ghost columns by reflection)
-  const double* ih;          // 1/h per column
-  const double* hx;          // second-order centred dh/dx per column
- const double* hxx;         // second-order centred d2h/dx2 per column
+  const double SA_GLOBAL* h;           // depth per column (ghost columns by reflection)
+  const double SA_GLOBAL* ih;          // 1/h per column
+  const double SA_GLOBAL* hx;          // second-order centred dh/dx per column
+  const double SA_GLOBAL* hxx;        // second-order centred d2h/dx2 per column
   // line-solve factors of the fixed still-water operator: ratio pc and inverse pivot at
   // [j * fstride + c] (fstride = 0: every column has the same factors), bed-row combination
   // factor per column
-  const double* fpc;
-  const double* finv;
-  const double* flo;         // sub-diagonal of the column systems (same layout)
-  const double* fgam;
+  const double SA_GLOBAL* fpc;
+  const double SA_GLOBAL* finv;
+  const double SA_GLOBAL* flo;         // sub-diagonal of the column systems (same layout)
+  const double SA_GLOBAL* fgam;
   int fstride;
-  double* f;                 // right-hand side of this level (level 0: unused, the input)
-  double* u;                 // smoothed iterate
-  double* o;                 // output of this level's cycle (level 0: unused, the output)
+  double SA_GLOBAL* f;                 // right-hand side of this level (level 0: unused, the input)
+  double SA_GLOBAL* u;                 // smoothed iterate
+  double SA_GLOBAL* o;                 // output of this level's cycle (level 0: unused, the output)
   // FP32 copies for the inner solve of the refinement path (null without it)
-  const float *fpc32, *finv32, *flo32, *fgam32;
-  float *f32, *u32, *o32;
+  const float SA_GLOBAL* fpc32;
+  const float SA_GLOBAL* finv32;
+  const float SA_GLOBAL* flo32;
+  const float SA_GLOBAL* fgam32;
+  float SA_GLOBAL* f32;
+  float SA_GLOBAL* u32;
+  float SA_GLOBAL* o32;
 };
 
 // Everything a kernel needs about one problem. Lives in device memory.
 struct Problem {
   int ncol, nl, nz, n, nphys, periodic;
   double dx, dsig;
-  const double* wsig;        // nl x 7 first-derivative weights in sigma (1/dsig included)
-  const int* ssig;           // nl window starts in sigma
-  const double* wchi;        // 7 x 7: rows 0-2 left windows, 3 centred, 4-6 right windows
-  const double* sig;         // nl sigma values
-  const double* h;           // ncol depth (extended)
-  const double* hchi;        // ncol sixth-order dh/dchi
-  double* geo;               // 4 x ncol: 1/d_prev, d_chi prev, 1/d_cur, d_chi cur
+  const double SA_GLOBAL* wsig;        // nl x 7 first-derivative weights in sigma (1/dsig included)
+  const int SA_GLOBAL* ssig;           // nl window starts in sigma
+  const double SA_GLOBAL* wchi;        // 7 x 7: rows 0-2 left windows, 3 centred, 4-6 right windows
+  const double SA_GLOBAL* sig;         // nl sigma values
+  const double SA_GLOBAL* h;           // ncol depth (extended)
+  const double SA_GLOBAL* hchi;        // ncol sixth-order dh/dchi
+  double SA_GLOBAL* geo;               // 4 x ncol: 1/d_prev, d_chi prev, 1/d_cur, d_chi cur
   // preconditioner
   int pc, nu1, nu2, nlev, tail;   // tail: first level run by a single workgroup
   double omega;
   Level lev[MAXLEV];
-  const double* cinv;        // dense inverse of the coarsest operator, cn x cn (transposed)
-  const float* cinv32;       // its FP32 rounding (refinement path)
+  const double SA_GLOBAL* cinv;        // dense inverse of the coarsest operator, cn x cn (transposed)
+  const float SA_GLOBAL* cinv32;       // its FP32 rounding (refinement path)
   int cn;
   // solver vectors
-  double *x, *xc, *r, *rc, *t, *V, *Y[2];
-  float *V32, *t32, *r32;    // inner basis and work vectors of the refinement path
+  double SA_GLOBAL* x;
+  double SA_GLOBAL* xc;
+  double SA_GLOBAL* r;
+  double SA_GLOBAL* rc;
+  double SA_GLOBAL* t;
+  double SA_GLOBAL* V;
+  double SA_GLOBAL* Y[2];
+  // inner basis and work vectors of the refinement path
+  float SA_GLOBAL* V32;
+  float SA_GLOBAL* t32;
+  float SA_GLOBAL* r32;
   // sketch / options
   int k, m, max_restarts;
   double tau_drop;
   int precision, max_refine;
   double rtol_inner;
   // synchronisation and reports
-  double* partials;          // 2 x G x PSTRIDE
-  unsigned* bar;             // barrier counter, generation
-  int* flags;                // NFLAGS
-  sa_solve_info* log;        // LOGCAP
+  double SA_GLOBAL* partials;          // 2 x G x PSTRIDE
+  unsigned SA_GLOBAL* bar;             // barrier counter, generation
+  int SA_GLOBAL* flags;                // NFLAGS
+  sa_solve_info SA_GLOBAL* log;        // LOGCAP
   int G;                     // workgroups per solve
 };
 
@@ -86,20 +109,20 @@ struct SolveArgs {
   int prev_guess;    // x0 = previous solution (else zero) when no sketch guess
   int ycur;          // sketch buffer holding Y before this call
   int log_slot;
-  const double* b;      // right-hand side (n)
-  const double* eta_p;  // previous-stage surface (nphys)
-  const double* eta_c;  // current-stage surface (nphys)
+  const double SA_GLOBAL* b;      // right-hand side (n)
+  const double SA_GLOBAL* eta_p;  // previous-stage surface (nphys)
+  const double SA_GLOBAL* eta_c;  // current-stage surface (nphys)
   double r;          // forgetting factor
   double rtol;
   double om[KMAX];   // sketch draws of the stored solution
-  unsigned long long* prof;  // NPHASE accumulated wall-clock ticks, or nullptr
-  sa_solve_info* out;        // a second copy of the report with the problem's flags folded
+  unsigned long long SA_GLOBAL* prof;  // NPHASE accumulated wall-clock ticks, or nullptr
+  sa_solve_info SA_GLOBAL* out;        // a second copy of the report with the problem's flags folded
                              // into its status (batched solves), or nullptr
 };
 
 // One solve of a batched launch: the workgroups [first, first + P->G) of the grid run it.
 struct BatchItem {
-  const Problem* P;
+  const Problem SA_GLOBAL* P;
   int first;
   int sketch;   // the sketch variant of the solve (EWMA guess mode)
   SolveArgs a;

@@ -370,9 +370,9 @@ static int launch_tick(sa_server* s, int* launched) {
       }
       bool ewma = false;
       SolveArgs a = sa_prepare_solve(p, &ewma);
-      a.out = sl.d_rep + nitems;
+      a.out = (decltype(a.out))(sl.d_rep + nitems);
       BatchItem& it = sl.h_items[nitems];
-      it.P = p->dp;
+      it.P = (decltype(it.P))p->dp;
       it.first = first;
       it.sketch = ewma ? 1 : 0;
       it.a = a;

@@ -100,3 +100,11 @@ def test_server_option_errors_need_no_gpu(binding):
         with pytest.raises(binding.SawaveError) as e:
             binding.Server(**bad)
         assert e.value.code == -1, bad
+
+
+def test_footprint_of_every_preconditioner_on_the_large_grid(binding):
+    # the LDS sizing of the coarsest solve applies to the V-cycle only
+    from paper_2511_18071_amd import workload as W
+    w = W.get("periodic_16385x33")
+    for pc in ("none", "line", "mg"):
+        assert binding.footprint(w, precond=pc, cluster=64) > 8 * w.n * (w.restart + 1)
