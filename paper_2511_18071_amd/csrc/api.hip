@@ -372,15 +372,17 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
       o_flo32(nlev, 0), o_fgam32(nlev, 0);
   for (int l = 0; l < nlev; ++l) {
     const size_t nlv = (size_t)levs[l].ncol * nl;
-    o_lh[l] = take(levs[l].ncol * 8); o_lhx[l] = take(levs[l].ncol * 8); o_lhxx[l] = take(levs[l].ncol * 8);
-    o_lih[l] = take(levs[l].ncol * 8);
-    o_fpc[l] = take(levs[l].fpc.size() * 8); o_finv[l] = take(levs[l].finv.size() * 8);
-    o_flo[l] = take(levs[l].flo.size() * 8);
+    // column data h | 1/h | h_x | h_xx and factors lo | pc | inv in one block each, so that a
+    // kernel reaches part q at base + q * stride
+    const size_t nc8 = (size_t)levs[l].ncol * 8, fs8 = levs[l].fpc.size() * 8;
+    o_lh[l] = take(4 * nc8); o_lih[l] = o_lh[l] + nc8; o_lhx[l] = o_lh[l] + 2 * nc8; o_lhxx[l] = o_lh[l] + 3 * nc8;
+    o_flo[l] = take(3 * fs8); o_fpc[l] = o_flo[l] + fs8; o_finv[l] = o_flo[l] + 2 * fs8;
     o_fgam[l] = take(levs[l].fgam.size() * 8);
     o_lf[l] = take(nlv * 8); o_lu[l] = take(nlv * 8); o_lo[l] = take(nlv * 8);
     if (ir) {
-      o_fpc32[l] = take(levs[l].fpc.size() * 4); o_finv32[l] = take(levs[l].finv.size() * 4);
-      o_flo32[l] = take(levs[l].flo.size() * 4); o_fgam32[l] = take(levs[l].fgam.size() * 4);
+      const size_t fs4 = levs[l].fpc.size() * 4;
+      o_flo32[l] = take(3 * fs4); o_fpc32[l] = o_flo32[l] + fs4; o_finv32[l] = o_flo32[l] + 2 * fs4;
+      o_fgam32[l] = take(levs[l].fgam.size() * 4);
       o_lf32[l] = take(nlv * 4); o_lu32[l] = take(nlv * 4); o_lo32[l] = take(nlv * 4);
     }
   }
@@ -466,6 +468,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     L.fpc = (decltype(L.fpc))(A + o_fpc[l]); L.finv = (decltype(L.finv))(A + o_finv[l]);
     L.fgam = (decltype(L.fgam))(A + o_fgam[l]); L.fstride = levs[l].fstride;
     L.flo = (decltype(L.flo))(A + o_flo[l]);
+    L.facstride = (int)levs[l].fpc.size();
     L.f = (decltype(L.f))(A + o_lf[l]); L.u = (decltype(L.u))(A + o_lu[l]); L.o = (decltype(L.o))(A + o_lo[l]);
     if (ir) {
       L.fpc32 = (decltype(L.fpc32))(A + o_fpc32[l]); L.finv32 = (decltype(L.finv32))(A + o_finv32[l]);

@@ -405,7 +405,7 @@ constexpr int TMS = TM + 4;  // stride of the per-thread line-solve scratch
 // precision (column data h, 1/h, h_x, h_xx stay FP64 and are rounded when staged).
 template <class S>
 struct Lv {
-  int nc, nx, fstride;
+  int nc, nx, fstride, facstride;
   S rdx;
   const double *h, *ih, *hx, *hxx;
   const S *fpc, *finv, *flo, *fgam;
@@ -416,10 +416,10 @@ template <class S>
 DEV Lv<S> level_view(const Problem& P, int l) {
   const Level& L = P.lev[l];
   if constexpr (std::is_same_v<S, float>)
-    return Lv<S>{L.ncol, L.nx, L.fstride, S(1.0 / L.dx), L.h, L.ih, L.hx, L.hxx,
+    return Lv<S>{L.ncol, L.nx, L.fstride, L.facstride, S(1.0 / L.dx), L.h, L.ih, L.hx, L.hxx,
                  L.fpc32, L.finv32, L.flo32, L.fgam32, L.f32, L.u32, L.o32};
   else
-    return Lv<S>{L.ncol, L.nx, L.fstride, 1.0 / L.dx, L.h, L.ih, L.hx, L.hxx, L.fpc, L.finv, L.flo, L.fgam,
+    return Lv<S>{L.ncol, L.nx, L.fstride, L.facstride, 1.0 / L.dx, L.h, L.ih, L.hx, L.hxx, L.fpc, L.finv, L.flo, L.fgam,
                  L.f, L.u, L.o};
 }
 
@@ -514,15 +514,14 @@ DEV int coarse_centre(const Problem& P, int C, int ncc, int ncf) {
 // column data q (0 h, 1 1/h, 2 h_x, 3 h_xx) of global column cg, rounded to S
 template <class S>
 DEV S coldata(const Lv<S>& L, int q, int cg) {
-  const double* src = q == 0 ? L.h : (q == 1 ? L.ih : (q == 2 ? L.hx : L.hxx));
-  return S(src[cg]);
+  return S(L.h[q * L.nc + cg]);  // h | 1/h | h_x | h_xx, ncol apart
 }
 
 // line-solve factor qq (0 lo, 1 pc, 2 inv) at level j of global column cg
 template <class S>
 DEV S factor(const Lv<S>& L, int qq, int j, int cg) {
-  const S* src = qq == 0 ? L.flo : (qq == 1 ? L.fpc : L.finv);
-  return src[(size_t)j * (L.fstride ? L.fstride : 1) + (L.fstride ? cg : 0)];
+  // lo | pc | inv, facstride apart
+  return L.flo[qq * L.facstride + j * (L.fstride ? L.fstride : 1) + (L.fstride ? cg : 0)];
 }
 
 // o = u + omega L^-1 (f - M u) on level l, u = (uin or 0) + (e ? P e : 0) formed on load.

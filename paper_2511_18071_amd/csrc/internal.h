@@ -47,6 +47,8 @@ struct Level {
   const double SA_GLOBAL* flo;         // sub-diagonal of the column systems (same layout)
   const double SA_GLOBAL* fgam;
   int fstride;
+  int facstride;             // flo, fpc, finv (and their FP32 copies) lie facstride apart;
+                             // h, ih, hx, hxx lie ncol apart
   double SA_GLOBAL* f;                 // right-hand side of this level (level 0: unused, the input)
   double SA_GLOBAL* u;                 // smoothed iterate
   double SA_GLOBAL* o;                 // output of this level's cycle (level 0: unused, the output)
