@@ -214,6 +214,40 @@ DEV void staged_segments(const int (&cnt)[NS], Ld ld, St st) {
   });
 }
 
+// Rows of one width: R rows of `width` (<= BLOCK) elements, row r element lc loaded by
+// ld(r, lc) and stored by st(r, lc, v). Threads form BLOCK / width row lanes of `width`
+// threads (lc = thread % width, no division per element); each thread issues the loads of U
+// rows before any of its stores.
+template <int U, class Ld, class St>
+DEV void staged_rows(int R, int width, Ld ld, St st) {
+  using T = std::decay_t<decltype(ld(0, 0))>;
+  const int RP = BLOCK / width;
+  const int lc = threadIdx.x % width, r0 = threadIdx.x / width;
+  if (r0 >= RP) return;
+  for (int base = r0; base < R; base += U * RP) {
+    T v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int r = base + q * RP;
+      v[q] = r < R ? ld(r, lc) : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int r = base + q * RP;
+      if (r < R) st(r, lc, v[q]);
+    }
+  }
+}
+
+// fn(r, lc) over R rows of `width` (<= BLOCK) elements, same thread layout as staged_rows
+template <class Fn>
+DEV void for_rows(int R, int width, Fn fn) {
+  const int RP = BLOCK / width;
+  const int lc = threadIdx.x % width, r0 = threadIdx.x / width;
+  if (r0 >= RP) return;
+  for (int r = r0; r < R; r += RP) fn(r, lc);
+}
+
 // ------------------------------------------------------------------------------------------
 // operator tiles
 struct Tiles {
@@ -541,41 +575,33 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
   for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
     const int c0 = t * TM, w = min(TM, nc - c0);
     const Stage st{c0 - 1, w + 2, nc, P.periodic};
-    const int wu = zero ? 0 : w + 2;
-    const int cnt[5] = {wu * nl, w * nl, 4 * wu, 3 * nl * w, w};
-    staged_segments<16>(cnt, [&](int q, int k) -> S {
-      if (q == 0 || q == 2) {  // u with the prolongated correction, column data
-        const int width = wu;
-        const int j = k / width, lc = k - j * width;
-        const int c = c0 - 1 + lc;
-        if (!st.has(c)) return q == 2 ? S(1) : S(0);
+    // rows of width w + 2 (column c0 - 1 + lc): u (with the prolongated correction) and column
+    // data over the halo, f, factors and gamma over the tile's own columns
+    const int ww = w + 2;
+    const int nu = zero ? 0 : nl, ncd = zero ? 0 : 4;
+    const int rf = nu, rcd = rf + nl, rfac = rcd + ncd, rgam = rfac + 3 * nl;
+    const int fsm = L.fstride ? L.fstride : 1;
+    staged_rows<8>(rgam + 1, ww, [&](int r, int lc) -> S {
+      const int c = c0 - 1 + lc;
+      const bool own = lc >= 1 && lc <= w;
+      if (r < rf) {
+        if (!st.has(c)) return S(0);
         const int cg = st.col(c);
-        if (q == 2) return coldata(L, j, cg);
-        S v = uin ? uin[(size_t)j * nc + cg] : S(0);
-        if (e) v += prolong_at(P, nc, ncc, e, cg, j);
+        S v = uin ? uin[(size_t)r * nc + cg] : S(0);
+        if (e) v += prolong_at(P, nc, ncc, e, cg, r);
         return v;
       }
-      if (q == 1) {
-        const int j = k / w, lc = k - j * w;
-        return f[(size_t)j * nc + c0 + lc];
-      }
-      if (q == 3) {
-        const int per = nl * w;
-        const int qq = k / per, r = k - qq * per;
-        const int j = r / w, lc = r - j * w;
-        return factor(L, qq, j, c0 + lc);
-      }
-      return L.fgam[L.fstride ? c0 + k : 0];
-    }, [&](int q, int k, S v) {
-      if (q == 0) { const int j = k / wu, lc = k - j * wu; su[j * LW + lc] = v; }
-      else if (q == 1) { const int j = k / w, lc = k - j * w; sr[j * TM + lc] = v; }
-      else if (q == 2) { const int j = k / wu, lc = k - j * wu; scd[j * LW + lc] = v; }
-      else if (q == 3) {
-        const int per = nl * w;
-        const int qq = k / per, r = k - qq * per;
-        const int j = r / w, lc = r - j * w;
-        sfac[qq * TM * nl + j * TM + lc] = v;
-      } else sgam[k] = v;
+      if (r < rcd) return own ? f[(size_t)(r - rf) * nc + c] : S(0);
+      if (r < rfac) return st.has(c) ? coldata(L, r - rcd, st.col(c)) : S(1);
+      if (r < rgam) return own ? L.flo[(r - rfac) * fsm + (L.fstride ? c : 0)] : S(0);
+      return own ? L.fgam[L.fstride ? c : 0] : S(0);
+    }, [&](int r, int lc, S v) {
+      if (r < rf) su[r * LW + lc] = v;
+      else if (!(lc >= 1 && lc <= w) && (r < rcd || r >= rfac)) return;
+      else if (r < rcd) sr[(r - rf) * TM + lc - 1] = v;
+      else if (r < rfac) scd[(r - rcd) * LW + lc] = v;
+      else if (r < rgam) sfac[(r - rfac) * TM + lc - 1] = v;
+      else sgam[lc - 1] = v;
     });
     __syncthreads();
     if (!zero) {
@@ -636,39 +662,23 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
   for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
     const int c0 = t * TM, w = min(TM, nc - c0);
     const Stage st{c0 - 2, w + 4, nc, P.periodic};
+    // rows of width w + 4 (column c0 - 2 + lc): f, column data, factors lo | pc | inv, gamma
     const int ww = w + 4;
-    const int cnt[4] = {ww * nl, 4 * ww, 3 * nl * ww, ww};
-    staged_segments<16>(cnt, [&](int q, int k) -> S {
-      if (q == 0) {
-        const int j = k / ww, lc = k - j * ww;
-        const int c = c0 - 2 + lc;
-        return st.has(c) ? f[(size_t)j * nc + st.col(c)] : S(0);
-      }
-      if (q == 1) {
-        const int j = k / ww, lc = k - j * ww;
-        const int c = c0 - 2 + lc;
-        if (!st.has(c)) return S(1);
-        return coldata(L, j, st.col(c));
-      }
-      if (q == 2) {
-        const int per = nl * ww;
-        const int qq = k / per, r = k - qq * per;
-        const int j = r / ww, lc = r - j * ww;
-        const int c = c0 - 2 + lc;
-        if (!st.has(c)) return qq == 2 ? S(1) : S(0);
-        return factor(L, qq, j, st.col(c));
-      }
-      const int c = c0 - 2 + k;
-      return st.has(c) ? L.fgam[L.fstride ? st.col(c) : 0] : S(0);
-    }, [&](int q, int k, S v) {
-      if (q == 0) { const int j = k / ww, lc = k - j * ww; sf[j * LW + lc] = v; su[j * LW + lc] = v; }
-      else if (q == 1) { const int j = k / ww, lc = k - j * ww; scd[j * LW + lc] = v; }
-      else if (q == 2) {
-        const int per = nl * ww;
-        const int qq = k / per, r = k - qq * per;
-        const int j = r / ww, lc = r - j * ww;
-        sfac[qq * LW * nl + j * LW + lc] = v;
-      } else sgam[k] = v;
+    const int rcd = nl, rfac = nl + 4, rgam = rfac + 3 * nl;
+    const int fsm = L.fstride ? L.fstride : 1;
+    staged_rows<8>(rgam + 1, ww, [&](int r, int lc) -> S {
+      const int c = c0 - 2 + lc;
+      if (!st.has(c)) return (r >= rcd && r < rfac) || (r >= rfac + 2 * nl && r < rgam) ? S(1) : S(0);
+      const int cg = st.col(c);
+      if (r < rcd) return f[(size_t)r * nc + cg];
+      if (r < rfac) return coldata(L, r - rcd, cg);
+      if (r < rgam) return L.flo[(r - rfac) * fsm + (L.fstride ? cg : 0)];
+      return L.fgam[L.fstride ? cg : 0];
+    }, [&](int r, int lc, S v) {
+      if (r < rcd) { sf[r * LW + lc] = v; su[r * LW + lc] = v; }
+      else if (r < rfac) scd[(r - rcd) * LW + lc] = v;
+      else if (r < rgam) sfac[(r - rfac) * LW + lc] = v;
+      else sgam[lc] = v;
     });
     __syncthreads();
     if (threadIdx.x < w + 4 && st.has(c0 - 2 + (int)threadIdx.x)) {
@@ -682,21 +692,19 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
       su[j * LW + lc] *= om;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < w * nl; i += BLOCK) {
-      const int j = i / w, lc = i - j * w;
-      u[(size_t)j * nc + c0 + lc] = su[j * LW + lc + 2];
-    }
+    for_rows(nl, w, [&](int j, int lc) { u[(size_t)j * nc + c0 + lc] = su[j * LW + lc + 2]; });
     auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
     auto F = [&](int cc, int jj) { return sf[jj * LW + st.slot(cc)]; };
     auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
     int Cfirst, Clast;
     coarse_range(P, c0, w, nc, ncc, Cfirst, Clast);
     const int ncw = Clast - Cfirst + 1;
-    for (int i = threadIdx.x; i < ncw * nl; i += BLOCK) {
-      const int j = i / ncw, C = Cfirst + i - j * ncw;
-      auto Rr = [&](int cc) { return F(cc, j) - m_apply<S>(P, nc, L.rdx, cc, j, U, CD); };
-      fc[(size_t)j * ncc + C] = restrict_at<S>(P, C, ncc, nxc, nc, Rr);
-    }
+    if (ncw > 0)
+      for_rows(nl, ncw, [&](int j, int k) {
+        const int C = Cfirst + k;
+        auto Rr = [&](int cc) { return F(cc, j) - m_apply<S>(P, nc, L.rdx, cc, j, U, CD); };
+        fc[(size_t)j * ncc + C] = restrict_at<S>(P, C, ncc, nxc, nc, Rr);
+      });
     __syncthreads();
   }
 }
