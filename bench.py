@@ -25,6 +25,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# counters of the solve kernel taken on this workload (FETCH_SIZE and WRITE_SIZE runs) and the
+# hash of the kernel sources they were taken with: the traffic is reported only while the
+# sources are unchanged
+COUNTERS = os.path.join(ROOT, "profiles", "sa_solve_kernel_bar_513x17_counters.md")
+KERNEL_SOURCES = ("paper_2511_18071_amd/csrc/device.h", "paper_2511_18071_amd/csrc/solve64.hip",
+                  "paper_2511_18071_amd/csrc/internal.h")
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, steps: int, warmup: int):
+    """HBM bytes per EWMA launch of the solve kernel from the committed counter summary, or
+    None when it was taken on other kernel sources or another run configuration."""
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip("` ")] = v.strip("` ")
+    try:
+        same = (fields["kernel-source-sha256"] == kernel_hash() and fields["workload"] == workload
+                and int(fields["steps"]) == steps and int(fields["warmup"]) == warmup)
+        return float(fields["hbm-bytes-per-launch"]) if same else None
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -374,7 +409,9 @@ def main():
                   "failed_solves": plain["failed"]},
         "speedup_vs_plain": round(plain["wall"] / ewma["wall"], 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": measured_traffic(w.name, args.steps, args.warmup),
+                     "kernel_source_sha256": kernel_hash(),
                      "kernel": "sa_solve_kernel", "kernel_ms": round(kernel_ms, 4),
                      "launches": len(ewma["all_infos"]),
                      "algorithmic_bytes_per_launch": round(bytes_per)},
