@@ -988,29 +988,45 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
 // ------------------------------------------------------------------------------------------
 // Arnoldi pieces. V holds raw (unnormalised) basis vectors; vs[i] scales V_i to unit norm.
 
-// red[i] = vs[i] * (V_i . w), i < nv; red[nv] = ||w||^2 if with_norm. Each thread streams its
-// elements of one vector at a time, four loads in flight per accumulator set. V and w are
-// stored in S; products and sums are FP64.
+// Per-wave partial dot products of w with the vectors V_0..V_{nv-1} (and with itself when
+// with_norm) over this workgroup's elements, into wsum[i * NWAVE + wave]. Vectors go in groups
+// of four and every thread takes two of its elements per step, so ten loads are in flight per
+// step; products and sums are FP64, in a fixed order.
+template <class S>
+DEV void dot_groups(const Problem& P, Cl& cl, const S* V, int nv, const S* w, bool with_norm, double* wsum) {
+  const int n = P.n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int stride = cl.G * BLOCK, e0 = cl.rank * BLOCK + threadIdx.x;
+  const int nred = nv + (with_norm ? 1 : 0);
+  for (int g0 = 0; g0 < nred; g0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int e = e0; e < n; e += 2 * stride) {
+      const bool ok2 = e + stride < n;
+      const double w0 = w[e], w1 = ok2 ? double(w[e + stride]) : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = g0 + q;
+        if (i < nred) {
+          const S* a = i < nv ? V + (size_t)i * n : w;
+          const double a0 = a[e], a1 = ok2 ? double(a[e + stride]) : 0.0;
+          acc[q] += a0 * w0 + a1 * w1;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double sum = wave_sum(acc[q]);
+      if (lane == 0 && g0 + q < nred) wsum[(g0 + q) * NWAVE + wave] = sum;
+    }
+  }
+}
+
+// red[i] = vs[i] * (V_i . w), i < nv; red[nv] = ||w||^2 if with_norm. V and w are stored in S.
 template <class S>
 DEV void phase_dots(const Problem& P, Cl& cl, const S* V, const double* vs, int nv, const S* w,
                     bool with_norm, double* wsum, double* red) {
-  const int n = P.n;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int stride = cl.G * BLOCK;
   const int nred = nv + (with_norm ? 1 : 0);
-  for (int i = 0; i < nred; ++i) {
-    const S* a = (i < nv) ? V + (size_t)i * n : w;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int e = cl.rank * BLOCK + threadIdx.x;
-    for (; e + 3 * stride < n; e += 4 * stride) {
-      const double a0 = a[e], a1 = a[e + stride], a2 = a[e + 2 * stride], a3 = a[e + 3 * stride];
-      const double w0 = w[e], w1 = w[e + stride], w2 = w[e + 2 * stride], w3 = w[e + 3 * stride];
-      s0 += a0 * w0; s1 += a1 * w1; s2 += a2 * w2; s3 += a3 * w3;
-    }
-    for (; e < n; e += stride) s0 += double(a[e]) * double(w[e]);
-    double sum = wave_sum((s0 + s1) + (s2 + s3));
-    if (lane == 0) wsum[i * NWAVE + wave] = sum;
-  }
+  dot_groups<S>(P, cl, V, nv, w, with_norm, wsum);
   __syncthreads();
   for (int i = threadIdx.x; i < nred; i += BLOCK) {
     const double sm = waves_sum(wsum + i * NWAVE);
@@ -1019,50 +1035,44 @@ DEV void phase_dots(const Problem& P, Cl& cl, const S* V, const double* vs, int 
   __syncthreads();
 }
 
-// w -= sum_i h[i] vs[i] V_i (in place); then red[i] = vs[i] (V_i . w) for i < nv when dots,
-// or red[0] = ||w||^2 when !dots. Basis loads go in groups of four.
+// w -= sum_i h[i] vs[i] V_i (in place, this workgroup's elements; groups of four vectors, two
+// elements per step); then red[i] = vs[i] (V_i . w) for i < nv when dots, or red[0] = ||w||^2
+// when !dots. The dots read back the stored (rounded) w.
 template <class S>
 DEV void phase_update(const Problem& P, Cl& cl, const S* V, const double* vs, const double* h, int nv,
                       S* w, bool dots, double* wsum, double* red) {
   const int n = P.n;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int stride = cl.G * BLOCK;
+  const int stride = cl.G * BLOCK, e0 = cl.rank * BLOCK + threadIdx.x;
   double nrm = 0.0;
-  if (dots)
-    for (int i = threadIdx.x; i < nv * NWAVE; i += BLOCK) wsum[i] = 0.0;
-  __syncthreads();
-  // each wave walks its own 64-element chunks so that per-chunk sums stay in one order
-  for (int base = cl.rank * BLOCK + wave * 64; base < n; base += stride) {
-    const int e = base + lane;
-    const bool ok = e < n;
-    const size_t ec = ok ? (size_t)e : 0;
-    double we = ok ? double(w[e]) : 0.0;
-    int i = 0;
-    for (; i + 3 < nv; i += 4) {
-      const double v0 = V[(size_t)i * n + ec], v1 = V[(size_t)(i + 1) * n + ec];
-      const double v2 = V[(size_t)(i + 2) * n + ec], v3 = V[(size_t)(i + 3) * n + ec];
-      we -= v0 * (h[i] * vs[i]);
-      we -= v1 * (h[i + 1] * vs[i + 1]);
-      we -= v2 * (h[i + 2] * vs[i + 2]);
-      we -= v3 * (h[i + 3] * vs[i + 3]);
-    }
-    for (; i < nv; ++i) we -= double(V[(size_t)i * n + ec]) * (h[i] * vs[i]);
-    const S ws = ok ? S(we) : S(0);
-    if (ok) w[e] = ws;
-    if (dots) {
-      for (int q = 0; q < nv; ++q) {
-        double p = double(V[(size_t)q * n + ec]) * double(ws);
-        p = wave_sum(p);
-        if (lane == 0) wsum[q * NWAVE + wave] += p;
+  for (int e = e0; e < n; e += 2 * stride) {
+    const bool ok2 = e + stride < n;
+    double w0 = w[e], w1 = ok2 ? double(w[e + stride]) : 0.0;
+    for (int i = 0; i < nv; i += 4) {
+      double a0[4], a1[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const S* v = V + (size_t)(i + q < nv ? i + q : i) * n;
+        a0[q] = v[e];
+        a1[q] = ok2 ? double(v[e + stride]) : 0.0;
       }
-    } else {
-      nrm += double(ws) * double(ws);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (i + q < nv) {
+          const double c = h[i + q] * vs[i + q];
+          w0 -= a0[q] * c;
+          w1 -= a1[q] * c;
+        }
+      }
     }
+    const S s0 = S(w0), s1 = S(w1);
+    w[e] = s0;
+    if (ok2) w[e + stride] = s1;
+    nrm += double(s0) * double(s0) + (ok2 ? double(s1) * double(s1) : 0.0);
   }
-  __syncthreads();
   if (dots) {
-    for (int i = threadIdx.x; i < nv; i += BLOCK)
-      red[i] = vs[i] * waves_sum(wsum + i * NWAVE);
+    dot_groups<S>(P, cl, V, nv, w, false, wsum);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nv; i += BLOCK) red[i] = vs[i] * waves_sum(wsum + i * NWAVE);
     __syncthreads();
   } else {
     block_sum_to(nrm, wsum, red, 0);
