@@ -440,7 +440,7 @@ constexpr int TMS = TM + 4;  // stride of the per-thread line-solve scratch
 template <class S>
 struct Lv {
   int nc, nx, fstride, facstride;
-  S rdx;
+  S rdx, rds;  // 1/dx of the level, 1/dsigma
   const double *h, *ih, *hx, *hxx;
   const S *fpc, *finv, *flo, *fgam;
   S *f, *u, *o;
@@ -450,10 +450,11 @@ template <class S>
 DEV Lv<S> level_view(const Problem& P, int l) {
   const Level& L = P.lev[l];
   if constexpr (std::is_same_v<S, float>)
-    return Lv<S>{L.ncol, L.nx, L.fstride, L.facstride, S(1.0 / L.dx), L.h, L.ih, L.hx, L.hxx,
+    return Lv<S>{L.ncol, L.nx, L.fstride, L.facstride, S(1.0 / L.dx), S(1.0 / P.dsig), L.h, L.ih, L.hx, L.hxx,
                  L.fpc32, L.finv32, L.flo32, L.fgam32, L.f32, L.u32, L.o32};
   else
-    return Lv<S>{L.ncol, L.nx, L.fstride, L.facstride, 1.0 / L.dx, L.h, L.ih, L.hx, L.hxx, L.fpc, L.finv, L.flo, L.fgam,
+    return Lv<S>{L.ncol, L.nx, L.fstride, L.facstride, 1.0 / L.dx, 1.0 / P.dsig, L.h, L.ih, L.hx, L.hxx, L.fpc, L.finv,
+                 L.flo, L.fgam,
                  L.f, L.u, L.o};
 }
 
@@ -474,15 +475,14 @@ struct Stage {
 // (M u)(c, j): U(cc, jj) returns the staged field at unwrapped column cc; CD(cc, q) the
 // staged column data q = 0 h, 1 1/h, 2 h_x, 3 h_xx of unwrapped column cc.
 template <class S, class U, class CD>
-DEV S m_apply(const Problem& P, int nc, S rdx, int c, int j, U u, CD cd) {
+DEV S m_apply(const Problem& P, int nc, S rdx, S rds, S oms, int c, int j, U u, CD cd) {
   const int nz = P.nz;
-  const S rds = S(1.0 / P.dsig);
   const S half = S(0.5), two = S(2), one = S(1), quarter = S(0.25);
   if (j == nz) return u(c, j);
   if (!P.periodic && (c == 0 || c == nc - 1)) {
     if (j == 0) return u(c, j);
     const int w = (c == 0) ? 1 : nc - 2;
-    const S s = cd(w, 2) * (one - S(P.sig[j])) * cd(w, 1);
+    const S s = cd(w, 2) * oms * cd(w, 1);
     const S gx = (u(w + 1, j) - u(w - 1, j)) * half * rdx + s * (u(w, j + 1) - u(w, j - 1)) * half * rds;
     return c == 0 ? -gx : gx;
   }
@@ -493,7 +493,6 @@ DEV S m_apply(const Problem& P, int nc, S rdx, int c, int j, U u, CD cd) {
     const S gx = (u(c + 1, 1) - u(c - 1, 1)) * half * rdx + s1 * dz;
     return -hx * gx - dz * ih;
   }
-  const S oms = one - S(P.sig[j]);
   const S s = hx * oms * ih;
   const S sxx = oms * cd(c, 3) * ih - two * oms * hx * hx * ih * ih;
   const S uc = u(c, j);
@@ -581,7 +580,7 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
     const int nu = zero ? 0 : nl, ncd = zero ? 0 : 4;
     const int rf = nu, rcd = rf + nl, rfac = rcd + ncd, rgam = rfac + 3 * nl;
     const int fsm = L.fstride ? L.fstride : 1;
-    staged_rows<8>(rgam + 1, ww, [&](int r, int lc) -> S {
+    staged_rows<16>(rgam + 1, ww, [&](int r, int lc) -> S {
       const int c = c0 - 1 + lc;
       const bool own = lc >= 1 && lc <= w;
       if (r < rf) {
@@ -609,7 +608,7 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
       auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
       for (int i = threadIdx.x; i < TM * nl; i += BLOCK) {
         const int j = i / TM, lc = i - j * TM;
-        if (lc < w) sr[i] -= m_apply<S>(P, nc, L.rdx, c0 + lc, j, U, CD);
+        if (lc < w) sr[i] -= m_apply<S>(P, nc, L.rdx, L.rds, S(1.0 - P.sig[j]), c0 + lc, j, U, CD);
       }
       __syncthreads();
     }
@@ -666,7 +665,7 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
     const int ww = w + 4;
     const int rcd = nl, rfac = nl + 4, rgam = rfac + 3 * nl;
     const int fsm = L.fstride ? L.fstride : 1;
-    staged_rows<8>(rgam + 1, ww, [&](int r, int lc) -> S {
+    staged_rows<16>(rgam + 1, ww, [&](int r, int lc) -> S {
       const int c = c0 - 2 + lc;
       if (!st.has(c)) return (r >= rcd && r < rfac) || (r >= rfac + 2 * nl && r < rgam) ? S(1) : S(0);
       const int cg = st.col(c);
@@ -702,7 +701,8 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
     if (ncw > 0)
       for_rows(nl, ncw, [&](int j, int k) {
         const int C = Cfirst + k;
-        auto Rr = [&](int cc) { return F(cc, j) - m_apply<S>(P, nc, L.rdx, cc, j, U, CD); };
+        const S oms = S(1.0 - P.sig[j]);
+        auto Rr = [&](int cc) { return F(cc, j) - m_apply<S>(P, nc, L.rdx, L.rds, oms, cc, j, U, CD); };
         fc[(size_t)j * ncc + C] = restrict_at<S>(P, C, ncc, nxc, nc, Rr);
       });
     __syncthreads();
@@ -743,7 +743,8 @@ DEV void phase_restrict(const Problem& P, Cl& cl, int l, const S* f, const S* u,
     const int ncw = Clast - Cfirst + 1;
     for (int i = threadIdx.x; i < ncw * nl; i += BLOCK) {
       const int j = i / ncw, C = Cfirst + i - j * ncw;
-      auto Rr = [&](int cc) { return F(cc, j) - m_apply<S>(P, nc, L.rdx, cc, j, U, CD); };
+      const S oms = S(1.0 - P.sig[j]);
+      auto Rr = [&](int cc) { return F(cc, j) - m_apply<S>(P, nc, L.rdx, L.rds, oms, cc, j, U, CD); };
       fc[(size_t)j * ncc + C] = restrict_at<S>(P, C, ncc, nxc, nc, Rr);
     }
     __syncthreads();
