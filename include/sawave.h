@@ -95,7 +95,7 @@ typedef struct {
                         /* the FP64 residual with the FP64 path's trigger rule              */
   double rtol_inner;    /* FP32 resolution: a cycle whose Arnoldi estimate has fallen to    */
                         /* this fraction of its start hands its checked candidate to the    */
-                        /* next correction (SA_FP32_IR), default 1e-5                       */
+                        /* next correction (SA_FP32_IR), default 1e-4                       */
   int32_t max_refine;   /* FP32 cycles cap (SA_FP32_IR), default 200; SA_NOCONV after      */
   int32_t cluster;      /* workgroups cooperating on one solve; 0 = chosen from the size  */
   int32_t profile;      /* 1: accumulate per-phase device time (sa_get_phase_times), 0      */

@@ -54,7 +54,7 @@ def _nrm(v) -> float:
     return float(np.sqrt(np.dot(v, v)))
 
 
-def solve(A, b, x0, minv, m: int, rtol: float, rtol_inner: float = 1e-5, max_refine: int = 200,
+def solve(A, b, x0, minv, m: int, rtol: float, rtol_inner: float = 1e-4, max_refine: int = 200,
           inner=np.float32, use_trigger: bool = True):
     """x with ||b - A x|| <= rtol ||b|| by refinement around single-precision GMRES cycles."""
     b = np.asarray(b, dtype=np.float64)

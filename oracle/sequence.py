@@ -40,7 +40,7 @@ class Options:
     n_init: int = 0
     tau_drop: float = TAU_DROP
     precision: str = "fp64"  # fp64 | fp32_ir
-    rtol_inner: float = 1e-5
+    rtol_inner: float = 1e-4
     max_refine: int = 200
 
 

@@ -47,7 +47,7 @@ extern "C" void sa_default_options(sa_options* o) {
   o->n_init = 0;
   o->tau_drop = 1e-7;
   o->precision = SA_FP64;
-  o->rtol_inner = 1e-5;
+  o->rtol_inner = 1e-4;
   o->max_refine = 200;
   o->cluster = 0;
   o->profile = 0;
@@ -326,19 +326,32 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   }
   const size_t head = (size_t)PSTRIDE + NWAVE * (MMAX + 2) + (size_t)(m + 1) * m + 2 * m + 2 * (m + 1) + m + KMAX +
                       4 * KMAX * KMAX + 8;
-  const int TWMh = TX + 3, TWGMh = TXG + 3;
+  const int TWMh = TX + 3;
   auto opcoef = [&](int W) { return (size_t)(49 + 9 * nl + 5 * (W + 6)); };
   const size_t need_op = (size_t)(TWMh + 12 + 2 * (TWMh + 6)) * nl + opcoef(TWMh) + NWAVE;
-  const size_t need_gram = opt.guess == SA_GUESS_EWMA
-                               ? (size_t)(k * TWGMh + TWGMh + TWGMh + 12 + 2 * (TWGMh + 6)) * nl + opcoef(TWGMh) : 0;
+  // block operator of the guess on tiles of tg columns (widest tile tg + 3)
+  auto need_gram_of = [&](int tg) {
+    const int Wg = tg + 3;
+    return opt.guess == SA_GUESS_EWMA ? (size_t)(k * Wg + Wg + Wg + 12 + 2 * (Wg + 6)) * nl + opcoef(Wg) : 0;
+  };
   const int TMSh = 64 + 4;  // preconditioner tile with its 2-column halo
   size_t need_pc = (size_t)5 * TMSh * nl + 5 * TMSh;
   if (opt.precond == SA_PC_MG && need_pc < (size_t)cn + BLOCK)
     need_pc = (size_t)cn + BLOCK;  // coarsest solve: f and partial sums
-  size_t big = need_op;
-  if (need_gram > big) big = need_gram;
-  if (need_pc > big) big = need_pc;
-  if (big < 2 * (size_t)BLOCK) big = 2 * (size_t)BLOCK;  // the Gram pass combines per-thread partials
+  auto big_of = [&](size_t need_gram) {
+    size_t big = need_op;
+    if (need_gram > big) big = need_gram;
+    if (need_pc > big) big = need_pc;
+    if (big < 2 * (size_t)BLOCK) big = 2 * (size_t)BLOCK;  // the Gram pass combines per-thread partials
+    return big;
+  };
+  // 32-column guess tiles (half the tiles per workgroup) when they fit the 160 KB of LDS
+  int txg = 32;
+  size_t big = big_of(need_gram_of(32));
+  if ((head + big) * sizeof(double) > 160 * 1024) {
+    txg = 16;
+    big = big_of(need_gram_of(16));
+  }
   p->lds_solve = (head + big) * sizeof(double);
   p->lds_op = need_op * sizeof(double);
   p->lds_pc = need_pc * sizeof(double);
@@ -488,7 +501,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   P.x = (decltype(P.x))(A + o_x); P.xc = (decltype(P.xc))(A + o_xc); P.r = (decltype(P.r))(A + o_r); P.rc = (decltype(P.rc))(A + o_rc);
   P.t = (decltype(P.t))(A + o_t); P.V = (decltype(P.V))(A + o_V);
   P.Y[0] = (std::remove_reference_t<decltype(P.Y[0])>)(A + o_Y0); P.Y[1] = (std::remove_reference_t<decltype(P.Y[1])>)(A + o_Y1);
-  P.k = k; P.m = m; P.max_restarts = opt.max_restarts; P.tau_drop = opt.tau_drop;
+  P.k = k; P.m = m; P.max_restarts = opt.max_restarts; P.tau_drop = opt.tau_drop; P.txg = txg;
   P.partials = (decltype(P.partials))(A + o_part); P.bar = (decltype(P.bar))(A + o_bar); P.flags = (decltype(P.flags))(A + o_flags);
   P.log = (decltype(P.log))(A + o_log); P.G = G;
   p->dp = (Problem*)(A + o_prob);

@@ -34,7 +34,6 @@ extern __shared__ double dyn_lds[];
 
 constexpr long SPIN_LIMIT = 1L << 25;
 constexpr int TWM = TX + 3;   // widest operator tile (a last wall tile absorbs up to 3 columns)
-constexpr int TWGM = TXG + 3;
 
 // ------------------------------------------------------------------------------------------
 // cluster of workgroups cooperating on one problem
@@ -267,9 +266,11 @@ DEV constexpr int opcoef_size(int W, int nl) { return 49 + 9 * nl + 5 * (W + 6);
 // 6-column halo, sgx/sgz (W+6) x nl gradient of the previous stage, sc the coefficient block
 // (x and sigma weights, sigma windows and values, per-column geometry of both stages). Every
 // operand of the stencil loops is in LDS. load(level, column, tile column) returns the input;
-// out(level, tile column, column, value) receives A x.
+// out(level, tile column, column, value) receives A x. coef = false keeps the coefficient
+// block of the previous call on the same tile (several inputs on one tile).
 template <class S, int W, class Load, class Out>
-DEV void tile_operator(const Problem& P, int c0, int w, Load load, S* sx, S* sgx, S* sgz, S* sc, Out out) {
+DEV void tile_operator(const Problem& P, int c0, int w, Load load, S* sx, S* sgx, S* sgz, S* sc, Out out,
+                       bool coef = true) {
   const int nc = P.ncol, nl = P.nl, nz = P.nz;
   constexpr int LX = W + 12, LG = W + 6;
   S* swchi = sc;                       // 49
@@ -281,23 +282,26 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, S* sx, S* sgx
   S* ghc = gdp + LG;                   // LG: h_chi
   S* gic = ghc + LG;                   // LG: 1/d cur
   S* gdc = gic + LG;                   // LG: d_chi cur
-  // stage the input with a 6-column halo: load(level, column, tile-local column)
-  staged<8>(LX * nl, [&](int i) -> S {
-    const int lj = i / LX, lc = i - lj * LX;
-    int c = c0 - 6 + lc;
-    S v = S(0);
-    if (lc < w + 12) {
-      if (P.periodic) {
-        c = ((c % nc) + nc) % nc;
-        v = load(lj, c, lc);
-      } else if (c >= 0 && c < nc) {
-        v = load(lj, c, lc);
-      }
-    }
-    return v;
-  }, [&](int i, S v) { sx[i] = v; });
+  // stage the input with a 6-column halo, load(level, column, tile-local column), and (coef)
+  // the coefficient block, in one batch of loads
+  const int nin = LX * nl;
   const int ncoef = 49 + 8 * nl;
-  staged<4>(ncoef + 5 * LG, [&](int i) -> S {
+  staged<8>(nin + (coef ? ncoef + 5 * LG : 0), [&](int i) -> S {
+    if (i < nin) {
+      const int lj = i / LX, lc = i - lj * LX;
+      int c = c0 - 6 + lc;
+      S v = S(0);
+      if (lc < w + 12) {
+        if (P.periodic) {
+          c = ((c % nc) + nc) % nc;
+          v = load(lj, c, lc);
+        } else if (c >= 0 && c < nc) {
+          v = load(lj, c, lc);
+        }
+      }
+      return v;
+    }
+    i -= nin;
     if (i < 49) return S(P.wchi[i]);
     if (i < 49 + 7 * nl) return S(P.wsig[i - 49]);
     if (i < 49 + 8 * nl) return S(P.sig[i - 49 - 7 * nl]);
@@ -308,10 +312,12 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, S* sx, S* sgx
     if (q == 2) return S(P.hchi[c]);
     return S(P.geo[(q < 2 ? q : q - 1) * nc + c]);
   }, [&](int i, S v) {
-    if (i < ncoef) swchi[i] = v;
-    else gip[i - ncoef] = v;
+    if (i < nin) sx[i] = v;
+    else if (i - nin < ncoef) swchi[i - nin] = v;
+    else gip[i - nin - ncoef] = v;
   });
-  for (int j = threadIdx.x; j < nl; j += BLOCK) sstart[j] = P.ssig[j];
+  if (coef)
+    for (int j = threadIdx.x; j < nl; j += BLOCK) sstart[j] = P.ssig[j];
   __syncthreads();
   // gradient of the previous stage: G_x = D_x p + sigma_x D_sigma p, G_z = D_sigma p / d
   for (int i = threadIdx.x; i < LG * nl; i += BLOCK) {
@@ -1190,12 +1196,13 @@ DEV dd dd_sqrt(dd a) {
 // sums compensated (TwoSum), so the Gram carries the accuracy a QR of W would: its
 // condition number is the square of W's, and the sketch's columns are nearly dependent.
 // Output: red[2 i], red[2 i + 1] = hi, lo of item i (pairs in row order, then c).
+template <int TG>
 DEV void phase_block_gram(const Problem& P, Cl& cl, const SolveArgs& a, const double* Yo, double* Yn,
                           double* lds, double* red) {
   const int nc = P.ncol, nl = P.nl, k = P.k;
   const size_t n = P.n;
-  const Tiles T = tiles_of(P, TXG);
-  constexpr int W = TWGM;
+  const Tiles T = tiles_of(P, TG);
+  constexpr int W = TG + 3;  // widest tile (a last wall tile absorbs up to 3 columns)
   double* sW = lds;                         // k x W x nl
   double* sb = sW + (size_t)k * W * nl;     // W x nl
   double* sx = sb + W * nl;                 // (W+12) x nl
@@ -1217,8 +1224,8 @@ DEV void phase_block_gram(const Problem& P, Cl& cl, const SolveArgs& a, const do
   }
   double accS = 0.0, accC = 0.0;
   for (int t = cl.rank; t < T.nt; t += cl.G) {
-    const int c0 = t * TXG;
-    const int w = (t == T.nt - 1) ? nc - c0 : TXG;
+    const int c0 = t * TG;
+    const int w = (t == T.nt - 1) ? nc - c0 : TG;
     for (int i = threadIdx.x; i < W * nl; i += BLOCK) {
       const int lj = i / W, lc = i - lj * W;
       sb[i] = (lc < w) ? a.b[(size_t)lj * nc + c0 + lc] : 0.0;
@@ -1239,7 +1246,7 @@ DEV void phase_block_gram(const Problem& P, Cl& cl, const SolveArgs& a, const do
       double* wcol = sW + (size_t)col * W * nl;
       tile_operator<double, W>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int, double v) {
         wcol[lj * W + lc] = v;
-      });
+      }, col == 0);
     }
     // zero the unused tile columns so that the products can run over the full W x nl
     for (int i = threadIdx.x; i < k * W * nl; i += BLOCK) {
@@ -1470,7 +1477,9 @@ DEV bool solve_start(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S
   double* Yn = P.Y[a.ycur ^ 1];
   int rank = 0;
   if (a.sketch_guess) {
-    phase_block_gram(P, cl, a, Yo, Yn, S.big, S.red);
+    // tiles of 32 columns when the block operator's LDS fits, else 16
+    if (P.txg == 32) phase_block_gram<32>(P, cl, a, Yo, Yn, S.big, S.red);
+    else phase_block_gram<16>(P, cl, a, Yo, Yn, S.big, S.red);
     const int nv = P.k * (P.k + 1) / 2 + P.k;
     cluster_sum_dd(cl, S.red, nv);
     clk.tick(PH_GUESS);

@@ -21,7 +21,6 @@ constexpr int KMAX = 16;          // largest sketch rank handled on the device
 constexpr int MMAX = 64;          // largest restart length
 constexpr int MAXLEV = 24;        // multigrid levels
 constexpr int TX = 64;            // columns per operator tile
-constexpr int TXG = 16;           // columns per tile of the block operator (sketch guess)
 constexpr int HW = 3;             // stencil half width (seven-point first derivatives)
 constexpr int NLMAX = 66;         // largest number of levels nz + 1
 constexpr int PSTRIDE = 320;      // doubles per workgroup in the reduction scratch
@@ -94,6 +93,7 @@ struct Problem {
   float SA_GLOBAL* r32;
   // sketch / options
   int k, m, max_restarts;
+  int txg;                   // columns per tile of the block operator of the guess (16 or 32)
   double tau_drop;
   int precision, max_refine;
   double rtol_inner;
