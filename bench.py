@@ -83,8 +83,8 @@ def parse():
 
 
 def default_cluster(w) -> int:
-    # one workgroup per ~4 operator tiles, at least 1, at most 64
-    return int(min(64, max(1, (w.ncol + 255) // 256 * 2)))
+    # the library's own default: one workgroup per 64-column tile of the finest level, at most 64
+    return int(min(64, max(1, (w.ncol + 63) // 64)))
 
 
 def traffic_bytes(w, infos, pcv, k) -> float:

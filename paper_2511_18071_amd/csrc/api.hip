@@ -317,8 +317,10 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
 
   // ---- cluster size and LDS
   const int m = opt.restart, k = opt.k;
+  // default cluster: one 64-column preconditioner tile of the finest level per workgroup
+  // (the passes of the V-cycle then take one tile-latency each), at most 64 workgroups
   int G = opt.cluster;
-  if (G <= 0) G = 1;
+  if (G <= 0) G = (ncol + 63) / 64 < 64 ? (ncol + 63) / 64 : 64;
   hipDeviceProp_t prop{};
   if (!bytes_only && hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
     delete p;
