@@ -347,12 +347,13 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     if (big < 2 * (size_t)BLOCK) big = 2 * (size_t)BLOCK;  // the Gram pass combines per-thread partials
     return big;
   };
-  // 32-column guess tiles (half the tiles per workgroup) when they fit the 160 KB of LDS
-  int txg = 32;
-  size_t big = big_of(need_gram_of(32));
-  if ((head + big) * sizeof(double) > 160 * 1024) {
-    txg = 16;
-    big = big_of(need_gram_of(16));
+  // the widest guess tiles (64, 32 or 16 columns: fewer tiles per workgroup) whose block
+  // operator fits the 160 KB of LDS
+  int txg = 64;
+  size_t big = big_of(need_gram_of(txg));
+  while (txg > 16 && (head + big) * sizeof(double) > 160 * 1024) {
+    txg /= 2;
+    big = big_of(need_gram_of(txg));
   }
   p->lds_solve = (head + big) * sizeof(double);
   p->lds_op = need_op * sizeof(double);

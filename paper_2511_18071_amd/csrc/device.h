@@ -1477,8 +1477,9 @@ DEV bool solve_start(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S
   double* Yn = P.Y[a.ycur ^ 1];
   int rank = 0;
   if (a.sketch_guess) {
-    // tiles of 32 columns when the block operator's LDS fits, else 16
-    if (P.txg == 32) phase_block_gram<32>(P, cl, a, Yo, Yn, S.big, S.red);
+    // the widest tiles (64, 32 or 16 columns) whose block operator fits the LDS
+    if (P.txg == 64) phase_block_gram<64>(P, cl, a, Yo, Yn, S.big, S.red);
+    else if (P.txg == 32) phase_block_gram<32>(P, cl, a, Yo, Yn, S.big, S.red);
     else phase_block_gram<16>(P, cl, a, Yo, Yn, S.big, S.red);
     const int nv = P.k * (P.k + 1) / 2 + P.k;
     cluster_sum_dd(cl, S.red, nv);

@@ -93,7 +93,7 @@ struct Problem {
   float SA_GLOBAL* r32;
   // sketch / options
   int k, m, max_restarts;
-  int txg;                   // columns per tile of the block operator of the guess (16 or 32)
+  int txg;                   // columns per tile of the block operator of the guess (16, 32, 64)
   double tau_drop;
   int precision, max_refine;
   double rtol_inner;
