@@ -74,8 +74,13 @@ def parse():
     ap.add_argument("--serve-sims", type=int, default=256, help="serving: simulations")
     ap.add_argument("--serve-systems", type=int, default=10, help="serving: systems per simulation")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving: offered solves/s (open loop)")
+    ap.add_argument("--serve-upw", type=int, default=20000,
+                    help="serving: unknowns per workgroup when the server sizes the clusters")
     ap.add_argument("--serve-baseline-stride", type=int, default=8,
                     help="serving: the one-at-a-time FP64 baseline solves every k-th simulation")
+    ap.add_argument("--operator-probe", default="", metavar="WORKLOAD",
+                    help="only apply the operator of WORKLOAD's first system 50 times (standalone "
+                         "kernel: one workgroup per 64-column tile) and print its rate")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes five times (the "
                          "reference kernel that scales HBM counter readings)")
@@ -253,7 +258,7 @@ def run_serving(args):
 
     def serve(arrivals, label):
         say(f"  {label}: opening {len(sims)} simulations ({time.perf_counter() - t_setup:.0f} s)")
-        srv = B.Server(stream=stream)
+        srv = B.Server(stream=stream, unknowns_per_workgroup=args.serve_upw)
         ids = [srv.open(w, precision="fp32_ir") for w in sims]
         if any(i is None for i in ids):
             raise RuntimeError("serving mix does not fit the HBM budget")
@@ -331,7 +336,8 @@ def run_serving(args):
         "data": "synthetic",
         "config": {"workload": f"serving_mix({len(sims)} simulations x {nsys} systems, seed 5)",
                    "unknowns_total": total_unknowns, "precision": "fp32 inner GMRES, fp64 refinement",
-                   "guess": "EWMA", "hbm_bytes_resident": sat["bytes"]},
+                   "guess": "EWMA", "hbm_bytes_resident": sat["bytes"],
+                   "unknowns_per_workgroup": args.serve_upw},
         "saturation": s_sat,
         "open_loop": dict(offered_solves_per_s=args.serve_rate, **s_ol),
         "baseline_one_at_a_time_fp64_cold": {
@@ -359,8 +365,37 @@ def copy_probe(nbytes: int):
     print(json.dumps({"copy_probe_bytes": n * 8, "launches": 5}), flush=True)
 
 
+def operator_probe(name: str, reps: int = 50):
+    """The standalone operator kernel on the first system of a workload: x and y in HBM, one
+    launch per application (plus the geometry kernel), synchronised each time."""
+    import torch
+    from paper_2511_18071_amd import binding as B
+    from paper_2511_18071_amd import workload as W
+    w = W.get(name)
+    ep, ec, ps = w.system(0)
+    e0, e1 = torch.from_numpy(ep).cuda(), torch.from_numpy(ec).cuda()
+    x = torch.from_numpy(ps).cuda()
+    y = torch.empty_like(x)
+    p = B.Problem.from_workload(w, stream=torch.cuda.current_stream(), precond="none", guess="cold")
+    p.set_surface(e0, e1)
+    for _ in range(5):
+        p.apply_operator(x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p.apply_operator(x, y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    p.close()
+    print(json.dumps({"operator_probe": name, "unknowns": w.n, "launches": reps + 5,
+                      "ms_per_application": round(1e3 * dt, 4)}), flush=True)
+
+
 def main():
     args = parse()
+    if args.operator_probe:
+        operator_probe(args.operator_probe)
+        return
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return

@@ -202,7 +202,7 @@ typedef struct {
                                   /* workgroups (at least one simulation's cluster)          */
   int32_t max_batch;              /* solves per tick, 0 = as many as are co-resident          */
   int32_t unknowns_per_workgroup; /* cluster size of simulations opened with cluster = 0:    */
-                                  /* ceil(n / this), 1..16, default 40000                    */
+                                  /* ceil(n / this), 1..16, default 20000                    */
   int32_t reserved;
 } sa_server_options;
 

@@ -93,7 +93,7 @@ extern "C" void sa_server_default_options(sa_server_options* o) {
   o->hbm_budget = 0;
   o->max_inflight = 4;
   o->max_batch = 0;
-  o->unknowns_per_workgroup = 40000;
+  o->unknowns_per_workgroup = 20000;
 }
 
 static int set_lds(sa_server* s, size_t lds) {
