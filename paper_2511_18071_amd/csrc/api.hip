@@ -130,6 +130,8 @@ static void centred_h(const std::vector<double>& h, int periodic, double dx, std
   }
 }
 
+static constexpr int TM_HOST = 64;  // the V-cycle's default tile width (device TM)
+
 static size_t round_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Elimination factors of the vertical line systems of the still-water operator on one level:
@@ -485,6 +487,9 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     L.fgam = (decltype(L.fgam))(A + o_fgam[l]); L.fstride = levs[l].fstride;
     L.flo = (decltype(L.flo))(A + o_flo[l]);
     L.facstride = (int)levs[l].fpc.size();
+    // narrower tiles where the cluster has more workgroups than 64-column tiles (not on the
+    // levels the rank-0 workgroup runs alone)
+    L.tm = (l < tail && (levs[l].ncol + 63) / 64 < G) ? 32 : TM_HOST;
     L.f = (decltype(L.f))(A + o_lf[l]); L.u = (decltype(L.u))(A + o_lu[l]); L.o = (decltype(L.o))(A + o_lo[l]);
     if (ir) {
       L.fpc32 = (decltype(L.fpc32))(A + o_fpc32[l]); L.finv32 = (decltype(L.finv32))(A + o_finv32[l]);

@@ -565,20 +565,20 @@ DEV S factor(const Lv<S>& L, int qq, int j, int cg) {
 
 // o = u + omega L^-1 (f - M u) on level l, u = (uin or 0) + (e ? P e : 0) formed on load.
 // Residuals are formed by all threads in LDS, then one thread per column eliminates.
-template <class S>
+template <class S, int TW = TM>
 DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, const S* e, S* o, S* lds) {
   const Lv<S> L = level_view<S>(P, l);
   const int nc = L.nc, nl = P.nl, nz = P.nz;
   const int ncc = e ? P.lev[l + 1].ncol : 0;
-  constexpr int LW = TM + 2;
+  constexpr int LW = TW + 2;
   S* su = lds;                 // LW x nl
-  S* sr = su + LW * nl;        // TM x nl: f, then the residual, then the correction
-  S* scd = sr + TM * nl;       // 4 x LW
-  S* sfac = scd + 4 * LW;      // 3 x TM x nl
-  S* sgam = sfac + 3 * TM * nl;  // TM
+  S* sr = su + LW * nl;        // TW x nl: f, then the residual, then the correction
+  S* scd = sr + TW * nl;       // 4 x LW
+  S* sfac = scd + 4 * LW;      // 3 x TW x nl
+  S* sgam = sfac + 3 * TW * nl;  // TW
   const bool zero = !uin && !e;
-  for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
-    const int c0 = t * TM, w = min(TM, nc - c0);
+  for (int t = cl.rank; t < (nc + TW - 1) / TW; t += cl.G) {
+    const int c0 = t * TW, w = min(TW, nc - c0);
     const Stage st{c0 - 1, w + 2, nc, P.periodic};
     // rows of width w + 2 (column c0 - 1 + lc): u (with the prolongated correction) and column
     // data over the halo, f, factors and gamma over the tile's own columns
@@ -603,29 +603,29 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
     }, [&](int r, int lc, S v) {
       if (r < rf) su[r * LW + lc] = v;
       else if (!(lc >= 1 && lc <= w) && (r < rcd || r >= rfac)) return;
-      else if (r < rcd) sr[(r - rf) * TM + lc - 1] = v;
+      else if (r < rcd) sr[(r - rf) * TW + lc - 1] = v;
       else if (r < rfac) scd[(r - rcd) * LW + lc] = v;
-      else if (r < rgam) sfac[(r - rfac) * TM + lc - 1] = v;
+      else if (r < rgam) sfac[(r - rfac) * TW + lc - 1] = v;
       else sgam[lc - 1] = v;
     });
     __syncthreads();
     if (!zero) {
       auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
       auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
-      for (int i = threadIdx.x; i < TM * nl; i += BLOCK) {
-        const int j = i / TM, lc = i - j * TM;
+      for (int i = threadIdx.x; i < TW * nl; i += BLOCK) {
+        const int j = i / TW, lc = i - j * TW;
         if (lc < w) sr[i] -= m_apply<S>(P, nc, L.rdx, L.rds, S(1.0 - P.sig[j]), c0 + lc, j, U, CD);
       }
       __syncthreads();
     }
     if (threadIdx.x < w) {
       const int lc = threadIdx.x;
-      line_solve<S>(nz, sgam[lc], sr + lc, TM, sfac + lc, sfac + TM * nl + lc, sfac + 2 * TM * nl + lc, TM);
+      line_solve<S>(nz, sgam[lc], sr + lc, TW, sfac + lc, sfac + TW * nl + lc, sfac + 2 * TW * nl + lc, TW);
     }
     __syncthreads();
     const S om = S(P.omega);
-    for (int i = threadIdx.x; i < TM * nl; i += BLOCK) {
-      const int j = i / TM, lc = i - j * TM;
+    for (int i = threadIdx.x; i < TW * nl; i += BLOCK) {
+      const int j = i / TW, lc = i - j * TW;
       if (lc < w) o[(size_t)j * nc + c0 + lc] = (zero ? S(0) : su[j * LW + lc + 1]) + om * sr[i];
     }
     __syncthreads();
@@ -653,19 +653,19 @@ DEV S restrict_at(const Problem& P, int C, int ncc, int nxc, int nc, RR Rr) {
 // Pre-smoothing from zero, residual and restriction in one pass (nu1 = 1):
 // u = omega L^-1 f on the tile plus a 2-column halo, u written for the tile's columns,
 // fc(C) = full weighting of f - M u at the fine columns around C's centre.
-template <class S>
+template <class S, int TW = TM>
 DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S* lds) {
   const Lv<S> L = level_view<S>(P, l);
   const int nc = L.nc, nl = P.nl, nz = P.nz;
   const int ncc = P.lev[l + 1].ncol, nxc = P.lev[l + 1].nx;
-  constexpr int LW = TM + 4;
+  constexpr int LW = TW + 4;
   S* sf = lds;                 // LW x nl
   S* su = sf + LW * nl;        // LW x nl
   S* scd = su + LW * nl;       // 4 x LW
   S* sfac = scd + 4 * LW;      // 3 x LW x nl
   S* sgam = sfac + 3 * LW * nl;  // LW
-  for (int t = cl.rank; t < ptiles(nc); t += cl.G) {
-    const int c0 = t * TM, w = min(TM, nc - c0);
+  for (int t = cl.rank; t < (nc + TW - 1) / TW; t += cl.G) {
+    const int c0 = t * TW, w = min(TW, nc - c0);
     const Stage st{c0 - 2, w + 4, nc, P.periodic};
     // rows of width w + 4 (column c0 - 2 + lc): f, column data, factors lo | pc | inv, gamma
     const int ww = w + 4;
@@ -877,7 +877,8 @@ DEV void mg_down(const Problem& P, Cl& cl, int l, const S* v, S* lds) {
   S* A = L.u;
   S* B = L.o;
   if (P.nu1 == 1) {
-    phase_down<S>(P, cl, l, f, A, Lc.f, lds);
+    if (P.lev[l].tm == 32) phase_down<S, 32>(P, cl, l, f, A, Lc.f, lds);
+    else phase_down<S, TM>(P, cl, l, f, A, Lc.f, lds);
     csync(cl);
     return;
   }
@@ -920,7 +921,9 @@ DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z
     return A;
   }
   S* dst = (P.nu2 == 1) ? out : B;
-  phase_sweep<S>(P, cl, l, f, A, e, dst, lds);  // first post-sweep, correction added on load
+  // first post-sweep, correction added on load (on the level's tile width)
+  if (P.lev[l].tm == 32) phase_sweep<S, 32>(P, cl, l, f, A, e, dst, lds);
+  else phase_sweep<S, TM>(P, cl, l, f, A, e, dst, lds);
   csync(cl);
   const S* prev = dst;
   for (int s = 1; s < P.nu2; ++s) {
