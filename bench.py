@@ -73,7 +73,8 @@ def parse():
     ap.add_argument("--cpu-solves", type=int, default=30)
     ap.add_argument("--serve-sims", type=int, default=256, help="serving: simulations")
     ap.add_argument("--serve-systems", type=int, default=10, help="serving: systems per simulation")
-    ap.add_argument("--serve-rate", type=float, default=200.0, help="serving: offered solves/s (open loop)")
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="serving: offered solves/s of the open loop (default: 0.7 x the measured saturation rate)")
     ap.add_argument("--serve-upw", type=int, default=20000,
                     help="serving: unknowns per workgroup when the server sizes the clusters")
     ap.add_argument("--serve-baseline-stride", type=int, default=8,
@@ -219,7 +220,8 @@ def run_serving(args):
 
     Inputs (surfaces and b = A p* of every system) are formed by the library's operator and
     resident in HBM first. Three runs on fresh simulations: saturation (every request queued
-    at t = 0, FIFO per simulation), open loop (Poisson arrivals at --serve-rate, round robin
+    at t = 0, FIFO per simulation), open loop (Poisson arrivals at --serve-rate, by default 70 %
+    of the saturation rate just measured, so that latency is that of a sustainable load; round robin
     over the simulations), both FP32-inner refinement with the EWMA guess through the server;
     and the one-at-a-time FP64 cold-start path (sa_solve, no sketch) on every k-th simulation.
     All at relative residual 1e-8 checked on the FP64 residual.
@@ -288,8 +290,9 @@ def run_serving(args):
         return dict(wall=wall, lat=np.array(lat), infos=infos, bytes=bytes_used)
 
     sat = serve(np.zeros(nreq), "saturation")
+    rate = args.serve_rate if args.serve_rate else 0.7 * nreq / sat["wall"]
     rng = np.random.default_rng(5)
-    arr = np.cumsum(rng.exponential(1.0 / args.serve_rate, nreq))
+    arr = np.cumsum(rng.exponential(1.0 / rate, nreq))
     ol = serve(arr, "open loop")
     say(f"  baseline: one-at-a-time FP64 cold start ({time.perf_counter() - t_setup:.0f} s)")
     # one-at-a-time FP64 cold start (sa_solve) on every k-th simulation
@@ -339,7 +342,7 @@ def run_serving(args):
                    "guess": "EWMA", "hbm_bytes_resident": sat["bytes"],
                    "unknowns_per_workgroup": args.serve_upw},
         "saturation": s_sat,
-        "open_loop": dict(offered_solves_per_s=args.serve_rate, **s_ol),
+        "open_loop": dict(offered_solves_per_s=round(rate, 2), **s_ol),
         "baseline_one_at_a_time_fp64_cold": {
             "solves_per_s": round(base_rate, 2), "solves": len(base_lat),
             "sample": f"every {args.serve_baseline_stride}th simulation, all its systems",
