@@ -43,37 +43,49 @@ struct Cl {
   int* flags;
   double* partials;
   int pbuf;
+  unsigned gen;  // barrier generation this workgroup last saw complete (thread 0 only)
 };
+
+// Workgroup `rank` of a cluster of G on problem P. Thread 0 reads the barrier generation once:
+// it advances only after all G workgroups have arrived at a barrier, and each reads it before
+// its first arrival, so all start from the same value; the barrier then tracks it locally.
+DEV Cl make_cl(const Problem& P, int rank, int G) {
+  Cl cl{rank, G, P.bar, P.flags, P.partials, 0, 0u};
+  if (threadIdx.x == 0 && G > 1) cl.gen = __hip_atomic_load(P.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return cl;
+}
 
 DEV bool aborted(const Cl& cl) {
   return __hip_atomic_load(cl.flags + FLAG_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// Barrier across the workgroups of the cluster (sense by generation counter). Every wait is
-// bounded: after SPIN_LIMIT polls the abort flag is raised and all waiters leave.
+// Barrier across the workgroups of the cluster (generation counter). Arrival is one release
+// fetch-add on the count; the last arrival resets the count and publishes the next generation;
+// the others poll the generation with relaxed loads and take one acquire fence once it moved.
+// Every wait is bounded: after SPIN_LIMIT polls the abort flag is raised and all waiters leave.
 DEV void csync(Cl& cl) {
   __syncthreads();
   if (cl.G == 1) return;
   if (threadIdx.x == 0) {
     unsigned* count = cl.bar;
     unsigned* gen = cl.bar + 1;
-    const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned g0 = cl.gen;
+    cl.gen = g0 + 1u;
+    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == (unsigned)cl.G - 1u) {
       __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(gen, g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       long spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-        __builtin_amdgcn_s_sleep(2);
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        __builtin_amdgcn_s_sleep(1);
         if (++spins > SPIN_LIMIT || aborted(cl)) {
           __hip_atomic_store(cl.flags + FLAG_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
@@ -970,7 +982,7 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
   const int lt = (cl.G > 1 && P.tail < L - 1) ? P.tail : L - 1;
   auto tk = [&](int slot) { if (ck) ck->dtick(slot); };
   for (int l = 0; l < lt; ++l) { mg_down<S>(P, cl, l, v, lds); tk(1 + 2 * l); }
-  Cl solo{0, 1, cl.bar, cl.flags, cl.partials, cl.pbuf};
+  Cl solo{0, 1, cl.bar, cl.flags, cl.partials, cl.pbuf, 0u};
   if (lt < L - 1) {
     if (cl.rank == 0)
       for (int l = lt; l < L - 1; ++l) { mg_down<S>(P, solo, l, v, lds); tk(1 + 2 * l); }
@@ -1829,7 +1841,7 @@ DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a, int rank
   const Problem& P = *PP;
   double* smem = dyn_lds;
   Smem S = carve(smem, P.m);
-  Cl cl{rank, P.G, P.bar, P.flags, P.partials, 0};
+  Cl cl = make_cl(P, rank, P.G);
   PhaseClock clk;
   clk.begin(a.prof != nullptr, rank, a.prof);
   sa_solve_info info;

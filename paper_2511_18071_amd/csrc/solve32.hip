@@ -16,7 +16,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_operator32_kernel(const P
                                                                          const float* x, float* y) {
   const Problem& P = *PP;
   double* smem = dyn_lds;
-  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
+  Cl cl = make_cl(P, (int)blockIdx.x, (int)gridDim.x);
   phase_operator_s<float>(P, cl, x, 1.0f, y, (float*)smem);
 }
 
@@ -25,7 +25,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond32_kernel(const Pr
                                                                         const float* v, float* z) {
   const Problem& P = *PP;
   double* smem = dyn_lds;
-  Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
+  Cl cl = make_cl(P, (int)blockIdx.x, P.G);
   precond<float>(P, cl, v, z, (float*)smem, nullptr);
 }
 

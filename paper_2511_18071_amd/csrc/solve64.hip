@@ -13,7 +13,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_solve_kernel(const BatchI
 extern "C" __global__ void __launch_bounds__(BLOCK) sa_geometry_kernel(const Problem* __restrict__ PP,
                                                                        const double* eta_p, const double* eta_c) {
   const Problem& P = *PP;
-  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
+  Cl cl = make_cl(P, (int)blockIdx.x, (int)gridDim.x);
   phase_geometry(P, cl, eta_p, eta_c);
 }
 
@@ -21,7 +21,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_operator_kernel(const Pro
                                                                        const double* x, double* y) {
   const Problem& P = *PP;
   double* smem = dyn_lds;
-  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
+  Cl cl = make_cl(P, (int)blockIdx.x, (int)gridDim.x);
   phase_operator(P, cl, x, 1.0, y, nullptr, smem, smem, 0);
 }
 
@@ -30,7 +30,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond_kernel(const Prob
                                                                       unsigned long long* prof) {
   const Problem& P = *PP;
   double* smem = dyn_lds;
-  Cl cl{(int)blockIdx.x, P.G, P.bar, P.flags, P.partials, 0};
+  Cl cl = make_cl(P, (int)blockIdx.x, P.G);
   PhaseClock clk;
   clk.begin(prof != nullptr, cl.rank, prof);
   precond<double>(P, cl, v, z, smem, &clk);
@@ -39,7 +39,7 @@ extern "C" __global__ void __launch_bounds__(BLOCK) sa_precond_kernel(const Prob
 
 extern "C" __global__ void __launch_bounds__(BLOCK) sa_push_kernel(const Problem* __restrict__ PP, SolveArgs a) {
   const Problem& P = *PP;
-  Cl cl{(int)blockIdx.x, (int)gridDim.x, P.bar, P.flags, P.partials, 0};
+  Cl cl = make_cl(P, (int)blockIdx.x, (int)gridDim.x);
   phase_push(P, cl, a, P.Y[a.ycur], P.Y[a.ycur ^ 1]);
 }
 
