@@ -46,12 +46,17 @@ struct Cl {
   unsigned gen;  // barrier generation this workgroup last saw complete (thread 0 only)
 };
 
+// The barrier word of a cluster: one 64-bit atomic, arrivals in the low half, the generation
+// (completed barriers) in the high half.
+DEV unsigned long long* bar_word(unsigned* bar) { return reinterpret_cast<unsigned long long*>(bar); }
+
 // Workgroup `rank` of a cluster of G on problem P. Thread 0 reads the barrier generation once:
 // it advances only after all G workgroups have arrived at a barrier, and each reads it before
 // its first arrival, so all start from the same value; the barrier then tracks it locally.
 DEV Cl make_cl(const Problem& P, int rank, int G) {
   Cl cl{rank, G, P.bar, P.flags, P.partials, 0, 0u};
-  if (threadIdx.x == 0 && G > 1) cl.gen = __hip_atomic_load(P.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0 && G > 1)
+    cl.gen = (unsigned)(__hip_atomic_load(bar_word(P.bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
   return cl;
 }
 
@@ -59,25 +64,29 @@ DEV bool aborted(const Cl& cl) {
   return __hip_atomic_load(cl.flags + FLAG_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// Barrier across the workgroups of the cluster (generation counter). Arrival is one release
-// fetch-add on the count; the last arrival resets the count and publishes the next generation;
-// the others poll the generation with relaxed loads and take one acquire fence once it moved.
-// Every wait is bounded: after SPIN_LIMIT polls the abort flag is raised and all waiters leave.
+// Barrier across the workgroups of the cluster. Arrival is one release fetch-add of 1 on the
+// barrier word; the barrier is complete once the arrivals of this generation reach G. The
+// arrival that completes it (it reads G - 1 arrivals) then subtracts G arrivals and adds one
+// generation in a single atomic; until then early arrivals at the next barrier count on top,
+// which the test below allows for. Waiters poll the word with relaxed loads and take one
+// acquire fence once the barrier is complete. Every wait is bounded: after SPIN_LIMIT polls the
+// abort flag is raised and all waiters leave.
 DEV void csync(Cl& cl) {
   __syncthreads();
   if (cl.G == 1) return;
   if (threadIdx.x == 0) {
-    unsigned* count = cl.bar;
-    unsigned* gen = cl.bar + 1;
-    const unsigned g0 = cl.gen;
+    unsigned long long* word = bar_word(cl.bar);
+    const unsigned g0 = cl.gen, G = (unsigned)cl.G;
     cl.gen = g0 + 1u;
-    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == (unsigned)cl.G - 1u) {
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(gen, g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long old = __hip_atomic_fetch_add(word, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if ((unsigned)(old >> 32) == g0 && (unsigned)old == G - 1u) {
+      __hip_atomic_fetch_add(word, (1ull << 32) - G, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       long spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+      for (;;) {
+        const unsigned long long v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned gv = (unsigned)(v >> 32);
+        if ((gv == g0 && (unsigned)v >= G) || (int)(gv - g0) > 0) break;
         __builtin_amdgcn_s_sleep(1);
         if (++spins > SPIN_LIMIT || aborted(cl)) {
           __hip_atomic_store(cl.flags + FLAG_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
