@@ -856,36 +856,33 @@ DEV void phase_copy(const Problem& P, Cl& cl, const S* src, D* dst, int len) {
   for (int i = cl.rank * BLOCK + threadIdx.x; i < len; i += cl.G * BLOCK) dst[i] = D(src[i]);
 }
 
-// per-phase wall-clock accounting (rank-0 workgroup, thread 0), enabled with a profile buffer
+// per-phase wall-clock accounting (rank-0 workgroup, thread 0), enabled with a profile buffer:
+// each tick adds the time since the previous one to its category in the buffer directly, so
+// that no per-category state stays live through the solve
 struct PhaseClock {
-  unsigned long long acc[NPHASE];
-  unsigned long long* detail;  // NPROF counters or nullptr
+  unsigned long long* out;     // NPHASE totals, then the detail counters; nullptr: off
   unsigned long long last, start;
-  bool on;
-  DEV void begin(bool enable, int rank, unsigned long long* det = nullptr) {
-    on = enable && rank == 0 && threadIdx.x == 0;
-    detail = on ? det : nullptr;
-    for (int i = 0; i < NPHASE; ++i) acc[i] = 0;
-    last = start = on ? wall_clock64() : 0;
+  DEV void begin(bool enable, int rank, unsigned long long* buf = nullptr) {
+    out = (enable && rank == 0 && threadIdx.x == 0) ? buf : nullptr;
+    last = start = out ? wall_clock64() : 0;
   }
   DEV void tick(int cat) {
-    if (!on) return;
+    if (!out) return;
     const unsigned long long now = wall_clock64();
-    acc[cat] += now - last;
+    atomicAdd(out + cat, now - last);
     last = now;
   }
-  // detailed tick: charged to the detail slot and to no total
+  // detailed tick: charged to the detail slot and to the preconditioner total
   DEV void dtick(int slot) {
-    if (!on) return;
+    if (!out) return;
     const unsigned long long now = wall_clock64();
-    if (detail) atomicAdd(detail + PH_MG + slot, now - last);
-    acc[PH_PREC] += now - last;
+    atomicAdd(out + PH_MG + slot, now - last);
+    atomicAdd(out + PH_PREC, now - last);
     last = now;
   }
-  DEV void flush(unsigned long long* out) {
-    if (!on) return;
-    acc[PH_TOTAL] = wall_clock64() - start;
-    for (int i = 0; i < NPHASE; ++i) atomicAdd(out + i, acc[i]);
+  DEV void flush(unsigned long long*) {
+    if (!out) return;
+    atomicAdd(out + PH_TOTAL, wall_clock64() - start);
   }
 };
 
