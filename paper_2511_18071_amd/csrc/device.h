@@ -725,12 +725,19 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
     int Cfirst, Clast;
     coarse_range(P, c0, w, nc, ncc, Cfirst, Clast);
     const int ncw = Clast - Cfirst + 1;
+    // the residual f - M u, once per fine node, on the columns the restriction reads
+    // ([c0 - 1, c0 + w]), in place of f; then the full weighting from it
+    for_rows(nl, w + 2, [&](int j, int k) {
+      const int cc = c0 - 1 + k;
+      if (!st.has(cc)) return;
+      const S oms = S(1.0 - P.sig[j]);
+      sf[j * LW + st.slot(cc)] = F(cc, j) - m_apply<S>(P, nc, L.rdx, L.rds, oms, cc, j, U, CD);
+    });
+    __syncthreads();
     if (ncw > 0)
       for_rows(nl, ncw, [&](int j, int k) {
-        const int C = Cfirst + k;
-        const S oms = S(1.0 - P.sig[j]);
-        auto Rr = [&](int cc) { return F(cc, j) - m_apply<S>(P, nc, L.rdx, L.rds, oms, cc, j, U, CD); };
-        fc[(size_t)j * ncc + C] = restrict_at<S>(P, C, ncc, nxc, nc, Rr);
+        auto Rr = [&](int cc) { return F(cc, j); };
+        fc[(size_t)j * ncc + Cfirst + k] = restrict_at<S>(P, Cfirst + k, ncc, nxc, nc, Rr);
       });
     __syncthreads();
   }
