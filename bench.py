@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # sources are unchanged
 COUNTERS = os.path.join(ROOT, "profiles", "sa_solve_kernel_bar_513x17_counters.md")
 KERNEL_SOURCES = ("paper_2511_18071_amd/csrc/device.h", "paper_2511_18071_amd/csrc/solve64.hip",
-                  "paper_2511_18071_amd/csrc/internal.h")
+                  "paper_2511_18071_amd/csrc/internal.h", "paper_2511_18071_amd/csrc/api.hip")
 
 
 def kernel_hash() -> str:
@@ -42,7 +42,7 @@ def kernel_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, steps: int, warmup: int):
+def measured_traffic(workload: str, steps: int, warmup: int, cluster: int):
     """HBM bytes per EWMA launch of the solve kernel from the committed counter summary, or
     None when it was taken on other kernel sources or another run configuration."""
     try:
@@ -56,7 +56,8 @@ def measured_traffic(workload: str, steps: int, warmup: int):
             fields[k.strip("` ")] = v.strip("` ")
     try:
         same = (fields["kernel-source-sha256"] == kernel_hash() and fields["workload"] == workload
-                and int(fields["steps"]) == steps and int(fields["warmup"]) == warmup)
+                and int(fields["steps"]) == steps and int(fields["warmup"]) == warmup
+                and int(fields["cluster"]) == cluster)
         return float(fields["hbm-bytes-per-launch"]) if same else None
     except (KeyError, ValueError):
         return None
@@ -89,8 +90,8 @@ def parse():
 
 
 def default_cluster(w) -> int:
-    # the library's own default: one workgroup per 64-column tile of the finest level, at most 64
-    return int(min(64, max(1, (w.ncol + 63) // 64)))
+    # the library's own default: one workgroup per 32-column tile of the finest level, at most 64
+    return int(min(64, max(1, (w.ncol + 31) // 32)))
 
 
 def traffic_bytes(w, infos, pcv, k) -> float:
@@ -448,7 +449,7 @@ def main():
         "speedup_vs_plain": round(plain["wall"] / ewma["wall"], 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": measured_traffic(w.name, args.steps, args.warmup),
+                     "traffic": measured_traffic(w.name, args.steps, args.warmup, G),
                      "kernel_source_sha256": kernel_hash(),
                      "kernel": "sa_solve_kernel", "kernel_ms": round(kernel_ms, 4),
                      "launches": len(ewma["all_infos"]),

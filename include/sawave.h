@@ -97,7 +97,7 @@ typedef struct {
                         /* this fraction of its start hands its checked candidate to the    */
                         /* next correction (SA_FP32_IR), default 1e-4                       */
   int32_t max_refine;   /* FP32 cycles cap (SA_FP32_IR), default 200; SA_NOCONV after      */
-  int32_t cluster;      /* workgroups cooperating on one solve; 0 = one per 64 columns    */
+  int32_t cluster;      /* workgroups cooperating on one solve; 0 = one per 32 columns    */
                         /* of the grid, at most 64                                         */
   int32_t profile;      /* 1: accumulate per-phase device time (sa_get_phase_times), 0      */
   int32_t coarse_max;   /* MG: coarsening stops at the first grid with at most this many    */

@@ -322,7 +322,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   // default cluster: one 64-column preconditioner tile of the finest level per workgroup
   // (the passes of the V-cycle then take one tile-latency each), at most 64 workgroups
   int G = opt.cluster;
-  if (G <= 0) G = (ncol + 63) / 64 < 64 ? (ncol + 63) / 64 : 64;
+  if (G <= 0) G = (ncol + 31) / 32 < 64 ? (ncol + 31) / 32 : 64;  // one 32-column tile of the finest level each
   hipDeviceProp_t prop{};
   if (!bytes_only && hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
     delete p;
@@ -487,9 +487,10 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     L.fgam = (decltype(L.fgam))(A + o_fgam[l]); L.fstride = levs[l].fstride;
     L.flo = (decltype(L.flo))(A + o_flo[l]);
     L.facstride = (int)levs[l].fpc.size();
-    // narrower tiles where the cluster has more workgroups than 64-column tiles (not on the
-    // levels the rank-0 workgroup runs alone)
-    L.tm = (l < tail && (levs[l].ncol + 63) / 64 < G) ? 32 : TM_HOST;
+    // 32-column tiles where the cluster has a workgroup for each of them (one round of tiles
+    // either way, more workgroups busy), else 64 (not on the levels the rank-0 workgroup runs
+    // alone)
+    L.tm = (l < tail && (levs[l].ncol + 31) / 32 <= G) ? 32 : TM_HOST;
     L.f = (decltype(L.f))(A + o_lf[l]); L.u = (decltype(L.u))(A + o_lu[l]); L.o = (decltype(L.o))(A + o_lo[l]);
     if (ir) {
       L.fpc32 = (decltype(L.fpc32))(A + o_fpc32[l]); L.finv32 = (decltype(L.finv32))(A + o_finv32[l]);

@@ -174,6 +174,7 @@ SOLVE_CASES = [
     ("bar_65x9", dict(coarse_max=50, cluster=2), 10),
     ("bar_513x17", dict(), 8),
     ("bar_513x17", dict(cluster=8), 8),
+    ("bar_513x17", dict(cluster=9), 6),
     ("bar_513x17", dict(cluster=1), 4),
 ]
 
