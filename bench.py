@@ -90,8 +90,8 @@ def parse():
 
 
 def default_cluster(w) -> int:
-    # the library's own default: one workgroup per 32-column tile of the finest level, at most 64
-    return int(min(64, max(1, (w.ncol + 31) // 32)))
+    # the library's own default: one workgroup per 32-column tile of the finest level, at most 128
+    return int(min(128, max(1, (w.ncol + 31) // 32)))
 
 
 def traffic_bytes(w, infos, pcv, k) -> float:

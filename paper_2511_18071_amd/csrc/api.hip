@@ -322,7 +322,9 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   // default cluster: one 64-column preconditioner tile of the finest level per workgroup
   // (the passes of the V-cycle then take one tile-latency each), at most 64 workgroups
   int G = opt.cluster;
-  if (G <= 0) G = (ncol + 31) / 32 < 64 ? (ncol + 31) / 32 : 64;  // one 32-column tile of the finest level each
+  // one 32-column tile of the finest level per workgroup, at most 128 (half the CUs: beyond,
+  // the cluster reductions cost more than the wider grid saves)
+  if (G <= 0) G = (ncol + 31) / 32 < 128 ? (ncol + 31) / 32 : 128;
   hipDeviceProp_t prop{};
   if (!bytes_only && hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
     delete p;
