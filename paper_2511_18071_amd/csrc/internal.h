@@ -46,8 +46,8 @@ struct Level {
   const double SA_GLOBAL* flo;         // sub-diagonal of the column systems (same layout)
   const double SA_GLOBAL* fgam;
   int fstride;
-  int tm;                    // tile width of the default V-cycle passes (64, or 32 on levels
-                             // with fewer 64-column tiles than cluster workgroups)
+  int tm;                    // tile width of the default V-cycle passes (32 on levels whose
+                             // 32-column tiles each get a cluster workgroup, else 64)
   int facstride;             // flo, fpc, finv (and their FP32 copies) lie facstride apart;
                              // h, ih, hx, hxx lie ncol apart
   double SA_GLOBAL* f;                 // right-hand side of this level (level 0: unused, the input)
