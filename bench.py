@@ -220,10 +220,11 @@ def run_serving(args):
     """Continuous batching of the serving mix (independent simulations of different sizes).
 
     Inputs (surfaces and b = A p* of every system) are formed by the library's operator and
-    resident in HBM first. Three runs on fresh simulations: saturation (every request queued
+    resident in HBM first. Four runs on fresh simulations: saturation (every request queued
     at t = 0, FIFO per simulation), open loop (Poisson arrivals at --serve-rate, by default 70 %
-    of the saturation rate just measured, so that latency is that of a sustainable load; round robin
-    over the simulations), both FP32-inner refinement with the EWMA guess through the server;
+    of the saturation rate just measured, so that latency is that of a sustainable load, and
+    again at the configuration's 200 solves/s, above saturation on one GPU; round robin
+    over the simulations), all three FP32-inner refinement with the EWMA guess through the server;
     and the one-at-a-time FP64 cold-start path (sa_solve, no sketch) on every k-th simulation.
     All at relative residual 1e-8 checked on the FP64 residual.
     """
@@ -295,6 +296,10 @@ def run_serving(args):
     rng = np.random.default_rng(5)
     arr = np.cumsum(rng.exponential(1.0 / rate, nreq))
     ol = serve(arr, "open loop")
+    # the arrival rate the serving configuration names (Poisson, 200 solves/s): above the
+    # saturation rate on one GPU, so its latencies are those of a growing queue
+    arr200 = np.cumsum(np.random.default_rng(7).exponential(1.0 / 200.0, nreq))
+    ol200 = serve(arr200, "open loop at 200/s")
     say(f"  baseline: one-at-a-time FP64 cold start ({time.perf_counter() - t_setup:.0f} s)")
     # one-at-a-time FP64 cold start (sa_solve) on every k-th simulation
     base_lat, base_its, base_bad = [], [], 0
@@ -344,6 +349,7 @@ def run_serving(args):
                    "unknowns_per_workgroup": args.serve_upw},
         "saturation": s_sat,
         "open_loop": dict(offered_solves_per_s=round(rate, 2), **s_ol),
+        "open_loop_200": dict(offered_solves_per_s=200.0, **stats(ol200)),
         "baseline_one_at_a_time_fp64_cold": {
             "solves_per_s": round(base_rate, 2), "solves": len(base_lat),
             "sample": f"every {args.serve_baseline_stride}th simulation, all its systems",
