@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--serve-systems", type=int, default=10, help="serving: systems per simulation")
     ap.add_argument("--serve-rate", type=float, default=None,
                     help="serving: offered solves/s of the open loop (default: 0.7 x the measured saturation rate)")
+    ap.add_argument("--serve-inflight", type=int, default=8,
+                    help="serving: ticks in flight (the process is given as many hardware queues)")
     ap.add_argument("--serve-upw", type=int, default=20000,
                     help="serving: unknowns per workgroup when the server sizes the clusters")
     ap.add_argument("--serve-baseline-stride", type=int, default=8,
@@ -262,7 +264,10 @@ def run_serving(args):
 
     def serve(arrivals, label):
         say(f"  {label}: opening {len(sims)} simulations ({time.perf_counter() - t_setup:.0f} s)")
-        srv = B.Server(stream=stream, unknowns_per_workgroup=args.serve_upw)
+        sopts = dict(unknowns_per_workgroup=args.serve_upw)
+        if args.serve_inflight:
+            sopts["max_inflight"] = args.serve_inflight
+        srv = B.Server(stream=stream, **sopts)
         ids = [srv.open(w, precision="fp32_ir") for w in sims]
         if any(i is None for i in ids):
             raise RuntimeError("serving mix does not fit the HBM budget")
@@ -346,7 +351,8 @@ def run_serving(args):
         "config": {"workload": f"serving_mix({len(sims)} simulations x {nsys} systems, seed 5)",
                    "unknowns_total": total_unknowns, "precision": "fp32 inner GMRES, fp64 refinement",
                    "guess": "EWMA", "hbm_bytes_resident": sat["bytes"],
-                   "unknowns_per_workgroup": args.serve_upw},
+                   "unknowns_per_workgroup": args.serve_upw, "ticks_in_flight": args.serve_inflight,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "saturation": s_sat,
         "open_loop": dict(offered_solves_per_s=round(rate, 2), **s_ol),
         "open_loop_200": dict(offered_solves_per_s=200.0, **stats(ol200)),
@@ -416,6 +422,10 @@ def main():
     from paper_2511_18071_amd import workload as W
 
     if args.workload == "serving":
+        # one hardware queue per tick stream (read when the HIP runtime starts, which has not
+        # happened yet): ticks that share a queue run one after the other
+        if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < args.serve_inflight:
+            os.environ["GPU_MAX_HW_QUEUES"] = str(args.serve_inflight)
         run_serving(args)
         return
     w = W.get(args.workload)

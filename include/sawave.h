@@ -197,8 +197,11 @@ typedef struct sa_server sa_server;
 
 typedef struct {
   int64_t hbm_budget;             /* device bytes the simulations may hold; 0 = 90% of free */
-  int32_t max_inflight;           /* ticks running at once, each on its own stream (1..4),   */
-                                  /* default 4; a tick gets capacity / max_inflight          */
+  int32_t max_inflight;           /* ticks running at once, each on its own stream (1..16),  */
+                                  /* default 4 (HIP's default of 4 hardware queues per       */
+                                  /* process; more ticks need GPU_MAX_HW_QUEUES raised as    */
+                                  /* well, else they share queues and serialise); a tick     */
+                                  /* gets capacity / max_inflight                            */
                                   /* workgroups (at least one simulation's cluster)          */
   int32_t max_batch;              /* solves per tick, 0 = as many as are co-resident          */
   int32_t unknowns_per_workgroup; /* cluster size of simulations opened with cluster = 0:    */

@@ -26,7 +26,7 @@ using namespace sa;
 
 namespace {
 
-constexpr int MAX_INFLIGHT = 4;
+constexpr int MAX_INFLIGHT = 16;
 
 double now_ms(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -96,7 +96,7 @@ def test_footprint_needs_no_gpu(binding):
 
 
 def test_server_option_errors_need_no_gpu(binding):
-    for bad in (dict(max_inflight=0), dict(max_inflight=9), dict(max_batch=-1), dict(unknowns_per_workgroup=0)):
+    for bad in (dict(max_inflight=0), dict(max_inflight=17), dict(max_batch=-1), dict(unknowns_per_workgroup=0)):
         with pytest.raises(binding.SawaveError) as e:
             binding.Server(**bad)
         assert e.value.code == -1, bad
