@@ -3,8 +3,9 @@
 // Each simulation is an ordinary problem (its own sketch, Krylov basis and hierarchy, all in
 // its own device arena) admitted when its arena fits the server's HBM budget. Requests (the
 // surfaces and right-hand side of a simulation's next system) queue per simulation, first in
-// first out. A tick takes the oldest request of idle simulations (round robin, at most one
-// request each, up to a workgroup budget) and runs them in one launch of the solve kernel:
+// first out. A tick takes the oldest request of idle simulations (at most one request each, up
+// to a workgroup budget: the next simulation in round-robin order and those whose next solve
+// is predicted to take at most twice as long) and runs them in one launch of the solve kernel:
 // consecutive workgroup clusters, one per request, each running the same solve as sa_solve.
 // Up to max_inflight ticks run at once, each on a stream of its own, so a long solve holds
 // back only its own tick: as soon as any tick ends, its simulations' next requests and newly
@@ -43,8 +44,16 @@ struct Sim {
   sa_problem* p = nullptr;
   int64_t bytes = 0;
   std::deque<Request> queue;
-  int inflight = 0;  // requests in launched ticks not yet harvested
+  int inflight = 0;    // requests in launched ticks not yet harvested
+  int last_iters = 100;  // Arnoldi steps of its last solve (a guess before the first)
 };
+
+// Predicted duration of a simulation's next solve, in arbitrary units: its last step count
+// times the work per workgroup, floored where a step is bound by latency rather than bytes.
+double predicted_cost(const Sim& m) {
+  const double per_wg = (double)m.p->n / (double)m.p->G;
+  return (m.last_iters + 2.0) * (per_wg > 4096.0 ? per_wg : 4096.0);
+}
 
 struct Entry {
   int sim;
@@ -302,6 +311,7 @@ static int harvest(sa_server* s, bool wait) {
       c.t_done_ms = t_done;
       Sim& m = s->sims[en.sim];
       m.inflight -= 1;
+      m.last_iters = c.info.iters;
       if (c.info.status == SA_EDEVICE) m.p->broken = true;
       s->ready.push_back(c);
     }
@@ -329,21 +339,33 @@ static int launch_tick(sa_server* s, int* launched) {
   // workgroups per tick: an equal share of the co-resident capacity per running tick (every
   // open simulation's cluster fits it)
   const int budget = s->capacity / s->opt.max_inflight;
-  // pick the requests: round robin from s->rr, at most one per idle simulation
+  // pick the requests, at most one per idle simulation: the first idle simulation with work
+  // from s->rr in round-robin order, then, scanning on, those whose next solve is predicted to
+  // take at most twice as long as the first one's (a tick lasts as long as its slowest solve,
+  // and every simulation is first within nsim ticks, so none is held back for good)
   std::vector<int> picked[2];
   int blocks[2] = {0, 0};
-  int total = 0, scanned = 0;
-  for (; scanned < nsim && total < maxb; ++scanned) {
+  int total = 0, first_id = -1;
+  double limit = 0.0;
+  for (int scanned = 0; scanned < nsim && total < maxb; ++scanned) {
     const int id = (s->rr + scanned) % nsim;
     Sim& m = s->sims[id];
     if (!m.p || m.queue.empty() || m.p->broken || m.inflight > 0) continue;
+    if (first_id >= 0 && predicted_cost(m) > limit) continue;
+    if (blocks[0] + blocks[1] + m.p->G > budget) {
+      if (first_id < 0) break;
+      continue;
+    }
     const int g = m.p->opt.precision == SA_FP32_IR ? 1 : 0;
-    if (blocks[0] + blocks[1] + m.p->G > budget) break;
     blocks[g] += m.p->G;
     picked[g].push_back(id);
     ++total;
+    if (first_id < 0) {
+      first_id = id;
+      limit = 2.0 * predicted_cost(m);
+    }
   }
-  s->rr = (s->rr + (scanned > 0 ? scanned : 1)) % (nsim > 0 ? nsim : 1);
+  s->rr = ((first_id >= 0 ? first_id : s->rr) + 1) % (nsim > 0 ? nsim : 1);
   if (total == 0) return SA_OK;
   const double t_launch = now_ms(s->t0);
   int nitems = 0;
