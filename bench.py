@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--serve-systems", type=int, default=10, help="serving: systems per simulation")
     ap.add_argument("--serve-rate", type=float, default=None,
                     help="serving: offered solves/s of the open loop (default: 0.7 x the measured saturation rate)")
-    ap.add_argument("--serve-inflight", type=int, default=8,
+    ap.add_argument("--serve-inflight", type=int, default=16,
                     help="serving: ticks in flight (the process is given as many hardware queues)")
     ap.add_argument("--serve-upw", type=int, default=20000,
                     help="serving: unknowns per workgroup when the server sizes the clusters")
