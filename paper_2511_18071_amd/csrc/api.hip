@@ -359,7 +359,23 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     txg /= 2;
     big = big_of(need_gram_of(txg));
   }
-  p->lds_solve = (head + big) * sizeof(double);
+  // line-solve constants (column data, factors, gamma) of the cluster levels on which every
+  // workgroup owns at most one tile, kept in LDS for a whole FP64 solve where there is room
+  // (staged once per solve instead of in every V-cycle pass)
+  std::vector<int> res_off(nlev, -1);
+  size_t res_total = 0;
+  if (opt.precond == SA_PC_MG && opt.nu1 == 1 && opt.nu2 == 1 && opt.precision == SA_FP64) {
+    const int lt = (G > 1 && tail < nlev - 1) ? tail : nlev - 1;
+    for (int l = 0; l < lt; ++l) {
+      const int tw = (levs[l].ncol + 31) / 32 <= G ? 32 : TM_HOST;
+      if ((levs[l].ncol + tw - 1) / tw > G) continue;
+      const size_t sz = (size_t)(5 + 3 * nl) * (tw + 4);
+      if ((head + big + res_total + sz) * sizeof(double) > 160 * 1024) continue;
+      res_off[l] = (int)res_total;
+      res_total += sz;
+    }
+  }
+  p->lds_solve = (head + big + res_total) * sizeof(double);
   p->lds_op = need_op * sizeof(double);
   p->lds_pc = need_pc * sizeof(double);
   if (p->lds_solve > 160 * 1024 && (bytes_only || p->lds_solve > (size_t)prop.sharedMemPerBlock)) {
@@ -480,6 +496,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   P.sig = (decltype(P.sig))(A + o_sig); P.h = (decltype(P.h))(A + o_h); P.hchi = (decltype(P.hchi))(A + o_hchi);
   P.geo = (decltype(P.geo))(A + o_geo);
   P.pc = opt.precond; P.nu1 = opt.nu1; P.nu2 = opt.nu2; P.nlev = nlev; P.omega = opt.omega; P.tail = tail;
+  P.res_base = res_total > 0 ? (int)(head + big) : -1;
   for (int l = 0; l < nlev; ++l) {
     Level& L = P.lev[l];
     L.ncol = levs[l].ncol; L.nx = levs[l].nx; L.dx = levs[l].dx;
@@ -493,6 +510,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     // either way, more workgroups busy), else 64 (not on the levels the rank-0 workgroup runs
     // alone)
     L.tm = (l < tail && (levs[l].ncol + 31) / 32 <= G) ? 32 : TM_HOST;
+    L.res = res_off[l];
     L.f = (decltype(L.f))(A + o_lf[l]); L.u = (decltype(L.u))(A + o_lu[l]); L.o = (decltype(L.o))(A + o_lo[l]);
     if (ir) {
       L.fpc32 = (decltype(L.fpc32))(A + o_fpc32[l]); L.finv32 = (decltype(L.finv32))(A + o_finv32[l]);

@@ -587,7 +587,8 @@ DEV S factor(const Lv<S>& L, int qq, int j, int cg) {
 // o = u + omega L^-1 (f - M u) on level l, u = (uin or 0) + (e ? P e : 0) formed on load.
 // Residuals are formed by all threads in LDS, then one thread per column eliminates.
 template <class S, int TW = TM>
-DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, const S* e, S* o, S* lds) {
+DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, const S* e, S* o, S* lds,
+                      const S* rc = nullptr) {
   const Lv<S> L = level_view<S>(P, l);
   const int nc = L.nc, nl = P.nl, nz = P.nz;
   const int ncc = e ? P.lev[l + 1].ncol : 0;
@@ -597,6 +598,14 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
   S* scd = sr + TW * nl;       // 4 x LW
   S* sfac = scd + 4 * LW;      // 3 x TW x nl
   S* sgam = sfac + 3 * TW * nl;  // TW
+  // or the workgroup's resident block rc of this level: the layout of the down pass (columns
+  // c0 - 2 .. c0 + w + 1, stride TW + 4), read at the offsets of this pass's columns
+  constexpr int LR = TW + 4;
+  const S* ccd = rc ? rc + 1 : scd;            // column c0 - 1 + lc at [lc]
+  const int cds = rc ? LR : LW;
+  const S* cfac = rc ? rc + 4 * LR + 2 : sfac;  // column c0 + lc at [lc]
+  const int fst = rc ? LR : TW;
+  const S* cgam = rc ? rc + (4 + 3 * nl) * LR + 2 : sgam;
   const bool zero = !uin && !e;
   for (int t = cl.rank; t < (nc + TW - 1) / TW; t += cl.G) {
     const int c0 = t * TW, w = min(TW, nc - c0);
@@ -607,7 +616,7 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
     const int nu = zero ? 0 : nl, ncd = zero ? 0 : 4;
     const int rf = nu, rcd = rf + nl, rfac = rcd + ncd, rgam = rfac + 3 * nl;
     const int fsm = L.fstride ? L.fstride : 1;
-    staged_rows<16>(rgam + 1, ww, [&](int r, int lc) -> S {
+    staged_rows<16>(rc ? rcd : rgam + 1, ww, [&](int r, int lc) -> S {
       const int c = c0 - 1 + lc;
       const bool own = lc >= 1 && lc <= w;
       if (r < rf) {
@@ -632,7 +641,7 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
     __syncthreads();
     if (!zero) {
       auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
-      auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
+      auto CD = [&](int cc, int q) { return ccd[q * cds + st.slot(cc)]; };
       for (int i = threadIdx.x; i < TW * nl; i += BLOCK) {
         const int j = i / TW, lc = i - j * TW;
         if (lc < w) sr[i] -= m_apply<S>(P, nc, L.rdx, L.rds, S(1.0 - P.sig[j]), c0 + lc, j, U, CD);
@@ -641,7 +650,7 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
     }
     if (threadIdx.x < w) {
       const int lc = threadIdx.x;
-      line_solve<S>(nz, sgam[lc], sr + lc, TW, sfac + lc, sfac + TW * nl + lc, sfac + 2 * TW * nl + lc, TW);
+      line_solve<S>(nz, cgam[lc], sr + lc, TW, cfac + lc, cfac + fst * nl + lc, cfac + 2 * fst * nl + lc, fst);
     }
     __syncthreads();
     const S om = S(P.omega);
@@ -675,16 +684,21 @@ DEV S restrict_at(const Problem& P, int C, int ncc, int nxc, int nc, RR Rr) {
 // u = omega L^-1 f on the tile plus a 2-column halo, u written for the tile's columns,
 // fc(C) = full weighting of f - M u at the fine columns around C's centre.
 template <class S, int TW = TM>
-DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S* lds) {
+DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S* lds, const S* rc = nullptr) {
   const Lv<S> L = level_view<S>(P, l);
   const int nc = L.nc, nl = P.nl, nz = P.nz;
   const int ncc = P.lev[l + 1].ncol, nxc = P.lev[l + 1].nx;
   constexpr int LW = TW + 4;
   S* sf = lds;                 // LW x nl
   S* su = sf + LW * nl;        // LW x nl
-  S* scd = su + LW * nl;       // 4 x LW
-  S* sfac = scd + 4 * LW;      // 3 x LW x nl
-  S* sgam = sfac + 3 * LW * nl;  // LW
+  // column data (4 x LW), factors (3 x LW x nl) and gamma (LW): staged below, or the
+  // workgroup's resident block rc of the same layout (its one tile of this level)
+  S* scd = su + LW * nl;
+  S* sfac = scd + 4 * LW;
+  S* sgam = sfac + 3 * LW * nl;
+  const S* ccd = rc ? rc : scd;
+  const S* cfac = rc ? rc + 4 * LW : sfac;
+  const S* cgam = rc ? rc + (4 + 3 * nl) * LW : sgam;
   for (int t = cl.rank; t < (nc + TW - 1) / TW; t += cl.G) {
     const int c0 = t * TW, w = min(TW, nc - c0);
     const Stage st{c0 - 2, w + 4, nc, P.periodic};
@@ -692,7 +706,8 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
     const int ww = w + 4;
     const int rcd = nl, rfac = nl + 4, rgam = rfac + 3 * nl;
     const int fsm = L.fstride ? L.fstride : 1;
-    staged_rows<16>(rgam + 1, ww, [&](int r, int lc) -> S {
+    // resident constants: only the nl rows of f are loaded
+    staged_rows<16>(rc ? nl : rgam + 1, ww, [&](int r, int lc) -> S {
       const int c = c0 - 2 + lc;
       if (!st.has(c)) return (r >= rcd && r < rfac) || (r >= rfac + 2 * nl && r < rgam) ? S(1) : S(0);
       const int cg = st.col(c);
@@ -709,7 +724,7 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
     __syncthreads();
     if (threadIdx.x < w + 4 && st.has(c0 - 2 + (int)threadIdx.x)) {
       const int lc = threadIdx.x;
-      line_solve<S>(nz, sgam[lc], su + lc, LW, sfac + lc, sfac + LW * nl + lc, sfac + 2 * LW * nl + lc, LW);
+      line_solve<S>(nz, cgam[lc], su + lc, LW, cfac + lc, cfac + LW * nl + lc, cfac + 2 * LW * nl + lc, LW);
     }
     __syncthreads();
     const S om = S(P.omega);
@@ -721,7 +736,7 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
     for_rows(nl, w, [&](int j, int lc) { u[(size_t)j * nc + c0 + lc] = su[j * LW + lc + 2]; });
     auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
     auto F = [&](int cc, int jj) { return sf[jj * LW + st.slot(cc)]; };
-    auto CD = [&](int cc, int q) { return scd[q * LW + st.slot(cc)]; };
+    auto CD = [&](int cc, int q) { return ccd[q * LW + st.slot(cc)]; };
     int Cfirst, Clast;
     coarse_range(P, c0, w, nc, ncc, Cfirst, Clast);
     const int ncw = Clast - Cfirst + 1;
@@ -741,6 +756,29 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
       });
     __syncthreads();
   }
+}
+
+// The line-solve constants (column data, factors, gamma) of this workgroup's tile of level l
+// (tile = rank), in the layout of the down pass's staging, into dst: kept in LDS through a
+// whole solve where the level has at most one tile per workgroup.
+template <class S, int TW>
+DEV void stage_resident(const Problem& P, const Cl& cl, int l, S* dst) {
+  const Lv<S> L = level_view<S>(P, l);
+  const int nc = L.nc, nl = P.nl;
+  constexpr int LW = TW + 4;
+  if (cl.rank >= (nc + TW - 1) / TW) return;
+  const int c0 = cl.rank * TW, w = min(TW, nc - c0);
+  const Stage st{c0 - 2, w + 4, nc, P.periodic};
+  const int fsm = L.fstride ? L.fstride : 1;
+  staged_rows<16>(5 + 3 * nl, w + 4, [&](int r, int lc) -> S {
+    const int c = c0 - 2 + lc;
+    // outside the grid: column data and inverse pivots 1, the rest 0 (as the down pass)
+    if (!st.has(c)) return (r < 4 || (r >= 4 + 2 * nl && r < 4 + 3 * nl)) ? S(1) : S(0);
+    const int cg = st.col(c);
+    if (r < 4) return coldata(L, r, cg);
+    if (r < 4 + 3 * nl) return L.flo[(r - 4) * fsm + (L.fstride ? cg : 0)];
+    return L.fgam[L.fstride ? cg : 0];
+  }, [&](int r, int lc, S v) { dst[r * LW + lc] = v; });
 }
 
 // fc = full weighting of f - M u (used when nu1 != 1)
@@ -895,15 +933,15 @@ struct PhaseClock {
 
 // one V-cycle level pair on the way down / up (cluster or single-workgroup view)
 template <class S>
-DEV void mg_down(const Problem& P, Cl& cl, int l, const S* v, S* lds) {
+DEV void mg_down(const Problem& P, Cl& cl, int l, const S* v, S* lds, const S* rc = nullptr) {
   const Lv<S> L = level_view<S>(P, l);
   const Lv<S> Lc = level_view<S>(P, l + 1);
   const S* f = l == 0 ? v : L.f;
   S* A = L.u;
   S* B = L.o;
   if (P.nu1 == 1) {
-    if (P.lev[l].tm == 32) phase_down<S, 32>(P, cl, l, f, A, Lc.f, lds);
-    else phase_down<S, TM>(P, cl, l, f, A, Lc.f, lds);
+    if (P.lev[l].tm == 32) phase_down<S, 32>(P, cl, l, f, A, Lc.f, lds, rc);
+    else phase_down<S, TM>(P, cl, l, f, A, Lc.f, lds, rc);
     csync(cl);
     return;
   }
@@ -929,7 +967,8 @@ DEV void mg_down(const Problem& P, Cl& cl, int l, const S* v, S* lds) {
 
 // returns the buffer holding level l's output; z is level 0's destination
 template <class S>
-DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z, S* lds) {
+DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z, S* lds,
+                   const S* rc = nullptr) {
   const Lv<S> L = level_view<S>(P, l);
   const S* f = l == 0 ? v : L.f;
   S* A = L.u;
@@ -947,8 +986,8 @@ DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z
   }
   S* dst = (P.nu2 == 1) ? out : B;
   // first post-sweep, correction added on load (on the level's tile width)
-  if (P.lev[l].tm == 32) phase_sweep<S, 32>(P, cl, l, f, A, e, dst, lds);
-  else phase_sweep<S, TM>(P, cl, l, f, A, e, dst, lds);
+  if (P.lev[l].tm == 32) phase_sweep<S, 32>(P, cl, l, f, A, e, dst, lds, rc);
+  else phase_sweep<S, TM>(P, cl, l, f, A, e, dst, lds, rc);
   csync(cl);
   const S* prev = dst;
   for (int s = 1; s < P.nu2; ++s) {
@@ -964,7 +1003,8 @@ DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z
 // the level-0 scratch (u, o of level 0). Levels from P.tail on (at most one tile wide) are
 // run by the rank-0 workgroup alone with workgroup barriers only. Ends with a cluster barrier.
 template <class S>
-DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock* ck = nullptr) {
+DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock* ck = nullptr,
+                 const S* res = nullptr) {
   const int n = P.n;
   if (P.pc == SA_PC_NONE) {
     phase_copy(P, cl, v, z, n);
@@ -994,7 +1034,9 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
   // (workgroup barriers only); the coarsest dense solve is shared by the whole cluster
   const int lt = (cl.G > 1 && P.tail < L - 1) ? P.tail : L - 1;
   auto tk = [&](int slot) { if (ck) ck->dtick(slot); };
-  for (int l = 0; l < lt; ++l) { mg_down<S>(P, cl, l, v, lds); tk(1 + 2 * l); }
+  // the resident constants of cluster level l (res: the solve's resident block, or none)
+  auto rc = [&](int l) -> const S* { return (res && P.lev[l].res >= 0) ? res + P.lev[l].res : nullptr; };
+  for (int l = 0; l < lt; ++l) { mg_down<S>(P, cl, l, v, lds, rc(l)); tk(1 + 2 * l); }
   Cl solo{0, 1, cl.bar, cl.flags, cl.partials, cl.pbuf, 0u};
   if (lt < L - 1) {
     if (cl.rank == 0)
@@ -1017,7 +1059,7 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
     e = (lt == 0) ? z : (P.nu2 == 0 ? Lt.u : Lt.o);
     if (lt == 0) return;
   }
-  for (int l = lt - 1; l >= 0; --l) { e = mg_up<S>(P, cl, l, v, e, z, lds); tk(2 + 2 * l); }
+  for (int l = lt - 1; l >= 0; --l) { e = mg_up<S>(P, cl, l, v, e, z, lds, rc(l)); tk(2 + 2 * l); }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1628,6 +1670,16 @@ DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, Ph
   double* V = P.V;
   double trigger = 0.0;
   int stage = ST_TRIGGER, j = 0;
+  // line-solve constants kept in LDS for the whole solve (levels with one tile per workgroup)
+  double* res = P.res_base >= 0 ? dyn_lds + P.res_base : nullptr;
+  if (res) {
+    for (int l = 0; l < P.nlev; ++l)
+      if (P.lev[l].res >= 0) {
+        if (P.lev[l].tm == 32) stage_resident<double, 32>(P, cl, l, res + P.lev[l].res);
+        else stage_resident<double, TM>(P, cl, l, res + P.lev[l].res);
+      }
+    __syncthreads();
+  }
   while (!aborted(cl)) {
     const double* src = a.b;
     double* dst = P.t;
@@ -1643,7 +1695,7 @@ DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, Ph
       src = P.t;
       dst = V + (size_t)(j + 1) * n;
     }
-    precond<double>(P, cl, src, dst, S.big, &clk);
+    precond<double>(P, cl, src, dst, S.big, &clk, res);
     clk.tick(PH_PREC);
     if (stage == ST_TRIGGER) {
       trigger = rtol * cluster_norm(P, cl, S, (const double*)P.t);
