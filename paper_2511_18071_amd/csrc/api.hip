@@ -362,20 +362,22 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   // line-solve constants (column data, factors, gamma) of the cluster levels on which every
   // workgroup owns at most one tile, kept in LDS for a whole FP64 solve where there is room
   // (staged once per solve instead of in every V-cycle pass)
+  // (in the solve's precision: doubles, or floats for the FP32 V-cycle of the refinement path)
   std::vector<int> res_off(nlev, -1);
   size_t res_total = 0;
-  if (opt.precond == SA_PC_MG && opt.nu1 == 1 && opt.nu2 == 1 && opt.precision == SA_FP64) {
+  const size_t res_esz = opt.precision == SA_FP32_IR ? sizeof(float) : sizeof(double);
+  if (opt.precond == SA_PC_MG && opt.nu1 == 1 && opt.nu2 == 1) {
     const int lt = (G > 1 && tail < nlev - 1) ? tail : nlev - 1;
     for (int l = 0; l < lt; ++l) {
       const int tw = (levs[l].ncol + 31) / 32 <= G ? 32 : TM_HOST;
       if ((levs[l].ncol + tw - 1) / tw > G) continue;
       const size_t sz = (size_t)(5 + 3 * nl) * (tw + 4);
-      if ((head + big + res_total + sz) * sizeof(double) > 160 * 1024) continue;
+      if ((head + big) * sizeof(double) + (res_total + sz) * res_esz > 160 * 1024) continue;
       res_off[l] = (int)res_total;
       res_total += sz;
     }
   }
-  p->lds_solve = (head + big + res_total) * sizeof(double);
+  p->lds_solve = (head + big) * sizeof(double) + (res_total * res_esz + 7) / 8 * 8;
   p->lds_op = need_op * sizeof(double);
   p->lds_pc = need_pc * sizeof(double);
   if (p->lds_solve > 160 * 1024 && (bytes_only || p->lds_solve > (size_t)prop.sharedMemPerBlock)) {

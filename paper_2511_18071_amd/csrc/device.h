@@ -1796,6 +1796,17 @@ DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, P
   double* rc = P.rc;
   double trigger = 0.0, beta = 0.0;
   int stage = ST_TRIGGER, j = 0;
+  // FP32 line-solve constants kept in LDS for the whole solve (levels with one tile per
+  // workgroup)
+  float* res = P.res_base >= 0 ? (float*)(dyn_lds + P.res_base) : nullptr;
+  if (res) {
+    for (int l = 0; l < P.nlev; ++l)
+      if (P.lev[l].res >= 0) {
+        if (P.lev[l].tm == 32) stage_resident<float, 32>(P, cl, l, res + P.lev[l].res);
+        else stage_resident<float, TM>(P, cl, l, res + P.lev[l].res);
+      }
+    __syncthreads();
+  }
   while (!aborted(cl)) {
     const float* src = r32;
     float* dst = P.t32;
@@ -1821,7 +1832,7 @@ DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, P
       src = P.t32;
       dst = V + (size_t)(j + 1) * n;
     }
-    precond<float>(P, cl, src, dst, lds, &clk);
+    precond<float>(P, cl, src, dst, lds, &clk, res);
     clk.tick(PH_PREC);
     if (stage == ST_TRIGGER) {
       trigger = rtol * nb * cluster_norm(P, cl, S, (const float*)P.t32);

@@ -48,8 +48,9 @@ struct Level {
   int fstride;
   int tm;                    // tile width of the default V-cycle passes (32 on levels whose
                              // 32-column tiles each get a cluster workgroup, else 64)
-  int res;                   // offset (doubles) of the level's line-solve constants inside
-                             // the solve kernel's resident LDS block, -1: staged every pass
+  int res;                   // offset (elements of the solve's precision) of the level's
+                             // line-solve constants inside the solve kernel's resident LDS
+                             // block, -1: staged every pass
   int facstride;             // flo, fpc, finv (and their FP32 copies) lie facstride apart;
                              // h, ih, hx, hxx lie ncol apart
   double SA_GLOBAL* f;                 // right-hand side of this level (level 0: unused, the input)
@@ -68,8 +69,8 @@ struct Level {
 // Everything a kernel needs about one problem. Lives in device memory.
 struct Problem {
   int ncol, nl, nz, n, nphys, periodic;
-  int res_base;              // dynamic-LDS offset (doubles) of the resident block of line-solve
-                             // constants of the FP64 solve kernel, -1: none
+  int res_base;              // dynamic-LDS offset (doubles) of the solve kernels' resident block
+                             // of line-solve constants, -1: none
   double dx, dsig;
   const double SA_GLOBAL* wsig;        // nl x 7 first-derivative weights in sigma (1/dsig included)
   const int SA_GLOBAL* ssig;           // nl window starts in sigma
