@@ -363,21 +363,26 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   // workgroup owns at most one tile, kept in LDS for a whole FP64 solve where there is room
   // (staged once per solve instead of in every V-cycle pass)
   // (in the solve's precision: doubles, or floats for the FP32 V-cycle of the refinement path)
+  // The block lives in the part of the phase scratch that only the guess uses (the Gram tiles):
+  // while GMRES runs, the scratch holds at most an operator tile or a preconditioner tile.
   std::vector<int> res_off(nlev, -1);
   size_t res_total = 0;
   const size_t res_esz = opt.precision == SA_FP32_IR ? sizeof(float) : sizeof(double);
+  const size_t gmres_scratch = need_op > need_pc ? need_op : need_pc;
   if (opt.precond == SA_PC_MG && opt.nu1 == 1 && opt.nu2 == 1) {
     const int lt = (G > 1 && tail < nlev - 1) ? tail : nlev - 1;
     for (int l = 0; l < lt; ++l) {
       const int tw = (levs[l].ncol + 31) / 32 <= G ? 32 : TM_HOST;
       if ((levs[l].ncol + tw - 1) / tw > G) continue;
       const size_t sz = (size_t)(5 + 3 * nl) * (tw + 4);
-      if ((head + big) * sizeof(double) + (res_total + sz) * res_esz > 160 * 1024) continue;
+      if ((head + gmres_scratch) * sizeof(double) + (res_total + sz) * res_esz > 160 * 1024) continue;
       res_off[l] = (int)res_total;
       res_total += sz;
     }
   }
-  p->lds_solve = (head + big) * sizeof(double) + (res_total * res_esz + 7) / 8 * 8;
+  const size_t res_end = (head + gmres_scratch) * sizeof(double) + (res_total * res_esz + 7) / 8 * 8;
+  p->lds_solve = (head + big) * sizeof(double);
+  if (res_total > 0 && res_end > p->lds_solve) p->lds_solve = res_end;
   p->lds_op = need_op * sizeof(double);
   p->lds_pc = need_pc * sizeof(double);
   if (p->lds_solve > 160 * 1024 && (bytes_only || p->lds_solve > (size_t)prop.sharedMemPerBlock)) {
@@ -498,7 +503,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   P.sig = (decltype(P.sig))(A + o_sig); P.h = (decltype(P.h))(A + o_h); P.hchi = (decltype(P.hchi))(A + o_hchi);
   P.geo = (decltype(P.geo))(A + o_geo);
   P.pc = opt.precond; P.nu1 = opt.nu1; P.nu2 = opt.nu2; P.nlev = nlev; P.omega = opt.omega; P.tail = tail;
-  P.res_base = res_total > 0 ? (int)(head + big) : -1;
+  P.res_base = res_total > 0 ? (int)(head + gmres_scratch) : -1;
   for (int l = 0; l < nlev; ++l) {
     Level& L = P.lev[l];
     L.ncol = levs[l].ncol; L.nx = levs[l].nx; L.dx = levs[l].dx;
