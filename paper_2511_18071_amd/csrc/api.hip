@@ -359,12 +359,12 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     txg /= 2;
     big = big_of(need_gram_of(txg));
   }
-  // line-solve constants (column data, factors, gamma) of the cluster levels on which every
-  // workgroup owns at most one tile, kept in LDS for a whole FP64 solve where there is room
-  // (staged once per solve instead of in every V-cycle pass)
-  // (in the solve's precision: doubles, or floats for the FP32 V-cycle of the refinement path)
-  // The block lives in the part of the phase scratch that only the guess uses (the Gram tiles):
-  // while GMRES runs, the scratch holds at most an operator tile or a preconditioner tile.
+  // Line-solve constants (column data, factors, gamma) of the cluster levels on which every
+  // workgroup owns at most one tile, kept in LDS for a whole solve where there is room (staged
+  // once per solve instead of in every V-cycle pass), in the solve's precision (floats for the
+  // FP32 V-cycle of the refinement path). The block lives in the part of the phase scratch that
+  // only the guess uses (the Gram tiles): while GMRES runs, the scratch holds at most an
+  // operator tile or a preconditioner tile.
   std::vector<int> res_off(nlev, -1);
   size_t res_total = 0;
   const size_t res_esz = opt.precision == SA_FP32_IR ? sizeof(float) : sizeof(double);
