@@ -504,7 +504,7 @@ struct Stage {
 template <class S, class U, class CD>
 DEV S m_apply(const Problem& P, int nc, S rdx, S rds, S oms, int c, int j, U u, CD cd) {
   const int nz = P.nz;
-  const S half = S(0.5), two = S(2), one = S(1), quarter = S(0.25);
+  const S half = S(0.5), two = S(2), quarter = S(0.25);
   if (j == nz) return u(c, j);
   if (!P.periodic && (c == 0 || c == nc - 1)) {
     if (j == 0) return u(c, j);
