@@ -504,6 +504,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   P.geo = (decltype(P.geo))(A + o_geo);
   P.pc = opt.precond; P.nu1 = opt.nu1; P.nu2 = opt.nu2; P.nlev = nlev; P.omega = opt.omega; P.tail = tail;
   P.res_base = res_total > 0 ? (int)(head + gmres_scratch) : -1;
+  P.tx = (ncol + 31) / 32 <= G ? 32 : TM_HOST;
   for (int l = 0; l < nlev; ++l) {
     Level& L = P.lev[l];
     L.ncol = levs[l].ncol; L.nx = levs[l].nx; L.dx = levs[l].dx;

@@ -11,7 +11,7 @@
 // Phases and what they compute:
 //   geometry   per-column 1/d and d_chi of both stages (Sec. 2.1, surface-subgrid D_chi)
 //   operator   y = A x, the mixed-stage grad^(i) . grad^(i-1) with ghost-node boundary rows
-//              (Sec. 3), LDS-staged tiles of TX columns x all levels, 7-point stencils
+//              (Sec. 3), LDS-staged tiles of 32 or TX columns x all levels, 7-point stencils
 //   guess      Y <- r Y + x omega^T fused with W = A Y, Gram W^T W and W^T b over LDS tiles,
 //              then the k x k least-squares solve and x0 = Y z (Alg. 2 with Alg. 4's V = Y)
 //   precond    fixed still-water V-cycle: column (line) solves, x-semicoarsening, dense
@@ -33,7 +33,6 @@ namespace sa {
 extern __shared__ double dyn_lds[];
 
 constexpr long SPIN_LIMIT = 1L << 25;
-constexpr int TWM = TX + 3;   // widest operator tile (a last wall tile absorbs up to 3 columns)
 
 // ------------------------------------------------------------------------------------------
 // cluster of workgroups cooperating on one problem
@@ -400,22 +399,24 @@ DEV void tile_operator(const Problem& P, int c0, int w, Load load, S* sx, S* sgx
 }
 
 // y = A x (b == nullptr) or y = b - A x with ||y||^2 and ||b||^2 into red[slot], red[slot+1]
-DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, double xs, double* y,
-                        const double* __restrict__ b, double* lds, double* red, int slot) {
+template <int OTX>
+DEV void phase_operator_t(const Problem& P, Cl& cl, const double* __restrict__ x, double xs, double* y,
+                          const double* __restrict__ b, double* lds, double* red, int slot) {
+  constexpr int W = OTX + 3;  // widest tile (a last wall tile absorbs up to 3 columns)
   const bool resid = b != nullptr;
-  const Tiles T = tiles_of(P, TX);
+  const Tiles T = tiles_of(P, OTX);
   double* sx = lds;
-  double* sgx = sx + (TWM + 12) * P.nl;
-  double* sgz = sgx + (TWM + 6) * P.nl;
-  double* sc = sgz + (TWM + 6) * P.nl;
-  double* wsum = sc + opcoef_size(TWM, P.nl);
+  double* sgx = sx + (W + 12) * P.nl;
+  double* sgz = sgx + (W + 6) * P.nl;
+  double* sc = sgz + (W + 6) * P.nl;
+  double* wsum = sc + opcoef_size(W, P.nl);
   const int nc = P.ncol;
   double acc = 0.0, accb = 0.0;
   for (int t = cl.rank; t < T.nt; t += cl.G) {
-    const int c0 = t * TX;
-    const int w = (t == T.nt - 1) ? nc - c0 : TX;
+    const int c0 = t * OTX;
+    const int w = (t == T.nt - 1) ? nc - c0 : OTX;
     auto load = [&](int lj, int c, int) { return x[(size_t)lj * nc + c] * xs; };
-    tile_operator<double, TWM>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int c, double v) {
+    tile_operator<double, W>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int c, double v) {
       const size_t e = (size_t)lj * nc + c;
       if (resid) {
         const double bb = b[e];
@@ -434,23 +435,38 @@ DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, 
   }
 }
 
+// on the operator tile width of the problem (32 columns where every such tile has a cluster
+// workgroup, else TX); the partial sums of the residual form go to red[slot], red[slot + 1]
+DEV void phase_operator(const Problem& P, Cl& cl, const double* __restrict__ x, double xs, double* y,
+                        const double* __restrict__ b, double* lds, double* red, int slot) {
+  if (P.tx == 32) phase_operator_t<32>(P, cl, x, xs, y, b, lds, red, slot);
+  else phase_operator_t<TX>(P, cl, x, xs, y, b, lds, red, slot);
+}
+
 // y = A (xs x) in the inner precision S (FP32 refinement path): same tiles, no residual form
-template <class S>
-DEV void phase_operator_s(const Problem& P, Cl& cl, const S* __restrict__ x, S xs, S* y, S* lds) {
-  const Tiles T = tiles_of(P, TX);
+template <class S, int OTX>
+DEV void phase_operator_st(const Problem& P, Cl& cl, const S* __restrict__ x, S xs, S* y, S* lds) {
+  constexpr int W = OTX + 3;
+  const Tiles T = tiles_of(P, OTX);
   S* sx = lds;
-  S* sgx = sx + (TWM + 12) * P.nl;
-  S* sgz = sgx + (TWM + 6) * P.nl;
-  S* sc = sgz + (TWM + 6) * P.nl;
+  S* sgx = sx + (W + 12) * P.nl;
+  S* sgz = sgx + (W + 6) * P.nl;
+  S* sc = sgz + (W + 6) * P.nl;
   const int nc = P.ncol;
   for (int t = cl.rank; t < T.nt; t += cl.G) {
-    const int c0 = t * TX;
-    const int w = (t == T.nt - 1) ? nc - c0 : TX;
+    const int c0 = t * OTX;
+    const int w = (t == T.nt - 1) ? nc - c0 : OTX;
     auto load = [&](int lj, int c, int) { return x[(size_t)lj * nc + c] * xs; };
-    tile_operator<S, TWM>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int c, S v) {
+    tile_operator<S, W>(P, c0, w, load, sx, sgx, sgz, sc, [&](int lj, int lc, int c, S v) {
       y[(size_t)lj * nc + c] = v;
     });
   }
+}
+
+template <class S>
+DEV void phase_operator_s(const Problem& P, Cl& cl, const S* __restrict__ x, S xs, S* y, S* lds) {
+  if (P.tx == 32) phase_operator_st<S, 32>(P, cl, x, xs, y, lds);
+  else phase_operator_st<S, TX>(P, cl, x, xs, y, lds);
 }
 
 // ------------------------------------------------------------------------------------------

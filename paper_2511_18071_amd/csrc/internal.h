@@ -69,6 +69,8 @@ struct Level {
 // Everything a kernel needs about one problem. Lives in device memory.
 struct Problem {
   int ncol, nl, nz, n, nphys, periodic;
+  int tx;                    // operator tile width: 32 where every 32-column tile has a cluster
+                             // workgroup, else 64
   int res_base;              // dynamic-LDS offset (doubles) of the solve kernels' resident block
                              // of line-solve constants, -1: none
   double dx, dsig;
