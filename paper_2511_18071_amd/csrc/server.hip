@@ -152,7 +152,7 @@ extern "C" int sa_server_create(const sa_server_options* optin, void* hip_stream
   if (rc != SA_OK) { delete s; return rc; }
   const int maxitems = s->capacity;
   hipError_t e = hipSuccess;
-  for (int i = 0; i < MAX_INFLIGHT && e == hipSuccess; ++i) {
+  for (int i = 0; i < s->opt.max_inflight && e == hipSuccess; ++i) {  // the slots in use only
     Slot& sl = s->slots[i];
     e = hipHostMalloc((void**)&sl.h_items, sizeof(BatchItem) * maxitems, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_rep, sizeof(sa_solve_info) * maxitems, hipHostMallocDefault);
