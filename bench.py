@@ -1,19 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the subspace-accelerated Poisson sequence on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bar_513x17]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload periodic_16385x33]
 
 A step is one LSERK45 time step of the synthetic simulation: five sequential mixed-stage
-Poisson solves (one per Runge-Kutta stage), each from the EWMA-subspace initial guess,
-GMRES to relative residual 1e-8 with the still-water V-cycle preconditioner, FP64.
-Inputs (surfaces at the stage times, manufactured right-hand sides b = A p* formed by the
-library's own operator) are resident in HBM before the timed region starts. The same K
-steps are then solved by the plain path (cold start x0 = 0, same GMRES) for the
-subspace-vs-plain comparison. Prints one JSON line.
+Poisson solves (one per Runge-Kutta stage), each from the EWMA-subspace initial guess
+(Alg. 2 with the sketch of Alg. 4), GMRES to relative residual 1e-8 with the still-water
+V-cycle preconditioner, FP64. The default workload is the large single simulation
+(periodic 16385 x 33, n = 557 056, GMRES(40), rank 16). Inputs (surfaces at the stage times,
+manufactured right-hand sides b = A p* formed by the library's own operator) are resident in
+HBM before the timed region starts. The same steps are then solved from the previous
+solution (the paper's baseline) and from a cold start (the plain path). Prints one JSON line;
+progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,16 +28,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# counters of the solve kernel taken on this workload (FETCH_SIZE and WRITE_SIZE runs) and the
-# hash of the kernel sources they were taken with: the traffic is reported only while the
-# sources are unchanged
-COUNTERS = os.path.join(ROOT, "profiles", "sa_solve_kernel_bar_513x17_counters.md")
+# kernel sources whose hash keys the committed counter summaries
 KERNEL_SOURCES = ("paper_2511_18071_amd/csrc/device.h", "paper_2511_18071_amd/csrc/solve64.hip",
                   "paper_2511_18071_amd/csrc/internal.h", "paper_2511_18071_amd/csrc/api.hip")
 
 
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
 def kernel_hash() -> str:
-    import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
@@ -42,36 +45,45 @@ def kernel_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, steps: int, warmup: int, cluster: int):
-    """HBM bytes per EWMA launch of the solve kernel from the committed counter summary, or
-    None when it was taken on other kernel sources or another run configuration."""
-    try:
-        text = open(COUNTERS).read()
-    except OSError:
-        return None
+def counters_path(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"sa_solve_kernel_{workload}_counters.md")
+
+
+def read_fields(path: str) -> dict:
     fields = {}
+    try:
+        text = open(path).read()
+    except OSError:
+        return fields
     for line in text.splitlines():
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
             fields[k.strip("` ")] = v.strip("` ")
+    return fields
+
+
+def measured_traffic(workload: str, steps: int, warmup: int, cluster: int):
+    """HBM bytes per EWMA launch of the solve kernel from the committed counter summary of the
+    workload, or None when it was taken on other kernel sources or another run configuration."""
+    f = read_fields(counters_path(workload))
     try:
-        same = (fields["kernel-source-sha256"] == kernel_hash() and fields["workload"] == workload
-                and int(fields["steps"]) == steps and int(fields["warmup"]) == warmup
-                and int(fields["cluster"]) == cluster)
-        return float(fields["hbm-bytes-per-launch"]) if same else None
+        same = (f["kernel-source-sha256"] == kernel_hash() and f["workload"] == workload
+                and int(f["steps"]) == steps and int(f["warmup"]) == warmup and int(f["cluster"]) == cluster)
+        return float(f["hbm-bytes-per-launch"]) if same else None
     except (KeyError, ValueError):
         return None
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--workload", default="bar_513x17")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="periodic_16385x33")
     ap.add_argument("--cluster", type=int, default=0, help="workgroups per solve (0 = size rule)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-solves", type=int, default=30)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the EWMA run (no previous/cold comparison, phases or bar leg)")
     ap.add_argument("--serve-sims", type=int, default=256, help="serving: simulations")
     ap.add_argument("--serve-systems", type=int, default=10, help="serving: systems per simulation")
     ap.add_argument("--serve-rate", type=float, default=None,
@@ -83,12 +95,11 @@ def parse():
     ap.add_argument("--serve-baseline-stride", type=int, default=8,
                     help="serving: the one-at-a-time FP64 baseline solves every k-th simulation")
     ap.add_argument("--operator-probe", default="", metavar="WORKLOAD",
-                    help="only apply the operator of WORKLOAD's first system 50 times (standalone "
-                         "kernel: one workgroup per 64-column tile) and print its rate")
+                    help="only apply the operator of WORKLOAD's first system 50 times and print its rate")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes five times (the "
                          "reference kernel that scales HBM counter readings)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def default_cluster(w) -> int:
@@ -135,87 +146,237 @@ def precond_vectors(w) -> float:
     return 12.0
 
 
-def run_gpu(args, w):
+def stage_inputs(B, w, nsys, G):
+    """Surfaces, manufactured solutions p* and right-hand sides b = A p* of the first nsys
+    systems, resident on the device."""
     import torch
-    from paper_2511_18071_amd import binding as B
-
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    nsys = 5 * (args.warmup + args.steps)
-    G = args.cluster or default_cluster(w)
-    # ---- stage the inputs: surfaces at the stage times and b = A p*
     etas = torch.empty((nsys, 2, w.nphys), dtype=torch.float64, device=dev)
     bs = torch.empty((nsys, w.n), dtype=torch.float64, device=dev)
-    with B.Problem.from_workload(w, stream=stream, cluster=G) as gen:
+    ps = torch.empty((nsys, w.n), dtype=torch.float64, device=dev)
+    with B.Problem.from_workload(w, stream=stream, cluster=G, precond="none", guess="cold") as gen:
         for s in range(nsys):
-            ep, ec, ps = w.system(s)
+            ep, ec, pst = w.system(s)
             etas[s, 0].copy_(torch.from_numpy(ep))
             etas[s, 1].copy_(torch.from_numpy(ec))
-            pst = torch.from_numpy(ps).to(dev)
+            ps[s].copy_(torch.from_numpy(pst))
+            torch.cuda.synchronize()
             gen.set_surface(etas[s, 0], etas[s, 1])
-            gen.apply_operator(pst, bs[s])
+            gen.apply_operator(ps[s], bs[s])
     torch.cuda.synchronize()
-
-    def run(mode):
-        # every launch of the solve kernel is bracketed by events on the problem's stream, the
-        # warm-up launches too, so the mean kernel time covers the same launches as a kernel
-        # trace of this process
-        p = B.Problem.from_workload(w, stream=stream, cluster=G, guess=mode)
-        nw = 5 * args.warmup
-        evw = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nw)]
-        for s in range(nw):
-            p.set_surface(etas[s, 0], etas[s, 1])
-            p.push_rhs(bs[s])
-            evw[2 * s].record(stream)
-            p.solve(sync=False)
-            evw[2 * s + 1].record(stream)
-        warm_infos = p.read_log()
-        torch.cuda.synchronize()
-        warm_lat = [evw[2 * i].elapsed_time(evw[2 * i + 1]) for i in range(nw)]
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * 5 * args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i, s in enumerate(range(nw, nsys)):
-            p.set_surface(etas[s, 0], etas[s, 1])
-            p.push_rhs(bs[s])
-            ev[2 * i].record(stream)
-            p.solve(sync=False)
-            ev[2 * i + 1].record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        infos = p.read_log()
-        lat = np.array([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(5 * args.steps)])
-        x = p.solution()
-        p.close()
-        bad = [i for i in infos if i.status != 0 or i.relres > w.rtol]
-        return dict(wall=wall, infos=infos, lat=lat, failed=len(bad), x=x,
-                    all_infos=warm_infos + infos, all_lat=np.concatenate([warm_lat, lat]))
-
-    ewma = run("ewma")
-    plain = run("cold")
-    return ewma, plain, G
+    return etas, bs, ps
 
 
-def cpu_baseline(w, nsolves):
-    from threadpoolctl import threadpool_limits
+def run_sequence(B, w, etas, bs, ps, mode, warmup_steps, steps, G, xs=None, **opts):
+    """One guess mode over the staged systems: 5 * warmup_steps untimed solves, then 5 * steps
+    timed ones. Every solve kernel launch is bracketed by events on the problem's stream (the
+    warm-up launches too, so the mean launch time covers the same launches as a kernel trace of
+    the process). Returns wall time of the timed solves, reports, event latencies and the
+    per-solve errors against p*."""
+    import torch
+    stream = torch.cuda.current_stream()
+    nw, nt = 5 * warmup_steps, 5 * steps
+    p = B.Problem.from_workload(w, stream=stream, cluster=G, guess=mode, **opts)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * (nw + nt))]
+    if xs is None:
+        xs = torch.empty((nw + nt, w.n), dtype=torch.float64, device="cuda:0")
+    for s in range(nw):
+        p.set_surface(etas[s, 0], etas[s, 1])
+        p.push_rhs(bs[s])
+        ev[2 * s].record(stream)
+        p.solve(sync=False)
+        ev[2 * s + 1].record(stream)
+        p.solution_async(xs[s])
+    warm_infos = p.read_log()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(nw, nw + nt):
+        p.set_surface(etas[s, 0], etas[s, 1])
+        p.push_rhs(bs[s])
+        ev[2 * s].record(stream)
+        p.solve(sync=False)
+        ev[2 * s + 1].record(stream)
+        p.solution_async(xs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    infos = p.read_log()
+    p.close()
+    lat = np.array([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(nw + nt)])
+    # forward error against the manufactured solution, per solve (after the timed region)
+    err = ((xs[: nw + nt] - ps[: nw + nt]).norm(dim=1) / ps[: nw + nt].norm(dim=1)).cpu().numpy()
+    all_infos = warm_infos + infos
+    bad = [i for i in infos if i.status != 0 or i.relres > w.rtol]
+    return dict(wall=wall, infos=infos, all_infos=all_infos, lat=lat[nw:], all_lat=lat, failed=len(bad),
+                err=err, nw=nw, xs=xs)
+
+
+def summary(w, r, nsol):
+    its = np.array([i.iters for i in r["infos"]])
+    nw = r["nw"]
+    rel = np.array([i.relres for i in r["infos"]])
+    return {"value": round(nsol / r["wall"], 3), "iters_per_solve": round(float(its.mean()), 3),
+            "p50_solve_ms": round(float(np.percentile(r["lat"], 50)), 4),
+            "p99_solve_ms": round(float(np.percentile(r["lat"], 99)), 4),
+            "max_relres": float(rel.max()), "failed_solves": r["failed"],
+            "err_vs_pstar_max": float(r["err"][nw:].max()), "err_vs_pstar_median": float(np.median(r["err"][nw:]))}
+
+
+def phase_breakdown(B, w, etas, bs, G, nsys=10):
+    """Device time per phase of the first nsys EWMA solves (profile mode: the first workgroup
+    reads the clock at each phase boundary)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    p = B.Problem.from_workload(w, stream=stream, cluster=G, profile=1)
+    for s in range(nsys):
+        p.set_surface(etas[s, 0], etas[s, 1])
+        p.push_rhs(bs[s])
+        p.solve(sync=False)
+    infos = p.read_log()
+    t, det = p.phase_times(detail=True)
+    p.close()
+    total = t["total"]
+    nlev = int(np.count_nonzero(det[1:49:2] > 0)) + 1
+    return {"solves": nsys, "iters": int(sum(i.iters for i in infos)), "total_ms": round(total, 3),
+            "share": {k: round(v / total, 4) for k, v in t.items() if k != "total"},
+            "precond_ms": {"coarsest": round(float(det[0]), 3),
+                           "down": [round(float(det[1 + 2 * l]), 3) for l in range(nlev)],
+                           "up": [round(float(det[2 + 2 * l]), 3) for l in range(nlev)],
+                           "tail_wait": round(float(det[48]), 3)}}
+
+
+def cpu_baseline(w, gpu_x0, gpu_info0):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload: the first
+    system of the sequence (the history is empty there, so the first solve of every guess mode
+    starts cold), timed with BLAS limited to one thread and with all threads. Its solution is
+    also the reference for the GPU's first solve (decisions and solution difference)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle.sequence import Simulation
 
-    with threadpool_limits(limits=1):
-        sim = Simulation.from_workload(w)
-        systems = []
-        for s in range(nsolves):
-            ep, ec, ps = w.system(s)
-            systems.append((ep, ec, sim.operator(ep, ec) @ ps))
-        t0 = time.perf_counter()
-        its = []
-        for ep, ec, b in systems:
-            its.append(sim.solve(ep, ec, b).info.iters)
-        dt = time.perf_counter() - t0
-    return dict(value=nsolves / dt, unit="solves/s", cores=1, kind="oracle",
-                sample=f"first {nsolves} systems of {w.name} (FP64 oracle: assembled CSR operator, "
-                       f"V-cycle, GMRES(30), EWMA rank {w.k} guess by Householder QR), "
-                       f"{np.mean(its):.2f} iterations/solve, one thread")
+    ep, ec, pst = w.system(0)
+    legs = {}
+    ref = None
+    for label, limit in (("one_thread", 1), ("all_threads", None)):
+        with threadpool_limits(limits=limit):
+            threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+            sim = Simulation.from_workload(w)
+            b = sim.operator(ep, ec) @ pst
+            t0 = time.perf_counter()
+            res = sim.solve(ep, ec, b)  # assembles the system's operator, guesses, runs GMRES
+            dt = time.perf_counter() - t0
+        legs[label] = dict(seconds=round(dt, 3), threads=int(threads if limit is None else 1), iters=res.info.iters)
+        say(f"  cpu baseline {label}: {dt:.1f} s, {res.info.iters} iterations")
+        ref = res
+    one = legs["one_thread"]
+    allc = legs["all_threads"]
+    dx = float(np.linalg.norm(gpu_x0 - ref.x) / np.linalg.norm(ref.x))
+    same = (gpu_info0.iters, gpu_info0.restarts, gpu_info0.checks) == (ref.info.iters, ref.info.restarts, ref.info.checks)
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {
+        "value": round(1.0 / one["seconds"], 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "sample": (f"system 0 of {w.name} (empty history, so a cold solve: {one['iters']} GMRES({w.restart}) "
+                   f"iterations; the oracle assembles the system's operator, applies the still-water V-cycle, "
+                   f"CGS2 and true-residual checks in FP64 NumPy/SciPy), one BLAS thread"),
+        "ms_per_iteration": round(1e3 * one["seconds"] / max(1, one["iters"]), 3),
+        "all_cores": {"value": round(1.0 / allc["seconds"], 5), "cores": allc["threads"], "nproc": nproc,
+                      "ms_per_iteration": round(1e3 * allc["seconds"] / max(1, allc["iters"]), 3)},
+        "gpu_vs_oracle_system0": {"same_decisions": bool(same), "gpu_iters": gpu_info0.iters,
+                                  "oracle_iters": ref.info.iters, "solution_rel_diff": dx,
+                                  "oracle_relres": float(ref.info.relres), "gpu_relres": float(gpu_info0.relres)},
+    }
+
+
+def run_main(args):
+    import torch
+    from paper_2511_18071_amd import binding as B
+    from paper_2511_18071_amd import workload as W
+
+    w = W.get(args.workload)
+    G = args.cluster or default_cluster(w)
+    nsys = 5 * (args.warmup + args.steps)
+    nsol = 5 * args.steps
+    say(f"bench: {w.name} n={w.n}, {nsys} systems, cluster {G}")
+    t0 = time.perf_counter()
+    etas, bs, ps = stage_inputs(B, w, nsys, G)
+    say(f"  inputs staged ({time.perf_counter() - t0:.1f} s)")
+    xs = torch.empty((nsys, w.n), dtype=torch.float64, device="cuda:0")
+    ewma = run_sequence(B, w, etas, bs, ps, "ewma", args.warmup, args.steps, G, xs)
+    x0 = xs[0].cpu().numpy()
+    info0 = ewma["all_infos"][0]
+    say(f"  ewma: {nsol / ewma['wall']:.2f} solves/s")
+    out_modes = {}
+    if not args.no_extra:
+        for mode in ("previous", "cold"):
+            r = run_sequence(B, w, etas, bs, ps, mode, args.warmup, args.steps, G, xs)
+            out_modes[mode] = r
+            say(f"  {mode}: {nsol / r['wall']:.2f} solves/s")
+    value = nsol / ewma["wall"]
+    kernel_ms = float(ewma["all_lat"].mean())
+    pcv = precond_vectors(w)
+    bytes_per = traffic_bytes(w, ewma["all_infos"], pcv, w.k) / len(ewma["all_infos"])
+    achieved = bytes_per / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w.name, args.steps, args.warmup, G)
+    s = summary(w, ewma, nsol)
+    out = {
+        "metric": "solves/s @relres 1e-8 (subspace vs plain), iters/solve, p99 solve latency",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * ewma["wall"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "nz": w.nz, "bc": w.bc, "unknowns": w.n,
+                   "systems_per_step": 5, "restart": w.restart, "rtol": w.rtol, "precond": "still-water V(1,1)",
+                   "guess": f"EWMA rank {w.k}, r={w.r}", "cluster_workgroups": G},
+        "iters_per_solve": s["iters_per_solve"],
+        "p50_solve_ms": s["p50_solve_ms"],
+        "p99_solve_ms": s["p99_solve_ms"],
+        "failed_solves": s["failed_solves"],
+        "errors": {"max_relres": s["max_relres"], "err_vs_pstar_max": s["err_vs_pstar_max"],
+                   "err_vs_pstar_median": s["err_vs_pstar_median"],
+                   "per_solve_relres": [float("%.3e" % i.relres) for i in ewma["infos"]],
+                   "per_solve_err_vs_pstar": [float("%.3e" % e) for e in ewma["err"][ewma["nw"]:]]},
+    }
+    if out_modes:
+        sp = summary(w, out_modes["previous"], nsol)
+        sc = summary(w, out_modes["cold"], nsol)
+        out["previous"] = dict(sp, guess="previous solution (the paper's baseline)")
+        out["plain"] = dict(sc, guess="cold (x0 = 0)")
+        out["speedup_vs_plain"] = round(out_modes["cold"]["wall"] / ewma["wall"], 3)
+        out["speedup_vs_previous"] = round(out_modes["previous"]["wall"] / ewma["wall"], 3)
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 5),
+                       "traffic": round(traffic) if traffic else None,
+                       "traffic_frac": round(traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5) if traffic else None,
+                       "kernel_source_sha256": kernel_hash(),
+                       "kernel": "sa_solve_kernel", "kernel_ms": round(kernel_ms, 4),
+                       "launches": len(ewma["all_infos"]),
+                       "algorithmic_bytes_per_launch": round(bytes_per)}
+    if not args.no_extra:
+        out["phases"] = phase_breakdown(B, w, etas, bs, G)
+        out["mfma_share"] = 0.0
+        say("  phases done")
+    del etas, bs, ps
+    torch.cuda.empty_cache()
+    if not args.no_extra and w.name != "bar_513x17":
+        wb = W.get("bar_513x17")
+        Gb = default_cluster(wb)
+        e2, b2, p2 = stage_inputs(B, wb, 5 * 25, Gb)
+        rb = run_sequence(B, wb, e2, b2, p2, "ewma", 5, 20, Gb)
+        rc = run_sequence(B, wb, e2, b2, p2, "cold", 5, 20, Gb)
+        out["bar_513x17"] = dict(summary(wb, rb, 100), plain_value=round(100 / rc["wall"], 3),
+                                 plain_iters_per_solve=round(float(np.mean([i.iters for i in rc["infos"]])), 3),
+                                 steps=20, warmup=5, cluster_workgroups=Gb, guess=f"EWMA rank {wb.k}, r={wb.r}")
+        say("  bar leg done")
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, x0, info0)
+    print(json.dumps(out), flush=True)
 
 
 def run_serving(args):
@@ -224,11 +385,12 @@ def run_serving(args):
     Inputs (surfaces and b = A p* of every system) are formed by the library's operator and
     resident in HBM first. Four runs on fresh simulations: saturation (every request queued
     at t = 0, FIFO per simulation), open loop (Poisson arrivals at --serve-rate, by default 70 %
-    of the saturation rate just measured, so that latency is that of a sustainable load, and
-    again at the configuration's 200 solves/s, above saturation on one GPU; round robin
-    over the simulations), all three FP32-inner refinement with the EWMA guess through the server;
-    and the one-at-a-time FP64 cold-start path (sa_solve, no sketch) on every k-th simulation.
-    All at relative residual 1e-8 checked on the FP64 residual.
+    of the saturation rate just measured, and again at the configuration's 200 solves/s;
+    round robin over the simulations), all three FP32-inner refinement with the EWMA guess
+    through the server; and the one-at-a-time FP64 cold-start path (sa_solve, no sketch) on
+    every k-th simulation. All at relative residual 1e-8 checked on the FP64 residual.
+    Latency is measured from each request's scheduled arrival time (not from when the host
+    loop got round to submitting it), on the server's clock.
     """
     import torch
     from paper_2511_18071_amd import binding as B
@@ -239,7 +401,6 @@ def run_serving(args):
     sims = W.serving_mix(args.serve_sims, seed=5, nsys=args.serve_systems)
     nsys = args.serve_systems
     t_setup = time.perf_counter()
-    say = lambda *a: print(*a, file=sys.stderr, flush=True)  # progress (the JSON line goes to stdout)
     say(f"serving: {len(sims)} simulations x {nsys} systems, {sum(w.n for w in sims)} unknowns")
     inputs = []
     with B.Server(stream=stream) as gen:
@@ -253,6 +414,7 @@ def run_serving(args):
                 ep, ec, ps = w.system(s)
                 eta[s, 0].copy_(torch.from_numpy(ep))
                 eta[s, 1].copy_(torch.from_numpy(ec))
+                torch.cuda.synchronize()
                 gen.apply_operator(sid, eta[s, 0], eta[s, 1], torch.from_numpy(ps).to(dev), bs[s])
             gen.close_sim(sid)
             inputs.append((eta, bs))
@@ -273,9 +435,12 @@ def run_serving(args):
             raise RuntimeError("serving mix does not fit the HBM budget")
         torch.cuda.synchronize()
         lat, infos = [], []
+        arrival_of = {}
         k = 0
         say(f"  {label}: serving {nreq} requests")
         t0 = time.perf_counter()
+        # server clock (ms since the server was created) at the host time t0
+        base_ms = srv.clock_ms()
         t_say = t0
         while k < nreq or srv.outstanding > 0:
             if time.perf_counter() - t_say > 10.0:
@@ -285,11 +450,13 @@ def run_serving(args):
             while k < nreq and arrivals[k] <= now:
                 i, s = order[k]
                 eta, bs = inputs[i]
-                srv.submit(ids[i], eta[s, 0], eta[s, 1], bs[s])
+                t = srv.submit(ids[i], eta[s, 0], eta[s, 1], bs[s])
+                arrival_of[t] = base_ms + 1e3 * arrivals[k]
                 k += 1
-            wait = k >= nreq or (arrivals[k] - (time.perf_counter() - t0)) > 0.002
-            for c in srv.poll(wait=wait and srv.outstanding > 0):
-                lat.append(c.t_done_ms - c.t_submit_ms)
+            # block only until the next arrival falls due, so that no arrival waits on the host
+            timeout = None if k >= nreq else max(0.0, arrivals[k] - (time.perf_counter() - t0))
+            for c in srv.poll(wait=srv.outstanding > 0, timeout_s=timeout):
+                lat.append(c.t_done_ms - arrival_of.pop(c.ticket))
                 infos.append(c.info)
         wall = time.perf_counter() - t0
         bytes_used = srv.bytes_used
@@ -301,12 +468,10 @@ def run_serving(args):
     rng = np.random.default_rng(5)
     arr = np.cumsum(rng.exponential(1.0 / rate, nreq))
     ol = serve(arr, "open loop")
-    # the arrival rate the serving configuration names (Poisson, 200 solves/s): above the
-    # saturation rate on one GPU, so its latencies are those of a growing queue
+    # the arrival rate the serving configuration names (Poisson, 200 solves/s)
     arr200 = np.cumsum(np.random.default_rng(7).exponential(1.0 / 200.0, nreq))
     ol200 = serve(arr200, "open loop at 200/s")
     say(f"  baseline: one-at-a-time FP64 cold start ({time.perf_counter() - t_setup:.0f} s)")
-    # one-at-a-time FP64 cold start (sa_solve) on every k-th simulation
     base_lat, base_its, base_bad = [], [], 0
     for i in range(0, len(sims), args.serve_baseline_stride):
         w = sims[i]
@@ -392,6 +557,7 @@ def operator_probe(name: str, reps: int = 50):
     e0, e1 = torch.from_numpy(ep).cuda(), torch.from_numpy(ec).cuda()
     x = torch.from_numpy(ps).cuda()
     y = torch.empty_like(x)
+    torch.cuda.synchronize()
     p = B.Problem.from_workload(w, stream=torch.cuda.current_stream(), precond="none", guess="cold")
     p.set_surface(e0, e1)
     for _ in range(5):
@@ -409,71 +575,29 @@ def operator_probe(name: str, reps: int = 50):
 
 def main():
     args = parse()
-    if args.operator_probe:
-        operator_probe(args.operator_probe)
-        return
-    if args.copy_probe:
-        copy_probe(args.copy_probe)
-        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build measures the one-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
-    from paper_2511_18071_amd import workload as W
-
-    if args.workload == "serving":
+    if args.operator_probe:
+        operator_probe(args.operator_probe)
+    elif args.copy_probe:
+        copy_probe(args.copy_probe)
+    elif args.workload == "serving":
         # one hardware queue per tick stream (read when the HIP runtime starts, which has not
         # happened yet): ticks that share a queue run one after the other
         if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < args.serve_inflight:
             os.environ["GPU_MAX_HW_QUEUES"] = str(args.serve_inflight)
         run_serving(args)
-        return
-    w = W.get(args.workload)
-    ewma, plain, G = run_gpu(args, w)
-    nsol = 5 * args.steps
-    value = nsol / ewma["wall"]
-    its = np.array([i.iters for i in ewma["infos"]])
-    its_plain = np.array([i.iters for i in plain["infos"]])
-    # roofline of the solve kernel over all its launches (warm-up included)
-    kernel_ms = float(ewma["all_lat"].mean())
-    pcv = precond_vectors(w)
-    bytes_per = traffic_bytes(w, ewma["all_infos"], pcv, w.k) / len(ewma["all_infos"])
-    achieved = bytes_per / (kernel_ms * 1e-3) / 1e9
-    out = {
-        "metric": "solves/s @relres 1e-8 (subspace vs plain), iters/solve, p99 solve latency",
-        "value": round(value, 2),
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * ewma["wall"] / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": w.name, "nx": w.nx, "nz": w.nz, "bc": w.bc, "unknowns": w.n,
-                   "systems_per_step": 5, "restart": w.restart, "rtol": w.rtol, "precond": "still-water V(1,1)",
-                   "guess": f"EWMA rank {w.k}, r={w.r}", "cluster_workgroups": G},
-        "iters_per_solve": round(float(its.mean()), 3),
-        "p50_solve_ms": round(float(np.percentile(ewma["lat"], 50)), 4),
-        "p99_solve_ms": round(float(np.percentile(ewma["lat"], 99)), 4),
-        "failed_solves": ewma["failed"],
-        "plain": {"value": round(nsol / plain["wall"], 2), "iters_per_solve": round(float(its_plain.mean()), 3),
-                  "p99_solve_ms": round(float(np.percentile(plain["lat"], 99)), 4), "guess": "cold (x0 = 0)",
-                  "failed_solves": plain["failed"]},
-        "speedup_vs_plain": round(plain["wall"] / ewma["wall"], 3),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": measured_traffic(w.name, args.steps, args.warmup, G),
-                     "kernel_source_sha256": kernel_hash(),
-                     "kernel": "sa_solve_kernel", "kernel_ms": round(kernel_ms, 4),
-                     "launches": len(ewma["all_infos"]),
-                     "algorithmic_bytes_per_launch": round(bytes_per)},
-    }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_solves)
-    print(json.dumps(out), flush=True)
+    else:
+        run_main(args)
+    # release every device resource before the interpreter's own teardown
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
 
 
 if __name__ == "__main__":

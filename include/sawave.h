@@ -11,7 +11,8 @@
  *     Neumann equation);
  *   - left-preconditioned restarted GMRES (Sec. 3) with a fixed still-water preconditioner;
  *   - the initial guess of Alg. 2 with the basis V = Y of the EWMA sketch of Alg. 4,
- *     Y <- r Y + x omega^T after every solve (Sec. 4.1.2).
+ *     Y <- r Y + x omega^T after every solve (Sec. 4.1.2), or with V = X Omega of the
+ *     randomized range finder of Alg. 3 over the K most recent solutions (Sec. 4.1.1).
  *
  * Grid and memory layout (all vectors of length n = ncol * (nz + 1), FP64 unless stated):
  *   node (level j, column c) has index j * ncol + c (x fastest). Level 0 is the ghost level
@@ -61,7 +62,7 @@ enum {
 
 enum { SA_PERIODIC = 0, SA_WALLS = 1 };
 enum { SA_PC_NONE = 0, SA_PC_LINE = 1, SA_PC_MG = 2 };
-enum { SA_GUESS_COLD = 0, SA_GUESS_PREVIOUS = 1, SA_GUESS_EWMA = 2 };
+enum { SA_GUESS_COLD = 0, SA_GUESS_PREVIOUS = 1, SA_GUESS_EWMA = 2, SA_GUESS_RANGE = 3 };
 enum { SA_FP64 = 0, SA_FP32_IR = 1 };
 enum { SA_MEM_HOST = 0, SA_MEM_DEVICE = 1 };
 enum { SA_SYNC = 0, SA_ASYNC = 1 };
@@ -102,6 +103,9 @@ typedef struct {
   int32_t profile;      /* 1: accumulate per-phase device time (sa_get_phase_times), 0      */
   int32_t coarse_max;   /* MG: coarsening stops at the first grid with at most this many    */
                         /* unknowns, solved exactly there (<= 1024), default 700            */
+  int32_t window;       /* SA_GUESS_RANGE: K, the solutions kept in the sliding window of   */
+                        /* the randomized range finder (Alg. 3, V = X Omega with the k x K  */
+                        /* Gaussian rows drawn as the solutions enter), k..32, default 16   */
 } sa_options;
 
 /* Per-solve report. iters counts Arnoldi steps over all cycles (FP32_IR: inner steps over
@@ -145,8 +149,13 @@ int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags);
  * At most `max` are copied; *n_out receives the number copied. The log holds 4096 entries. */
 int sa_read_log(sa_problem* p, sa_solve_info* out, int32_t max, int32_t* n_out);
 
-/* Copy the last solution (n values) to host or device memory. */
+/* Copy the last solution (n values) to host or device memory; waits for the stream. */
 int sa_get_solution(sa_problem* p, double* x, int32_t mem);
+
+/* Enqueue a copy of the last solution into device memory x (n values) on the problem's
+ * stream and return at once (no wait): after an SA_ASYNC solve, x receives that solve's
+ * solution once the stream reaches the copy. x must stay valid until then. */
+int sa_get_solution_async(sa_problem* p, double* x);
 
 /* y = A(eta_prev, eta_cur) x with the current surfaces (Sec. 3 mixed-stage operator).
  * x, y: n values in `mem` memory. */
@@ -187,12 +196,19 @@ int sa_get_phase_times(sa_problem* p, double* out, int32_t n);
 
 /* ---- continuous-batching server ---------------------------------------------------------
  * Many independent simulations (each an sa_problem with its own sketch and hierarchy) on one
- * GPU. Simulations are admitted when their device arena fits the HBM budget; requests (the
- * surfaces and right-hand side of a simulation's next system) queue per simulation, first in
- * first out; a tick runs the oldest request of as many simulations as fit into one launch,
- * one workgroup cluster per request; up to max_inflight ticks are queued on the stream, so
- * requests arriving while a tick runs join the next one. A solve in a tick computes exactly
- * what sa_solve computes for that simulation. Not thread-safe: one host thread drives it. */
+ * GPU. Simulations are admitted when their device arena fits the HBM budget (with
+ * queue_admission, one that does not fit yet waits and is admitted, oldest first, once closed
+ * simulations have freed enough); requests (the surfaces and right-hand side of a
+ * simulation's next system) queue per simulation, first in first out; a tick runs the oldest
+ * request of as many simulations as fit into one launch, one workgroup cluster per request;
+ * up to max_inflight ticks run at once, so requests arriving while a tick runs join the next
+ * one. A solve in a tick computes exactly what sa_solve computes for that simulation.
+ * Thread safety: every sa_server_* call takes the server's lock, so requests may be submitted
+ * and completions polled from different host threads (a waiting poll releases the lock while
+ * it waits). Problems returned by sa_server_problem follow the rules of a single problem.
+ * Stream ordering: device inputs are read after the work the caller had enqueued on the
+ * server's stream (the one given at creation) when it submitted them; the solves themselves
+ * run on the server's own streams. */
 typedef struct sa_server sa_server;
 
 typedef struct {
@@ -206,14 +222,18 @@ typedef struct {
   int32_t max_batch;              /* solves per tick, 0 = as many as are co-resident          */
   int32_t unknowns_per_workgroup; /* cluster size of simulations opened with cluster = 0:    */
                                   /* ceil(n / this), 1..16, default 20000                    */
-  int32_t reserved;
+  int32_t queue_admission;        /* 1: sa_server_open of a simulation over the budget       */
+                                  /* returns an id that waits for admission; 0 (default):    */
+                                  /* SA_EBUSY                                                */
 } sa_server_options;
 
 typedef struct {
   uint64_t ticket;                /* from sa_server_submit                                    */
   int32_t sim;
   int32_t reserved;
-  sa_solve_info info;             /* as sa_solve reports it; status < 0 for SA_EGEOM etc.    */
+  sa_solve_info info;             /* as sa_solve reports it; status < 0 for SA_EGEOM etc.;   */
+                                  /* SA_EDEVICE for the requests of a simulation whose solve */
+                                  /* timed out on the device, and for those still queued     */
   double t_submit_ms;             /* server clock: ms since sa_server_create                  */
   double t_launch_ms;             /* when its tick was enqueued                               */
   double t_done_ms;               /* when its tick finished on the device                     */
@@ -224,25 +244,46 @@ int sa_server_create(const sa_server_options* opt, void* hip_stream, sa_server**
 /* Waits for all work, destroys every open simulation. */
 void sa_server_destroy(sa_server* s);
 /* Admit a simulation (arguments as sa_create; opt->cluster = 0 picks the cluster size from
- * its size). SA_EBUSY (nothing allocated) when its arena would exceed the HBM budget. */
+ * its size). SA_EBUSY (nothing allocated) when its arena would exceed the HBM budget, unless
+ * queue_admission is set: then *sim is valid at once, requests may be submitted, and the
+ * simulation is created when it fits (sa_server_admitted). A simulation larger than the whole
+ * budget is always refused. */
 int sa_server_open(sa_server* s, const sa_grid* grid, const double* h, const sa_options* opt, int32_t* sim);
-/* Free a simulation without queued or running requests (else SA_EBUSY). */
+/* 1: the simulation holds its device arena; 0: waiting for admission; -1: no such simulation
+ * (or its admission failed). */
+int32_t sa_server_admitted(const sa_server* s, int32_t sim);
+/* Free a simulation without queued or running requests (else SA_EBUSY); a simulation that
+ * failed on the device can always be closed once its running tick has been harvested. Frees
+ * budget for simulations waiting for admission. */
 int sa_server_close(sa_server* s, int32_t sim);
 /* Queue the next system of `sim`. Host inputs (eta: nphys values each, b: n values) are copied
- * before return; device inputs must stay valid until the request completes. */
+ * before return; device inputs must stay valid until the request completes. x_out (same
+ * memory kind as the inputs, n values, or NULL) receives the solution when the request's
+ * completion is harvested. */
 int sa_server_submit(sa_server* s, int32_t sim, const double* eta_prev, const double* eta_cur, const double* b,
-                     int32_t mem, uint64_t* ticket);
-/* Harvest finished ticks, launch new ones from the queues, return up to `max` completions
- * (oldest tick first). wait != 0: block until at least one completion is available when
- * work is outstanding. */
-int sa_server_poll(sa_server* s, sa_completion* out, int32_t max, int32_t* n_out, int32_t wait);
+                     int32_t mem, double* x_out, uint64_t* ticket);
+/* Harvest finished ticks, admit waiting simulations, launch new ticks from the queues, return
+ * up to `max` completions (oldest tick first). wait_us = 0: no waiting; < 0: wait until at
+ * least one completion is available while a tick runs; > 0: wait at most that many
+ * microseconds for one. */
+int sa_server_poll(sa_server* s, sa_completion* out, int32_t max, int32_t* n_out, int32_t wait_us);
 /* Requests queued, running or completed but not yet returned by sa_server_poll. */
 int64_t sa_server_outstanding(const sa_server* s);
-/* Device bytes held by the open simulations. */
+/* Device bytes held by the admitted simulations. */
 int64_t sa_server_bytes_used(const sa_server* s);
-/* The problem of an open simulation with no request running (for sa_get_solution,
+/* The server's clock (ms since sa_server_create; the clock of sa_completion's times). */
+double sa_server_clock_ms(const sa_server* s);
+/* Counters since creation: out[0] ticks launched, [1] solves launched, [2] host ms spent
+ * forming and enqueuing ticks, [3] ms from enqueue to completion summed over the ticks. */
+int sa_server_stats(const sa_server* s, double* out, int32_t n);
+/* The problem of an admitted simulation with no request running (for sa_get_solution,
  * sa_read_log; no sa_solve on it); NULL while one of its requests is in a running tick. */
 sa_problem* sa_server_problem(sa_server* s, int32_t sim);
+
+/* Failure-handling tests: raise the problem's device abort flag, which every bounded wait of
+ * its solve kernel checks, so that its next solve returns at once with SA_EDEVICE (every
+ * kernel still exits normally) and the problem becomes unusable. */
+int sa_debug_abort(sa_problem* p);
 
 /* Thread-local message of the last hard error ("" if none). */
 const char* sa_last_error(void);

@@ -16,6 +16,7 @@ Modules, each following the passage it cites:
                      V-cycle (the still-water preconditioner role of Sec. 3)
 * ``gmres``         left-preconditioned restarted GMRES (Saad & Schultz 1986, Sec. 3)
 * ``subspace``      EWMA sketch (Alg. 4) and the least-squares initial guess (Alg. 2)
+* ``rangefinder``   randomized range finder over a sliding window of solutions (Alg. 3)
 * ``rng``           the counter-based Gaussian stream that draws the sketch vectors
 * ``sequence``      the per-system driver: guess, solve, push the solution into the sketch
 

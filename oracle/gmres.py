@@ -15,6 +15,12 @@ restart cap are not stated in the paper; readings:
 * the iteration count is the number of Arnoldi steps over all cycles; x0 already inside
   the tolerance returns after zero iterations (Sec. 5.1 observes such solves).
 
+Every decision compares a value with a threshold; ``Info.margins`` records, per kind of
+decision, the smallest |ln(value / threshold)| the solve met: 'residual' (initial accept,
+every true-residual check and cycle end), 'trigger' (the Arnoldi estimate against the check
+threshold, every step) and 'breakdown' (every step), so that a caller can tell a solve whose
+decisions are clear-cut from one that sits at a tie.
+
 Pins (tests/test_oracle_gmres.py): dense LU on small systems, convergence in at most p steps
 for a diagonal matrix with p distinct eigenvalues, zero/one step for the identity,
 restart bookkeeping on a non-normal system that needs several cycles.
@@ -37,6 +43,15 @@ class Info:
     relres0: float = 0.0
     relres: float = 0.0
     checks: int = 0
+    margins: dict = None
+
+    def note(self, kind: str, value: float, threshold: float):
+        """Record the margin of the decision value <= threshold of the given kind."""
+        if self.margins is None:
+            self.margins = {}
+        if threshold > 0.0 and value > 0.0 and np.isfinite(value):
+            m = abs(float(np.log(value / threshold)))
+            self.margins[kind] = min(self.margins.get(kind, np.inf), m)
 
 
 def _nrm(v) -> float:
@@ -53,6 +68,7 @@ def gmres(A, b, x0, minv, m: int, rtol: float, max_restarts: int = 200):
     r = b - A @ x
     rn = _nrm(r)
     info.relres0 = info.relres = rn / nb
+    info.note("residual", rn, rtol * nb)
     if rn <= rtol * nb:
         return x, info
     trigger = rtol * _nrm(minv(b))
@@ -80,6 +96,7 @@ def gmres(A, b, x0, minv, m: int, rtol: float, max_restarts: int = 200):
             hn = _nrm(w)
             col[j + 1] = hn
             breakdown = hn <= BREAKDOWN_RATIO * w0
+            info.note("breakdown", hn, BREAKDOWN_RATIO * w0)
             for i in range(j):
                 t = cs[i] * col[i] + sn[i] * col[i + 1]
                 col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1]
@@ -90,12 +107,14 @@ def gmres(A, b, x0, minv, m: int, rtol: float, max_restarts: int = 200):
             H[:, j] = col
             g[j + 1] = -sn[j] * g[j]
             g[j] = cs[j] * g[j]
+            info.note("trigger", abs(g[j + 1]), trigger)
             if breakdown or abs(g[j + 1]) <= trigger:
                 y = _back_substitute(H[: j + 1, : j + 1], g[: j + 1])
                 xc = x + V[: j + 1].T @ y
                 rc = b - A @ xc
                 rcn = _nrm(rc)
                 info.checks += 1
+                info.note("residual", rcn, rtol * nb)
                 if rcn <= rtol * nb:
                     info.relres = rcn / nb
                     return xc, info
@@ -111,6 +130,7 @@ def gmres(A, b, x0, minv, m: int, rtol: float, max_restarts: int = 200):
             r = b - A @ x
             rn = _nrm(r)
             info.relres = rn / nb
+            info.note("residual", rn, rtol * nb)
             if rn <= rtol * nb:
                 return x, info
         info.relres = rn / nb

@@ -19,6 +19,7 @@ from . import gmres as _gmres
 from . import precond as _precond
 from . import refine as _refine
 from .discretization import Grid, mixed_stage_operator
+from .rangefinder import RangeFinder
 from .subspace import TAU_DROP, EWMASketch, guess
 
 
@@ -33,8 +34,10 @@ class Options:
     omega: float = 0.5
     max_levels: int = 32
     coarse_max: int = 700
-    guess: str = "ewma"  # cold | previous | ewma
+    guess: str = "ewma"  # cold | previous | ewma | range (Alg. 3, V = X Omega)
     k: int = 8
+    window: int = 16  # K, solutions kept by the range finder (guess = 'range')
+    orthonormalize: bool = False  # range finder: V = Q
     r: float = 0.9
     seed: int = 0
     n_init: int = 0
@@ -50,6 +53,7 @@ class Result:
     info: _gmres.Info
     rank: int = 0
     x0: np.ndarray = field(default=None, repr=False)
+    margins: dict = None  # smallest decision margin per kind: 'drop' (guess) and gmres.Info's
 
 
 class Simulation:
@@ -59,31 +63,39 @@ class Simulation:
         self.opts = opts
         self.minv = _precond.make(self.grid, self.h, opts.precond, opts.nu1, opts.nu2, opts.omega,
                                   opts.max_levels, opts.coarse_max)
-        self.sketch = EWMASketch(self.grid.n, opts.k, opts.r, opts.seed) if opts.guess == "ewma" else None
+        if opts.guess == "ewma":
+            self.sketch = EWMASketch(self.grid.n, opts.k, opts.r, opts.seed)
+        elif opts.guess == "range":
+            self.sketch = RangeFinder(self.grid.n, opts.window, opts.k, opts.seed, opts.orthonormalize)
+        else:
+            self.sketch = None
         self.x_prev = None
         self.solves = 0
 
     @classmethod
     def from_workload(cls, w, **overrides):
-        kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, k=w.k, r=w.r, seed=w.seed)
+        kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=getattr(w, "nu2", 1), k=w.k, r=w.r,
+                  seed=w.seed)
         kw.update(overrides)
         return cls(w.nx, w.nz, w.bc, w.length, w.depth(), Options(**kw))
 
     def operator(self, eta_prev, eta_cur):
         return mixed_stage_operator(self.grid, self.h, eta_prev, eta_cur)
 
-    def initial_guess(self, A, b):
+    def initial_guess(self, A, b, stats=None):
         o, n = self.opts, self.grid.n
         prev = self.x_prev if self.x_prev is not None else np.zeros(n)
         if o.guess == "cold":
             return np.zeros(n), 0
         if o.guess == "previous" or self.sketch.pushes == 0 or self.solves < o.n_init:
             return prev.copy(), 0
-        return guess(A, self.sketch.Y, b, o.tau_drop)
+        V = self.sketch.basis() if o.guess == "range" else self.sketch.Y
+        return guess(A, V, b, o.tau_drop, stats)
 
     def solve(self, eta_prev, eta_cur, b) -> Result:
         A = self.operator(eta_prev, eta_cur)
-        x0, rank = self.initial_guess(A, b)
+        stats = {}
+        x0, rank = self.initial_guess(A, b, stats)
         o = self.opts
         if o.precision == "fp32_ir":
             x, info = _refine.solve(A, b, x0, self.minv, o.restart, o.rtol, o.rtol_inner, o.max_refine)
@@ -93,4 +105,7 @@ class Simulation:
             self.sketch.push(x)
         self.x_prev = x
         self.solves += 1
-        return Result(x=x, info=info, rank=rank, x0=x0)
+        margins = dict(getattr(info, "margins", None) or {})
+        if "margin" in stats:
+            margins["drop"] = stats["margin"]
+        return Result(x=x, info=info, rank=rank, x0=x0, margins=margins)

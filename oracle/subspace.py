@@ -41,10 +41,11 @@ class EWMASketch:
         self.pushes += 1
 
 
-def householder_lstsq_drop(W, b, tau_drop: float = TAU_DROP):
+def householder_lstsq_drop(W, b, tau_drop: float = TAU_DROP, stats: dict | None = None):
     """Least squares min ||W z - b|| by Householder QR, columns in order, dropping any column
     whose projected norm |R_jj| < tau_drop * (norm of that column). Returns (z, kept) with z
-    defined on the kept columns only."""
+    defined on the kept columns only. ``stats['margin']`` (when given) receives the smallest
+    |ln(|R_jj| / (tau_drop ||W e_j||))| over the drop decisions."""
     W = np.array(W, dtype=np.float64, copy=True)
     n, k = W.shape
     reflectors = []  # (v, beta) acting on rows rank..n-1
@@ -59,6 +60,8 @@ def householder_lstsq_drop(W, b, tau_drop: float = TAU_DROP):
         rank = len(kept)
         tail = col[rank:]
         tn = np.sqrt(tail @ tail)
+        if stats is not None and tn > 0.0:
+            stats["margin"] = min(stats.get("margin", np.inf), abs(float(np.log(tn / (tau_drop * cn)))))
         if tn < tau_drop * cn:
             continue
         alpha = -tn if tail[0] >= 0.0 else tn
@@ -84,12 +87,13 @@ def householder_lstsq_drop(W, b, tau_drop: float = TAU_DROP):
     return z, kept
 
 
-def guess(A, Y, b, tau_drop: float = TAU_DROP):
-    """x0 = Y D z* with z* = argmin ||A Y D z - b|| (Alg. 2 with V = Y, column-scaled)."""
+def guess(A, Y, b, tau_drop: float = TAU_DROP, stats: dict | None = None):
+    """x0 = Y D z* with z* = argmin ||A Y D z - b|| (Alg. 2 with V = Y, column-scaled).
+    ``stats`` receives the margin of the drop decisions (householder_lstsq_drop)."""
     W = A @ Y
     norms = np.sqrt(np.einsum("ij,ij->j", W, W))
     scale = np.where(norms > 0.0, 1.0 / np.where(norms > 0.0, norms, 1.0), 0.0)
-    z, kept = householder_lstsq_drop(W * scale[None, :], b, tau_drop)
+    z, kept = householder_lstsq_drop(W * scale[None, :], b, tau_drop, stats)
     x0 = np.zeros(Y.shape[0])
     if kept:
         x0 = Y[:, kept] @ (z * scale[kept])

@@ -20,7 +20,7 @@ SA_OK, SA_NOCONV = 0, 1
 SA_EBUSY = -7
 SA_PERIODIC, SA_WALLS = 0, 1
 SA_PC = {"none": 0, "line": 1, "mg": 2}
-SA_GUESS = {"cold": 0, "previous": 1, "ewma": 2}
+SA_GUESS = {"cold": 0, "previous": 1, "ewma": 2, "range": 3}
 SA_PRECISION = {"fp64": 0, "fp32_ir": 1}
 SA_MEM_HOST, SA_MEM_DEVICE = 0, 1
 SA_SYNC, SA_ASYNC = 0, 1
@@ -37,7 +37,7 @@ class SaOptions(C.Structure):
         ("max_levels", C.c_int32), ("guess", C.c_int32), ("k", C.c_int32), ("r", C.c_double),
         ("seed", C.c_uint64), ("n_init", C.c_int32), ("tau_drop", C.c_double),
         ("precision", C.c_int32), ("rtol_inner", C.c_double), ("max_refine", C.c_int32),
-        ("cluster", C.c_int32), ("profile", C.c_int32), ("coarse_max", C.c_int32),
+        ("cluster", C.c_int32), ("profile", C.c_int32), ("coarse_max", C.c_int32), ("window", C.c_int32),
     ]
 
 
@@ -50,7 +50,7 @@ class SaSolveInfo(C.Structure):
 
 class SaServerOptions(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
-                ("unknowns_per_workgroup", C.c_int32), ("reserved", C.c_int32)]
+                ("unknowns_per_workgroup", C.c_int32), ("queue_admission", C.c_int32)]
 
 
 class SaCompletion(C.Structure):
@@ -115,6 +115,8 @@ def _load():
         "sa_solve": (C.c_int, [P, C.POINTER(SaSolveInfo), C.c_int32]),
         "sa_read_log": (C.c_int, [P, C.POINTER(SaSolveInfo), C.c_int32, C.POINTER(C.c_int32)]),
         "sa_get_solution": (C.c_int, [P, P, C.c_int32]),
+        "sa_get_solution_async": (C.c_int, [P, P]),
+        "sa_debug_abort": (C.c_int, [P]),
         "sa_apply_operator": (C.c_int, [P, P, P, C.c_int32]),
         "sa_apply_precond": (C.c_int, [P, P, P, C.c_int32]),
         "sa_apply_operator_f32": (C.c_int, [P, P, P, C.c_int32]),
@@ -131,7 +133,10 @@ def _load():
         "sa_server_destroy": (None, [P]),
         "sa_server_open": (C.c_int, [P, C.POINTER(SaGrid), D, C.POINTER(SaOptions), C.POINTER(C.c_int32)]),
         "sa_server_close": (C.c_int, [P, C.c_int32]),
-        "sa_server_submit": (C.c_int, [P, C.c_int32, P, P, P, C.c_int32, C.POINTER(C.c_uint64)]),
+        "sa_server_submit": (C.c_int, [P, C.c_int32, P, P, P, C.c_int32, P, C.POINTER(C.c_uint64)]),
+        "sa_server_admitted": (C.c_int32, [P, C.c_int32]),
+        "sa_server_clock_ms": (C.c_double, [P]),
+        "sa_server_stats": (C.c_int, [P, D, C.c_int32]),
         "sa_server_poll": (C.c_int, [P, C.POINTER(SaCompletion), C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
         "sa_server_outstanding": (C.c_int64, [P]),
         "sa_server_bytes_used": (C.c_int64, [P]),
@@ -215,7 +220,7 @@ def make_options(**opts) -> SaOptions:
 
 def workload_args(w, **overrides):
     """(grid, depth, options) of a synthetic workload."""
-    kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, k=w.k, r=w.r, seed=w.seed)
+    kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=w.nu2, k=w.k, r=w.r, seed=w.seed)
     kw.update(overrides)
     grid = SaGrid(w.nx, w.nz, SA_PERIODIC if w.bc == "periodic" else SA_WALLS, float(w.length))
     return grid, np.ascontiguousarray(w.depth(), dtype=np.float64), make_options(**kw)
@@ -249,7 +254,7 @@ class Problem:
 
     @classmethod
     def from_workload(cls, w, stream=None, **overrides):
-        kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, k=w.k, r=w.r, seed=w.seed)
+        kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=w.nu2, k=w.k, r=w.r, seed=w.seed)
         kw.update(overrides)
         return cls(w.nx, w.nz, w.bc, w.length, w.depth(), stream=stream, **kw)
 
@@ -302,6 +307,14 @@ class Problem:
             out = np.zeros(self.n)
         p, m, _ = _ptr(out, self.n)
         _check(lib.sa_get_solution(self._h, p, m))
+        return out
+
+    def solution_async(self, out):
+        """Enqueue a copy of the last solution into the device tensor `out` (no wait)."""
+        p, m, _ = _ptr(out, self.n)
+        if m != SA_MEM_DEVICE:
+            raise ValueError("solution_async writes device memory only")
+        _check(lib.sa_get_solution_async(self._h, p))
         return out
 
     def apply_operator(self, x, out=None):
@@ -408,7 +421,8 @@ class Server:
         self.close()
 
     def open(self, w, **overrides) -> int | None:
-        """Admit workload w; None when its arena does not fit the HBM budget now."""
+        """Admit workload w; None when its arena does not fit the HBM budget now (without
+        queue_admission), else its simulation id (check admitted() with queue_admission)."""
         grid, h, o = workload_args(w, **overrides)
         sid = C.c_int32(-1)
         code = lib.sa_server_open(self._h, C.byref(grid), h.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o),
@@ -419,33 +433,54 @@ class Server:
         self._sims[sid.value] = (w.n, w.nx - 1 if w.bc == "periodic" else w.nx)
         return sid.value
 
+    def admitted(self, sim: int) -> int:
+        return int(lib.sa_server_admitted(self._h, sim))
+
     def close_sim(self, sim: int):
         _check(lib.sa_server_close(self._h, sim))
         self._sims.pop(sim, None)
 
-    def submit(self, sim: int, eta_prev, eta_cur, b) -> int:
+    def submit(self, sim: int, eta_prev, eta_cur, b, x_out=None) -> int:
+        """Queue the next system of `sim`; x_out (same memory kind as the inputs) receives the
+        solution when the completion is harvested."""
         n, nphys = self._sims[sim]
         pa, ma, ka = _ptr(eta_prev, nphys)
         pb, mb, kb = _ptr(eta_cur, nphys)
         pr, mr, kr = _ptr(b, n)
+        px, kx = C.c_void_p(0), None
+        if x_out is not None:
+            px, mx, kx = _ptr(x_out, n)
+            if mx != ma or (mx == SA_MEM_HOST and kx is not x_out):
+                raise ValueError("x_out must be a contiguous float64 array in the inputs' memory")
         if not (ma == mb == mr):
             raise ValueError("all inputs must live in the same memory")
         t = C.c_uint64(0)
-        _check(lib.sa_server_submit(self._h, sim, pa, pb, pr, ma, C.byref(t)))
-        if ma == SA_MEM_DEVICE:
-            self._keep[t.value] = (ka, kb, kr)  # device inputs stay alive until completion
+        _check(lib.sa_server_submit(self._h, sim, pa, pb, pr, ma, px, C.byref(t)))
+        if ma == SA_MEM_DEVICE or kx is not None:
+            self._keep[t.value] = (ka, kb, kr, kx)  # inputs and output stay alive until completion
         return t.value
 
-    def poll(self, wait: bool = False, max_entries: int = 1024) -> list:
+    def poll(self, wait: bool = False, timeout_s: float | None = None, max_entries: int = 1024) -> list:
+        """Completions harvested so far; with wait, block until one is available (at most
+        timeout_s seconds when given)."""
         buf = (SaCompletion * max_entries)()
         cnt = C.c_int32(0)
-        _check(lib.sa_server_poll(self._h, buf, max_entries, C.byref(cnt), 1 if wait else 0))
+        wait_us = 0 if not wait else (-1 if timeout_s is None else max(1, int(timeout_s * 1e6)))
+        _check(lib.sa_server_poll(self._h, buf, max_entries, C.byref(cnt), wait_us))
         out = []
         for i in range(cnt.value):
             c = buf[i]
             self._keep.pop(c.ticket, None)
             out.append(Completion(c.ticket, c.sim, SolveInfo.of(c.info), c.t_submit_ms, c.t_launch_ms, c.t_done_ms))
         return out
+
+    def clock_ms(self) -> float:
+        return float(lib.sa_server_clock_ms(self._h))
+
+    def stats(self) -> dict:
+        out = np.zeros(4)
+        _check(lib.sa_server_stats(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), 4))
+        return dict(ticks=int(out[0]), solves=int(out[1]), launch_host_ms=float(out[2]), tick_ms=float(out[3]))
 
     @property
     def outstanding(self) -> int:
@@ -470,6 +505,13 @@ class Server:
         _check(lib.sa_set_surface(p, pa, pb, ma))
         _check(lib.sa_apply_operator(p, px, py, mx))
         return out
+
+    def debug_abort(self, sim: int):
+        """Raise the device abort flag of an idle simulation (failure-handling tests)."""
+        p = lib.sa_server_problem(self._h, sim)
+        if not p:
+            raise SawaveError(-1, f"simulation {sim} has no idle problem")
+        _check(lib.sa_debug_abort(p))
 
     def solution(self, sim: int, out=None):
         n, _ = self._sims[sim]

@@ -52,6 +52,7 @@ extern "C" void sa_default_options(sa_options* o) {
   o->cluster = 0;
   o->profile = 0;
   o->coarse_max = 700;
+  o->window = 16;
 }
 
 extern "C" const char* sa_last_error(void) { return g_err.c_str(); }
@@ -71,45 +72,6 @@ extern "C" int sa_sketch_draws(uint64_t seed, int64_t index, int32_t k, double* 
 
 // ---------------------------------------------------------------------------------------
 // host-side tables
-
-static void sigma_table(int nl, double dsig, std::vector<double>& w, std::vector<int>& s) {
-  w.assign((size_t)nl * 7, 0.0);
-  s.assign(nl, 0);
-  double nodes[7], c[14];
-  for (int j = 0; j < nl; ++j) {
-    const int st = window_start(j, nl, 7);
-    for (int m = 0; m < 7; ++m) nodes[m] = (double)(st + m);
-    fornberg((double)j, nodes, 7, 1, c);
-    for (int m = 0; m < 7; ++m) w[(size_t)j * 7 + m] = c[m * 2 + 1] / dsig;
-    s[j] = st;
-  }
-}
-
-static void chi_table(int ncol, double dx, std::vector<double>& w) {
-  w.assign(49, 0.0);
-  double nodes[7], c[14];
-  for (int m = 0; m < 7; ++m) nodes[m] = (double)m;
-  for (int row = 0; row < 7; ++row) {
-    // rows 0-2: node 0,1,2 of a left window; 3: centre; 4-6: nodes 4,5,6 of a right window
-    const double z = row < 3 ? row : (row == 3 ? 3.0 : (double)row);
-    fornberg(z, nodes, 7, 1, c);
-    for (int m = 0; m < 7; ++m) w[row * 7 + m] = c[m * 2 + 1] / dx;
-  }
-  (void)ncol;
-}
-
-static std::vector<double> extend(const double* v, int nphys, int periodic) {
-  std::vector<double> e;
-  if (periodic) {
-    e.assign(v, v + nphys);
-  } else {
-    e.resize(nphys + 2);
-    e[0] = v[1];
-    for (int i = 0; i < nphys; ++i) e[i + 1] = v[i];
-    e[nphys + 1] = v[nphys - 2];
-  }
-  return e;
-}
 
 // second-order centred dh/dx, d2h/dx2 on the extended column grid
 static void centred_h(const std::vector<double>& h, int periodic, double dx, std::vector<double>& hx,
@@ -214,8 +176,10 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   if (opt.precond < SA_PC_NONE || opt.precond > SA_PC_MG) return sa_fail(SA_EARG, "sa_create: unknown precond");
   if (opt.nu1 < 0 || opt.nu2 < 0 || opt.nu1 > 8 || opt.nu2 > 8) return sa_fail(SA_EARG, "sa_create: sweeps in [0, 8]");
   if (opt.precond == SA_PC_LINE && opt.nu1 < 1) return sa_fail(SA_EARG, "sa_create: line preconditioner needs nu1 >= 1");
-  if (opt.guess < SA_GUESS_COLD || opt.guess > SA_GUESS_EWMA) return sa_fail(SA_EARG, "sa_create: unknown guess mode");
+  if (opt.guess < SA_GUESS_COLD || opt.guess > SA_GUESS_RANGE) return sa_fail(SA_EARG, "sa_create: unknown guess mode");
   if (opt.k < 1 || opt.k > KMAX) return sa_fail(SA_EARG, "sa_create: k must be in [1, %d]", KMAX);
+  if (opt.guess == SA_GUESS_RANGE && (opt.window < opt.k || opt.window > KWIN))
+    return sa_fail(SA_EARG, "sa_create: window must be in [k, %d]", KWIN);
   if (!(opt.r >= 0.0 && opt.r <= 1.0)) return sa_fail(SA_EARG, "sa_create: r must be in [0, 1]");
   if (opt.precision != SA_FP64 && opt.precision != SA_FP32_IR) return sa_fail(SA_EARG, "sa_create: unknown precision");
   if (opt.precision == SA_FP32_IR && !(opt.rtol_inner > 0.0 && opt.rtol_inner < 1.0))
@@ -244,23 +208,10 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   const double dx = grid->length / (grid->nx - 1), dsig = 1.0 / (grid->nz - 1);
 
   // ---- tables
-  std::vector<double> wsig, wchi, sig(nl);
-  std::vector<int> ssig;
-  sigma_table(nl, dsig, wsig, ssig);
-  chi_table(ncol, dx, wchi);
-  for (int j = 0; j < nl; ++j) sig[j] = (j - 1) * dsig;
-  std::vector<double> hext = extend(h, nphys, periodic);
-  std::vector<double> hchi(ncol, 0.0);
-  for (int c = 0; c < ncol; ++c) {
-    int row, start;
-    if (periodic) { row = 3; start = c - 3; }
-    else if (c < 3) { row = c; start = 0; }
-    else if (c > ncol - 4) { row = 4 + c - (ncol - 3); start = ncol - 7; }
-    else { row = 3; start = c - 3; }
-    double s = 0.0;
-    for (int m = 0; m < 7; ++m) s += wchi[row * 7 + m] * hext[((start + m) % ncol + ncol) % ncol];
-    hchi[c] = s;
-  }
+  OperatorTables tb;
+  operator_tables(ncol, nl, nphys, periodic, dx, dsig, h, tb);
+  const std::vector<double>&wsig = tb.wsig, &wchi = tb.wchi, &sig = tb.sig, &hext = tb.hext, &hchi = tb.hchi;
+  const std::vector<int>& ssig = tb.ssig;
 
   // ---- still-water hierarchy
   struct HL { int nx, ncol; double dx; std::vector<double> h, ih, hx, hxx, fpc, finv, flo, fgam; int fstride; };
@@ -289,7 +240,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
       std::vector<double> hc;
       for (size_t i = 0; i < hphys.size(); i += 2) hc.push_back(hphys[i]);
       hphys = hc;
-      c.h = extend(hphys.data(), (int)hphys.size(), periodic);
+      c.h = extend_columns(hphys.data(), (int)hphys.size(), periodic);
       for (double v : c.h) c.ih.push_back(1.0 / v);
       centred_h(c.h, periodic, c.dx, c.hx, c.hxx);
       levs.push_back(c);
@@ -338,7 +289,8 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   // block operator of the guess on tiles of tg columns (widest tile tg + 3)
   auto need_gram_of = [&](int tg) {
     const int Wg = tg + 3;
-    return opt.guess == SA_GUESS_EWMA ? (size_t)(k * Wg + Wg + Wg + 12 + 2 * (Wg + 6)) * nl + opcoef(Wg) : 0;
+    const bool sk = opt.guess == SA_GUESS_EWMA || opt.guess == SA_GUESS_RANGE;
+    return sk ? (size_t)(k * Wg + Wg + Wg + 12 + 2 * (Wg + 6)) * nl + opcoef(Wg) : 0;
   };
   const int TMSh = 64 + 4;  // preconditioner tile with its 2-column halo
   size_t need_pc = (size_t)5 * TMSh * nl + 5 * TMSh;
@@ -369,7 +321,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   size_t res_total = 0;
   const size_t res_esz = opt.precision == SA_FP32_IR ? sizeof(float) : sizeof(double);
   const size_t gmres_scratch = need_op > need_pc ? need_op : need_pc;
-  if (opt.precond == SA_PC_MG && opt.nu1 == 1 && opt.nu2 == 1) {
+  if (opt.precond == SA_PC_MG && opt.nu1 == 1 && opt.nu2 >= 1) {
     const int lt = (G > 1 && tail < nlev - 1) ? tail : nlev - 1;
     for (int l = 0; l < lt; ++l) {
       const int tw = (levs[l].ncol + 31) / 32 <= G ? 32 : TM_HOST;
@@ -435,8 +387,10 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
                o_r32 = ir ? take((size_t)n * 4) : 0;
   const size_t o_x = take((size_t)n * 8), o_xc = take((size_t)n * 8), o_r = take((size_t)n * 8),
                o_rc = take((size_t)n * 8), o_t = take((size_t)n * 8), o_V = take((size_t)(m + 1) * n * 8);
-  const size_t ysz = opt.guess == SA_GUESS_EWMA ? (size_t)k * n * 8 : 8;
-  const size_t o_Y0 = take(ysz), o_Y1 = take(ysz);
+  const bool range = opt.guess == SA_GUESS_RANGE;
+  const size_t ysz = opt.guess == SA_GUESS_EWMA || range ? (size_t)k * n * 8 : 8;
+  const size_t o_Y0 = take(ysz), o_Y1 = take(range ? 8 : ysz);
+  const size_t o_Xr = take(range ? (size_t)opt.window * n * 8 : 8), o_Om = take((size_t)KWIN * KMAX * 8);
   const size_t o_part = take((size_t)2 * G * PSTRIDE * 8), o_bar = take(64), o_flags = take(NFLAGS * 4),
                o_log = take(LOGCAP * sizeof(sa_solve_info)), o_b = take((size_t)n * 8), o_eta = take(2 * (size_t)nphys * 8),
                o_prob = take(sizeof(Problem)), o_prof = take(NPROF * 8);
@@ -538,6 +492,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   P.x = (decltype(P.x))(A + o_x); P.xc = (decltype(P.xc))(A + o_xc); P.r = (decltype(P.r))(A + o_r); P.rc = (decltype(P.rc))(A + o_rc);
   P.t = (decltype(P.t))(A + o_t); P.V = (decltype(P.V))(A + o_V);
   P.Y[0] = (std::remove_reference_t<decltype(P.Y[0])>)(A + o_Y0); P.Y[1] = (std::remove_reference_t<decltype(P.Y[1])>)(A + o_Y1);
+  P.Xr = (decltype(P.Xr))(A + o_Xr); P.Om = (decltype(P.Om))(A + o_Om); P.K = range ? opt.window : 0;
   P.k = k; P.m = m; P.max_restarts = opt.max_restarts; P.tau_drop = opt.tau_drop; P.txg = txg;
   P.partials = (decltype(P.partials))(A + o_part); P.bar = (decltype(P.bar))(A + o_bar); P.flags = (decltype(P.flags))(A + o_flags);
   P.log = (decltype(P.log))(A + o_log); P.G = G;
@@ -671,12 +626,16 @@ static hipError_t launch_cluster(sa_problem* p, const void* fn, void** args, siz
 SolveArgs sa_prepare_solve(sa_problem* p, bool* ewma_out) {
   SolveArgs a = base_args(p);
   const sa_options& o = p->opt;
-  const bool ewma = o.guess == SA_GUESS_EWMA;
-  a.push = ewma && p->unpushed;
+  const bool ewma = o.guess == SA_GUESS_EWMA, range = o.guess == SA_GUESS_RANGE;
+  const bool sk = ewma || range;
+  a.push = sk && p->unpushed;
   if (a.push) splitmix_gaussians(o.seed, p->pushes, o.k, a.om);
   const int64_t pushes_after = p->pushes + (a.push ? 1 : 0);
-  a.sketch_guess = ewma && pushes_after > 0 && p->solves >= o.n_init;
-  a.prev_guess = p->have_solution && (o.guess == SA_GUESS_PREVIOUS || (ewma && !a.sketch_guess));
+  a.sketch_guess = sk && pushes_after > 0 && p->solves >= o.n_init;
+  a.prev_guess = p->have_solution && (o.guess == SA_GUESS_PREVIOUS || (sk && !a.sketch_guess));
+  a.range = range ? 1 : 0;
+  a.range_slot = (range && a.push) ? (int)(p->pushes % o.window) : -1;
+  a.window = range ? (int)(pushes_after < o.window ? pushes_after : o.window) : 0;
   a.log_slot = (int)(p->log_pos % LOGCAP);
   *ewma_out = ewma;
   return a;
@@ -684,10 +643,10 @@ SolveArgs sa_prepare_solve(sa_problem* p, bool* ewma_out) {
 
 void sa_commit_solve(sa_problem* p, const SolveArgs& a) {
   if (a.push) {
-    p->ycur ^= 1;
+    if (!a.range) p->ycur ^= 1;  // the EWMA sketch ping-pongs; the range finder's ring does not
     p->pushes += 1;
   }
-  p->unpushed = p->opt.guess == SA_GUESS_EWMA;
+  p->unpushed = p->opt.guess == SA_GUESS_EWMA || p->opt.guess == SA_GUESS_RANGE;
   p->have_solution = true;
   p->solves += 1;
   p->log_pos += 1;
@@ -752,6 +711,20 @@ extern "C" int sa_get_solution(sa_problem* p, double* x, int32_t mem) {
   if (!p || !x || (mem != SA_MEM_HOST && mem != SA_MEM_DEVICE)) return sa_fail(SA_EARG, "sa_get_solution: bad arguments");
   HIPCHK(hipMemcpyAsync(x, p->hp.x, (size_t)p->n * 8, kind_from(mem, false), p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
+  return SA_OK;
+}
+
+extern "C" int sa_debug_abort(sa_problem* p) {
+  if (!p) return sa_fail(SA_EARG, "sa_debug_abort: null problem");
+  const int one = 1;
+  HIPCHK(hipMemcpyAsync(p->hp.flags + FLAG_ABORT, &one, sizeof one, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return SA_OK;
+}
+
+extern "C" int sa_get_solution_async(sa_problem* p, double* x) {
+  if (!p || !x) return sa_fail(SA_EARG, "sa_get_solution_async: null argument");
+  HIPCHK(hipMemcpyAsync(x, p->hp.x, (size_t)p->n * 8, hipMemcpyDeviceToDevice, p->stream));
   return SA_OK;
 }
 

@@ -33,6 +33,7 @@ namespace sa {
 extern __shared__ double dyn_lds[];
 
 constexpr long SPIN_LIMIT = 1L << 25;
+static_assert(NWAVE * (MMAX + 2) >= BLOCK, "the cluster-sum scratch (wsum) holds one double per thread");
 
 // ------------------------------------------------------------------------------------------
 // cluster of workgroups cooperating on one problem
@@ -43,6 +44,7 @@ struct Cl {
   double* partials;
   int pbuf;
   unsigned gen;  // barrier generation this workgroup last saw complete (thread 0 only)
+  double* scr;   // BLOCK doubles of LDS for the cluster sums (nullptr: sums read serially)
 };
 
 // The barrier word of a cluster: one 64-bit atomic, arrivals in the low half, the generation
@@ -53,7 +55,7 @@ DEV unsigned long long* bar_word(unsigned* bar) { return reinterpret_cast<unsign
 // it advances only after all G workgroups have arrived at a barrier, and each reads it before
 // its first arrival, so all start from the same value; the barrier then tracks it locally.
 DEV Cl make_cl(const Problem& P, int rank, int G) {
-  Cl cl{rank, G, P.bar, P.flags, P.partials, 0, 0u};
+  Cl cl{rank, G, P.bar, P.flags, P.partials, 0, 0u, nullptr};
   if (threadIdx.x == 0 && G > 1)
     cl.gen = (unsigned)(__hip_atomic_load(bar_word(P.bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
   return cl;
@@ -105,7 +107,10 @@ DEV double wave_sum(double v) {
 }
 
 // red[0..nv) holds this workgroup's sums; afterwards it holds the cluster sums (same on all
-// workgroups, summed in rank order).
+// workgroups: every workgroup adds the G partials in the same fixed order). With an LDS
+// scratch the G x nv loads are spread over the whole workgroup: thread (q, i) adds the
+// partials g = q, q + Q, ... of value i (Q = BLOCK / nv threads per value, all loads issued
+// before the adds), then the Q sums of each value are added in q order.
 DEV void cluster_sum(Cl& cl, double* red, int nv) {
   __syncthreads();
   if (cl.G == 1) return;
@@ -113,10 +118,37 @@ DEV void cluster_sum(Cl& cl, double* red, int nv) {
   for (int i = threadIdx.x; i < nv; i += BLOCK) part[cl.rank * PSTRIDE + i] = red[i];
   cl.pbuf ^= 1;
   csync(cl);
-  for (int i = threadIdx.x; i < nv; i += BLOCK) {
+  const int Q = nv <= BLOCK ? BLOCK / nv : 1;
+  if (!cl.scr || Q < 2) {
+    for (int i = threadIdx.x; i < nv; i += BLOCK) {
+      double s = 0.0;
+      for (int g = 0; g < cl.G; ++g) s += part[g * PSTRIDE + i];
+      red[i] = s;
+    }
+    __syncthreads();
+    return;
+  }
+  const int q = threadIdx.x / nv, i = threadIdx.x - q * nv;
+  if (q < Q) {
+    constexpr int U = 8;
     double s = 0.0;
-    for (int g = 0; g < cl.G; ++g) s += part[g * PSTRIDE + i];
-    red[i] = s;
+    for (int g0 = q; g0 < cl.G; g0 += U * Q) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int g = g0 + u * Q;
+        v[u] = g < cl.G ? part[g * PSTRIDE + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += v[u];
+    }
+    cl.scr[q * nv + i] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nv; t += BLOCK) {
+    double s = 0.0;
+    for (int qq = 0; qq < Q; ++qq) s += cl.scr[qq * nv + t];
+    red[t] = s;
   }
   __syncthreads();
 }
@@ -981,7 +1013,18 @@ DEV void mg_down(const Problem& P, Cl& cl, int l, const S* v, S* lds, const S* r
   csync(cl);
 }
 
-// returns the buffer holding level l's output; z is level 0's destination
+// the buffer that holds level l's output after its up pass (l > 0): the post-sweeps alternate
+// between the level's two work vectors, starting from u, so an odd count ends in o
+template <class S>
+DEV const S* level_output(const Problem& P, int l) {
+  const Lv<S> L = level_view<S>(P, l);
+  return (P.nu2 % 2 == 1) ? (const S*)L.o : (const S*)L.u;
+}
+
+// returns the buffer holding level l's output; z is level 0's destination. Post-sweeps never
+// run in place (a sweep reads one halo column of its neighbour tiles, which other workgroups
+// write in the same phase): they alternate between the level's two work vectors, the first
+// adding the prolongated coarse correction on load, and at level 0 the last one writes z.
 template <class S>
 DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z, S* lds,
                    const S* rc = nullptr) {
@@ -989,7 +1032,6 @@ DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z
   const S* f = l == 0 ? v : L.f;
   S* A = L.u;
   S* B = L.o;
-  S* out = (l == 0) ? z : B;
   if (P.nu2 == 0) {
     phase_prolong<S>(P, cl, l, e, A);
     csync(cl);
@@ -1000,19 +1042,17 @@ DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z
     }
     return A;
   }
-  S* dst = (P.nu2 == 1) ? out : B;
-  // first post-sweep, correction added on load (on the level's tile width)
-  if (P.lev[l].tm == 32) phase_sweep<S, 32>(P, cl, l, f, A, e, dst, lds, rc);
-  else phase_sweep<S, TM>(P, cl, l, f, A, e, dst, lds, rc);
-  csync(cl);
-  const S* prev = dst;
-  for (int s = 1; s < P.nu2; ++s) {
-    S* nd = (s == P.nu2 - 1) ? out : ((prev == B) ? A : B);
-    phase_sweep<S>(P, cl, l, f, prev, nullptr, nd, lds);
+  const S* prev = A;
+  const S* corr = e;
+  for (int s = 0; s < P.nu2; ++s) {
+    S* nd = (l == 0 && s == P.nu2 - 1) ? z : (prev == B ? A : B);
+    if (P.lev[l].tm == 32) phase_sweep<S, 32>(P, cl, l, f, prev, corr, nd, lds, rc);
+    else phase_sweep<S, TM>(P, cl, l, f, prev, corr, nd, lds, rc);
     csync(cl);
     prev = nd;
+    corr = nullptr;
   }
-  return out;
+  return prev;
 }
 
 // z = M^-1 v in precision S. v and z are level-0 vectors distinct from each other and from
@@ -1053,7 +1093,7 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
   // the resident constants of cluster level l (res: the solve's resident block, or none)
   auto rc = [&](int l) -> const S* { return (res && P.lev[l].res >= 0) ? res + P.lev[l].res : nullptr; };
   for (int l = 0; l < lt; ++l) { mg_down<S>(P, cl, l, v, lds, rc(l)); tk(1 + 2 * l); }
-  Cl solo{0, 1, cl.bar, cl.flags, cl.partials, cl.pbuf, 0u};
+  Cl solo{0, 1, cl.bar, cl.flags, cl.partials, cl.pbuf, 0u, nullptr};
   if (lt < L - 1) {
     if (cl.rank == 0)
       for (int l = lt; l < L - 1; ++l) { mg_down<S>(P, solo, l, v, lds); tk(1 + 2 * l); }
@@ -1071,8 +1111,7 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
     csync(cl);
     tk(2 * MAXLEV);
     // every workgroup knows which buffer holds the tail's output
-    const Lv<S> Lt = level_view<S>(P, lt);
-    e = (lt == 0) ? z : (P.nu2 == 0 ? Lt.u : Lt.o);
+    e = (lt == 0) ? z : level_output<S>(P, lt);
     if (lt == 0) return;
   }
   for (int l = lt - 1; l >= 0; --l) { e = mg_up<S>(P, cl, l, v, e, z, lds, rc(l)); tk(2 + 2 * l); }
@@ -1207,6 +1246,45 @@ DEV void phase_push(const Problem& P, Cl& cl, const SolveArgs& a, const double* 
       Yn[(c + 3) * n + e] = a.r * y3 + a.om[c + 3] * xe;
     }
     for (; c < P.k; ++c) Yn[c * n + e] = a.r * Yo[c * n + e] + a.om[c] * xe;
+  }
+}
+
+// Randomized range finder (Alg. 3): the previous solution enters ring slot a.range_slot
+// (replacing the oldest one once the window is full) and V = X Omega over the a.window slots
+// in use, column c of V = sum_s Omega[s][c] x_s, elementwise (no halo), slots in ring order.
+// The rows of Omega of the slots are staged in LDS (lds: KWIN * KMAX doubles); the new slot's
+// row comes with the solve's draws a.om and is stored for the later solves by the first
+// workgroup (the other workgroups never read that row from memory in this phase).
+DEV void phase_range_form(const Problem& P, Cl& cl, const SolveArgs& a, double* V, double* lds) {
+  const size_t n = P.n;
+  const int k = P.k, win = a.window, slot = a.range_slot;
+  for (int i = threadIdx.x; i < win * KMAX; i += BLOCK) {
+    const int sl = i / KMAX, c = i - sl * KMAX;
+    lds[i] = (sl == slot) ? (c < k ? a.om[c] : 0.0) : P.Om[i];
+  }
+  __syncthreads();
+  if (cl.rank == 0 && slot >= 0)
+    for (int c = threadIdx.x; c < KMAX; c += BLOCK) P.Om[(size_t)slot * KMAX + c] = c < k ? a.om[c] : 0.0;
+  for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK) {
+    double acc[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
+    for (int sl = 0; sl < win; ++sl) {
+      double xs;
+      if (sl == slot) {
+        xs = P.x[e];
+        P.Xr[(size_t)sl * n + e] = xs;
+      } else {
+        xs = P.Xr[(size_t)sl * n + e];
+      }
+      const double* om = lds + sl * KMAX;
+#pragma unroll
+      for (int c = 0; c < KMAX; ++c)
+        if (c < k) acc[c] += om[c] * xs;
+    }
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c)
+      if (c < k) V[(size_t)c * n + e] = acc[c];
   }
 }
 
@@ -1562,20 +1640,32 @@ DEV bool solve_start(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S
   const double* Yo = P.Y[a.ycur];
   double* Yn = P.Y[a.ycur ^ 1];
   int rank = 0;
+  if (a.range) {
+    // range finder: the ring takes the previous solution and V = X Omega goes to Y[0]; the
+    // block pass below then reads V as it is (no fused update)
+    if (a.push || a.sketch_guess) {
+      phase_range_form(P, cl, a, P.Y[0], S.big);
+      csync(cl);
+    }
+    Yo = P.Y[0];
+    Yn = P.Y[0];
+  }
   if (a.sketch_guess) {
+    SolveArgs ab = a;
+    if (a.range) ab.push = 0;
     // the widest tiles (64, 32 or 16 columns) whose block operator fits the LDS
-    if (P.txg == 64) phase_block_gram<64>(P, cl, a, Yo, Yn, S.big, S.red);
-    else if (P.txg == 32) phase_block_gram<32>(P, cl, a, Yo, Yn, S.big, S.red);
-    else phase_block_gram<16>(P, cl, a, Yo, Yn, S.big, S.red);
+    if (P.txg == 64) phase_block_gram<64>(P, cl, ab, Yo, Yn, S.big, S.red);
+    else if (P.txg == 32) phase_block_gram<32>(P, cl, ab, Yo, Yn, S.big, S.red);
+    else phase_block_gram<16>(P, cl, ab, Yo, Yn, S.big, S.red);
     const int nv = P.k * (P.k + 1) / 2 + P.k;
     cluster_sum_dd(cl, S.red, nv);
     clk.tick(PH_GUESS);
     rank = small_solve(P, S.red, P.tau_drop, S.z, S.scr);
     csync(cl);  // every tile has read x (the previous solution) before it is overwritten
     clk.tick(PH_SMALL);
-    phase_sketch_combine(P, cl, a.push ? Yn : Yo, S.z);
+    phase_sketch_combine(P, cl, ab.push ? Yn : Yo, S.z);
   } else {
-    if (a.push) phase_push(P, cl, a, Yo, Yn);
+    if (a.push && !a.range) phase_push(P, cl, a, Yo, Yn);
     if (!a.prev_guess) {
       csync(cl);
       for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) P.x[e] = 0.0;
@@ -1934,6 +2024,7 @@ DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a, int rank
   double* smem = dyn_lds;
   Smem S = carve(smem, P.m);
   Cl cl = make_cl(P, rank, P.G);
+  cl.scr = S.wsum;  // NWAVE * (MMAX + 2) >= BLOCK doubles, free whenever a cluster sum runs
   PhaseClock clk;
   clk.begin(a.prof != nullptr, rank, a.prof);
   sa_solve_info info;

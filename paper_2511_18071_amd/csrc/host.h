@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "tables.h"
 
 namespace sa {
 extern "C" __global__ void sa_solve_kernel(const BatchItem*, int, BatchItem);

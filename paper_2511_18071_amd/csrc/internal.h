@@ -26,6 +26,7 @@ constexpr int NLMAX = 66;         // largest number of levels nz + 1
 constexpr int PSTRIDE = 320;      // doubles per workgroup in the reduction scratch
 constexpr int LOGCAP = 4096;      // solve reports kept on the device
 constexpr int COARSE_MAX = 1024;  // largest coarsest-grid size solved by a dense inverse
+constexpr int KWIN = 32;          // largest window of the randomized range finder
 
 // Flags written by kernels (device int array).
 enum { FLAG_GEOM = 0, FLAG_NONFINITE = 1, FLAG_ABORT = 2, NFLAGS = 4 };
@@ -96,6 +97,11 @@ struct Problem {
   double SA_GLOBAL* t;
   double SA_GLOBAL* V;
   double SA_GLOBAL* Y[2];
+  // randomized range finder: ring of the K most recent solutions (K x n, slot s at s * n) and
+  // the row of Omega of each slot (K x KMAX)
+  double SA_GLOBAL* Xr;
+  double SA_GLOBAL* Om;
+  int K;
   // inner basis and work vectors of the refinement path
   float SA_GLOBAL* V32;
   float SA_GLOBAL* t32;
@@ -119,6 +125,9 @@ struct SolveArgs {
   int sketch_guess;  // x0 from the sketch (Alg. 2 with V = Y)
   int prev_guess;    // x0 = previous solution (else zero) when no sketch guess
   int ycur;          // sketch buffer holding Y before this call
+  int range;         // the guess comes from the range finder (V = X Omega, kept in Y[0])
+  int range_slot;    // ring slot the previous solution enters (push), else -1
+  int window;        // ring slots in use after the push (slots 0 .. window - 1)
   int log_slot;
   const double SA_GLOBAL* b;      // right-hand side (n)
   const double SA_GLOBAL* eta_p;  // previous-stage surface (nphys)

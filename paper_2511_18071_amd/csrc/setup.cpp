@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "tables.h"
 
 namespace sa {
 
@@ -41,6 +42,56 @@ int window_start(int i, int npts, int width) {
   if (s > npts - width) s = npts - width;
   if (s < 0) s = 0;
   return s;
+}
+
+std::vector<double> extend_columns(const double* v, int nphys, int periodic) {
+  std::vector<double> e;
+  if (periodic) {
+    e.assign(v, v + nphys);
+  } else {
+    e.resize(nphys + 2);
+    e[0] = v[1];
+    for (int i = 0; i < nphys; ++i) e[i + 1] = v[i];
+    e[nphys + 1] = v[nphys - 2];
+  }
+  return e;
+}
+
+void operator_tables(int ncol, int nl, int nphys, int periodic, double dx, double dsig, const double* h,
+                     OperatorTables& t) {
+  double nodes[7], c[14];
+  // sigma: seven-point windows, centred where the levels allow, shifted inside at the ends
+  t.wsig.assign((size_t)nl * 7, 0.0);
+  t.ssig.assign(nl, 0);
+  for (int j = 0; j < nl; ++j) {
+    const int st = window_start(j, nl, 7);
+    for (int m = 0; m < 7; ++m) nodes[m] = (double)(st + m);
+    fornberg((double)j, nodes, 7, 1, c);
+    for (int m = 0; m < 7; ++m) t.wsig[(size_t)j * 7 + m] = c[m * 2 + 1] / dsig;
+    t.ssig[j] = st;
+  }
+  // x: the seven windows a column can need (rows 0-2: node 0, 1, 2 of a left window; 3:
+  // centre; 4-6: node 4, 5, 6 of a right window)
+  t.wchi.assign(49, 0.0);
+  for (int m = 0; m < 7; ++m) nodes[m] = (double)m;
+  for (int row = 0; row < 7; ++row) {
+    fornberg((double)row, nodes, 7, 1, c);
+    for (int m = 0; m < 7; ++m) t.wchi[row * 7 + m] = c[m * 2 + 1] / dx;
+  }
+  t.sig.resize(nl);
+  for (int j = 0; j < nl; ++j) t.sig[j] = (j - 1) * dsig;
+  t.hext = extend_columns(h, nphys, periodic);
+  t.hchi.assign(ncol, 0.0);
+  for (int col = 0; col < ncol; ++col) {
+    int row, start;
+    if (periodic) { row = 3; start = col - 3; }
+    else if (col < 3) { row = col; start = 0; }
+    else if (col > ncol - 4) { row = 4 + col - (ncol - 3); start = ncol - 7; }
+    else { row = 3; start = col - 3; }
+    double s = 0.0;
+    for (int m = 0; m < 7; ++m) s += t.wchi[row * 7 + m] * t.hext[((start + m) % ncol + ncol) % ncol];
+    t.hchi[col] = s;
+  }
 }
 
 // SplitMix64 (Steele, Lea & Flood 2014) as a counter-based stream: output i of seed s is

@@ -28,8 +28,18 @@ def test_default_cluster_rule():
     assert bench.default_cluster(W.get("tiny_17x7")) == 1
 
 
+def test_defaults_match_the_driver_command():
+    # the driver runs `bench.py --gpus 1 --steps 20 --warmup 5`: the same as the defaults, on
+    # the large single simulation
+    a = bench.parse([])
+    assert (a.gpus, a.steps, a.warmup, a.workload) == (1, 20, 5, "periodic_16385x33")
+
+
 def test_counter_summary_is_used_only_for_its_own_configuration():
-    text = open(bench.COUNTERS).read()
+    path = bench.counters_path("periodic_16385x33")
+    if not os.path.exists(path):
+        path = bench.counters_path("bar_513x17")
+    text = open(path).read()
     fields = dict(re.findall(r"^- ([a-z0-9-]+): `([^`]*)`", text, flags=re.M))
     wl, steps, warm, cl = fields["workload"], int(fields["steps"]), int(fields["warmup"]), int(fields["cluster"])
     got = bench.measured_traffic(wl, steps, warm, cl)

@@ -17,6 +17,7 @@ import pytest
 
 from oracle.sequence import Simulation
 from paper_2511_18071_amd import workload as W
+from tests.parity_rules import check_decisions, margins_text
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +37,7 @@ def B():
 
 @pytest.mark.parametrize("name,kw", [("bar_65x9", {}), ("periodic_65x9", dict(precision="fp32_ir", rtol=1e-10))])
 def test_zero_rhs(B, name, kw):
-    w = W.get(name)
+    w = W.get(name, seed=41 if name == "bar_65x9" else None)  # clear decisions (>= 3 % margins)
     _say(f"[edge zero rhs] {name} {kw}")
     ora = Simulation.from_workload(w, **kw)
     p = B.Problem.from_workload(w, stream=0, cluster=2, **kw)
@@ -58,7 +59,7 @@ def test_zero_rhs(B, name, kw):
 
 
 def test_repeated_system_accepts_the_guess(B):
-    w = W.get("bar_65x9")
+    w = W.get("bar_65x9", seed=41)  # clear decisions (>= 3 % margins)
     _say("[edge repeated system] bar_65x9")
     ora = Simulation.from_workload(w)
     p = B.Problem.from_workload(w, stream=0, cluster=3)
@@ -112,7 +113,8 @@ def test_ragged_single_column_tiles(B):
         info = p.solve()
         x = p.solution()
         dx = np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x)
-        _say(f"   sys {s}: gpu it={info.iters} | oracle it={ro.info.iters} | dx={dx:.2e}")
+        _say(f"   sys {s}: gpu it={info.iters} ck={info.checks} rank={info.rank} | oracle it={ro.info.iters} "
+             f"ck={ro.info.checks} rank={ro.rank} | dx={dx:.2e} | margin {margins_text(ro)}")
         assert info.status == 0 and info.relres <= w.rtol and dx <= 1e-7
-        assert abs(info.iters - ro.info.iters) <= 2
+        check_decisions(info, ro, w.n, f"ragged walls nx={w.nx} system {s}")
     p.close()

@@ -18,6 +18,7 @@ from oracle import precond as opc
 from oracle.discretization import Grid, mixed_stage_operator
 from oracle.sequence import Simulation
 from paper_2511_18071_amd import workload as W
+from tests.parity_rules import check_decisions, margins_text
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +51,7 @@ def test_fullsize_operator_and_precond(B):
     ratio = (np.abs(y - A @ x) / bound).max()
     _say(f"   operator: max err/(|A||x|) {ratio:.3e}")
     assert ratio <= 1e-11
-    minv = opc.make(g, w.depth(), "mg")
+    minv = opc.make(g, w.depth(), "mg", 1, w.nu2)  # the workload's V(1, nu2), as the problem
     kappa = np.linalg.cond(minv.levels[-1]["m"].toarray())
     tol = max(1e-11, 8.0 * kappa * np.finfo(float).eps)
     for v in (x, ps):
@@ -82,14 +83,9 @@ def test_fullsize_solves(B):
         _say(f"   sys {s}: gpu it={info.iters} rs={info.restarts} ck={info.checks} rank={info.rank} "
              f"relres={info.relres:.3e} (oracle operator {relres:.3e}) | oracle it={ro.info.iters} "
              f"rs={ro.info.restarts} ck={ro.info.checks} rank={ro.rank} | dx={dx:.2e}")
+        _say(f"   oracle margins {margins_text(ro)}")
         assert info.status == 0
-        gd = (info.iters, info.restarts, info.checks, info.rank)
-        od = (ro.info.iters, ro.info.restarts, ro.info.checks, ro.rank)
-        if gd != od:
-            first = info if info.iters < ro.info.iters else ro.info
-            assert info.rank == ro.rank and info.restarts == ro.info.restarts, (gd, od)
-            assert 0 < abs(info.iters - ro.info.iters) <= 2, (gd, od)
-            assert first.relres >= 0.99 * w.rtol, (gd, od, first.relres)
+        if check_decisions(info, ro, w.n, f"{NAME} system {s}"):
             ties += 1
         assert ties <= 1
         assert relres <= w.rtol * (1 + 1e-6)

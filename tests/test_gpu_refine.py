@@ -72,12 +72,12 @@ def test_operator_f32_parity(B, name):
 
 
 @pytest.mark.parametrize("name,cmax", [("periodic_65x9", 40), ("bar_65x9", 50), ("bar_513x17", 700),
-                                       ("periodic_65x9", 700)])
+                                       ("periodic_65x9", 700), ("periodic_257x33", 200)])
 def test_precond_f32_parity(B, name, cmax):
     w = W.get(name)
     _say(f"[precond f32] {name} coarse_max={cmax}")
     g = Grid(w.nx, w.nz, w.bc, w.length)
-    minv = opc.make(g, w.depth(), "mg", coarse_max=cmax)
+    minv = opc.make(g, w.depth(), "mg", 1, w.nu2, coarse_max=cmax)  # the workload's V(1, nu2)
     kappa = np.linalg.cond(minv.levels[-1]["m"].toarray())
     tol = max(1e-5, 8.0 * kappa * U32)
     p = B.Problem.from_workload(w, stream=0, precision="fp32_ir", coarse_max=cmax)

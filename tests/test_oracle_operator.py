@@ -170,3 +170,58 @@ def test_rejects_nonpositive_depth():
     h = np.full(g.ncol, 0.1)
     with pytest.raises(ValueError):
         mixed_stage_operator(g, h, -0.2 + 0 * h, 0 * h)
+
+
+@pytest.mark.parametrize("bc", ["periodic", "walls"])
+def test_low_order_operator_boundary_rows_second_order(bc):
+    """M's bed and wall rows (still water, d = h) converge at second order to the analytic
+    normal derivative of the previous-stage gradient at eta = 0: -h_chi F_chi - F_z at the
+    bed, -+F_chi at the left / right wall, with F_chi = P_chi + sigma_x P_sigma,
+    sigma_x = h_chi (1 - sigma)/h and F_z = P_sigma / h (Sec. 3 discrete Neumann equation
+    with the still-water geometry); its PDE rows converge to the sigma-transformed Laplacian
+    on the same grid. A flipped sign, a dropped h_chi or 1/h, or a wall row taken at the
+    wrong column changes the limit."""
+    L, h, _, _, P = _fields(bc)
+    hx = sym.diff(h, X)
+    sx = hx * (1 - S) / h
+    Fx = sym.diff(P, X) + sx * sym.diff(P, S)
+    Fz = sym.diff(P, S) / h
+    y = sym.diff(Fx, X) + sx * sym.diff(Fx, S) + sym.diff(Fz, S) / h
+    f = lambda e: sym.lambdify((X, S), e, "numpy")
+    an = dict(h=f(h), ep=f(0 * X), ec=f(0 * X), P=f(P), y=f(y), bed=f(-hx * Fx - Fz), Fx=f(Fx))
+    Lf = float(L)
+    e_pde, e_bed, e_wall = [], [], []
+    for nx, nz in [(33, 17), (65, 33), (129, 65)]:
+        g, hh, _, _, p, XX, SS = _grid_fields(bc, nx, nz, an, Lf)
+        yv = (low_order_operator(g, hh) @ p).reshape(g.nl, g.ncol)
+        kind = g.row_kinds().reshape(g.nl, g.ncol)
+        yex = np.broadcast_to(an["y"](XX, SS), XX.shape)
+        e_pde.append(np.abs(yv - yex)[kind == 0].max())
+        cols = np.nonzero(kind[0] == 2)[0]
+        bed_ex = np.broadcast_to(an["bed"](XX[1, cols], 0 * XX[1, cols]), cols.shape)
+        e_bed.append(np.abs(yv[0, cols] - bed_ex).max())
+        if bc == "walls":
+            lev = np.arange(1, g.nz)
+            left = -np.broadcast_to(an["Fx"](0 * g.sig[lev], g.sig[lev]), lev.shape)
+            right = np.broadcast_to(an["Fx"](Lf + 0 * g.sig[lev], g.sig[lev]), lev.shape)
+            e_wall.append(max(np.abs(yv[lev, 0] - left).max(), np.abs(yv[lev, -1] - right).max()))
+    rate = lambda e: np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    assert np.all(rate(e_pde) > 1.8), (e_pde, rate(e_pde))
+    assert np.all(rate(e_bed) > 1.8), (e_bed, rate(e_bed))
+    if bc == "walls":
+        assert np.all(rate(e_wall) > 1.8), (e_wall, rate(e_wall))
+
+
+def test_low_order_boundary_pin_catches_planted_mistakes(monkeypatch):
+    """The boundary pin above fails for a plausible mistake planted in the oracle: the bed
+    row without its h_chi term (planted by zeroing h_chi in the assembly of boundary rows)."""
+    import oracle.discretization as D
+
+    orig = D._assemble
+
+    def planted(grid, pde, gchi, gz, h_chi):
+        return orig(grid, pde, gchi, gz, 0.0 * np.asarray(h_chi))
+
+    monkeypatch.setattr(D, "_assemble", planted)
+    with pytest.raises(AssertionError):
+        test_low_order_operator_boundary_rows_second_order("walls")
