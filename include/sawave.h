@@ -161,6 +161,19 @@ int sa_get_solution_async(sa_problem* p, double* x);
  * x, y: n values in `mem` memory. */
 int sa_apply_operator(sa_problem* p, const double* x, double* y, int32_t mem);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): y = A(eta_prev, eta_cur) x as sa_apply_operator
+ * computes it, with no problem object and no allocation. grid, h, eta_prev, eta_cur: host
+ * arrays as for sa_create / sa_set_surface (copied); x, y: device arrays of n values; the work
+ * is ordered on hip_stream (NULL = the default stream) and the call waits for it. The
+ * operator tables, geometry and flags live in a static device array of the library, about
+ * 2.1 MB per GPU and held until the process ends, so grids are limited to 32770 columns
+ * (SA_EARG beyond, before any device work). Every call on one GPU reuses that array: calls
+ * that overlap on one GPU (several host threads or streams) race and must be serialised by
+ * the caller. */
+int sa_apply_operator_static(const sa_grid* grid, const double* h, const double* eta_prev, const double* eta_cur,
+                             const double* x, double* y, void* hip_stream);
+
 /* y = M^-1 x, the fixed still-water preconditioner of the problem. */
 int sa_apply_precond(sa_problem* p, const double* x, double* y, int32_t mem);
 

@@ -119,6 +119,7 @@ def _load():
         "sa_debug_abort": (C.c_int, [P]),
         "sa_apply_operator": (C.c_int, [P, P, P, C.c_int32]),
         "sa_apply_precond": (C.c_int, [P, P, P, C.c_int32]),
+        "sa_apply_operator_static": (C.c_int, [C.POINTER(SaGrid), D, D, D, P, P, P]),
         "sa_apply_operator_f32": (C.c_int, [P, P, P, C.c_int32]),
         "sa_apply_precond_f32": (C.c_int, [P, P, P, C.c_int32]),
         "sa_sketch_draws": (C.c_int, [C.c_uint64, C.c_int64, C.c_int32, D]),
@@ -224,6 +225,22 @@ def workload_args(w, **overrides):
     kw.update(overrides)
     grid = SaGrid(w.nx, w.nz, SA_PERIODIC if w.bc == "periodic" else SA_WALLS, float(w.length))
     return grid, np.ascontiguousarray(w.depth(), dtype=np.float64), make_options(**kw)
+
+
+def apply_operator_static(w, eta_prev, eta_cur, x, y, stream=None):
+    """y = A(eta_prev, eta_cur) x of workload w's grid through the allocation-free entry point
+    (x, y: device tensors; eta: host arrays)."""
+    grid, h, _ = workload_args(w)
+    e1 = np.ascontiguousarray(eta_prev, dtype=np.float64)
+    e2 = np.ascontiguousarray(eta_cur, dtype=np.float64)
+    px, mx, _ = _ptr(x, w.n)
+    py, my, _ = _ptr(y, w.n)
+    if mx != SA_MEM_DEVICE or my != SA_MEM_DEVICE:
+        raise ValueError("x and y must be device tensors")
+    D = C.POINTER(C.c_double)
+    _check(lib.sa_apply_operator_static(C.byref(grid), h.ctypes.data_as(D), e1.ctypes.data_as(D),
+                                        e2.ctypes.data_as(D), px, py, _stream_handle(stream)))
+    return y
 
 
 def footprint(w, **overrides) -> int:
