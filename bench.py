@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+RANGE_WINDOW = 20  # K of the range-finder comparison (Alg. 3; the paper's bar runs use K = 20)
 # kernel sources whose hash keys the committed counter summaries
 KERNEL_SOURCES = ("paper_2511_18071_amd/csrc/device.h", "paper_2511_18071_amd/csrc/solve64.hip",
                   "paper_2511_18071_amd/csrc/internal.h", "paper_2511_18071_amd/csrc/api.hip")
@@ -139,11 +140,12 @@ def traffic_bytes(w, infos, pcv, k) -> float:
 
 
 def precond_vectors(w) -> float:
-    """Vectors moved by one V(1,1) cycle of the still-water preconditioner: per level the
-    down pass reads f and writes u and the coarse f (2.5), the up pass reads u, f and the
-    coarse correction and writes the output (3.5); levels halve in size, so the hierarchy
-    moves 6 x (1 + 1/2 + 1/4 + ...) ~ 12 fine-grid vectors."""
-    return 12.0
+    """Vectors moved by one V(1, nu2) cycle of the still-water preconditioner: per level the
+    down pass reads f and writes u and the coarse f (2.5), the first up pass reads u, f and
+    the coarse correction and writes the output (3.5), every further post-sweep reads its
+    input and f and writes its output (3); levels halve in size, so the hierarchy moves
+    (6 + 3 (nu2 - 1)) x (1 + 1/2 + 1/4 + ...) fine-grid vectors: 12 for V(1,1), 18 for V(1,2)."""
+    return 2.0 * (6.0 + 3.0 * (getattr(w, "nu2", 1) - 1))
 
 
 def stage_inputs(B, w, nsys, G):
@@ -307,8 +309,9 @@ def run_main(args):
     say(f"  ewma: {nsol / ewma['wall']:.2f} solves/s")
     out_modes = {}
     if not args.no_extra:
-        for mode in ("previous", "cold"):
-            r = run_sequence(B, w, etas, bs, ps, mode, args.warmup, args.steps, G, xs)
+        for mode in ("previous", "cold", "range"):
+            extra = dict(window=RANGE_WINDOW) if mode == "range" else {}
+            r = run_sequence(B, w, etas, bs, ps, mode, args.warmup, args.steps, G, xs, **extra)
             out_modes[mode] = r
             say(f"  {mode}: {nsol / r['wall']:.2f} solves/s")
     value = nsol / ewma["wall"]
@@ -332,8 +335,8 @@ def run_main(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "nz": w.nz, "bc": w.bc, "unknowns": w.n,
-                   "systems_per_step": 5, "restart": w.restart, "rtol": w.rtol, "precond": "still-water V(1,1)",
-                   "guess": f"EWMA rank {w.k}, r={w.r}", "cluster_workgroups": G},
+                   "systems_per_step": 5, "restart": w.restart, "rtol": w.rtol, "precond": f"still-water V(1,{w.nu2})",
+                   "guess": f"EWMA rank {w.k}, r={w.r}, column drop {w.tau_drop:g}", "cluster_workgroups": G},
         "iters_per_solve": s["iters_per_solve"],
         "p50_solve_ms": s["p50_solve_ms"],
         "p99_solve_ms": s["p99_solve_ms"],
@@ -348,6 +351,8 @@ def run_main(args):
         sc = summary(w, out_modes["cold"], nsol)
         out["previous"] = dict(sp, guess="previous solution (the paper's baseline)")
         out["plain"] = dict(sc, guess="cold (x0 = 0)")
+        out["range_finder"] = dict(summary(w, out_modes["range"], nsol),
+                                   guess=f"Alg. 3 range finder, V = X Omega, window K = {RANGE_WINDOW}, k = {w.k}")
         out["speedup_vs_plain"] = round(out_modes["cold"]["wall"] / ewma["wall"], 3)
         out["speedup_vs_previous"] = round(out_modes["previous"]["wall"] / ewma["wall"], 3)
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -370,8 +375,13 @@ def run_main(args):
         e2, b2, p2 = stage_inputs(B, wb, 5 * 25, Gb)
         rb = run_sequence(B, wb, e2, b2, p2, "ewma", 5, 20, Gb)
         rc = run_sequence(B, wb, e2, b2, p2, "cold", 5, 20, Gb)
+        rp = run_sequence(B, wb, e2, b2, p2, "previous", 5, 20, Gb)
+        rr = run_sequence(B, wb, e2, b2, p2, "range", 5, 20, Gb, window=RANGE_WINDOW)
+        its = lambda r: round(float(np.mean([i.iters for i in r["infos"]])), 3)
         out["bar_513x17"] = dict(summary(wb, rb, 100), plain_value=round(100 / rc["wall"], 3),
-                                 plain_iters_per_solve=round(float(np.mean([i.iters for i in rc["infos"]])), 3),
+                                 plain_iters_per_solve=its(rc),
+                                 previous_value=round(100 / rp["wall"], 3), previous_iters_per_solve=its(rp),
+                                 range_finder_value=round(100 / rr["wall"], 3), range_finder_iters_per_solve=its(rr),
                                  steps=20, warmup=5, cluster_workgroups=Gb, guess=f"EWMA rank {wb.k}, r={wb.r}")
         say("  bar leg done")
     if not args.no_cpu:

@@ -188,6 +188,21 @@ int sa_apply_precond_f32(sa_problem* p, const float* x, float* y, int32_t mem);
  * host only, no device needed: out[a] = omega_a, a < k (k <= 64). */
 int sa_sketch_draws(uint64_t seed, int64_t index, int32_t k, double* out);
 
+/* Checkpoint of the solver state that carries from one solve to the next (Alg. 4's sketch Y
+ * or Alg. 3's window of solutions and their rows of Omega, the last solution, which the
+ * next solve stores in the sketch first, and the counters: stored solutions, which is the
+ * position of the sketch's random stream, solves and report-log position). buf == NULL:
+ * *len receives the size in bytes. Otherwise buf (host memory, *len bytes) receives the
+ * state, waiting for the problem's stream; SA_EARG with *len = the size needed when it is too
+ * small. The state is a plain byte image for this library's build (host byte order). */
+int sa_save_state(const sa_problem* p, void* buf, size_t* len);
+
+/* Restore a state saved from a problem of the same grid and sketch options (guess mode, k,
+ * window, r, seed, precision; SA_EARG otherwise) into p: its next solves compute exactly
+ * what the saved problem's next solves would have computed, on any problem created with
+ * those arguments (bathymetry and the other options are the caller's to keep equal). */
+int sa_load_state(sa_problem* p, const void* buf, size_t len);
+
 /* Copy the sketch Y (n x k, column-major: Y[a * n + i]) to host or device memory. */
 int sa_get_sketch(sa_problem* p, double* y, int32_t mem);
 

@@ -117,6 +117,8 @@ def _load():
         "sa_get_solution": (C.c_int, [P, P, C.c_int32]),
         "sa_get_solution_async": (C.c_int, [P, P]),
         "sa_debug_abort": (C.c_int, [P]),
+        "sa_save_state": (C.c_int, [P, P, C.POINTER(C.c_size_t)]),
+        "sa_load_state": (C.c_int, [P, P, C.c_size_t]),
         "sa_apply_operator": (C.c_int, [P, P, P, C.c_int32]),
         "sa_apply_precond": (C.c_int, [P, P, P, C.c_int32]),
         "sa_apply_operator_static": (C.c_int, [C.POINTER(SaGrid), D, D, D, P, P, P]),
@@ -221,7 +223,8 @@ def make_options(**opts) -> SaOptions:
 
 def workload_args(w, **overrides):
     """(grid, depth, options) of a synthetic workload."""
-    kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=w.nu2, k=w.k, r=w.r, seed=w.seed)
+    kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=w.nu2, tau_drop=w.tau_drop, k=w.k, r=w.r,
+              seed=w.seed)
     kw.update(overrides)
     grid = SaGrid(w.nx, w.nz, SA_PERIODIC if w.bc == "periodic" else SA_WALLS, float(w.length))
     return grid, np.ascontiguousarray(w.depth(), dtype=np.float64), make_options(**kw)
@@ -271,7 +274,8 @@ class Problem:
 
     @classmethod
     def from_workload(cls, w, stream=None, **overrides):
-        kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=w.nu2, k=w.k, r=w.r, seed=w.seed)
+        kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=w.nu2, tau_drop=w.tau_drop, k=w.k, r=w.r,
+              seed=w.seed)
         kw.update(overrides)
         return cls(w.nx, w.nz, w.bc, w.length, w.depth(), stream=stream, **kw)
 
@@ -325,6 +329,18 @@ class Problem:
         p, m, _ = _ptr(out, self.n)
         _check(lib.sa_get_solution(self._h, p, m))
         return out
+
+    def save_state(self) -> bytes:
+        """The solver state carried between solves (sketch, last solution, counters)."""
+        ln = C.c_size_t(0)
+        _check(lib.sa_save_state(self._h, None, C.byref(ln)))
+        buf = C.create_string_buffer(ln.value)
+        _check(lib.sa_save_state(self._h, buf, C.byref(ln)))
+        return buf.raw[: ln.value]
+
+    def load_state(self, state: bytes):
+        buf = C.create_string_buffer(state, len(state))
+        _check(lib.sa_load_state(self._h, buf, len(state)))
 
     def solution_async(self, out):
         """Enqueue a copy of the last solution into the device tensor `out` (no wait)."""

@@ -714,6 +714,100 @@ extern "C" int sa_get_solution(sa_problem* p, double* x, int32_t mem) {
   return SA_OK;
 }
 
+// ---- checkpoint of the solver state ----------------------------------------------------
+// Layout: a fixed header (what must match the problem it is loaded into, and the counters),
+// then the last solution x (n doubles), then the sketch: Y (k x n, EWMA) or the ring of the
+// range finder (K x n) followed by its rows of Omega (KWIN x KMAX).
+namespace {
+struct StateHeader {
+  char magic[8];
+  int32_t version, guess, precision, k, window, nx, nz, bc;
+  int64_t n, pushes, solves, log_pos;
+  int32_t unpushed, have_solution, pad[2];
+  double r;
+  uint64_t seed;
+};
+constexpr char STATE_MAGIC[8] = {'S', 'A', 'W', 'A', 'V', 'E', 'S', 'T'};
+
+size_t state_doubles(const sa_problem* p) {
+  size_t d = (size_t)p->n;
+  if (p->opt.guess == SA_GUESS_EWMA) d += (size_t)p->opt.k * p->n;
+  if (p->opt.guess == SA_GUESS_RANGE) d += (size_t)p->opt.window * p->n + (size_t)KWIN * KMAX;
+  return d;
+}
+}  // namespace
+
+extern "C" int sa_save_state(const sa_problem* pc, void* buf, size_t* len) {
+  if (!pc || !len) return sa_fail(SA_EARG, "sa_save_state: null argument");
+  sa_problem* p = const_cast<sa_problem*>(pc);
+  const size_t need = sizeof(StateHeader) + state_doubles(p) * 8;
+  if (!buf) {
+    *len = need;
+    return SA_OK;
+  }
+  if (*len < need) {
+    *len = need;
+    return sa_fail(SA_EARG, "sa_save_state: buffer of %zu bytes, %zu needed", *len, need);
+  }
+  if (p->broken) return sa_fail(SA_EDEVICE, "problem unusable after a device error");
+  StateHeader h;
+  memset(&h, 0, sizeof h);
+  memcpy(h.magic, STATE_MAGIC, 8);
+  h.version = 1;
+  h.guess = p->opt.guess; h.precision = p->opt.precision; h.k = p->opt.k; h.window = p->opt.window;
+  h.nx = p->grid.nx; h.nz = p->grid.nz; h.bc = p->grid.bc;
+  h.n = p->n; h.pushes = p->pushes; h.solves = p->solves; h.log_pos = p->log_pos;
+  h.unpushed = p->unpushed ? 1 : 0; h.have_solution = p->have_solution ? 1 : 0;
+  h.r = p->opt.r; h.seed = p->opt.seed;
+  char* out = (char*)buf;
+  memcpy(out, &h, sizeof h);
+  double* d = (double*)(out + sizeof h);
+  const size_t n = (size_t)p->n;
+  HIPCHK(hipMemcpyAsync(d, p->hp.x, n * 8, hipMemcpyDeviceToHost, p->stream));
+  if (p->opt.guess == SA_GUESS_EWMA)
+    HIPCHK(hipMemcpyAsync(d + n, p->hp.Y[p->ycur], (size_t)p->opt.k * n * 8, hipMemcpyDeviceToHost, p->stream));
+  if (p->opt.guess == SA_GUESS_RANGE) {
+    HIPCHK(hipMemcpyAsync(d + n, p->hp.Xr, (size_t)p->opt.window * n * 8, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipMemcpyAsync(d + n + (size_t)p->opt.window * n, p->hp.Om, (size_t)KWIN * KMAX * 8,
+                          hipMemcpyDeviceToHost, p->stream));
+  }
+  HIPCHK(hipStreamSynchronize(p->stream));
+  *len = need;
+  return SA_OK;
+}
+
+extern "C" int sa_load_state(sa_problem* p, const void* buf, size_t len) {
+  if (!p || !buf) return sa_fail(SA_EARG, "sa_load_state: null argument");
+  if (p->broken) return sa_fail(SA_EDEVICE, "problem unusable after a device error");
+  StateHeader h;
+  if (len < sizeof h) return sa_fail(SA_EARG, "sa_load_state: %zu bytes is no saved state", len);
+  memcpy(&h, buf, sizeof h);
+  if (memcmp(h.magic, STATE_MAGIC, 8) != 0 || h.version != 1) return sa_fail(SA_EARG, "sa_load_state: not a saved state");
+  if (h.n != p->n || h.nx != p->grid.nx || h.nz != p->grid.nz || h.bc != p->grid.bc || h.guess != p->opt.guess ||
+      h.k != p->opt.k || (h.guess == SA_GUESS_RANGE && h.window != p->opt.window) || h.r != p->opt.r ||
+      h.seed != p->opt.seed || h.precision != p->opt.precision)
+    return sa_fail(SA_EARG, "sa_load_state: the state belongs to another grid or other options");
+  if (len != sizeof h + state_doubles(p) * 8) return sa_fail(SA_EARG, "sa_load_state: truncated state");
+  const double* d = (const double*)((const char*)buf + sizeof h);
+  const size_t n = (size_t)p->n;
+  HIPCHK(hipMemcpyAsync(p->hp.x, d, n * 8, hipMemcpyHostToDevice, p->stream));
+  if (p->opt.guess == SA_GUESS_EWMA)
+    HIPCHK(hipMemcpyAsync(p->hp.Y[0], d + n, (size_t)p->opt.k * n * 8, hipMemcpyHostToDevice, p->stream));
+  if (p->opt.guess == SA_GUESS_RANGE) {
+    HIPCHK(hipMemcpyAsync(p->hp.Xr, d + n, (size_t)p->opt.window * n * 8, hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(p->hp.Om, d + n + (size_t)p->opt.window * n, (size_t)KWIN * KMAX * 8,
+                          hipMemcpyHostToDevice, p->stream));
+  }
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->ycur = 0;
+  p->pushes = h.pushes;
+  p->solves = h.solves;
+  p->log_pos = p->log_read = h.log_pos;
+  p->unpushed = h.unpushed != 0;
+  p->have_solution = h.have_solution != 0;
+  return SA_OK;
+}
+
 extern "C" int sa_debug_abort(sa_problem* p) {
   if (!p) return sa_fail(SA_EARG, "sa_debug_abort: null problem");
   const int one = 1;

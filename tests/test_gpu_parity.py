@@ -204,6 +204,12 @@ SOLVE_CASES = [
     ("bar_65x9", dict(cluster=3), 8, 41),
     ("periodic_65x9", dict(coarse_max=40), 4, 9),
     ("bar_65x9", dict(coarse_max=50, cluster=2), 10, 2),
+    # Alg. 3: V = X Omega over a sliding window of K solutions
+    ("tiny_17x7", dict(guess="range", window=6, k=3), 10, 5),
+    ("periodic_65x9", dict(guess="range", window=8, k=8), 12, 3),
+    ("bar_65x9", dict(guess="range", window=12, k=6), 16, 7),
+    ("periodic_257x33", dict(guess="range", window=20, k=16), 16, None),
+    ("bar_513x17", dict(guess="range", window=20, k=15), 8, None),
     ("periodic_257x33", dict(), 24, None),
     ("periodic_257x33", dict(cluster=3), 12, None),
     ("bar_513x17", dict(), 8, None),
