@@ -104,8 +104,8 @@ def parse(argv=None):
 
 
 def default_cluster(w) -> int:
-    # the library's own default: one workgroup per 32-column tile of the finest level, at most 128
-    return int(min(128, max(1, (w.ncol + 31) // 32)))
+    # the library's own default: one workgroup per 32-column tile of the finest level, at most 256
+    return int(min(256, max(1, (w.ncol + 31) // 32)))
 
 
 def traffic_bytes(w, infos, pcv, k) -> float:
@@ -470,8 +470,9 @@ def run_serving(args):
                 infos.append(c.info)
         wall = time.perf_counter() - t0
         bytes_used = srv.bytes_used
+        ticks = srv.stats()
         srv.close()
-        return dict(wall=wall, lat=np.array(lat), infos=infos, bytes=bytes_used)
+        return dict(wall=wall, lat=np.array(lat), infos=infos, bytes=bytes_used, ticks=ticks)
 
     sat = serve(np.zeros(nreq), "saturation")
     rate = args.serve_rate if args.serve_rate else 0.7 * nreq / sat["wall"]
@@ -502,7 +503,12 @@ def run_serving(args):
     def stats(r):
         its = np.array([i.iters for i in r["infos"]])
         bad = sum(1 for i in r["infos"] if i.status != 0 or i.relres > 1e-8)
+        t = r["ticks"]
+        nt = max(1, t["ticks"])
         return dict(solves_per_s=round(nreq / r["wall"], 2), wall_s=round(r["wall"], 3),
+                    ticks=t["ticks"], solves_per_tick=round(t["solves"] / nt, 2),
+                    host_ms_per_tick_launch=round(t["launch_host_ms"] / nt, 4),
+                    ms_per_tick_enqueue_to_done=round(t["tick_ms"] / nt, 3),
                     p50_ms=round(float(np.percentile(r["lat"], 50)), 3),
                     p99_ms=round(float(np.percentile(r["lat"], 99)), 3),
                     iters_per_solve=round(float(its.mean()), 3),

@@ -99,7 +99,7 @@ typedef struct {
                         /* next correction (SA_FP32_IR), default 1e-4                       */
   int32_t max_refine;   /* FP32 cycles cap (SA_FP32_IR), default 200; SA_NOCONV after      */
   int32_t cluster;      /* workgroups cooperating on one solve; 0 = one per 32 columns    */
-                        /* of the grid, at most 128                                        */
+                        /* of the grid, at most 256                                        */
   int32_t profile;      /* 1: accumulate per-phase device time (sa_get_phase_times), 0      */
   int32_t coarse_max;   /* MG: coarsening stops at the first grid with at most this many    */
                         /* unknowns, solved exactly there (<= 1024), default 700            */

@@ -273,16 +273,17 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   // default cluster: one 64-column preconditioner tile of the finest level per workgroup
   // (the passes of the V-cycle then take one tile-latency each), at most 64 workgroups
   int G = opt.cluster;
-  // one 32-column tile of the finest level per workgroup, at most 128 (half the CUs: beyond,
-  // the cluster reductions cost more than the wider grid saves)
-  if (G <= 0) G = (ncol + 31) / 32 < 128 ? (ncol + 31) / 32 : 128;
+  // one 32-column tile of the finest level per workgroup, at most 256 (one per CU: the
+  // cluster sums spread their loads over the workgroup and the coarse V-cycle levels meet
+  // at sub-cluster barriers, so the whole chip pays on the large grids)
+  if (G <= 0) G = (ncol + 31) / 32 < 256 ? (ncol + 31) / 32 : 256;
   hipDeviceProp_t prop{};
   if (!bytes_only && hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
     delete p;
     return sa_fail(SA_EDEVICE, "hipGetDeviceProperties failed");
   }
   const size_t head = (size_t)PSTRIDE + NWAVE * (MMAX + 2) + (size_t)(m + 1) * m + 2 * m + 2 * (m + 1) + m + KMAX +
-                      4 * KMAX * KMAX + 8;
+                      4 * KMAX * KMAX + 8 + 16;
   const int TWMh = TX + 3;
   auto opcoef = [&](int W) { return (size_t)(49 + 9 * nl + 5 * (W + 6)); };
   const size_t need_op = (size_t)(TWMh + 12 + 2 * (TWMh + 6)) * nl + opcoef(TWMh) + NWAVE;
@@ -391,7 +392,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   const size_t ysz = opt.guess == SA_GUESS_EWMA || range ? (size_t)k * n * 8 : 8;
   const size_t o_Y0 = take(ysz), o_Y1 = take(range ? 8 : ysz);
   const size_t o_Xr = take(range ? (size_t)opt.window * n * 8 : 8), o_Om = take((size_t)KWIN * KMAX * 8);
-  const size_t o_part = take((size_t)2 * G * PSTRIDE * 8), o_bar = take(64), o_flags = take(NFLAGS * 4),
+  const size_t o_part = take((size_t)2 * G * PSTRIDE * 8), o_bar = take(64 * (1 + MAXLEV)), o_flags = take(NFLAGS * 4),
                o_log = take(LOGCAP * sizeof(sa_solve_info)), o_b = take((size_t)n * 8), o_eta = take(2 * (size_t)nphys * 8),
                o_prob = take(sizeof(Problem)), o_prof = take(NPROF * 8);
   p->arena_bytes = off;

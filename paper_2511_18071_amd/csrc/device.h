@@ -45,7 +45,15 @@ struct Cl {
   int pbuf;
   unsigned gen;  // barrier generation this workgroup last saw complete (thread 0 only)
   double* scr;   // BLOCK doubles of LDS for the cluster sums (nullptr: sums read serially)
+  unsigned* sgen;  // LDS, MAXLEV: generation of each level's sub-cluster barrier word seen by
+                   // this workgroup (thread 0), nullptr: every barrier spans the cluster
 };
+
+// The barrier word of the sub-cluster barrier of V-cycle level l (64 bytes apart, after the
+// cluster's own word).
+DEV unsigned long long* sub_word(unsigned* bar, int l) {
+  return reinterpret_cast<unsigned long long*>(bar + 16 * (1 + l));
+}
 
 // The barrier word of a cluster: one 64-bit atomic, arrivals in the low half, the generation
 // (completed barriers) in the high half.
@@ -55,7 +63,7 @@ DEV unsigned long long* bar_word(unsigned* bar) { return reinterpret_cast<unsign
 // it advances only after all G workgroups have arrived at a barrier, and each reads it before
 // its first arrival, so all start from the same value; the barrier then tracks it locally.
 DEV Cl make_cl(const Problem& P, int rank, int G) {
-  Cl cl{rank, G, P.bar, P.flags, P.partials, 0, 0u, nullptr};
+  Cl cl{rank, G, P.bar, P.flags, P.partials, 0, 0u, nullptr, nullptr};
   if (threadIdx.x == 0 && G > 1)
     cl.gen = (unsigned)(__hip_atomic_load(bar_word(P.bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
   return cl;
@@ -72,31 +80,50 @@ DEV bool aborted(const Cl& cl) {
 // which the test below allows for. Waiters poll the word with relaxed loads and take one
 // acquire fence once the barrier is complete. Every wait is bounded: after SPIN_LIMIT polls the
 // abort flag is raised and all waiters leave.
+// One arrival of thread 0 at the barrier on `word` among G workgroups, whose generation this
+// workgroup last saw complete is gen (advanced here).
+DEV void bar_arrive_wait(Cl& cl, unsigned long long* word, unsigned& gen, unsigned G) {
+  const unsigned g0 = gen;
+  gen = g0 + 1u;
+  const unsigned long long old = __hip_atomic_fetch_add(word, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if ((unsigned)(old >> 32) == g0 && (unsigned)old == G - 1u) {
+    __hip_atomic_fetch_add(word, (1ull << 32) - G, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    long spins = 0;
+    for (;;) {
+      const unsigned long long v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned gv = (unsigned)(v >> 32);
+      if ((gv == g0 && (unsigned)v >= G) || (int)(gv - g0) > 0) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > SPIN_LIMIT || aborted(cl)) {
+        __hip_atomic_store(cl.flags + FLAG_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 DEV void csync(Cl& cl) {
   __syncthreads();
   if (cl.G == 1) return;
-  if (threadIdx.x == 0) {
-    unsigned long long* word = bar_word(cl.bar);
-    const unsigned g0 = cl.gen, G = (unsigned)cl.G;
-    cl.gen = g0 + 1u;
-    const unsigned long long old = __hip_atomic_fetch_add(word, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if ((unsigned)(old >> 32) == g0 && (unsigned)old == G - 1u) {
-      __hip_atomic_fetch_add(word, (1ull << 32) - G, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      long spins = 0;
-      for (;;) {
-        const unsigned long long v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned gv = (unsigned)(v >> 32);
-        if ((gv == g0 && (unsigned)v >= G) || (int)(gv - g0) > 0) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > SPIN_LIMIT || aborted(cl)) {
-          __hip_atomic_store(cl.flags + FLAG_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (threadIdx.x == 0) bar_arrive_wait(cl, bar_word(cl.bar), cl.gen, (unsigned)cl.G);
+  __syncthreads();
+}
+
+// Barrier among the workgroups of rank < parts only (the V-cycle passes of a level with fewer
+// tiles than workgroups, and the pass that consumes their output), on level l's own word;
+// the other workgroups do not take part and go on to their next barrier, which every
+// workgroup of rank < parts reaches only after this one. parts >= G (or no generation
+// table): a barrier of the whole cluster.
+DEV void lsync(Cl& cl, int parts, int l) {
+  if (!cl.sgen || parts >= cl.G) {
+    csync(cl);
+    return;
   }
+  __syncthreads();
+  if (cl.rank >= parts) return;
+  if (threadIdx.x == 0) bar_arrive_wait(cl, sub_word(cl.bar, l), cl.sgen[l], (unsigned)parts);
   __syncthreads();
 }
 
@@ -979,9 +1006,27 @@ struct PhaseClock {
   }
 };
 
-// one V-cycle level pair on the way down / up (cluster or single-workgroup view)
+// tiles of level l at its V-cycle tile width: the workgroups of rank < this have work there
+DEV int level_tiles(const Problem& P, int l) {
+  const int tw = P.lev[l].tm;
+  return (P.lev[l].ncol + tw - 1) / tw;
+}
+
+// Workgroups that take part in the sub-cluster barriers of cluster level l (levels < lt):
+// the most tiles any cluster level from l on has, so that the participants never grow on the
+// way down (a workgroup that skips a level's barrier has no tile on any coarser level) and
+// every pass's producers and consumers are inside the barriers around it.
+DEV int sub_parts(const Problem& P, int l, int lt) {
+  int q = 0;
+  for (int i = l; i < lt; ++i) q = max(q, level_tiles(P, i));
+  return q;
+}
+
+// one V-cycle level pair on the way down / up (cluster or single-workgroup view). parts > 0:
+// the next pass reads only what the workgroups of rank < parts wrote, so the barrier after
+// the down pass spans those workgroups only (on level l's word).
 template <class S>
-DEV void mg_down(const Problem& P, Cl& cl, int l, const S* v, S* lds, const S* rc = nullptr) {
+DEV void mg_down(const Problem& P, Cl& cl, int l, const S* v, S* lds, const S* rc = nullptr, int parts = 0) {
   const Lv<S> L = level_view<S>(P, l);
   const Lv<S> Lc = level_view<S>(P, l + 1);
   const S* f = l == 0 ? v : L.f;
@@ -990,7 +1035,8 @@ DEV void mg_down(const Problem& P, Cl& cl, int l, const S* v, S* lds, const S* r
   if (P.nu1 == 1) {
     if (P.lev[l].tm == 32) phase_down<S, 32>(P, cl, l, f, A, Lc.f, lds, rc);
     else phase_down<S, TM>(P, cl, l, f, A, Lc.f, lds, rc);
-    csync(cl);
+    if (parts > 0) lsync(cl, parts, l);
+    else csync(cl);
     return;
   }
   const S* prev = nullptr;
@@ -1027,7 +1073,7 @@ DEV const S* level_output(const Problem& P, int l) {
 // adding the prolongated coarse correction on load, and at level 0 the last one writes z.
 template <class S>
 DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z, S* lds,
-                   const S* rc = nullptr) {
+                   const S* rc = nullptr, int parts = 0, int parts_up = 0) {
   const Lv<S> L = level_view<S>(P, l);
   const S* f = l == 0 ? v : L.f;
   S* A = L.u;
@@ -1048,7 +1094,11 @@ DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z
     S* nd = (l == 0 && s == P.nu2 - 1) ? z : (prev == B ? A : B);
     if (P.lev[l].tm == 32) phase_sweep<S, 32>(P, cl, l, f, prev, corr, nd, lds, rc);
     else phase_sweep<S, TM>(P, cl, l, f, prev, corr, nd, lds, rc);
-    csync(cl);
+    // the next pass: this level's next sweep (parts, level l's word), else the up pass of
+    // level l - 1 (parts_up >= parts, level l - 1's word), else (level 0) the whole cluster
+    if (parts <= 0 || l == 0) csync(cl);
+    else if (s < P.nu2 - 1) lsync(cl, parts, l);
+    else lsync(cl, parts_up, l - 1);
     prev = nd;
     corr = nullptr;
   }
@@ -1092,8 +1142,13 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
   auto tk = [&](int slot) { if (ck) ck->dtick(slot); };
   // the resident constants of cluster level l (res: the solve's resident block, or none)
   auto rc = [&](int l) -> const S* { return (res && P.lev[l].res >= 0) ? res + P.lev[l].res : nullptr; };
-  for (int l = 0; l < lt; ++l) { mg_down<S>(P, cl, l, v, lds, rc(l)); tk(1 + 2 * l); }
-  Cl solo{0, 1, cl.bar, cl.flags, cl.partials, cl.pbuf, 0u, nullptr};
+  // sub-cluster barriers between the passes of the cluster levels; the last cluster level
+  // before the coarsest solve (no single-workgroup levels between) ends with a cluster barrier
+  for (int l = 0; l < lt; ++l) {
+    mg_down<S>(P, cl, l, v, lds, rc(l), (l + 1 < lt || lt < L - 1) ? sub_parts(P, l, lt) : 0);
+    tk(1 + 2 * l);
+  }
+  Cl solo{0, 1, cl.bar, cl.flags, cl.partials, cl.pbuf, 0u, nullptr, nullptr};
   if (lt < L - 1) {
     if (cl.rank == 0)
       for (int l = lt; l < L - 1; ++l) { mg_down<S>(P, solo, l, v, lds); tk(1 + 2 * l); }
@@ -1114,7 +1169,10 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
     e = (lt == 0) ? z : level_output<S>(P, lt);
     if (lt == 0) return;
   }
-  for (int l = lt - 1; l >= 0; --l) { e = mg_up<S>(P, cl, l, v, e, z, lds, rc(l)); tk(2 + 2 * l); }
+  for (int l = lt - 1; l >= 0; --l) {
+    e = mg_up<S>(P, cl, l, v, e, z, lds, rc(l), sub_parts(P, l, lt), l > 0 ? sub_parts(P, l - 1, lt) : 0);
+    tk(2 + 2 * l);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1596,6 +1654,7 @@ struct Smem {
   double* y;      // m
   double* z;      // KMAX
   double* scr;    // 4 KMAX^2 + 8
+  unsigned* sgen; // 32 unsigned (16 doubles): sub-cluster barrier generations
   double* big;    // phase scratch
 };
 
@@ -1611,7 +1670,8 @@ DEV Smem carve(double* s, int m) {
   S.y = S.vs + m + 1;
   S.z = S.y + m;
   S.scr = S.z + KMAX;
-  S.big = S.scr + 4 * KMAX * KMAX + 8;
+  S.sgen = (unsigned*)(S.scr + 4 * KMAX * KMAX + 8);
+  S.big = S.scr + 4 * KMAX * KMAX + 8 + 16;
   return S;
 }
 
@@ -2025,6 +2085,15 @@ DEV void solve_body(const Problem* __restrict__ PP, const SolveArgs& a, int rank
   Smem S = carve(smem, P.m);
   Cl cl = make_cl(P, rank, P.G);
   cl.scr = S.wsum;  // NWAVE * (MMAX + 2) >= BLOCK doubles, free whenever a cluster sum runs
+  // sub-cluster barriers of the V-cycle levels: every workgroup starts from the generations
+  // the words hold (no barrier is in flight between launches)
+  if (P.G > 1) {
+    if (threadIdx.x < MAXLEV)
+      S.sgen[threadIdx.x] = (unsigned)(__hip_atomic_load(sub_word(P.bar, threadIdx.x), __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT) >> 32);
+    __syncthreads();
+    cl.sgen = S.sgen;
+  }
   PhaseClock clk;
   clk.begin(a.prof != nullptr, rank, a.prof);
   sa_solve_info info;

@@ -22,9 +22,9 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_default_cluster_rule():
-    # one workgroup per 32-column tile of the finest level, at most 128
+    # one workgroup per 32-column tile of the finest level, at most 256
     assert bench.default_cluster(W.get("bar_513x17")) == 17
-    assert bench.default_cluster(W.get("periodic_16385x33")) == 128
+    assert bench.default_cluster(W.get("periodic_16385x33")) == 256
     assert bench.default_cluster(W.get("tiny_17x7")) == 1
 
 
