@@ -89,9 +89,9 @@ def parse(argv=None):
     ap.add_argument("--serve-systems", type=int, default=10, help="serving: systems per simulation")
     ap.add_argument("--serve-rate", type=float, default=None,
                     help="serving: offered solves/s of the open loop (default: 0.7 x the measured saturation rate)")
-    ap.add_argument("--serve-inflight", type=int, default=16,
+    ap.add_argument("--serve-inflight", type=int, default=8,
                     help="serving: ticks in flight (the process is given as many hardware queues)")
-    ap.add_argument("--serve-upw", type=int, default=20000,
+    ap.add_argument("--serve-upw", type=int, default=10000,
                     help="serving: unknowns per workgroup when the server sizes the clusters")
     ap.add_argument("--serve-baseline-stride", type=int, default=8,
                     help="serving: the one-at-a-time FP64 baseline solves every k-th simulation")
@@ -444,8 +444,8 @@ def run_serving(args):
         if any(i is None for i in ids):
             raise RuntimeError("serving mix does not fit the HBM budget")
         torch.cuda.synchronize()
-        lat, infos = [], []
-        arrival_of = {}
+        lat, infos, who = [], [], []
+        arrival_of, req_of = {}, {}
         k = 0
         say(f"  {label}: serving {nreq} requests")
         t0 = time.perf_counter()
@@ -462,17 +462,19 @@ def run_serving(args):
                 eta, bs = inputs[i]
                 t = srv.submit(ids[i], eta[s, 0], eta[s, 1], bs[s])
                 arrival_of[t] = base_ms + 1e3 * arrivals[k]
+                req_of[t] = (i, s)
                 k += 1
             # block only until the next arrival falls due, so that no arrival waits on the host
             timeout = None if k >= nreq else max(0.0, arrivals[k] - (time.perf_counter() - t0))
             for c in srv.poll(wait=srv.outstanding > 0, timeout_s=timeout):
                 lat.append(c.t_done_ms - arrival_of.pop(c.ticket))
                 infos.append(c.info)
+                who.append(req_of.pop(c.ticket))
         wall = time.perf_counter() - t0
         bytes_used = srv.bytes_used
         ticks = srv.stats()
         srv.close()
-        return dict(wall=wall, lat=np.array(lat), infos=infos, bytes=bytes_used, ticks=ticks)
+        return dict(wall=wall, lat=np.array(lat), infos=infos, who=who, bytes=bytes_used, ticks=ticks)
 
     sat = serve(np.zeros(nreq), "saturation")
     rate = args.serve_rate if args.serve_rate else 0.7 * nreq / sat["wall"]
@@ -502,7 +504,7 @@ def run_serving(args):
 
     def stats(r):
         its = np.array([i.iters for i in r["infos"]])
-        bad = sum(1 for i in r["infos"] if i.status != 0 or i.relres > 1e-8)
+        bad = [(w, i) for w, i in zip(r["who"], r["infos"]) if i.status != 0 or i.relres > 1e-8]
         t = r["ticks"]
         nt = max(1, t["ticks"])
         return dict(solves_per_s=round(nreq / r["wall"], 2), wall_s=round(r["wall"], 3),
@@ -513,7 +515,11 @@ def run_serving(args):
                     p99_ms=round(float(np.percentile(r["lat"], 99)), 3),
                     iters_per_solve=round(float(its.mean()), 3),
                     refinements_per_solve=round(float(np.mean([i.refinements for i in r["infos"]])), 3),
-                    max_relres=float(max(i.relres for i in r["infos"])), failed_solves=bad)
+                    max_relres=float(max(i.relres for i in r["infos"])), failed_solves=len(bad),
+                    device_failed=t["device_failed"],
+                    failures=[dict(sim=w[0], system=w[1], status=i.status, iters=i.iters, restarts=i.restarts,
+                                   refinements=i.refinements, relres0=float("%.3e" % i.relres0),
+                                   relres=float("%.3e" % i.relres)) for w, i in bad[:16]])
 
     s_sat, s_ol = stats(sat), stats(ol)
     out = {
@@ -533,6 +539,8 @@ def run_serving(args):
                    "unknowns_total": total_unknowns, "precision": "fp32 inner GMRES, fp64 refinement",
                    "guess": "EWMA", "hbm_bytes_resident": sat["bytes"],
                    "unknowns_per_workgroup": args.serve_upw, "ticks_in_flight": args.serve_inflight,
+                   "coresident_workgroups": sat["ticks"]["capacity"],
+                   "workgroups_per_tick": sat["ticks"]["tick_budget"],
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "saturation": s_sat,
         "open_loop": dict(offered_solves_per_s=round(rate, 2), **s_ol),

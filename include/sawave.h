@@ -302,7 +302,10 @@ int64_t sa_server_bytes_used(const sa_server* s);
 /* The server's clock (ms since sa_server_create; the clock of sa_completion's times). */
 double sa_server_clock_ms(const sa_server* s);
 /* Counters since creation: out[0] ticks launched, [1] solves launched, [2] host ms spent
- * forming and enqueuing ticks, [3] ms from enqueue to completion summed over the ticks. */
+ * forming and enqueuing ticks, [3] ms from enqueue to completion summed over the ticks,
+ * [4] co-resident workgroups of the solve kernels (the capacity ticks share), [5] workgroups
+ * per tick (capacity / max_inflight), [6] solves that ended with SA_EDEVICE on the device.
+ * Fills the first min(n, 7) entries. */
 int sa_server_stats(const sa_server* s, double* out, int32_t n);
 /* The problem of an admitted simulation with no request running (for sa_get_solution,
  * sa_read_log; no sa_solve on it); NULL while one of its requests is in a running tick. */

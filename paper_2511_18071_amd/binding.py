@@ -8,6 +8,7 @@ missing the import of this module raises, there is no fallback.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 import os
 from dataclasses import dataclass
 
@@ -285,6 +286,10 @@ class Problem:
             self._h = None
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down: the runtime (or a profiler wrapped
+        # around it) may already be gone; the process exit releases the device memory
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -442,6 +447,10 @@ class Server:
             self._h = None
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down: the runtime (or a profiler wrapped
+        # around it) may already be gone; the process exit releases the device memory
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -511,9 +520,10 @@ class Server:
         return float(lib.sa_server_clock_ms(self._h))
 
     def stats(self) -> dict:
-        out = np.zeros(4)
-        _check(lib.sa_server_stats(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), 4))
-        return dict(ticks=int(out[0]), solves=int(out[1]), launch_host_ms=float(out[2]), tick_ms=float(out[3]))
+        out = np.zeros(7)
+        _check(lib.sa_server_stats(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), 7))
+        return dict(ticks=int(out[0]), solves=int(out[1]), launch_host_ms=float(out[2]), tick_ms=float(out[3]),
+                    capacity=int(out[4]), tick_budget=int(out[5]), device_failed=int(out[6]))
 
     @property
     def outstanding(self) -> int:

@@ -123,6 +123,7 @@ struct sa_server {
   double ev0_ms = 0.0;
   // statistics (sa_server_stats)
   double st_solves = 0.0, st_launch_ms = 0.0, st_tick_ms = 0.0;
+  double st_device_failed = 0.0;  // solves that ended with SA_EDEVICE (a bounded wait gave up)
 };
 
 extern "C" void sa_server_default_options(sa_server_options* o) {
@@ -463,6 +464,7 @@ static int harvest(sa_server* s) {
         HIPCHK(hipStreamSynchronize(sl.stream));
       }
       if (c.info.status == SA_EDEVICE) {
+        s->st_device_failed += 1.0;
         m.p->broken = true;
         m.failed = true;
         m.code = SA_EDEVICE;
@@ -650,8 +652,10 @@ extern "C" double sa_server_clock_ms(const sa_server* s) { return s ? now_ms(s->
 extern "C" int sa_server_stats(const sa_server* s, double* out, int32_t n) {
   if (!s || !out || n < 1) return sa_fail(SA_EARG, "sa_server_stats: bad arguments");
   std::lock_guard<std::mutex> lk(s->mu);
-  const double v[4] = {(double)s->launches, s->st_solves, s->st_launch_ms, s->st_tick_ms};
-  for (int i = 0; i < n && i < 4; ++i) out[i] = v[i];
+  const double v[7] = {(double)s->launches, s->st_solves,     s->st_launch_ms,
+                       s->st_tick_ms,       (double)s->capacity, (double)(s->capacity / s->opt.max_inflight),
+                       s->st_device_failed};
+  for (int i = 0; i < n && i < 7; ++i) out[i] = v[i];
   return SA_OK;
 }
 
