@@ -285,10 +285,11 @@ class Problem:
             lib.sa_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP calls while the interpreter shuts down: the runtime (or a profiler wrapped
-        # around it) may already be gone; the process exit releases the device memory
-        if sys.is_finalizing():
+        # around it) may already be gone; the process exit releases the device memory (the
+        # check is bound at definition: module globals may be cleared by then)
+        if _finalizing():
             return
         try:
             self.close()
@@ -446,10 +447,11 @@ class Server:
             lib.sa_server_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP calls while the interpreter shuts down: the runtime (or a profiler wrapped
-        # around it) may already be gone; the process exit releases the device memory
-        if sys.is_finalizing():
+        # around it) may already be gone; the process exit releases the device memory (the
+        # check is bound at definition: module globals may be cleared by then)
+        if _finalizing():
             return
         try:
             self.close()

@@ -609,19 +609,86 @@ DEV S m_apply(const Problem& P, int nc, S rdx, S rds, S oms, int c, int j, U u, 
 // row (coupling levels 0 and 2) is combined with row 1 (factor gam) so the system is
 // tridiagonal; lo, pc, inv are the precomputed sub-diagonal, elimination ratios and inverse
 // pivots (free-surface row: identity). Level stride rs for r, fs for the factors.
+// The recurrences run in blocks of LSB levels: the operands of the next block are read from
+// LDS before the current block's results are written back, so the dependent chain is the
+// arithmetic alone, not an LDS round trip per level (same operations in the same order as
+// the plain level-by-level loop, which finishes the levels left over).
+constexpr int LSB = 4;
 template <class S>
 DEV void line_solve(int nz, S gam, S* __restrict__ r, int rs, const S* __restrict__ lo, const S* __restrict__ pc,
                     const S* __restrict__ inv, int fs) {
   S pd = (r[0] - gam * r[rs]) * inv[0];
   r[0] = pd;
-#pragma unroll 4
-  for (int j = 1; j < nz; ++j) {
+  // forward elimination, levels 1 .. nz - 1
+  int j = 1;
+  if (nz - 1 >= LSB) {
+    S ra[LSB], la[LSB], ia[LSB];
+#pragma unroll
+    for (int q = 0; q < LSB; ++q) {
+      ra[q] = r[(1 + q) * rs];
+      la[q] = lo[(1 + q) * fs];
+      ia[q] = inv[(1 + q) * fs];
+    }
+    for (; j + 2 * LSB <= nz; j += LSB) {  // levels j .. j+3 now, j+4 .. j+7 (< nz) read ahead
+      S rb[LSB], lb[LSB], ib[LSB];
+#pragma unroll
+      for (int q = 0; q < LSB; ++q) {
+        rb[q] = r[(j + LSB + q) * rs];
+        lb[q] = lo[(j + LSB + q) * fs];
+        ib[q] = inv[(j + LSB + q) * fs];
+      }
+#pragma unroll
+      for (int q = 0; q < LSB; ++q) {
+        pd = (ra[q] - la[q] * pd) * ia[q];
+        r[(j + q) * rs] = pd;
+      }
+#pragma unroll
+      for (int q = 0; q < LSB; ++q) { ra[q] = rb[q]; la[q] = lb[q]; ia[q] = ib[q]; }
+    }
+#pragma unroll
+    for (int q = 0; q < LSB; ++q) {
+      pd = (ra[q] - la[q] * pd) * ia[q];
+      r[(j + q) * rs] = pd;
+    }
+    j += LSB;
+  }
+  for (; j < nz; ++j) {
     pd = (r[j * rs] - lo[j * fs] * pd) * inv[j * fs];
     r[j * rs] = pd;
   }
+  // back substitution, levels nz - 1 .. 0 (the free-surface row nz is the identity)
   S d = r[nz * rs];
-#pragma unroll 4
-  for (int j = nz - 1; j >= 0; --j) {
+  j = nz - 1;
+  if (nz >= LSB) {
+    S rv[LSB], pv[LSB];
+#pragma unroll
+    for (int q = 0; q < LSB; ++q) {
+      rv[q] = r[(j - q) * rs];
+      pv[q] = pc[(j - q) * fs];
+    }
+    for (; j >= 2 * LSB - 1; j -= LSB) {  // levels j .. j-3 now, j-4 .. j-7 (>= 0) read ahead
+      S rw[LSB], pw[LSB];
+#pragma unroll
+      for (int q = 0; q < LSB; ++q) {
+        rw[q] = r[(j - LSB - q) * rs];
+        pw[q] = pc[(j - LSB - q) * fs];
+      }
+#pragma unroll
+      for (int q = 0; q < LSB; ++q) {
+        d = rv[q] - pv[q] * d;
+        r[(j - q) * rs] = d;
+      }
+#pragma unroll
+      for (int q = 0; q < LSB; ++q) { rv[q] = rw[q]; pv[q] = pw[q]; }
+    }
+#pragma unroll
+    for (int q = 0; q < LSB; ++q) {
+      d = rv[q] - pv[q] * d;
+      r[(j - q) * rs] = d;
+    }
+    j -= LSB;
+  }
+  for (; j >= 0; --j) {
     d = r[j * rs] - pc[j * fs] * d;
     r[j * rs] = d;
   }
@@ -636,6 +703,21 @@ DEV S prolong_at(const Problem& P, int ncf, int ncc, const S* e, int c, int j) {
   if (c == 0 || c == ncf - 1) return ec[c == 0 ? 0 : ncc - 1];
   const int p = c - 1;
   return (p & 1) ? half * (ec[((p - 1) >> 1) + 1] + ec[((p + 1) >> 1) + 1]) : ec[(p >> 1) + 1];
+}
+
+// the coarse columns (and whether two are averaged) prolong_at reads for fine column c
+DEV void prolong_cols(const Problem& P, int ncf, int ncc, int c, int& i0, int& i1, bool& odd) {
+  odd = false;
+  i1 = 0;
+  if (P.periodic) {
+    if (c & 1) { odd = true; i0 = (c - 1) >> 1; i1 = wrapc((c + 1) >> 1, ncc); }
+    else i0 = c >> 1;
+    return;
+  }
+  if (c == 0 || c == ncf - 1) { i0 = c == 0 ? 0 : ncc - 1; return; }
+  const int p = c - 1;
+  if (p & 1) { odd = true; i0 = ((p - 1) >> 1) + 1; i1 = ((p + 1) >> 1) + 1; }
+  else i0 = (p >> 1) + 1;
 }
 
 DEV int ptiles(int nc) { return (nc + TM - 1) / TM; }
@@ -691,28 +773,64 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
     const int nu = zero ? 0 : nl, ncd = zero ? 0 : 4;
     const int rf = nu, rcd = rf + nl, rfac = rcd + ncd, rgam = rfac + 3 * nl;
     const int fsm = L.fstride ? L.fstride : 1;
-    staged_rows<16>(rc ? rcd : rgam + 1, ww, [&](int r, int lc) -> S {
-      const int c = c0 - 1 + lc;
-      const bool own = lc >= 1 && lc <= w;
-      if (r < rf) {
-        if (!st.has(c)) return S(0);
-        const int cg = st.col(c);
-        S v = uin ? uin[(size_t)r * nc + cg] : S(0);
-        if (e) v += prolong_at(P, nc, ncc, e, cg, r);
-        return v;
+    // u and f: each thread owns one column of the rows it stages (the column's wrap, halo
+    // and prolongation stencil worked out once), so the loads of all its rows are issued
+    // together with no per-element branching
+    {
+      const int RP = BLOCK / ww;
+      const int lc = threadIdx.x % ww, r0 = threadIdx.x / ww;
+      if (r0 < RP) {
+        const int c = c0 - 1 + lc;
+        const bool has = st.has(c), own = lc >= 1 && lc <= w;
+        const int cg = has ? st.col(c) : 0;
+        int i0 = 0, i1 = 0;
+        bool odd = false;
+        if (e && has) prolong_cols(P, nc, ncc, cg, i0, i1, odd);
+        // u (with the prolongated correction) and f of each row in one batch of loads
+        constexpr int U = 6;
+        for (int rb = r0; rb < nl; rb += U * RP) {
+          S v[U], g[U];
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int r = rb + q * RP;
+            S t = S(0);
+            if (!zero && r < nl && has) {
+              t = uin ? uin[(size_t)r * nc + cg] : S(0);
+              if (e) {
+                const S* er = e + (size_t)r * ncc;
+                t += odd ? S(0.5) * (er[i0] + er[i1]) : er[i0];
+              }
+            }
+            v[q] = t;
+            g[q] = (own && r < nl) ? f[(size_t)r * nc + c] : S(0);
+          }
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int r = rb + q * RP;
+            if (r < nl) {
+              if (!zero) su[r * LW + lc] = v[q];
+              if (own) sr[r * TW + lc - 1] = g[q];
+            }
+          }
+        }
       }
-      if (r < rcd) return own ? f[(size_t)(r - rf) * nc + c] : S(0);
-      if (r < rfac) return st.has(c) ? coldata(L, r - rcd, st.col(c)) : S(1);
-      if (r < rgam) return own ? L.flo[(r - rfac) * fsm + (L.fstride ? c : 0)] : S(0);
-      return own ? L.fgam[L.fstride ? c : 0] : S(0);
-    }, [&](int r, int lc, S v) {
-      if (r < rf) su[r * LW + lc] = v;
-      else if (!(lc >= 1 && lc <= w) && (r < rcd || r >= rfac)) return;
-      else if (r < rcd) sr[(r - rf) * TW + lc - 1] = v;
-      else if (r < rfac) scd[(r - rcd) * LW + lc] = v;
-      else if (r < rgam) sfac[(r - rfac) * TW + lc - 1] = v;
-      else sgam[lc - 1] = v;
-    });
+    }
+    // column data over the halo, factors and gamma over the own columns (unless resident)
+    if (!rc)
+      staged_rows<16>(rgam + 1 - rcd, ww, [&](int rr, int lc) -> S {
+        const int r = rr + rcd;
+        const int c = c0 - 1 + lc;
+        const bool own = lc >= 1 && lc <= w;
+        if (r < rfac) return st.has(c) ? coldata(L, r - rcd, st.col(c)) : S(1);
+        if (r < rgam) return own ? L.flo[(r - rfac) * fsm + (L.fstride ? c : 0)] : S(0);
+        return own ? L.fgam[L.fstride ? c : 0] : S(0);
+      }, [&](int rr, int lc, S v) {
+        const int r = rr + rcd;
+        if (!(lc >= 1 && lc <= w) && r >= rfac) return;
+        if (r < rfac) scd[(r - rcd) * LW + lc] = v;
+        else if (r < rgam) sfac[(r - rfac) * TW + lc - 1] = v;
+        else sgam[lc - 1] = v;
+      });
     __syncthreads();
     if (!zero) {
       auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
@@ -781,21 +899,46 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
     const int ww = w + 4;
     const int rcd = nl, rfac = nl + 4, rgam = rfac + 3 * nl;
     const int fsm = L.fstride ? L.fstride : 1;
-    // resident constants: only the nl rows of f are loaded
-    staged_rows<16>(rc ? nl : rgam + 1, ww, [&](int r, int lc) -> S {
-      const int c = c0 - 2 + lc;
-      if (!st.has(c)) return (r >= rcd && r < rfac) || (r >= rfac + 2 * nl && r < rgam) ? S(1) : S(0);
-      const int cg = st.col(c);
-      if (r < rcd) return f[(size_t)r * nc + cg];
-      if (r < rfac) return coldata(L, r - rcd, cg);
-      if (r < rgam) return L.flo[(r - rfac) * fsm + (L.fstride ? cg : 0)];
-      return L.fgam[L.fstride ? cg : 0];
-    }, [&](int r, int lc, S v) {
-      if (r < rcd) { sf[r * LW + lc] = v; su[r * LW + lc] = v; }
-      else if (r < rfac) scd[(r - rcd) * LW + lc] = v;
-      else if (r < rgam) sfac[(r - rfac) * LW + lc] = v;
-      else sgam[lc] = v;
-    });
+    // f: each thread owns one column of the rows it stages (wrap and halo worked out once)
+    {
+      const int RP = BLOCK / ww;
+      const int lc = threadIdx.x % ww, r0 = threadIdx.x / ww;
+      if (r0 < RP) {
+        const int c = c0 - 2 + lc;
+        const bool has = st.has(c);
+        const int cg = has ? st.col(c) : 0;
+        constexpr int U = 8;
+        for (int rb = r0; rb < nl; rb += U * RP) {
+          S v[U];
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int r = rb + q * RP;
+            v[q] = (r < nl && has) ? f[(size_t)r * nc + cg] : S(0);
+          }
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int r = rb + q * RP;
+            if (r < nl) { sf[r * LW + lc] = v[q]; su[r * LW + lc] = v[q]; }
+          }
+        }
+      }
+    }
+    // column data, factors lo | pc | inv and gamma (unless resident)
+    if (!rc)
+      staged_rows<16>(rgam + 1 - rcd, ww, [&](int rr, int lc) -> S {
+        const int r = rr + rcd;
+        const int c = c0 - 2 + lc;
+        if (!st.has(c)) return (r < rfac) || (r >= rfac + 2 * nl && r < rgam) ? S(1) : S(0);
+        const int cg = st.col(c);
+        if (r < rfac) return coldata(L, r - rcd, cg);
+        if (r < rgam) return L.flo[(r - rfac) * fsm + (L.fstride ? cg : 0)];
+        return L.fgam[L.fstride ? cg : 0];
+      }, [&](int rr, int lc, S v) {
+        const int r = rr + rcd;
+        if (r < rfac) scd[(r - rcd) * LW + lc] = v;
+        else if (r < rgam) sfac[(r - rfac) * LW + lc] = v;
+        else sgam[lc] = v;
+      });
     __syncthreads();
     if (threadIdx.x < w + 4 && st.has(c0 - 2 + (int)threadIdx.x)) {
       const int lc = threadIdx.x;
