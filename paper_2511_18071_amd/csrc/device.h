@@ -32,7 +32,8 @@ namespace sa {
 // dynamic LDS of every kernel (size given at launch)
 extern __shared__ double dyn_lds[];
 
-constexpr long SPIN_LIMIT = 1L << 25;
+constexpr long SPIN_LIMIT = 1L << 24;
+constexpr long POLL_FAST = 64;
 static_assert(NWAVE * (MMAX + 2) >= BLOCK, "the cluster-sum scratch (wsum) holds one double per thread");
 
 // ------------------------------------------------------------------------------------------
@@ -78,7 +79,10 @@ DEV bool aborted(const Cl& cl) {
 // arrival that completes it (it reads G - 1 arrivals) then subtracts G arrivals and adds one
 // generation in a single atomic; until then early arrivals at the next barrier count on top,
 // which the test below allows for. Waiters poll the word with relaxed loads and take one
-// acquire fence once the barrier is complete. Every wait is bounded: after SPIN_LIMIT polls the
+// acquire fence once the barrier is complete. A wait that outlasts POLL_FAST polls backs off
+// (a longer sleep between polls, the abort flag read every 64th poll): many workgroups left
+// waiting while a few run the coarse V-cycle passes would otherwise keep the memory system
+// busy with reads of the same two words. Every wait is bounded: after SPIN_LIMIT polls the
 // abort flag is raised and all waiters leave.
 // One arrival of thread 0 at the barrier on `word` among G workgroups, whose generation this
 // workgroup last saw complete is gen (advanced here).
@@ -94,8 +98,10 @@ DEV void bar_arrive_wait(Cl& cl, unsigned long long* word, unsigned& gen, unsign
       const unsigned long long v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned gv = (unsigned)(v >> 32);
       if ((gv == g0 && (unsigned)v >= G) || (int)(gv - g0) > 0) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > SPIN_LIMIT || aborted(cl)) {
+      if (spins < POLL_FAST) __builtin_amdgcn_s_sleep(1);
+      else __builtin_amdgcn_s_sleep(8);
+      ++spins;
+      if (spins > SPIN_LIMIT || ((spins & 63) == 0 && aborted(cl))) {
         __hip_atomic_store(cl.flags + FLAG_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
