@@ -392,7 +392,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   const size_t ysz = opt.guess == SA_GUESS_EWMA || range ? (size_t)k * n * 8 : 8;
   const size_t o_Y0 = take(ysz), o_Y1 = take(range ? 8 : ysz);
   const size_t o_Xr = take(range ? (size_t)opt.window * n * 8 : 8), o_Om = take((size_t)KWIN * KMAX * 8);
-  const size_t o_part = take((size_t)2 * G * PSTRIDE * 8), o_bar = take(64 * (1 + MAXLEV)), o_flags = take(NFLAGS * 4),
+  const size_t o_part = take((size_t)2 * (G + 1) * PSTRIDE * 8), o_bar = take(64 * (1 + MAXLEV)), o_flags = take(NFLAGS * 4),
                o_log = take(LOGCAP * sizeof(sa_solve_info)), o_b = take((size_t)n * 8), o_eta = take(2 * (size_t)nphys * 8),
                o_prob = take(sizeof(Problem)), o_prof = take(NPROF * 8);
   p->arena_bytes = off;

@@ -50,6 +50,11 @@ struct Cl {
                    // this workgroup (thread 0), nullptr: every barrier spans the cluster
 };
 
+// LDS word (in the sub-cluster generation table, after the levels' entries) through which
+// the thread that arrives at a cluster sum's barrier tells its workgroup it arrived last
+constexpr int SGEN_LAST = 31;
+static_assert(MAXLEV < SGEN_LAST, "the generation table holds the levels and the last-arrival word");
+
 // The barrier word of the sub-cluster barrier of V-cycle level l (64 bytes apart, after the
 // cluster's own word).
 DEV unsigned long long* sub_word(unsigned* bar, int l) {
@@ -139,18 +144,12 @@ DEV double wave_sum(double v) {
   return v;
 }
 
-// red[0..nv) holds this workgroup's sums; afterwards it holds the cluster sums (same on all
-// workgroups: every workgroup adds the G partials in the same fixed order). With an LDS
-// scratch the G x nv loads are spread over the whole workgroup: thread (q, i) adds the
-// partials g = q, q + Q, ... of value i (Q = BLOCK / nv threads per value, all loads issued
-// before the adds), then the Q sums of each value are added in q order.
-DEV void cluster_sum(Cl& cl, double* red, int nv) {
-  __syncthreads();
-  if (cl.G == 1) return;
-  double* part = cl.partials + (size_t)cl.pbuf * cl.G * PSTRIDE;
-  for (int i = threadIdx.x; i < nv; i += BLOCK) part[cl.rank * PSTRIDE + i] = red[i];
-  cl.pbuf ^= 1;
-  csync(cl);
+// the G partial records of value 0 .. nv-1 at part (PSTRIDE apart) added into red, in one
+// fixed order (the same on whichever workgroup runs it). With an LDS scratch the G x nv loads
+// are spread over the whole workgroup: thread (q, i) adds the partials g = q, q + Q, ... of
+// value i (Q = BLOCK / nv threads per value, all loads issued before the adds), then the Q
+// sums of each value are added in q order.
+DEV void combine_partials(const Cl& cl, const double* part, double* red, int nv) {
   const int Q = nv <= BLOCK ? BLOCK / nv : 1;
   if (!cl.scr || Q < 2) {
     for (int i = threadIdx.x; i < nv; i += BLOCK) {
@@ -182,6 +181,70 @@ DEV void cluster_sum(Cl& cl, double* red, int nv) {
     double s = 0.0;
     for (int qq = 0; qq < Q; ++qq) s += cl.scr[qq * nv + t];
     red[t] = s;
+  }
+  __syncthreads();
+}
+
+// Wait (thread 0) until the generation of `word` moves past g0, then acquire. Bounded and
+// backing off like the barrier's own wait.
+DEV void bar_wait_generation(Cl& cl, unsigned long long* word, unsigned g0) {
+  long spins = 0;
+  for (;;) {
+    const unsigned long long v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int)((unsigned)(v >> 32) - g0) > 0) break;
+    if (spins < POLL_FAST) __builtin_amdgcn_s_sleep(1);
+    else __builtin_amdgcn_s_sleep(8);
+    ++spins;
+    if (spins > SPIN_LIMIT || ((spins & 63) == 0 && aborted(cl))) {
+      __hip_atomic_store(cl.flags + FLAG_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// red[0..nv) holds this workgroup's sums; afterwards it holds the cluster sums, the same bits
+// on every workgroup. Each workgroup writes its record of partials and arrives at the cluster
+// barrier; the arrival that completes it (its workgroup has then seen every record) adds the
+// G records in the fixed order of combine_partials, writes the sums after the records and
+// only then releases the barrier, so the other workgroups read nv values instead of G x nv.
+// The records alternate between two buffers of G + 1 records (the next sum writes the other
+// one, and the one after it starts only once every workgroup has read this one).
+DEV void cluster_sum(Cl& cl, double* red, int nv) {
+  __syncthreads();
+  if (cl.G == 1) return;
+  double* part = cl.partials + (size_t)cl.pbuf * (cl.G + 1) * PSTRIDE;
+  double* total = part + (size_t)cl.G * PSTRIDE;
+  for (int i = threadIdx.x; i < nv; i += BLOCK) part[cl.rank * PSTRIDE + i] = red[i];
+  cl.pbuf ^= 1;
+  if (!cl.sgen) {  // no LDS flag word: every workgroup adds the records itself
+    csync(cl);
+    combine_partials(cl, part, red, nv);
+    return;
+  }
+  __syncthreads();
+  unsigned* last = cl.sgen + SGEN_LAST;
+  unsigned long long* word = bar_word(cl.bar);
+  const unsigned g0 = cl.gen;
+  if (threadIdx.x == 0) {
+    cl.gen = g0 + 1u;
+    const unsigned long long old = __hip_atomic_fetch_add(word, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const bool done = (unsigned)(old >> 32) == g0 && (unsigned)old == (unsigned)cl.G - 1u;
+    if (done) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *last = done ? 1u : 0u;
+  }
+  __syncthreads();
+  if (*last) {
+    combine_partials(cl, part, red, nv);
+    for (int i = threadIdx.x; i < nv; i += BLOCK) total[i] = red[i];
+    __syncthreads();
+    // one atomic: the arrivals back to 0 and the generation advanced, after the sums
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(word, (1ull << 32) - (unsigned long long)cl.G, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    if (threadIdx.x == 0) bar_wait_generation(cl, word, g0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nv; i += BLOCK) red[i] = total[i];
   }
   __syncthreads();
 }
@@ -1657,7 +1720,7 @@ DEV void phase_block_gram(const Problem& P, Cl& cl, const SolveArgs& a, const do
 DEV void cluster_sum_dd(Cl& cl, double* red, int nv) {
   __syncthreads();
   if (cl.G == 1) return;
-  double* part = cl.partials + (size_t)cl.pbuf * cl.G * PSTRIDE;
+  double* part = cl.partials + (size_t)cl.pbuf * (cl.G + 1) * PSTRIDE;
   for (int i = threadIdx.x; i < 2 * nv; i += BLOCK) part[cl.rank * PSTRIDE + i] = red[i];
   cl.pbuf ^= 1;
   csync(cl);

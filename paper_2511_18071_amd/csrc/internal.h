@@ -113,7 +113,7 @@ struct Problem {
   int precision, max_refine;
   double rtol_inner;
   // synchronisation and reports
-  double SA_GLOBAL* partials;          // 2 x G x PSTRIDE
+  double SA_GLOBAL* partials;          // 2 x (G + 1) x PSTRIDE: records, then the sums
   unsigned SA_GLOBAL* bar;             // barrier counter, generation
   int SA_GLOBAL* flags;                // NFLAGS
   sa_solve_info SA_GLOBAL* log;        // LOGCAP
