@@ -213,22 +213,27 @@ class Workload:
 
 def smoothing_sweeps(dx: float, h_min: float, nz: int) -> int:
     """Post-smoothing sweeps of the still-water V-cycle for a grid (a configuration choice,
-    not solver arithmetic): two where the x coupling of the operator is more than four times
-    its sigma coupling at the shallowest column, (h_min dsigma / dx)^2 > 4, else one. On such
-    grids a single damped line-Jacobi post-sweep leaves high x-frequency content in the
-    preconditioned vector, where the sixth-order operator is nearly singular relative to the
-    second-order one, and GMRES needs four to five times more steps (measured with the oracle:
-    197 against 40 on the 257 x 33 grid of the large simulation's resolution). The same grids
-    take the subspace guess's least-squares column drop threshold at 1e-2 instead of 1e-7
-    (``drop_threshold``)."""
-    return 2 if (h_min / (nz - 1) / dx) ** 2 > 4.0 else 1
+    not solver arithmetic), from the ratio q = (h_min dsigma / dx)^2 of the operator's x
+    coupling to its sigma coupling at the shallowest column: three where q > 20, two where
+    q > 2, else one. On such grids a single damped line-Jacobi post-sweep leaves high
+    x-frequency content in the preconditioned vector, where the sixth-order operator is nearly
+    singular relative to the second-order one, and GMRES needs several times more steps:
+    measured with the oracle, 197 against 40 on the 257 x 33 grid of the large simulation's
+    resolution (q = 6.5); on the GPU, cold solves of serving-mix grids took 178 / 40 / 38
+    steps with one / two / three sweeps at q = 3.7, 148 / 39 / 27 at q = 26 and 147 / 47 / 30
+    at q = 74 (where three sweeps are also the fastest per solve), 263 / 116 / 100 at q = 8.7
+    (two sweeps the fastest). The same grids take the subspace guess's least-squares column
+    drop threshold at 1e-2 instead of 1e-7 (``drop_threshold``)."""
+    q = (h_min / (nz - 1) / dx) ** 2
+    return 3 if q > 20.0 else 2 if q > 2.0 else 1
 
 
 def drop_threshold(nu2: int) -> float:
     """Column drop threshold of the subspace guess's least squares (a configuration choice).
     Where the preconditioned operator is nearly singular on high x-frequency content (the
     grids that take two post-sweeps), directions the least squares resolves only from nearly
-    dependent sketch columns put the guess's error there, where GMRES converges slowly:
+    dependent sketch columns put the guess's error there, where GMRES converges slowly (the
+    grids that take two or more post-sweeps):
     measured on the large simulation, 125 systems, 92 Arnoldi steps per solve at 1e-7
     against 8.2 at 1e-2 (12 from the previous solution). Elsewhere 1e-7 (the bar: 7.6 steps
     at 1e-7, 15 at 1e-2)."""
