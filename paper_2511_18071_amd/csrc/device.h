@@ -856,7 +856,7 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
         bool odd = false;
         if (e && has) prolong_cols(P, nc, ncc, cg, i0, i1, odd);
         // u (with the prolongated correction) and f of each row in one batch of loads
-        constexpr int U = 6;
+        constexpr int U = 3;
         for (int rb = r0; rb < nl; rb += U * RP) {
           S v[U], g[U];
 #pragma unroll
