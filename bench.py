@@ -384,6 +384,28 @@ def run_main(args):
                                  range_finder_value=round(100 / rr["wall"], 3), range_finder_iters_per_solve=its(rr),
                                  steps=20, warmup=5, cluster_workgroups=Gb, guess=f"EWMA rank {wb.k}, r={wb.r}")
         say("  bar leg done")
+        # the precision variant of the bar: FP32 inner GMRES with FP64 refinement against the
+        # all-FP64 path, both to relative residual 1e-10 on the FP64 residual, same systems
+        tight = 1e-10
+        r64 = run_sequence(B, wb, e2, b2, p2, "ewma", 5, 20, Gb, rtol=tight)
+        r32 = run_sequence(B, wb, e2, b2, p2, "ewma", 5, 20, Gb, rtol=tight, precision="fp32_ir")
+        nw = r64["nw"]
+        dx = ((r32["xs"] - r64["xs"]).norm(dim=1) / r64["xs"].norm(dim=1)).cpu().numpy()[nw:]
+
+        def prec_summary(r):
+            rel = np.array([i.relres for i in r["infos"]])
+            return {"value": round(100 / r["wall"], 3),
+                    "iters_per_solve": round(float(np.mean([i.iters for i in r["infos"]])), 3),
+                    "refinements_per_solve": round(float(np.mean([i.refinements for i in r["infos"]])), 3),
+                    "max_relres": float(rel.max()),
+                    "failed_solves": int(sum(1 for i in r["infos"] if i.status != 0 or i.relres > tight)),
+                    "err_vs_pstar_max": float(r["err"][nw:].max())}
+        out["precision_bar_513x17"] = {
+            "rtol": tight, "fp64": prec_summary(r64), "fp32_inner_fp64_refinement": prec_summary(r32),
+            "time_to_accuracy_fp64_over_fp32": round(r64["wall"] / r32["wall"], 3),
+            "solution_diff_fp32_vs_fp64_max": float(dx.max()), "solution_diff_fp32_vs_fp64_median": float(np.median(dx)),
+            "steps": 20, "warmup": 5, "cluster_workgroups": Gb}
+        say("  precision leg done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, x0, info0)
     print(json.dumps(out), flush=True)
