@@ -291,31 +291,65 @@ def _bar(name, nx, nz, seed, nsys, restart, k, r, scale=1.0, a0=0.01, dtau=0.025
     return w
 
 
+def hierarchy_fits(nx: int, nz: int, bc: str, coarse_max: int = 700, dense_max: int = 1024) -> bool:
+    """Whether the still-water hierarchy of a grid ends on a coarsest grid the dense coarse
+    solve takes (a property of the grid sizes, the same rule sa_create applies): columns
+    halve while the level has more than coarse_max unknowns and an even count to halve
+    (periodic: ncol even; walls: nx - 1 even), and the level where that stops must have at
+    most dense_max unknowns."""
+    nl = nz + 1
+    ncol = nx - 1 if bc == "periodic" else nx + 2
+    for _ in range(23):
+        if ncol * nl <= coarse_max:
+            break
+        if bc == "periodic":
+            if ncol % 2 or ncol // 2 < 4:
+                break
+            ncol //= 2
+        else:
+            if (nx - 1) % 2 or (nx - 1) // 2 + 1 < 3:
+                break
+            nx = (nx - 1) // 2 + 1
+            ncol = nx + 2
+    return ncol * nl <= dense_max
+
+
+def nearest_fitting_nx(nx_u: float, nz: int, bc: str, nx_range=(257, 8193)) -> int:
+    """The grid size closest to nx_u (ties to the smaller) inside nx_range whose hierarchy
+    fits (``hierarchy_fits``)."""
+    c = int(round(nx_u))
+    for d in range(0, nx_range[1] - nx_range[0] + 1):
+        for nx in (c - d, c + d):
+            if nx_range[0] <= nx <= nx_range[1] and hierarchy_fits(nx, nz, bc):
+                return nx
+    raise ValueError("no grid size in range has a fitting hierarchy")
+
+
 def serving_mix(nsims: int = 256, seed: int = 5, nsys: int = 50, nx_range=(257, 8193),
                 nz_choices=(9, 17, 33)) -> list[Workload]:
     """Independent simulations of different sizes for the continuous-batching server:
-    nx uniform in nx_range, moved to the nearest 64 q + 1 with q = 2^a b, b in {1, 3, 5, 7}
-    (grids that halve down to a few columns, so the still-water V-cycle reaches a small
-    coarsest grid), nz from nz_choices, flat (periodic) or submerged-bar (walls, bar scaled to
-    the domain) bathymetry, H/L uniform in [0.01, 0.08] (periodic waves capped at 0.7 of the
-    breaking limit at their kh), history rank uniform in 8..16, forgetting factor 0.9."""
+    nx uniform in nx_range, moved to the nearest size whose still-water hierarchy ends on a
+    coarsest grid of at most 1024 unknowns (``nearest_fitting_nx``: the semicoarsening halves
+    even column counts only; the sizes that fit lie a few per cent apart at most), nz from
+    nz_choices, flat (periodic) or submerged-bar (walls, bar scaled to the domain)
+    bathymetry, H/L uniform in [0.01, 0.08] (periodic waves capped at 0.7 of the breaking
+    limit at their kh), history rank uniform in 8..16, forgetting factor 0.9."""
     rng = np.random.default_rng(seed)
-    qs = sorted({(2 ** a) * b for a in range(12) for b in (1, 3, 5, 7)})
     sims = []
     for i in range(nsims):
         nx_u = float(rng.uniform(nx_range[0], nx_range[1]))
-        q = min(qs, key=lambda v: (abs(64 * v + 1 - nx_u), v))
-        nx = 64 * q + 1
         nz = int(rng.choice(nz_choices))
         k = int(rng.integers(8, 17))
         steep = float(rng.uniform(0.01, 0.08))
         if rng.uniform() < 0.5:
             kh = float(rng.uniform(0.5, 2.0))
+            nx = nearest_fitting_nx(nx_u, nz, "periodic", nx_range)
             # at most the steepest fraction of the breaking limit the paper runs (0.7, Sec. 5.1)
             steep = min(steep, 0.7 * battjes_max_steepness(kh))
             w = _stream(f"serve{i:03d}", nx, nz, kh, max(1, (nx - 1) // 256), 4, steep,
                         seed * 1000 + i, nsys, 30, k, 0.9)
         else:
+            nx = nearest_fitting_nx(nx_u, nz, "walls", nx_range)
             w = _bar(f"serve{i:03d}", nx, nz, seed * 1000 + i, nsys, 30, k, 0.9,
                      scale=(nx - 1) / 512.0, a0=0.01 * steep / 0.03)
         sims.append(w)

@@ -108,3 +108,24 @@ def test_footprint_of_every_preconditioner_on_the_large_grid(binding):
     w = W.get("periodic_16385x33")
     for pc in ("none", "line", "mg"):
         assert binding.footprint(w, precond=pc, cluster=64) > 8 * w.n * (w.restart + 1)
+
+
+def test_library_hierarchy_rule_matches_the_serving_grid_rule(binding):
+    """The grid sizes the serving mix picks are the ones sa_create accepts: the dry run that
+    computes a footprint builds the hierarchy and refuses a coarsest grid above 1024 unknowns
+    (no GPU needed)."""
+    from paper_2511_18071_amd import workload as W
+    cases = [(4097, 33, "periodic"), (4096, 33, "periodic"), (1985, 33, "periodic"), (961, 33, "periodic"),
+             (4097, 9, "walls"), (4098, 9, "walls"), (1025, 17, "walls"), (1031, 17, "walls")]
+    for nx, nz, bc in cases:
+        if bc == "periodic":
+            w = W._stream("t", nx, nz, 2.0, 1, 4, 0.05, 1, 2, 30, 8, 0.9)
+        else:
+            w = W._bar("t", nx, nz, 1, 2, 30, 8, 0.9, scale=(nx - 1) / 512.0, a0=0.01)
+        fits = W.hierarchy_fits(nx, nz, bc)
+        try:
+            binding.footprint(w)
+            ok = True
+        except binding.SawaveError:
+            ok = False
+        assert ok == fits, (nx, nz, bc, fits)

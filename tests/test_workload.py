@@ -82,4 +82,29 @@ def test_serving_mix_is_seeded():
     b = W.serving_mix(8, seed=5, nsys=3)
     assert [(w.nx, w.nz, w.bc, w.k) for w in a] == [(w.nx, w.nz, w.bc, w.k) for w in b]
     for w in a:
-        assert (w.nx - 1) % 64 == 0 and 257 <= w.nx <= 8193 and w.nz in (9, 17, 33) and 8 <= w.k <= 16
+        assert W.hierarchy_fits(w.nx, w.nz, w.bc) and 257 <= w.nx <= 8193
+        assert w.nz in (9, 17, 33) and 8 <= w.k <= 16
+
+
+def test_serving_mix_grid_sizes_stay_near_the_uniform_draw():
+    """nx is the uniform draw moved to the nearest size whose hierarchy fits: within a few
+    per cent, and the draw itself when it fits."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        nx_u = float(rng.uniform(257, 8193))
+        nz = int(rng.choice((9, 17, 33)))
+        bc = "periodic" if rng.uniform() < 0.5 else "walls"
+        nx = W.nearest_fitting_nx(nx_u, nz, bc)
+        assert W.hierarchy_fits(nx, nz, bc)
+        assert abs(nx - nx_u) <= 0.04 * nx_u
+        if W.hierarchy_fits(int(round(nx_u)), nz, bc):
+            assert nx == int(round(nx_u))
+
+
+def test_hierarchy_fits_rule():
+    # periodic nz = 33 (34 levels): 4096 columns halve to 16 (544 unknowns); 4095 is odd
+    assert W.hierarchy_fits(4097, 33, "periodic") and not W.hierarchy_fits(4096, 33, "periodic")
+    # 1984 = 31 * 64 columns end at 31 x 34 = 1054 > 1024 unknowns; 960 = 15 * 64 at 15 x 34
+    assert not W.hierarchy_fits(1985, 33, "periodic") and W.hierarchy_fits(961, 33, "periodic")
+    # walls: nx - 1 must halve; 4097 points halve down, 4098 do not
+    assert W.hierarchy_fits(4097, 9, "walls") and not W.hierarchy_fits(4098, 9, "walls")
