@@ -622,7 +622,7 @@ def operator_probe(name: str, reps: int = 50):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build measures the one-GPU path (asked for {args.gpus}).",
+        print(f"bench.py runs on one GPU only: it measures the one-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
     if args.operator_probe:
