@@ -93,6 +93,9 @@ def parse(argv=None):
                     help="serving: ticks in flight (the process is given as many hardware queues)")
     ap.add_argument("--serve-upw", type=int, default=10000,
                     help="serving: unknowns per workgroup when the server sizes the clusters")
+    ap.add_argument("--serve-precision", default="fp32_ir", choices=["fp32_ir", "fp64"],
+                    help="serving: precision of the batched solves (the configuration's FP32 inner GMRES with FP64 "
+                         "refinement, or FP64 throughout)")
     ap.add_argument("--serve-baseline-stride", type=int, default=8,
                     help="serving: the one-at-a-time FP64 baseline solves every k-th simulation")
     ap.add_argument("--operator-probe", default="", metavar="WORKLOAD",
@@ -462,7 +465,7 @@ def run_serving(args):
         if args.serve_inflight:
             sopts["max_inflight"] = args.serve_inflight
         srv = B.Server(stream=stream, **sopts)
-        ids = [srv.open(w, precision="fp32_ir") for w in sims]
+        ids = [srv.open(w, precision=args.serve_precision) for w in sims]
         if any(i is None for i in ids):
             raise RuntimeError("serving mix does not fit the HBM budget")
         torch.cuda.synchronize()
@@ -555,10 +558,11 @@ def run_serving(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64" if args.serve_precision == "fp32_ir" else "f64",
         "data": "synthetic",
         "config": {"workload": f"serving_mix({len(sims)} simulations x {nsys} systems, seed 5)",
-                   "unknowns_total": total_unknowns, "precision": "fp32 inner GMRES, fp64 refinement",
+                   "unknowns_total": total_unknowns,
+                   "precision": "fp32 inner GMRES, fp64 refinement" if args.serve_precision == "fp32_ir" else "fp64",
                    "guess": "EWMA", "hbm_bytes_resident": sat["bytes"],
                    "unknowns_per_workgroup": args.serve_upw, "ticks_in_flight": args.serve_inflight,
                    "coresident_workgroups": sat["ticks"]["capacity"],
