@@ -75,7 +75,8 @@ class Simulation:
     @classmethod
     def from_workload(cls, w, **overrides):
         kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=getattr(w, "nu2", 1),
-                  tau_drop=getattr(w, "tau_drop", TAU_DROP), k=w.k, r=w.r, seed=w.seed)
+                  tau_drop=getattr(w, "tau_drop", TAU_DROP), k=w.k, r=w.r, seed=w.seed,
+                  coarse_max=getattr(w, "coarse_max", 700))
         kw.update(overrides)
         return cls(w.nx, w.nz, w.bc, w.length, w.depth(), Options(**kw))
 

@@ -225,7 +225,7 @@ def make_options(**opts) -> SaOptions:
 def workload_args(w, **overrides):
     """(grid, depth, options) of a synthetic workload."""
     kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=w.nu2, tau_drop=w.tau_drop, k=w.k, r=w.r,
-              seed=w.seed)
+              seed=w.seed, coarse_max=w.coarse_max)
     kw.update(overrides)
     grid = SaGrid(w.nx, w.nz, SA_PERIODIC if w.bc == "periodic" else SA_WALLS, float(w.length))
     return grid, np.ascontiguousarray(w.depth(), dtype=np.float64), make_options(**kw)
@@ -276,7 +276,7 @@ class Problem:
     @classmethod
     def from_workload(cls, w, stream=None, **overrides):
         kw = dict(restart=w.restart, rtol=w.rtol, precond=w.precond, nu2=w.nu2, tau_drop=w.tau_drop, k=w.k, r=w.r,
-              seed=w.seed)
+              seed=w.seed, coarse_max=w.coarse_max)
         kw.update(overrides)
         return cls(w.nx, w.nz, w.bc, w.length, w.depth(), stream=stream, **kw)
 

@@ -51,7 +51,7 @@ def test_fullsize_operator_and_precond(B):
     ratio = (np.abs(y - A @ x) / bound).max()
     _say(f"   operator: max err/(|A||x|) {ratio:.3e}")
     assert ratio <= 1e-11
-    minv = opc.make(g, w.depth(), "mg", 1, w.nu2)  # the workload's V(1, nu2), as the problem
+    minv = opc.make(g, w.depth(), "mg", 1, w.nu2, coarse_max=w.coarse_max)  # the workload's V(1, nu2), as the problem
     kappa = np.linalg.cond(minv.levels[-1]["m"].toarray())
     tol = max(1e-11, 8.0 * kappa * np.finfo(float).eps)
     for v in (x, ps):

@@ -133,6 +133,7 @@ def test_precond_parity(B, name, pc, nu, omega, cmax):
 
 @pytest.mark.parametrize("name,nu2,cluster,cmax", [
     ("periodic_257x33", 2, 0, 700), ("periodic_257x33", 2, 3, 700), ("periodic_257x33", 3, 0, 200),
+    ("periodic_257x33", 2, 0, 1088), ("periodic_257x33", 2, 5, 1088),
     ("bar_65x9", 2, 2, 50), ("bar_513x17", 2, 0, 100),
 ])
 def test_precond_parity_post_sweeps(B, name, nu2, cluster, cmax):

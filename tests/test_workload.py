@@ -82,7 +82,7 @@ def test_serving_mix_is_seeded():
     b = W.serving_mix(8, seed=5, nsys=3)
     assert [(w.nx, w.nz, w.bc, w.k) for w in a] == [(w.nx, w.nz, w.bc, w.k) for w in b]
     for w in a:
-        assert W.hierarchy_fits(w.nx, w.nz, w.bc) and 257 <= w.nx <= 8193
+        assert W.hierarchy_fits(w.nx, w.nz, w.bc, dense_max=1024) and 257 <= w.nx <= 8193
         assert w.nz in (9, 17, 33) and 8 <= w.k <= 16
 
 
@@ -95,16 +95,18 @@ def test_serving_mix_grid_sizes_stay_near_the_uniform_draw():
         nz = int(rng.choice((9, 17, 33)))
         bc = "periodic" if rng.uniform() < 0.5 else "walls"
         nx = W.nearest_fitting_nx(nx_u, nz, bc)
-        assert W.hierarchy_fits(nx, nz, bc)
+        assert W.hierarchy_fits(nx, nz, bc, dense_max=1024)
         assert abs(nx - nx_u) <= 0.04 * nx_u
-        if W.hierarchy_fits(int(round(nx_u)), nz, bc):
+        if W.hierarchy_fits(int(round(nx_u)), nz, bc, dense_max=1024):
             assert nx == int(round(nx_u))
 
 
 def test_hierarchy_fits_rule():
     # periodic nz = 33 (34 levels): 4096 columns halve to 16 (544 unknowns); 4095 is odd
     assert W.hierarchy_fits(4097, 33, "periodic") and not W.hierarchy_fits(4096, 33, "periodic")
-    # 1984 = 31 * 64 columns end at 31 x 34 = 1054 > 1024 unknowns; 960 = 15 * 64 at 15 x 34
-    assert not W.hierarchy_fits(1985, 33, "periodic") and W.hierarchy_fits(961, 33, "periodic")
+    # 1984 = 31 * 64 columns end at 31 x 34 = 1054 unknowns: over the serving mix's 1024, within
+    # the library's 2048; 3968 = 31 * 128 the same; 63 * 64 at 63 x 34 = 2142 over both
+    assert not W.hierarchy_fits(1985, 33, "periodic", dense_max=1024) and W.hierarchy_fits(1985, 33, "periodic")
+    assert not W.hierarchy_fits(4033, 33, "periodic") and W.hierarchy_fits(961, 33, "periodic", dense_max=1024)
     # walls: nx - 1 must halve; 4097 points halve down, 4098 do not
     assert W.hierarchy_fits(4097, 9, "walls") and not W.hierarchy_fits(4098, 9, "walls")
