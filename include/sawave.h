@@ -102,7 +102,7 @@ typedef struct {
                         /* of the grid, at most 256                                        */
   int32_t profile;      /* 1: accumulate per-phase device time (sa_get_phase_times), 0      */
   int32_t coarse_max;   /* MG: coarsening stops at the first grid with at most this many    */
-                        /* unknowns, solved exactly there (<= 2048), default 700            */
+                        /* unknowns, solved exactly there (<= 4096), default 700            */
   int32_t window;       /* SA_GUESS_RANGE: K, the solutions kept in the sliding window of   */
                         /* the randomized range finder (Alg. 3, V = X Omega with the k x K  */
                         /* Gaussian rows drawn as the solutions enter), k..32, default 16   */

@@ -25,7 +25,7 @@ constexpr int HW = 3;             // stencil half width (seven-point first deriv
 constexpr int NLMAX = 66;         // largest number of levels nz + 1
 constexpr int PSTRIDE = 320;      // doubles per workgroup in the reduction scratch
 constexpr int LOGCAP = 4096;      // solve reports kept on the device
-constexpr int COARSE_MAX = 2048;  // largest coarsest-grid size solved by a dense inverse
+constexpr int COARSE_MAX = 4096;  // largest coarsest-grid size solved by a dense inverse
 constexpr int KWIN = 32;          // largest window of the randomized range finder
 
 // Flags written by kernels (device int array).

@@ -1,5 +1,8 @@
 // Host-side setup of a problem: difference weights, still-water coarse-grid inverse and the
 // sketch random stream. Plain C++ (no device code).
+#include <atomic>
+#include <algorithm>
+#include <thread>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -171,35 +174,66 @@ int dense_still_water_inverse(int ncol, int nx, int nl, int periodic, double dx,
       at(row, c, j - 1, azz - sxx * 0.5 * rds);
     }
   }
-  // Gauss-Jordan elimination with partial pivoting: inv = a^-1
+  // Gauss-Jordan elimination with partial pivoting: inv = a^-1. The row updates of each
+  // column step are split over host threads (the rows are independent within a step, so the
+  // result does not depend on the split); a spin barrier separates the steps.
   std::vector<double> e((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) e[(size_t)i * n + i] = 1.0;
-  for (int col = 0; col < n; ++col) {
-    int piv = col;
-    double best = fabs(a[(size_t)col * n + col]);
-    for (int r = col + 1; r < n; ++r) {
-      const double v = fabs(a[(size_t)r * n + col]);
-      if (v > best) best = v, piv = r;
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int nthr = std::max(1, std::min({(int)(hw ? hw : 1), 16, n / 128}));
+  std::atomic<int> arrived{0}, phase{0}, failed{0};
+  auto barrier = [&]() {
+    const int ph = phase.load(std::memory_order_acquire);
+    if (arrived.fetch_add(1, std::memory_order_acq_rel) == nthr - 1) {
+      arrived.store(0, std::memory_order_relaxed);
+      phase.fetch_add(1, std::memory_order_release);
+    } else {
+      while (phase.load(std::memory_order_acquire) == ph) std::this_thread::yield();
     }
-    if (!(best > 0.0)) return -1;
-    if (piv != col) {
-      for (int q = 0; q < n; ++q) {
-        double t = a[(size_t)col * n + q]; a[(size_t)col * n + q] = a[(size_t)piv * n + q]; a[(size_t)piv * n + q] = t;
-        t = e[(size_t)col * n + q]; e[(size_t)col * n + q] = e[(size_t)piv * n + q]; e[(size_t)piv * n + q] = t;
+  };
+  auto work = [&](int t) {
+    const int r0 = (int)((long)n * t / nthr), r1 = (int)((long)n * (t + 1) / nthr);
+    for (int col = 0; col < n; ++col) {
+      if (t == 0) {
+        int piv = col;
+        double best = fabs(a[(size_t)col * n + col]);
+        for (int r = col + 1; r < n; ++r) {
+          const double v = fabs(a[(size_t)r * n + col]);
+          if (v > best) best = v, piv = r;
+        }
+        if (!(best > 0.0)) {
+          failed.store(1, std::memory_order_relaxed);
+        } else {
+          if (piv != col) {
+            for (int q = 0; q < n; ++q) {
+              double v = a[(size_t)col * n + q]; a[(size_t)col * n + q] = a[(size_t)piv * n + q]; a[(size_t)piv * n + q] = v;
+              v = e[(size_t)col * n + q]; e[(size_t)col * n + q] = e[(size_t)piv * n + q]; e[(size_t)piv * n + q] = v;
+            }
+          }
+          const double d = 1.0 / a[(size_t)col * n + col];
+          for (int q = 0; q < n; ++q) a[(size_t)col * n + q] *= d, e[(size_t)col * n + q] *= d;
+        }
       }
-    }
-    const double d = 1.0 / a[(size_t)col * n + col];
-    for (int q = 0; q < n; ++q) a[(size_t)col * n + q] *= d, e[(size_t)col * n + q] *= d;
-    for (int r = 0; r < n; ++r) {
-      if (r == col) continue;
-      const double f = a[(size_t)r * n + col];
-      if (f == 0.0) continue;
-      for (int q = 0; q < n; ++q) {
-        a[(size_t)r * n + q] -= f * a[(size_t)col * n + q];
-        e[(size_t)r * n + q] -= f * e[(size_t)col * n + q];
+      barrier();
+      if (failed.load(std::memory_order_relaxed)) return;
+      // columns left of col are zero in the pivot row: their updates would subtract zeros
+      for (int r = r0; r < r1; ++r) {
+        if (r == col) continue;
+        const double f = a[(size_t)r * n + col];
+        if (f == 0.0) continue;
+        for (int q = col; q < n; ++q) a[(size_t)r * n + q] -= f * a[(size_t)col * n + q];
+        for (int q = 0; q < n; ++q) e[(size_t)r * n + q] -= f * e[(size_t)col * n + q];
       }
+      barrier();
     }
+  };
+  {
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthr; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto& th : pool) th.join();
   }
+  if (failed.load()) return -1;
   // stored transposed: inv[j * n + i] = (a^-1)[i][j], so device rows read coalesced
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) inv[(size_t)j * n + i] = e[(size_t)i * n + j];

@@ -231,12 +231,14 @@ def smoothing_sweeps(dx: float, h_min: float, nz: int) -> int:
 
 def large_coarsest(nz: int) -> int:
     """Hierarchy limit of the large simulation's family (a configuration choice): coarsening
-    stops at 32 columns (32 (nz + 1) unknowns) instead of at most 700 unknowns, one V-cycle
-    level fewer, with the dense coarse inverse formed once per simulation on the host (about a
-    second at 1 088 unknowns). Measured on the 16385 x 33 simulation, 125 EWMA systems: 147.4
-    against 141.7 solves/s at the same 8.21 Arnoldi steps per solve (and 47 cold). Grids of
-    the serving mix keep 700: their setup would take that second per simulation."""
-    return 32 * (nz + 1)
+    stops at 64 columns (64 (nz + 1) unknowns) instead of at most 700 unknowns, two V-cycle
+    levels fewer on the 16385 x 33 grid, with the dense coarse inverse formed once per
+    simulation on the host (half a second at 2 176 unknowns on sixteen threads). Measured on
+    the 16385 x 33 simulation, 125 EWMA systems, at the same 8.21 Arnoldi steps per solve (and
+    47 cold): 141.7 solves/s at 700 unknowns (16 columns), 148.9 at 32 columns, 154.9 at 64.
+    Grids of the serving mix keep 700: their admission would pay the host inverse per
+    simulation."""
+    return 64 * (nz + 1)
 
 
 def drop_threshold(nu2: int) -> float:
@@ -302,7 +304,7 @@ def _bar(name, nx, nz, seed, nsys, restart, k, r, scale=1.0, a0=0.01, dtau=0.025
     return w
 
 
-DENSE_MAX = 2048  # the largest coarsest grid sa_create solves by a dense inverse
+DENSE_MAX = 4096  # the largest coarsest grid sa_create solves by a dense inverse
 
 
 def hierarchy_fits(nx: int, nz: int, bc: str, coarse_max: int = 700, dense_max: int = DENSE_MAX) -> bool:
@@ -332,7 +334,7 @@ def nearest_fitting_nx(nx_u: float, nz: int, bc: str, nx_range=(257, 8193), dens
     """The grid size closest to nx_u (ties to the smaller) inside nx_range whose hierarchy
     fits (``hierarchy_fits``) with a coarsest grid of at most dense_max unknowns (1024 for the
     serving mix: the host forms each simulation's dense coarse inverse at admission, a tenth of
-    a second at 1024 unknowns and eight times more at the library's 2048)."""
+    a second at 1024 unknowns and far more at the library's 4096)."""
     c = int(round(nx_u))
     for d in range(0, nx_range[1] - nx_range[0] + 1):
         for nx in (c - d, c + d):

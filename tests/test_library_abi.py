@@ -112,10 +112,10 @@ def test_footprint_of_every_preconditioner_on_the_large_grid(binding):
 
 def test_library_hierarchy_rule_matches_the_serving_grid_rule(binding):
     """The grid sizes the serving mix picks are the ones sa_create accepts: the dry run that
-    computes a footprint builds the hierarchy and refuses a coarsest grid above 2048 unknowns
+    computes a footprint builds the hierarchy and refuses a coarsest grid above 4096 unknowns
     (no GPU needed)."""
     from paper_2511_18071_amd import workload as W
-    cases = [(4097, 33, "periodic"), (4096, 33, "periodic"), (1985, 33, "periodic"), (4033, 33, "periodic"),
+    cases = [(4097, 33, "periodic"), (4096, 33, "periodic"), (1985, 33, "periodic"), (4065, 33, "periodic"),
              (961, 33, "periodic"),
              (4097, 9, "walls"), (4098, 9, "walls"), (1025, 17, "walls"), (1031, 17, "walls")]
     for nx, nz, bc in cases:

@@ -105,8 +105,8 @@ def test_hierarchy_fits_rule():
     # periodic nz = 33 (34 levels): 4096 columns halve to 16 (544 unknowns); 4095 is odd
     assert W.hierarchy_fits(4097, 33, "periodic") and not W.hierarchy_fits(4096, 33, "periodic")
     # 1984 = 31 * 64 columns end at 31 x 34 = 1054 unknowns: over the serving mix's 1024, within
-    # the library's 2048; 3968 = 31 * 128 the same; 63 * 64 at 63 x 34 = 2142 over both
+    # the library's 4096; 4064 = 127 * 32 at 127 x 34 = 4318 over both
     assert not W.hierarchy_fits(1985, 33, "periodic", dense_max=1024) and W.hierarchy_fits(1985, 33, "periodic")
-    assert not W.hierarchy_fits(4033, 33, "periodic") and W.hierarchy_fits(961, 33, "periodic", dense_max=1024)
+    assert not W.hierarchy_fits(4065, 33, "periodic") and W.hierarchy_fits(961, 33, "periodic", dense_max=1024)
     # walls: nx - 1 must halve; 4097 points halve down, 4098 do not
     assert W.hierarchy_fits(4097, 9, "walls") and not W.hierarchy_fits(4098, 9, "walls")
