@@ -409,6 +409,14 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
       delete p;
       return sa_fail(SA_EARG, "sa_create: singular coarsest operator");
     }
+    // few rows per workgroup: keep the inverse row by row (each workgroup then streams its own
+    // rows with coalesced loads); else transposed (a thread per row, coalesced across rows)
+    if ((cn + G - 1) / G <= CN_ROWS) {
+      std::vector<double> rm(cinv_n);
+      for (int i = 0; i < cn; ++i)
+        for (int j = 0; j < cn; ++j) rm[(size_t)i * cn + j] = cinv[(size_t)j * cn + i];
+      cinv.swap(rm);
+    }
   }
   if (hipMalloc((void**)&p->arena, off) != hipSuccess) {
     delete p;
@@ -484,7 +492,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
       L.f32 = L.u32 = L.o32 = nullptr;
     }
   }
-  P.cinv = (decltype(P.cinv))(A + o_cinv); P.cn = cn;
+  P.cinv = (decltype(P.cinv))(A + o_cinv); P.cn = cn; P.cinv_rows = (cn + G - 1) / G <= CN_ROWS ? 1 : 0;
   P.cinv32 = ir ? (decltype(P.cinv32))(A + o_cinv32) : nullptr;
   P.V32 = ir ? (decltype(P.V32))(A + o_V32) : nullptr;
   P.t32 = ir ? (decltype(P.t32))(A + o_t32) : nullptr;

@@ -1139,6 +1139,40 @@ DEV void phase_coarse(const Problem& P, Cl& cl, const S* f, S* o, S* lds) {
   const int r1 = min(cn, r0 + R);
   if (r0 >= r1) return;
   const int rows = r1 - r0;
+  if (P.cinv_rows) {
+    // the inverse row by row (at most CN_ROWS rows here): the workgroup streams its rows in
+    // groups of RB, every thread adding the entries j = t, t + BLOCK, ... of each row, then a
+    // fixed-order reduction over the waves
+    constexpr int RB = 8;
+    for (int rb = 0; rb < rows; rb += RB) {
+      const int nr = min(RB, rows - rb);
+      S acc[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) acc[u] = S(0);
+      for (int j = threadIdx.x; j < cn; j += BLOCK) {
+        const S x = sf[j];
+#pragma unroll
+        for (int u = 0; u < RB; ++u)
+          if (u < nr) acc[u] += ci[(size_t)(r0 + rb + u) * cn + j] * x;
+      }
+      const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        S v = acc[u];
+#pragma unroll
+        for (int o2 = 32; o2 > 0; o2 >>= 1) v += __shfl_xor(v, o2, 64);
+        if (lane == 0) part[wave * RB + u] = v;
+      }
+      __syncthreads();
+      if (threadIdx.x < nr) {
+        S sum = S(0);
+        for (int wv = 0; wv < NWAVE; ++wv) sum += part[wv * RB + threadIdx.x];
+        o[r0 + rb + threadIdx.x] = sum;
+      }
+      __syncthreads();
+    }
+    return;
+  }
   const int Q = rows < BLOCK ? BLOCK / rows : 1;
   const int t = threadIdx.x;
   const int q = t / rows, rl = t - q * rows;

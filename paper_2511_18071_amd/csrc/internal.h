@@ -26,6 +26,7 @@ constexpr int NLMAX = 66;         // largest number of levels nz + 1
 constexpr int PSTRIDE = 320;      // doubles per workgroup in the reduction scratch
 constexpr int LOGCAP = 4096;      // solve reports kept on the device
 constexpr int COARSE_MAX = 4096;  // largest coarsest-grid size solved by a dense inverse
+constexpr int CN_ROWS = 64;       // at most this many coarse rows per workgroup: the inverse is kept row by row
 constexpr int KWIN = 32;          // largest window of the randomized range finder
 
 // Flags written by kernels (device int array).
@@ -86,9 +87,10 @@ struct Problem {
   int pc, nu1, nu2, nlev, tail;   // tail: first level run by a single workgroup
   double omega;
   Level lev[MAXLEV];
-  const double SA_GLOBAL* cinv;        // dense inverse of the coarsest operator, cn x cn (transposed)
+  const double SA_GLOBAL* cinv;        // dense inverse of the coarsest operator, cn x cn (layout: cinv_rows)
   const float SA_GLOBAL* cinv32;       // its FP32 rounding (refinement path)
   int cn;
+  int cinv_rows;  // 1: cinv stored row by row (a workgroup owns at most CN_ROWS rows), 0: transposed
   // solver vectors
   double SA_GLOBAL* x;
   double SA_GLOBAL* xc;
