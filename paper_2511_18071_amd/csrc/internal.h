@@ -26,7 +26,7 @@ constexpr int NLMAX = 66;         // largest number of levels nz + 1
 constexpr int PSTRIDE = 320;      // doubles per workgroup in the reduction scratch
 constexpr int LOGCAP = 4096;      // solve reports kept on the device
 constexpr int COARSE_MAX = 4096;  // largest coarsest-grid size solved by a dense inverse
-constexpr int CN_ROWS = 64;       // at most this many coarse rows per workgroup: the inverse is kept row by row
+constexpr int CN_ROWS = 16;       // at most this many coarse rows per workgroup: the inverse is kept row by row
 constexpr int KWIN = 32;          // largest window of the randomized range finder
 
 // Flags written by kernels (device int array).
