@@ -327,7 +327,8 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     for (int l = 0; l < lt; ++l) {
       const int tw = (levs[l].ncol + 31) / 32 <= G ? 32 : TM_HOST;
       if ((levs[l].ncol + tw - 1) / tw > G) continue;
-      const size_t sz = (size_t)(5 + 3 * nl) * (tw + 4);
+      // a uniform level keeps its column data and one shared set of factors and gamma
+      const size_t sz = levs[l].fstride == 0 ? (size_t)4 * (tw + 4) + 3 * nl + 1 : (size_t)(5 + 3 * nl) * (tw + 4);
       if ((head + gmres_scratch) * sizeof(double) + (res_total + sz) * res_esz > 160 * 1024) continue;
       res_off[l] = (int)res_total;
       res_total += sz;

@@ -810,6 +810,13 @@ DEV S factor(const Lv<S>& L, int qq, int j, int cg) {
   return L.flo[qq * L.facstride + j * (L.fstride ? L.fstride : 1) + (L.fstride ? cg : 0)];
 }
 
+// value i of a uniform level's one set of line-solve constants: the factors lo | pc | inv
+// (nl levels each, i < 3 nl), then gamma
+template <class S>
+DEV S uniform_factor(const Lv<S>& L, int nl, int i) {
+  return i < 3 * nl ? L.flo[i] : L.fgam[0];
+}
+
 // o = u + omega L^-1 (f - M u) on level l, u = (uin or 0) + (e ? P e : 0) formed on load.
 // Residuals are formed by all threads in LDS, then one thread per column eliminates.
 template <class S, int TW = TM>
@@ -829,9 +836,13 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
   constexpr int LR = TW + 4;
   const S* ccd = rc ? rc + 1 : scd;            // column c0 - 1 + lc at [lc]
   const int cds = rc ? LR : LW;
-  const S* cfac = rc ? rc + 4 * LR + 2 : sfac;  // column c0 + lc at [lc]
-  const int fst = rc ? LR : TW;
-  const S* cgam = rc ? rc + (4 + 3 * nl) * LR + 2 : sgam;
+  // factors of column c0 + lc at [lc * cst], level stride fst, gamma after the 3 nl factor
+  // rows; on a uniform level every column shares one set (cst = 0, level stride 1)
+  const bool uni = L.fstride == 0;
+  const int cst = uni ? 0 : 1;
+  const S* cfac = rc ? rc + 4 * LR + 2 * cst : sfac;
+  const int fst = uni ? 1 : (rc ? LR : TW);
+  const S* cgam = cfac + 3 * fst * nl;
   const bool zero = !uin && !e;
   for (int t = cl.rank; t < (nc + TW - 1) / TW; t += cl.G) {
     const int c0 = t * TW, w = min(TW, nc - c0);
@@ -884,9 +895,12 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
         }
       }
     }
-    // column data over the halo, factors and gamma over the own columns (unless resident)
-    if (!rc)
-      staged_rows<16>(rgam + 1 - rcd, ww, [&](int rr, int lc) -> S {
+    // column data over the halo, factors and gamma over the own columns (unless resident;
+    // a uniform level's one set of factors and gamma: one value per thread, in the same batch)
+    if (!rc) {
+      const int nf = uni ? 3 * nl + 1 : 0;
+      const S fv = (int)threadIdx.x < nf ? uniform_factor(L, nl, threadIdx.x) : S(0);
+      staged_rows<16>((uni ? rfac : rgam + 1) - rcd, ww, [&](int rr, int lc) -> S {
         const int r = rr + rcd;
         const int c = c0 - 1 + lc;
         const bool own = lc >= 1 && lc <= w;
@@ -900,6 +914,8 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
         else if (r < rgam) sfac[(r - rfac) * TW + lc - 1] = v;
         else sgam[lc - 1] = v;
       });
+      if ((int)threadIdx.x < nf) sfac[threadIdx.x] = fv;
+    }
     __syncthreads();
     if (!zero) {
       auto U = [&](int cc, int jj) { return su[jj * LW + st.slot(cc)]; };
@@ -911,8 +927,8 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
       __syncthreads();
     }
     if (threadIdx.x < w) {
-      const int lc = threadIdx.x;
-      line_solve<S>(nz, cgam[lc], sr + lc, TW, cfac + lc, cfac + fst * nl + lc, cfac + 2 * fst * nl + lc, fst);
+      const int lc = threadIdx.x, lf = lc * cst;
+      line_solve<S>(nz, cgam[lf], sr + lc, TW, cfac + lf, cfac + fst * nl + lf, cfac + 2 * fst * nl + lf, fst);
     }
     __syncthreads();
     const S om = S(P.omega);
@@ -959,8 +975,12 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
   S* sfac = scd + 4 * LW;
   S* sgam = sfac + 3 * LW * nl;
   const S* ccd = rc ? rc : scd;
+  // factors of column c0 - 2 + lc at [lc * cst], level stride fst, gamma after them (one
+  // shared set on a uniform level: cst = 0, level stride 1)
+  const bool uni = L.fstride == 0;
+  const int cst = uni ? 0 : 1, fst = uni ? 1 : LW;
   const S* cfac = rc ? rc + 4 * LW : sfac;
-  const S* cgam = rc ? rc + (4 + 3 * nl) * LW : sgam;
+  const S* cgam = cfac + 3 * fst * nl;
   for (int t = cl.rank; t < (nc + TW - 1) / TW; t += cl.G) {
     const int c0 = t * TW, w = min(TW, nc - c0);
     const Stage st{c0 - 2, w + 4, nc, P.periodic};
@@ -992,9 +1012,12 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
         }
       }
     }
-    // column data, factors lo | pc | inv and gamma (unless resident)
-    if (!rc)
-      staged_rows<16>(rgam + 1 - rcd, ww, [&](int rr, int lc) -> S {
+    // column data, factors lo | pc | inv and gamma (unless resident; a uniform level's one
+    // set: one value per thread, in the same batch)
+    if (!rc) {
+      const int nf = uni ? 3 * nl + 1 : 0;
+      const S fv = (int)threadIdx.x < nf ? uniform_factor(L, nl, threadIdx.x) : S(0);
+      staged_rows<16>((uni ? rfac : rgam + 1) - rcd, ww, [&](int rr, int lc) -> S {
         const int r = rr + rcd;
         const int c = c0 - 2 + lc;
         if (!st.has(c)) return (r < rfac) || (r >= rfac + 2 * nl && r < rgam) ? S(1) : S(0);
@@ -1008,10 +1031,12 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
         else if (r < rgam) sfac[(r - rfac) * LW + lc] = v;
         else sgam[lc] = v;
       });
+      if ((int)threadIdx.x < nf) sfac[threadIdx.x] = fv;
+    }
     __syncthreads();
     if (threadIdx.x < w + 4 && st.has(c0 - 2 + (int)threadIdx.x)) {
-      const int lc = threadIdx.x;
-      line_solve<S>(nz, cgam[lc], su + lc, LW, cfac + lc, cfac + LW * nl + lc, cfac + 2 * LW * nl + lc, LW);
+      const int lc = threadIdx.x, lf = lc * cst;
+      line_solve<S>(nz, cgam[lf], su + lc, LW, cfac + lf, cfac + fst * nl + lf, cfac + 2 * fst * nl + lf, fst);
     }
     __syncthreads();
     const S om = S(P.omega);
@@ -1046,8 +1071,9 @@ DEV void phase_down(const Problem& P, Cl& cl, int l, const S* f, S* u, S* fc, S*
 }
 
 // The line-solve constants (column data, factors, gamma) of this workgroup's tile of level l
-// (tile = rank), in the layout of the down pass's staging, into dst: kept in LDS through a
-// whole solve where the level has at most one tile per workgroup.
+// (tile = rank), in the layout of the down pass's staging (a uniform level: the column data
+// rows, then its one set of factors and gamma), into dst: kept in LDS through a whole solve
+// where the level has at most one tile per workgroup.
 template <class S, int TW>
 DEV void stage_resident(const Problem& P, const Cl& cl, int l, S* dst) {
   const Lv<S> L = level_view<S>(P, l);
@@ -1057,7 +1083,10 @@ DEV void stage_resident(const Problem& P, const Cl& cl, int l, S* dst) {
   const int c0 = cl.rank * TW, w = min(TW, nc - c0);
   const Stage st{c0 - 2, w + 4, nc, P.periodic};
   const int fsm = L.fstride ? L.fstride : 1;
-  staged_rows<16>(5 + 3 * nl, w + 4, [&](int r, int lc) -> S {
+  // a uniform level: column data over the window, then its one set of factors and gamma
+  const int nf = L.fstride == 0 ? 3 * nl + 1 : 0;
+  const S fv = (int)threadIdx.x < nf ? uniform_factor(L, nl, threadIdx.x) : S(0);
+  staged_rows<16>(nf ? 4 : 5 + 3 * nl, w + 4, [&](int r, int lc) -> S {
     const int c = c0 - 2 + lc;
     // outside the grid: column data and inverse pivots 1, the rest 0 (as the down pass)
     if (!st.has(c)) return (r < 4 || (r >= 4 + 2 * nl && r < 4 + 3 * nl)) ? S(1) : S(0);
@@ -1066,6 +1095,7 @@ DEV void stage_resident(const Problem& P, const Cl& cl, int l, S* dst) {
     if (r < 4 + 3 * nl) return L.flo[(r - 4) * fsm + (L.fstride ? cg : 0)];
     return L.fgam[L.fstride ? cg : 0];
   }, [&](int r, int lc, S v) { dst[r * LW + lc] = v; });
+  if ((int)threadIdx.x < nf) dst[4 * LW + threadIdx.x] = fv;
 }
 
 // fc = full weighting of f - M u (used when nu1 != 1)
