@@ -12,6 +12,8 @@ Modules, each following the passage it cites:
 * ``discretization`` grid, sigma-transform geometry (Sec. 2.1), the mixed-stage operator
                      with ghost-node Neumann rows (Sec. 3, discrete pressure and Neumann
                      equations) and the low-order still-water preconditioner operator
+* ``operator3d``    the mixed-stage operator on a (chi, gamma, sigma) grid (Sec. 2.1 in three
+                     dimensions, Sec. 3)
 * ``precond``       fixed preconditioners: vertical line Jacobi and an x-semicoarsening
                      V-cycle (the still-water preconditioner role of Sec. 3)
 * ``gmres``         left-preconditioned restarted GMRES (Saad & Schultz 1986, Sec. 3)
