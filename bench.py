@@ -100,6 +100,8 @@ def parse(argv=None):
                     help="serving: the one-at-a-time FP64 baseline solves every k-th simulation")
     ap.add_argument("--operator-probe", default="", metavar="WORKLOAD",
                     help="only apply the operator of WORKLOAD's first system 50 times and print its rate")
+    ap.add_argument("--operator3d-probe", default="", metavar="GRID",
+                    help="time only the three-dimensional operator kernel on a wave field, e.g. 513x513x17_p_p")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes five times (the "
                          "reference kernel that scales HBM counter readings)")
@@ -623,13 +625,48 @@ def operator_probe(name: str, reps: int = 50):
                       "ms_per_application": round(1e3 * dt, 4)}), flush=True)
 
 
+def operator3d_probe(name: str, reps: int = 50) -> dict:
+    """The three-dimensional operator kernel on a wave field: x and y resident in HBM, one
+    launch per application on the current stream, bracketed by HIP events (the geometry
+    kernel runs once, at set_surface). Algorithmic bytes per application: read x, write y."""
+    import torch
+    from paper_2511_18071_amd import binding as B
+    from paper_2511_18071_amd import workload as W
+    w = W.wave3d(name)
+    ep, ec, ps = w.system(0)
+    st = torch.cuda.current_stream()
+    x = torch.from_numpy(ps).cuda()
+    y = torch.empty_like(x)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+    with B.Operator3D(w.nx, w.ny, w.nz, w.bc_x, w.bc_y, w.length_x, w.length_y, w.depth(), stream=st) as op:
+        op.set_surface(ep, ec)
+        for _ in range(5):
+            op.apply(x, y)
+        op.sync()
+        for i in range(reps):
+            ev[2 * i].record(st)
+            op.apply(x, y)
+            ev[2 * i + 1].record(st)
+        op.sync()
+        wg = op.workgroups
+    ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps)]))
+    nbytes = 16.0 * w.n
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": name, "unknowns": w.n, "workgroups": wg, "launches": reps + 5,
+            "ms_per_application": round(ms, 5), "algorithmic_bytes": int(nbytes),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "gflops": round(170.0 * w.n / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: it measures the one-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
-    if args.operator_probe:
+    if args.operator3d_probe:
+        print(json.dumps({"operator3d_probe": operator3d_probe(args.operator3d_probe)}), flush=True)
+    elif args.operator_probe:
         operator_probe(args.operator_probe)
     elif args.copy_probe:
         copy_probe(args.copy_probe)

@@ -174,6 +174,48 @@ int sa_apply_operator(sa_problem* p, const double* x, double* y, int32_t mem);
 int sa_apply_operator_static(const sa_grid* grid, const double* h, const double* eta_prev, const double* eta_cur,
                              const double* x, double* y, void* hip_stream);
 
+/* ---- The mixed-stage operator on a three-dimensional grid -------------------------------
+ * Sec. 2.1 writes the sigma-transform for (chi, gamma, sigma) with d = h + eta over the plane
+ * and the push-forward grad = (d/dchi + sigma_x d/dsigma, d/dgamma + sigma_y d/dsigma,
+ * sigma_z d/dsigma); Sec. 3 couples two stages through grad^(i) . grad^(i-1) with ghost-node
+ * Neumann rows. The operator here is that product in composed first-derivative form (seven-point
+ * sixth-order stencils), with identity rows on the free surface and on nodes beyond two
+ * boundaries, the bed row n . grad^(i-1) p with n = (-h_chi, -h_gamma, -1) on the ghost level,
+ * and -+ the chi (gamma) component of grad^(i-1) p on the ghost columns (rows) beyond walls.
+ *
+ * Grid: nx, ny points in chi and gamma with both ends included (periodic: nx - 1 distinct
+ * columns, length_x = period; walls: one ghost column beyond each wall), nz sigma levels from
+ * bed to surface plus one ghost level below the bed. Vectors: n = (nz + 1) * nrow * ncol values,
+ * node (level j, row r, column c) at (j * nrow + r) * ncol + c, ncol = nx - 1 (periodic) or
+ * nx + 2 (walls), likewise nrow. Host plane arrays (h, eta): nyp x nxp values, chi fastest,
+ * physical points only (nx - 1 or nx per row). */
+typedef struct {
+  int32_t nx, ny;     /* points in chi and gamma, both ends included (>= 9 periodic, >= 7 walls) */
+  int32_t nz;         /* sigma levels bed..surface, 6 <= nz <= 65                             */
+  int32_t bc_x, bc_y; /* SA_PERIODIC | SA_WALLS per direction                                 */
+  double length_x, length_y;
+} sa_grid3;
+
+typedef struct sa_op3d sa_op3d;
+
+/* Tables and still-water depth (host h, copied) of one grid; device work is ordered on
+ * hip_stream (NULL = the default stream). SA_EARG for a bad grid, SA_EGEOM for h <= 0. */
+int sa_op3d_create(const sa_grid3* grid, const double* h, void* hip_stream, sa_op3d** out);
+/* Surfaces of the previous and the current stage (mem: SA_MEM_HOST, copied, checked at once:
+ * SA_EGEOM when h + eta <= 0 or non-finite; SA_MEM_DEVICE: read on the stream, a bad surface
+ * is reported by the next host-memory apply or sa_op3d_sync). Forms the geometry of both. */
+int sa_op3d_set_surface(sa_op3d* op, const double* eta_prev, const double* eta_cur, int32_t mem);
+/* y = A(eta_prev, eta_cur) x. SA_MEM_HOST: staged, waits, reports SA_EGEOM; SA_MEM_DEVICE:
+ * x and y are device arrays of n values, the kernel is enqueued and the call returns at once
+ * (x must stay alive and y untouched until the stream reaches it). */
+int sa_op3d_apply(sa_op3d* op, const double* x, double* y, int32_t mem);
+/* Waits for the stream; SA_EGEOM if a device surface was invalid (the surfaces must be set again). */
+int sa_op3d_sync(sa_op3d* op);
+int64_t sa_op3d_size(const sa_op3d* op);
+/* workgroups of one operator launch (tiles of 32 x 8 columns) */
+int sa_op3d_workgroups(const sa_op3d* op);
+void sa_op3d_destroy(sa_op3d* op);
+
 /* y = M^-1 x, the fixed still-water preconditioner of the problem. */
 int sa_apply_precond(sa_problem* p, const double* x, double* y, int32_t mem);
 

@@ -49,6 +49,11 @@ class SaSolveInfo(C.Structure):
     ]
 
 
+class SaGrid3(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc_x", C.c_int32), ("bc_y", C.c_int32),
+                ("length_x", C.c_double), ("length_y", C.c_double)]
+
+
 class SaServerOptions(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
                 ("unknowns_per_workgroup", C.c_int32), ("queue_admission", C.c_int32)]
@@ -132,6 +137,13 @@ def _load():
         "sa_build_info": (C.c_char_p, []),
         "sa_get_phase_times": (C.c_int, [P, D, C.c_int32]),
         "sa_problem_footprint": (C.c_int, [C.POINTER(SaGrid), D, C.POINTER(SaOptions), C.POINTER(C.c_int64)]),
+        "sa_op3d_create": (C.c_int, [C.POINTER(SaGrid3), D, P, C.POINTER(P)]),
+        "sa_op3d_set_surface": (C.c_int, [P, P, P, C.c_int32]),
+        "sa_op3d_apply": (C.c_int, [P, P, P, C.c_int32]),
+        "sa_op3d_sync": (C.c_int, [P]),
+        "sa_op3d_size": (C.c_int64, [P]),
+        "sa_op3d_workgroups": (C.c_int, [P]),
+        "sa_op3d_destroy": (None, [P]),
         "sa_server_default_options": (None, [C.POINTER(SaServerOptions)]),
         "sa_server_create": (C.c_int, [C.POINTER(SaServerOptions), P, C.POINTER(P)]),
         "sa_server_destroy": (None, [P]),
@@ -568,3 +580,73 @@ class Server:
         ptr, m, _ = _ptr(out, n)
         _check(lib.sa_get_solution(p, ptr, m))
         return out
+
+
+class Operator3D:
+    """The mixed-stage operator on a (chi, gamma, sigma) grid (see include/sawave.h, sa_op3d_*).
+
+    h, eta: plane arrays of the physical points (ny or ny - 1 rows of nx or nx - 1 values, chi
+    fastest); vectors: (nz + 1) x nrow x ncol values, chi fastest. numpy arrays are staged and
+    waited for; CUDA tensors are read and written on the operator's stream without waiting."""
+
+    def __init__(self, nx: int, ny: int, nz: int, bc_x: str, bc_y: str, length_x: float, length_y: float, h,
+                 stream=None):
+        code = lambda bc: SA_PERIODIC if bc == "periodic" else SA_WALLS
+        self.grid = SaGrid3(nx, ny, nz, code(bc_x), code(bc_y), float(length_x), float(length_y))
+        self.nxp = nx - 1 if bc_x == "periodic" else nx
+        self.nyp = ny - 1 if bc_y == "periodic" else ny
+        hh = np.ascontiguousarray(h, dtype=np.float64)
+        if hh.size != self.nxp * self.nyp:
+            raise ValueError(f"h must hold {self.nyp} x {self.nxp} values")
+        self._stream = _stream_handle(stream)
+        handle = C.c_void_p()
+        _check(lib.sa_op3d_create(C.byref(self.grid), hh.ctypes.data_as(C.POINTER(C.c_double)), self._stream,
+                                  C.byref(handle)))
+        self._h = handle
+        self.n = int(lib.sa_op3d_size(handle))
+        self.workgroups = int(lib.sa_op3d_workgroups(handle))
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sa_op3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_surface(self, eta_prev, eta_cur):
+        npl = self.nxp * self.nyp
+        pa, ma, ka = _ptr(eta_prev, npl)
+        pb, mb, kb = _ptr(eta_cur, npl)
+        if ma != mb:
+            raise ValueError("both surfaces must live in the same memory")
+        self._keep = [ka, kb]
+        _check(lib.sa_op3d_set_surface(self._h, pa, pb, ma))
+
+    def apply(self, x, y=None):
+        """y = A x; returns y (a new numpy array for numpy input)."""
+        px, mx, kx = _ptr(x, self.n)
+        if y is None:
+            if mx == SA_MEM_DEVICE:
+                raise ValueError("give y for device input")
+            y = np.empty(self.n)
+        py, my, ky = _ptr(y, self.n)
+        if mx != my:
+            raise ValueError("x and y must live in the same memory")
+        _check(lib.sa_op3d_apply(self._h, px, py, mx))
+        return y
+
+    def sync(self):
+        _check(lib.sa_op3d_sync(self._h))

@@ -413,3 +413,104 @@ def get(name: str, seed: int | None = None) -> Workload:
 
 
 NAMES = ("periodic_65x9", "bar_513x17", "periodic_16385x33", "tiny_17x7", "bar_65x9", "periodic_257x33")
+
+
+@dataclass
+class Wave3D:
+    """Seeded inputs of the three-dimensional operator: a wave field over a (chi, gamma) plane.
+
+    Plane arrays hold the physical points only (ny or ny - 1 rows of nx or nx - 1 values, chi
+    fastest); node (level j, row r, column c) of a vector sits at (j * nrow + r) * ncol + c with
+    the grid conventions of the two-dimensional workloads applied in both directions. The depth
+    is a flat bed (periodic directions) or a shoal rising across the walls, the surface a sum
+    of oblique harmonics with random phases translating at their linear phase speed, and the
+    vector a manufactured pressure of the two-dimensional form with the plane's surface."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    bc_x: str
+    bc_y: str
+    length_x: float
+    length_y: float
+    seed: int
+    amplitude: float = 0.02
+    nharm: int = 4
+
+    def _n(self, m, bc):
+        return m - 1 if bc == "periodic" else m
+
+    @property
+    def ncol(self) -> int:
+        return self.nx - 1 if self.bc_x == "periodic" else self.nx + 2
+
+    @property
+    def nrow(self) -> int:
+        return self.ny - 1 if self.bc_y == "periodic" else self.ny + 2
+
+    @property
+    def n(self) -> int:
+        return self.ncol * self.nrow * (self.nz + 1)
+
+    def _axes(self, ghosts: bool):
+        dx = self.length_x / (self.nx - 1)
+        dy = self.length_y / (self.ny - 1)
+        if ghosts:
+            xc = np.arange(self.ncol) * dx if self.bc_x == "periodic" else (np.arange(self.ncol) - 1) * dx
+            yc = np.arange(self.nrow) * dy if self.bc_y == "periodic" else (np.arange(self.nrow) - 1) * dy
+        else:
+            xc = np.arange(self._n(self.nx, self.bc_x)) * dx
+            yc = np.arange(self._n(self.ny, self.bc_y)) * dy
+        return np.meshgrid(xc, yc)  # (rows, cols)
+
+    def depth(self, ghosts: bool = False) -> np.ndarray:
+        X, Y = self._axes(ghosts)
+        h = np.ones_like(X)
+        if self.bc_x == "walls":
+            h = h - 0.3 * np.exp(-((X - 0.6 * self.length_x) / (0.15 * self.length_x)) ** 2)
+        if self.bc_y == "walls":
+            h = h - 0.2 * np.cos(np.pi * Y / self.length_y) ** 2
+        return h
+
+    def _modes(self):
+        rng = np.random.default_rng(self.seed)
+        kx = 2 * np.pi / self.length_x * rng.integers(1, 4, self.nharm)
+        ky = 2 * np.pi / self.length_y * rng.integers(-3, 4, self.nharm)
+        amp = self.amplitude * 0.6 ** np.arange(self.nharm)
+        ph = rng.uniform(0, 2 * np.pi, self.nharm)
+        return kx, ky, amp, ph
+
+    def surface(self, tau: float, ghosts: bool = False) -> np.ndarray:
+        X, Y = self._axes(ghosts)
+        kx, ky, amp, ph = self._modes()
+        eta = np.zeros_like(X)
+        for a, b, c, p in zip(kx, ky, amp, ph):
+            k = math.hypot(a, b)
+            om = math.sqrt(G * k * math.tanh(k))
+            eta += c * np.cos(a * X + b * Y - om * tau + p)
+        return eta
+
+    def pressure(self, tau: float) -> np.ndarray:
+        eta = self.surface(tau, ghosts=True)
+        d = self.depth(ghosts=True) + eta
+        sig = (np.arange(self.nz + 1) - 1.0) / (self.nz - 1)
+        kap = 2 * np.pi / self.length_x
+        s = sig[:, None, None]
+        p = G * eta[None] * (1 - s) * np.cosh(kap * s * d[None]) / np.cosh(kap * d[None])
+        return p.reshape(-1)
+
+    def system(self, s: int, dtau: float = 0.01):
+        """(eta_prev, eta_cur, p*) of system s: surfaces at s dtau and (s + 1/2) dtau."""
+        t0, t1 = s * dtau, (s + 0.5) * dtau
+        return self.surface(t0), self.surface(t1), self.pressure(t1)
+
+
+def wave3d(name: str, seed: int = 11) -> Wave3D:
+    """Named inputs of the three-dimensional operator: 'NXxNYxNZ_bcx_bcy' (bc: p periodic,
+    w walls), e.g. the benchmark's '513x513x17_p_p' (4.7 M unknowns)."""
+    dims, bx, by = name.split("_")
+    nx, ny, nz = (int(v) for v in dims.split("x"))
+    bc = {"p": "periodic", "w": "walls"}
+    lx = 2 * np.pi * 8 if bx == "p" else 10.0
+    ly = 2 * np.pi * 8 if by == "p" else 10.0
+    return Wave3D(name, nx, ny, nz, bc[bx], bc[by], lx, ly, seed)
