@@ -146,11 +146,15 @@ class VCycle:
 
 def make(grid: Grid, h_phys, kind: str = "mg", nu1: int = 1, nu2: int = 1, omega: float = 0.5,
          max_levels: int = 32, coarse_max: int = COARSE_MAX):
-    """The fixed map M^-1 of a simulation: 'none', 'line' (nu1 sweeps) or 'mg'."""
+    """The fixed map M^-1 of a simulation: 'none', 'line' (nu1 sweeps), 'mg' or 'ilu0' (the
+    paper's incomplete LU of the sixth-order operator at still water, oracle/ilu.py)."""
     if kind == "none":
         return lambda v: np.array(v, dtype=np.float64, copy=True)
     if kind == "line":
         return LineJacobi(grid, low_order_operator(grid, h_phys), nu1, omega)
     if kind == "mg":
         return VCycle(grid, h_phys, nu1, nu2, omega, max_levels, coarse_max)
+    if kind == "ilu0":
+        from .ilu import ILU0
+        return ILU0(grid, h_phys)
     raise ValueError(kind)

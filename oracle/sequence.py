@@ -28,7 +28,7 @@ class Options:
     restart: int = 30
     max_restarts: int = 200
     rtol: float = 1e-8
-    precond: str = "mg"  # none | line | mg
+    precond: str = "mg"  # none | line | mg | ilu0
     nu1: int = 1
     nu2: int = 1
     omega: float = 0.5
