@@ -9,7 +9,10 @@ in the natural ordering of the unknowns (level-major, chi fastest).
 
 ILU(0) (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Sec. 10.3): a unit lower
 triangular L and an upper triangular U whose non-zero patterns are the strictly lower and the
-upper part of A's pattern, such that (L U)_ij = a_ij wherever a_ij is in A's pattern. Computed
+upper part of A's pattern, such that (L U)_ij = a_ij wherever a_ij is in A's pattern.
+Reading: A's pattern is structural, every node pair the composed seven-point stencils couple
+(a coefficient that vanishes at still water, such as sigma_x on a flat bed or at the surface,
+keeps its place), so that the factorisation does not depend on which sums cancel in rounding. Computed
 row by row (the IKJ order): for row i and each k < i in the row's pattern, in increasing k,
 l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for every j > k of row k that is in row i's
 pattern. The map applied is z = U^-1 (L^-1 v) by forward and backward substitution.
@@ -25,16 +28,51 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .discretization import Grid, mixed_stage_operator
+from .discretization import Grid, _assemble, mixed_stage_operator
+from .fd import diff_matrix
 
 
-def ilu0(a: sp.spmatrix):
-    """(L, U) of ILU(0): L unit lower (diagonal stored), U upper, both CSR on A's pattern."""
+def structural_pattern(grid: Grid, width: int = 7) -> sp.csr_matrix:
+    """Every (row, column) the composed operator's stencils reach, as a 0/1 CSR matrix: the
+    mixed-stage form of discretization.mixed_stage_operator with every weight and coefficient
+    replaced by one (no sum can cancel)."""
+    def ones(m):
+        m = sp.csr_matrix(m, copy=True)
+        m.data[:] = 1.0
+        return m
+    dx = grid.along_x(ones(diff_matrix(grid.ncol, grid.dx, 1, width, grid.periodic)))
+    ds = grid.along_sigma(ones(diff_matrix(grid.nl, grid.dsig, 1, width, False)))
+    gchi = dx + ds
+    pde = dx @ gchi + ds @ gchi + ds @ ds
+    a = abs(_assemble(grid, pde, gchi, ds, np.ones(grid.ncol)))
+    a.data[:] = 1.0
+    a.sort_indices()
+    return a
+
+
+def ilu0(a: sp.spmatrix, pattern: sp.spmatrix | None = None):
+    """(L, U) of ILU(0): L unit lower (diagonal stored), U upper, both CSR on the pattern
+    (A's stored entries when none is given; a given pattern must contain them)."""
     a = sp.csr_matrix(a, dtype=np.float64, copy=True)
     a.sum_duplicates()
     a.sort_indices()
     n = a.shape[0]
-    ptr, ind, val = a.indptr, a.indices, a.data
+    if pattern is not None:
+        p = sp.csr_matrix(pattern, copy=True)
+        p.sort_indices()
+        ptr, ind = p.indptr.astype(np.int64), p.indices.astype(np.int64)
+        val = np.zeros(ind.size)
+        where = np.full(n, -1, dtype=np.int64)
+        for i in range(n):
+            where[ind[ptr[i]:ptr[i + 1]]] = np.arange(ptr[i], ptr[i + 1])
+            cols = a.indices[a.indptr[i]:a.indptr[i + 1]]
+            pos = where[cols]
+            if np.any(pos < 0):
+                raise ValueError(f"row {i} of A reaches outside the pattern")
+            val[pos] = a.data[a.indptr[i]:a.indptr[i + 1]]
+            where[ind[ptr[i]:ptr[i + 1]]] = -1
+    else:
+        ptr, ind, val = a.indptr, a.indices, a.data
     diag = np.empty(n, dtype=np.int64)
     for i in range(n):
         row = ind[ptr[i]:ptr[i + 1]]
@@ -73,7 +111,8 @@ class ILU0:
     def __init__(self, grid: Grid, h_phys):
         zero = np.zeros(grid.nx - 1 if grid.periodic else grid.nx)
         self.a = mixed_stage_operator(grid, h_phys, zero, zero)
-        self.L, self.U = ilu0(self.a)
+        self.pattern = structural_pattern(grid)
+        self.L, self.U = ilu0(self.a, self.pattern)
 
     def __call__(self, v):
         y = spla.spsolve_triangular(self.L, np.asarray(v, dtype=np.float64), lower=True, unit_diagonal=True)

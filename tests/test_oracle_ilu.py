@@ -4,7 +4,7 @@
   ILU(0) is the exact LU factorisation without pivoting, computed here by the textbook dense
   Doolittle recurrence.
 * On the sixth-order still-water operator of the solver (the factorisation the solver uses),
-  (L U)_ij = a_ij at every (i, j) of A's pattern (Saad, Sec. 10.3), L is unit lower
+  (L U)_ij = a_ij at every (i, j) of A's structural pattern (Saad, Sec. 10.3), L is unit lower
   triangular and U upper triangular inside the pattern, and the entries of L U outside the
   pattern (the dropped fill) are not all zero, so the factorisation really is incomplete.
 * The map solves (L U) z = v.
@@ -60,8 +60,8 @@ def test_still_water_factorisation_matches_a_on_its_pattern(name):
     L, U = m.L, m.U
     assert abs(sp.tril(L, -1) - (L - sp.identity(g.n))).max() == 0.0 and np.all(L.diagonal() == 1.0)
     assert abs(sp.triu(U) - U).max() == 0.0
-    pat = a.copy()
-    pat.data[:] = 1.0
+    pat = m.pattern
+    assert (abs(a) - abs(a).multiply(pat)).nnz == 0  # the structural pattern holds A's entries
     # L and U stay inside A's pattern
     assert (sp.csr_matrix(abs(L - sp.identity(g.n))) - sp.csr_matrix(abs(L - sp.identity(g.n))).multiply(pat)).nnz == 0
     assert (sp.csr_matrix(abs(U)) - sp.csr_matrix(abs(U)).multiply(pat)).nnz == 0
