@@ -411,6 +411,21 @@ def run_main(args):
             "solution_diff_fp32_vs_fp64_max": float(dx.max()), "solution_diff_fp32_vs_fp64_median": float(np.median(dx)),
             "steps": 20, "warmup": 5, "cluster_workgroups": Gb}
         say("  precision leg done")
+        # the paper's preconditioner: ILU(0) of the sixth-order operator at still water (one
+        # workgroup, level-scheduled substitutions) against the V-cycle, same systems, at the
+        # benchmark's rtol 1e-8 and at the paper's bar tolerance 1e-4
+        ilu = {}
+        for rt in (w.rtol if w.name == "bar_513x17" else 1e-8, 1e-4):
+            row = {}
+            for pc in ("ilu0", "mg"):
+                for mode in ("ewma", "previous"):
+                    r = run_sequence(B, wb, e2, b2, p2, mode, 5, 20, Gb, precond=pc, rtol=rt)
+                    row[f"{pc}_{mode}"] = {"value": round(100 / r["wall"], 3), "iters_per_solve": its(r),
+                                           "failed_solves": r["failed"]}
+            ilu[f"rtol_{rt:g}"] = row
+        out["ilu0_bar_513x17"] = dict(ilu, steps=20, warmup=5, cluster_workgroups_ilu0=1,
+                                      cluster_workgroups_mg=Gb)
+        say("  ILU(0) leg done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, x0, info0)
     print(json.dumps(out), flush=True)

@@ -61,7 +61,7 @@ enum {
 };
 
 enum { SA_PERIODIC = 0, SA_WALLS = 1 };
-enum { SA_PC_NONE = 0, SA_PC_LINE = 1, SA_PC_MG = 2 };
+enum { SA_PC_NONE = 0, SA_PC_LINE = 1, SA_PC_MG = 2, SA_PC_ILU0 = 3 };
 enum { SA_GUESS_COLD = 0, SA_GUESS_PREVIOUS = 1, SA_GUESS_EWMA = 2, SA_GUESS_RANGE = 3 };
 enum { SA_FP64 = 0, SA_FP32_IR = 1 };
 enum { SA_MEM_HOST = 0, SA_MEM_DEVICE = 1 };
@@ -79,7 +79,11 @@ typedef struct {
   int32_t restart;      /* GMRES restart length m (1..64), default 30                      */
   int32_t max_restarts; /* default 200                                                     */
   double rtol;          /* true relative residual ||b - A x|| / ||b||, default 1e-8         */
-  int32_t precond;      /* SA_PC_*, default SA_PC_MG                                       */
+  int32_t precond;      /* SA_PC_*, default SA_PC_MG. SA_PC_ILU0: the paper's preconditioner */
+                        /* (Sec. 3): ILU(0) of the sixth-order operator at eta = 0 on its   */
+                        /* structural pattern, factored on the host at creation, applied   */
+                        /* by level-scheduled substitution on one workgroup (cluster forced */
+                        /* to 1; FP64 only: SA_EARG with SA_FP32_IR)                        */
   int32_t nu1, nu2;     /* smoothing sweeps (MG) / sweeps (LINE: nu1), default 1, 1        */
   double omega;         /* line-Jacobi damping, default 0.5                                */
   int32_t max_levels;   /* MG levels including the finest, default 32 (as deep as possible)*/

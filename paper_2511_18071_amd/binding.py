@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsawave.so")
 SA_OK, SA_NOCONV = 0, 1
 SA_EBUSY = -7
 SA_PERIODIC, SA_WALLS = 0, 1
-SA_PC = {"none": 0, "line": 1, "mg": 2}
+SA_PC = {"none": 0, "line": 1, "mg": 2, "ilu0": 3}
 SA_GUESS = {"cold": 0, "previous": 1, "ewma": 2, "range": 3}
 SA_PRECISION = {"fp64": 0, "fp32_ir": 1}
 SA_MEM_HOST, SA_MEM_DEVICE = 0, 1

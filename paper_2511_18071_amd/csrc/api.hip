@@ -1,6 +1,7 @@
 // C ABI of the solver library (declared in include/sawave.h): problem set-up, buffer
 // ownership, kernel launches and the per-solve report log.
 #include "host.h"
+#include "ilu.h"
 
 using namespace sa;
 
@@ -173,7 +174,9 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   if (opt.restart < 1 || opt.restart > MMAX) return sa_fail(SA_EARG, "sa_create: restart must be in [1, %d]", MMAX);
   if (opt.max_restarts < 0) return sa_fail(SA_EARG, "sa_create: max_restarts < 0");
   if (!(opt.rtol >= 0.0)) return sa_fail(SA_EARG, "sa_create: rtol must be >= 0");
-  if (opt.precond < SA_PC_NONE || opt.precond > SA_PC_MG) return sa_fail(SA_EARG, "sa_create: unknown precond");
+  if (opt.precond < SA_PC_NONE || opt.precond > SA_PC_ILU0) return sa_fail(SA_EARG, "sa_create: unknown precond");
+  if (opt.precond == SA_PC_ILU0 && opt.precision != SA_FP64)
+    return sa_fail(SA_EARG, "sa_create: the ILU(0) preconditioner runs in FP64 only");
   if (opt.nu1 < 0 || opt.nu2 < 0 || opt.nu1 > 8 || opt.nu2 > 8) return sa_fail(SA_EARG, "sa_create: sweeps in [0, 8]");
   if (opt.precond == SA_PC_LINE && opt.nu1 < 1) return sa_fail(SA_EARG, "sa_create: line preconditioner needs nu1 >= 1");
   if (opt.guess < SA_GUESS_COLD || opt.guess > SA_GUESS_RANGE) return sa_fail(SA_EARG, "sa_create: unknown guess mode");
@@ -212,6 +215,15 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   operator_tables(ncol, nl, nphys, periodic, dx, dsig, h, tb);
   const std::vector<double>&wsig = tb.wsig, &wchi = tb.wchi, &sig = tb.sig, &hext = tb.hext, &hchi = tb.hchi;
   const std::vector<int>& ssig = tb.ssig;
+  IluFactors ilu;
+  if (opt.precond == SA_PC_ILU0) {
+    const int rc = ilu_still_water(ncol, nl, periodic, tb, ilu);
+    if (rc != 0) {
+      delete p;
+      return sa_fail(SA_EARG, "sa_create: ILU(0) of the still-water operator failed (%s)",
+                     rc == -1 ? "missing diagonal" : "zero pivot");
+    }
+  }
 
   // ---- still-water hierarchy
   struct HL { int nx, ncol; double dx; std::vector<double> h, ih, hx, hxx, fpc, finv, flo, fgam; int fstride; };
@@ -277,6 +289,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   // cluster sums spread their loads over the workgroup and the coarse V-cycle levels meet
   // at sub-cluster barriers, so the whole chip pays on the large grids)
   if (G <= 0) G = (ncol + 31) / 32 < 256 ? (ncol + 31) / 32 : 256;
+  if (opt.precond == SA_PC_ILU0) G = 1;  // the substitutions run on one workgroup
   hipDeviceProp_t prop{};
   if (!bytes_only && hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
     delete p;
@@ -396,6 +409,13 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   const size_t o_part = take((size_t)2 * (G + 1) * PSTRIDE * 8), o_bar = take(64 * (1 + MAXLEV)), o_flags = take(NFLAGS * 4),
                o_log = take(LOGCAP * sizeof(sa_solve_info)), o_b = take((size_t)n * 8), o_eta = take(2 * (size_t)nphys * 8),
                o_prob = take(sizeof(Problem)), o_prof = take(NPROF * 8);
+  const bool il = opt.precond == SA_PC_ILU0;
+  const size_t o_ilp = take(il ? (size_t)(n + 1) * 4 : 8), o_ilc = take(il ? ilu.lcol.size() * 4 : 8),
+               o_ilv = take(il ? ilu.lval.size() * 8 : 8), o_iup = take(il ? (size_t)(n + 1) * 4 : 8),
+               o_iuc = take(il ? ilu.ucol.size() * 4 : 8), o_iuv = take(il ? ilu.uval.size() * 8 : 8),
+               o_idi = take(il ? (size_t)n * 8 : 8), o_ifp = take(il ? ilu.fptr.size() * 4 : 8),
+               o_ifr = take(il ? (size_t)n * 4 : 8), o_ibp = take(il ? ilu.bptr.size() * 4 : 8),
+               o_ibr = take(il ? (size_t)n * 4 : 8);
   p->arena_bytes = off;
   if (bytes_only) {
     *bytes_only = (int64_t)off;
@@ -446,6 +466,19 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     if (e == hipSuccess) e = up(o_fgam[l], levs[l].fgam.data(), levs[l].fgam.size() * 8);
   }
   if (e == hipSuccess && !cinv.empty()) e = up(o_cinv, cinv.data(), cinv.size() * 8);
+  if (il) {
+    if (e == hipSuccess) e = up(o_ilp, ilu.lptr.data(), ilu.lptr.size() * 4);
+    if (e == hipSuccess && !ilu.lcol.empty()) e = up(o_ilc, ilu.lcol.data(), ilu.lcol.size() * 4);
+    if (e == hipSuccess && !ilu.lval.empty()) e = up(o_ilv, ilu.lval.data(), ilu.lval.size() * 8);
+    if (e == hipSuccess) e = up(o_iup, ilu.uptr.data(), ilu.uptr.size() * 4);
+    if (e == hipSuccess && !ilu.ucol.empty()) e = up(o_iuc, ilu.ucol.data(), ilu.ucol.size() * 4);
+    if (e == hipSuccess && !ilu.uval.empty()) e = up(o_iuv, ilu.uval.data(), ilu.uval.size() * 8);
+    if (e == hipSuccess) e = up(o_idi, ilu.dinv.data(), ilu.dinv.size() * 8);
+    if (e == hipSuccess) e = up(o_ifp, ilu.fptr.data(), ilu.fptr.size() * 4);
+    if (e == hipSuccess) e = up(o_ifr, ilu.frows.data(), ilu.frows.size() * 4);
+    if (e == hipSuccess) e = up(o_ibp, ilu.bptr.data(), ilu.bptr.size() * 4);
+    if (e == hipSuccess) e = up(o_ibr, ilu.brows.data(), ilu.brows.size() * 4);
+  }
   if (ir) {
     auto up32 = [&](size_t o, const std::vector<double>& v) {
       std::vector<float> f(v.begin(), v.end());
@@ -493,6 +526,13 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
       L.f32 = L.u32 = L.o32 = nullptr;
     }
   }
+  P.ilu_lptr = (decltype(P.ilu_lptr))(A + o_ilp); P.ilu_lcol = (decltype(P.ilu_lcol))(A + o_ilc);
+  P.ilu_lval = (decltype(P.ilu_lval))(A + o_ilv); P.ilu_uptr = (decltype(P.ilu_uptr))(A + o_iup);
+  P.ilu_ucol = (decltype(P.ilu_ucol))(A + o_iuc); P.ilu_uval = (decltype(P.ilu_uval))(A + o_iuv);
+  P.ilu_dinv = (decltype(P.ilu_dinv))(A + o_idi); P.ilu_fptr = (decltype(P.ilu_fptr))(A + o_ifp);
+  P.ilu_frows = (decltype(P.ilu_frows))(A + o_ifr); P.ilu_bptr = (decltype(P.ilu_bptr))(A + o_ibp);
+  P.ilu_brows = (decltype(P.ilu_brows))(A + o_ibr);
+  P.ilu_nf = il ? ilu.nlev_f : 0; P.ilu_nb = il ? ilu.nlev_b : 0;
   P.cinv = (decltype(P.cinv))(A + o_cinv); P.cn = cn; P.cinv_rows = (cn + G - 1) / G <= CN_ROWS ? 1 : 0;
   P.cinv32 = ir ? (decltype(P.cinv32))(A + o_cinv32) : nullptr;
   P.V32 = ir ? (decltype(P.V32))(A + o_V32) : nullptr;

@@ -1381,6 +1381,36 @@ DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z
   return prev;
 }
 
+// z = U^-1 L^-1 v of the ILU(0) factors by level-scheduled substitution, on the rank-0
+// workgroup: the rows of one level are independent; a wave takes a row, its lanes the row's
+// entries, and a wave reduction in a fixed order gives the row's sum. Workgroup barriers
+// separate the levels. Arithmetic in FP64 whatever S is.
+template <class S>
+DEV void ilu_apply(const Problem& P, Cl& cl, const S* v, S* z) {
+  if (cl.rank != 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int l = 0; l < P.ilu_nf; ++l) {
+    for (int q = P.ilu_fptr[l] + wave; q < P.ilu_fptr[l + 1]; q += NWAVE) {
+      const int i = P.ilu_frows[q];
+      double s = 0.0;
+      for (int e = P.ilu_lptr[i] + lane; e < P.ilu_lptr[i + 1]; e += 64) s += P.ilu_lval[e] * (double)z[P.ilu_lcol[e]];
+      s = wave_sum(s);
+      if (lane == 0) z[i] = (S)((double)v[i] - s);
+    }
+    __syncthreads();
+  }
+  for (int l = 0; l < P.ilu_nb; ++l) {
+    for (int q = P.ilu_bptr[l] + wave; q < P.ilu_bptr[l + 1]; q += NWAVE) {
+      const int i = P.ilu_brows[q];
+      double s = 0.0;
+      for (int e = P.ilu_uptr[i] + lane; e < P.ilu_uptr[i + 1]; e += 64) s += P.ilu_uval[e] * (double)z[P.ilu_ucol[e]];
+      s = wave_sum(s);
+      if (lane == 0) z[i] = (S)(((double)z[i] - s) * P.ilu_dinv[i]);
+    }
+    __syncthreads();
+  }
+}
+
 // z = M^-1 v in precision S. v and z are level-0 vectors distinct from each other and from
 // the level-0 scratch (u, o of level 0). Levels from P.tail on (at most one tile wide) are
 // run by the rank-0 workgroup alone with workgroup barriers only. Ends with a cluster barrier.
@@ -1390,6 +1420,11 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
   const int n = P.n;
   if (P.pc == SA_PC_NONE) {
     phase_copy(P, cl, v, z, n);
+    csync(cl);
+    return;
+  }
+  if (P.pc == SA_PC_ILU0) {
+    ilu_apply<S>(P, cl, v, z);
     csync(cl);
     return;
   }

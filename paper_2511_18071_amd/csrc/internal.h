@@ -87,6 +87,20 @@ struct Problem {
   int pc, nu1, nu2, nlev, tail;   // tail: first level run by a single workgroup
   double omega;
   Level lev[MAXLEV];
+  // ILU(0) of the still-water operator (pc == SA_PC_ILU0): strictly lower L and strictly upper U
+  // by row, 1/u_ii, and the rows of each level of the forward and the backward substitution
+  const int SA_GLOBAL* ilu_lptr;
+  const int SA_GLOBAL* ilu_lcol;
+  const double SA_GLOBAL* ilu_lval;
+  const int SA_GLOBAL* ilu_uptr;
+  const int SA_GLOBAL* ilu_ucol;
+  const double SA_GLOBAL* ilu_uval;
+  const double SA_GLOBAL* ilu_dinv;
+  const int SA_GLOBAL* ilu_fptr;
+  const int SA_GLOBAL* ilu_frows;
+  const int SA_GLOBAL* ilu_bptr;
+  const int SA_GLOBAL* ilu_brows;
+  int ilu_nf, ilu_nb;
   const double SA_GLOBAL* cinv;        // dense inverse of the coarsest operator, cn x cn (layout: cinv_rows)
   const float SA_GLOBAL* cinv32;       // its FP32 rounding (refinement path)
   int cn;
