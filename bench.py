@@ -213,7 +213,7 @@ def run_sequence(B, w, etas, bs, ps, mode, warmup_steps, steps, G, xs=None, **op
     # forward error against the manufactured solution, per solve (after the timed region)
     err = ((xs[: nw + nt] - ps[: nw + nt]).norm(dim=1) / ps[: nw + nt].norm(dim=1)).cpu().numpy()
     all_infos = warm_infos + infos
-    bad = [i for i in infos if i.status != 0 or i.relres > w.rtol]
+    bad = [i for i in infos if i.status != 0 or i.relres > opts.get("rtol", w.rtol)]
     return dict(wall=wall, infos=infos, all_infos=all_infos, lat=lat[nw:], all_lat=lat, failed=len(bad),
                 err=err, nw=nw, xs=xs)
 

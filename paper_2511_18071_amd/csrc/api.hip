@@ -3,6 +3,8 @@
 #include "host.h"
 #include "ilu.h"
 
+static_assert(sa::ILU_SLOTS == 2 * sa::NWAVE, "an ILU(0) step holds two rows per wavefront");
+
 using namespace sa;
 
 static thread_local std::string g_err;
@@ -221,7 +223,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     if (rc != 0) {
       delete p;
       return sa_fail(SA_EARG, "sa_create: ILU(0) of the still-water operator failed (%s)",
-                     rc == -1 ? "missing diagonal" : "zero pivot");
+                     rc == -1 ? "missing diagonal" : rc == -2 ? "zero pivot" : "a factor row longer than 64");
     }
   }
 
@@ -310,6 +312,9 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   size_t need_pc = (size_t)5 * TMSh * nl + 5 * TMSh;
   if (opt.precond == SA_PC_MG && need_pc < (size_t)cn + BLOCK)
     need_pc = (size_t)cn + BLOCK;  // coarsest solve: f and partial sums
+  // ILU(0): z in the phase scratch during the substitutions where it fits
+  const bool ilu_lds = opt.precond == SA_PC_ILU0 && n <= ILU_LDS_MAX;
+  if (ilu_lds && need_pc < (size_t)n) need_pc = (size_t)n;
   auto big_of = [&](size_t need_gram) {
     size_t big = need_op;
     if (need_gram > big) big = need_gram;
@@ -410,12 +415,10 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
                o_log = take(LOGCAP * sizeof(sa_solve_info)), o_b = take((size_t)n * 8), o_eta = take(2 * (size_t)nphys * 8),
                o_prob = take(sizeof(Problem)), o_prof = take(NPROF * 8);
   const bool il = opt.precond == SA_PC_ILU0;
-  const size_t o_ilp = take(il ? (size_t)(n + 1) * 4 : 8), o_ilc = take(il ? ilu.lcol.size() * 4 : 8),
-               o_ilv = take(il ? ilu.lval.size() * 8 : 8), o_iup = take(il ? (size_t)(n + 1) * 4 : 8),
-               o_iuc = take(il ? ilu.ucol.size() * 4 : 8), o_iuv = take(il ? ilu.uval.size() * 8 : 8),
-               o_idi = take(il ? (size_t)n * 8 : 8), o_ifp = take(il ? ilu.fptr.size() * 4 : 8),
-               o_ifr = take(il ? (size_t)n * 4 : 8), o_ibp = take(il ? ilu.bptr.size() * 4 : 8),
-               o_ibr = take(il ? (size_t)n * 4 : 8);
+  const size_t o_ifr = take(il ? ilu.frow.size() * 4 : 8), o_ifc = take(il ? ilu.fcol.size() * 4 : 8),
+               o_ifv = take(il ? ilu.fval.size() * 8 : 8), o_ibr = take(il ? ilu.brow.size() * 4 : 8),
+               o_ibc = take(il ? ilu.bcol.size() * 4 : 8), o_ibv = take(il ? ilu.bval.size() * 8 : 8),
+               o_idi = take(il ? ilu.bdinv.size() * 8 : 8);
   p->arena_bytes = off;
   if (bytes_only) {
     *bytes_only = (int64_t)off;
@@ -467,17 +470,13 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   }
   if (e == hipSuccess && !cinv.empty()) e = up(o_cinv, cinv.data(), cinv.size() * 8);
   if (il) {
-    if (e == hipSuccess) e = up(o_ilp, ilu.lptr.data(), ilu.lptr.size() * 4);
-    if (e == hipSuccess && !ilu.lcol.empty()) e = up(o_ilc, ilu.lcol.data(), ilu.lcol.size() * 4);
-    if (e == hipSuccess && !ilu.lval.empty()) e = up(o_ilv, ilu.lval.data(), ilu.lval.size() * 8);
-    if (e == hipSuccess) e = up(o_iup, ilu.uptr.data(), ilu.uptr.size() * 4);
-    if (e == hipSuccess && !ilu.ucol.empty()) e = up(o_iuc, ilu.ucol.data(), ilu.ucol.size() * 4);
-    if (e == hipSuccess && !ilu.uval.empty()) e = up(o_iuv, ilu.uval.data(), ilu.uval.size() * 8);
-    if (e == hipSuccess) e = up(o_idi, ilu.dinv.data(), ilu.dinv.size() * 8);
-    if (e == hipSuccess) e = up(o_ifp, ilu.fptr.data(), ilu.fptr.size() * 4);
-    if (e == hipSuccess) e = up(o_ifr, ilu.frows.data(), ilu.frows.size() * 4);
-    if (e == hipSuccess) e = up(o_ibp, ilu.bptr.data(), ilu.bptr.size() * 4);
-    if (e == hipSuccess) e = up(o_ibr, ilu.brows.data(), ilu.brows.size() * 4);
+    if (e == hipSuccess) e = up(o_ifr, ilu.frow.data(), ilu.frow.size() * 4);
+    if (e == hipSuccess) e = up(o_ifc, ilu.fcol.data(), ilu.fcol.size() * 4);
+    if (e == hipSuccess) e = up(o_ifv, ilu.fval.data(), ilu.fval.size() * 8);
+    if (e == hipSuccess) e = up(o_ibr, ilu.brow.data(), ilu.brow.size() * 4);
+    if (e == hipSuccess) e = up(o_ibc, ilu.bcol.data(), ilu.bcol.size() * 4);
+    if (e == hipSuccess) e = up(o_ibv, ilu.bval.data(), ilu.bval.size() * 8);
+    if (e == hipSuccess) e = up(o_idi, ilu.bdinv.data(), ilu.bdinv.size() * 8);
   }
   if (ir) {
     auto up32 = [&](size_t o, const std::vector<double>& v) {
@@ -526,13 +525,12 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
       L.f32 = L.u32 = L.o32 = nullptr;
     }
   }
-  P.ilu_lptr = (decltype(P.ilu_lptr))(A + o_ilp); P.ilu_lcol = (decltype(P.ilu_lcol))(A + o_ilc);
-  P.ilu_lval = (decltype(P.ilu_lval))(A + o_ilv); P.ilu_uptr = (decltype(P.ilu_uptr))(A + o_iup);
-  P.ilu_ucol = (decltype(P.ilu_ucol))(A + o_iuc); P.ilu_uval = (decltype(P.ilu_uval))(A + o_iuv);
-  P.ilu_dinv = (decltype(P.ilu_dinv))(A + o_idi); P.ilu_fptr = (decltype(P.ilu_fptr))(A + o_ifp);
-  P.ilu_frows = (decltype(P.ilu_frows))(A + o_ifr); P.ilu_bptr = (decltype(P.ilu_bptr))(A + o_ibp);
-  P.ilu_brows = (decltype(P.ilu_brows))(A + o_ibr);
-  P.ilu_nf = il ? ilu.nlev_f : 0; P.ilu_nb = il ? ilu.nlev_b : 0;
+  P.ilu_frow = (decltype(P.ilu_frow))(A + o_ifr);
+  P.ilu_fcol = (decltype(P.ilu_fcol))(A + o_ifc); P.ilu_fval = (decltype(P.ilu_fval))(A + o_ifv);
+  P.ilu_brow = (decltype(P.ilu_brow))(A + o_ibr);
+  P.ilu_bcol = (decltype(P.ilu_bcol))(A + o_ibc); P.ilu_bval = (decltype(P.ilu_bval))(A + o_ibv);
+  P.ilu_dinv = (decltype(P.ilu_dinv))(A + o_idi);
+  P.ilu_nf = il ? ilu.nstep_f : 0; P.ilu_nb = il ? ilu.nstep_b : 0; P.ilu_lds = ilu_lds ? 1 : 0;
   P.cinv = (decltype(P.cinv))(A + o_cinv); P.cn = cn; P.cinv_rows = (cn + G - 1) / G <= CN_ROWS ? 1 : 0;
   P.cinv32 = ir ? (decltype(P.cinv32))(A + o_cinv32) : nullptr;
   P.V32 = ir ? (decltype(P.V32))(A + o_V32) : nullptr;

@@ -1382,33 +1382,92 @@ DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z
 }
 
 // z = U^-1 L^-1 v of the ILU(0) factors by level-scheduled substitution, on the rank-0
-// workgroup: the rows of one level are independent; a wave takes a row, its lanes the row's
-// entries, and a wave reduction in a fixed order gives the row's sum. Workgroup barriers
-// separate the levels. Arithmetic in FP64 whatever S is.
+// workgroup. A substitution is a sequence of steps of 16 independent rows (a level of the
+// schedule, or part of one); wave w takes slots w and w + 8 of a step, its lanes the row's
+// entries (one record of 64), and a wave reduction in a fixed order gives the row's sum.
+// Workgroup barriers separate the steps. A step's own work is short against a load's latency,
+// so each wave keeps the records of its two slots of the next three steps in registers, loaded
+// three steps before they are used; every address follows from the step number, and only the
+// reads of z wait on the step before. Arithmetic in FP64 whatever S is.
+
 template <class S>
-DEV void ilu_apply(const Problem& P, Cl& cl, const S* v, S* z) {
-  if (cl.rank != 0) return;
+DEV void ilu_sweep(int nstep, const int SA_GLOBAL* row, const int SA_GLOBAL* col, const double SA_GLOBAL* val,
+                   const double SA_GLOBAL* dinv, const S* v, S* z, double* zl) {
+  // zl: z in LDS (all n values), else z in global memory
+  auto zget = [&](int c) { return zl ? zl[c] : (double)z[c]; };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int l = 0; l < P.ilu_nf; ++l) {
-    for (int q = P.ilu_fptr[l] + wave; q < P.ilu_fptr[l + 1]; q += NWAVE) {
-      const int i = P.ilu_frows[q];
-      double s = 0.0;
-      for (int e = P.ilu_lptr[i] + lane; e < P.ilu_lptr[i + 1]; e += 64) s += P.ilu_lval[e] * (double)z[P.ilu_lcol[e]];
-      s = wave_sum(s);
-      if (lane == 0) z[i] = (S)((double)v[i] - s);
+  struct Rec { int r, c; double a, g; };  // row, this lane's column and value, the row's 1/u_ii
+  auto fetch = [&](int t, int k) {
+    Rec q{-1, -1, 0.0, 0.0};
+    if (t < nstep) {
+      const long s = (long)t * (2 * NWAVE) + wave + k * NWAVE;
+      q.r = row[s];
+      q.c = col[s * 64 + lane];
+      q.a = val[s * 64 + lane];
+      if (dinv) q.g = dinv[s];
     }
+    return q;
+  };
+  // forward: z_r = v_r - sum (v already copied into zl when z lives in LDS); backward:
+  // z_r = (z_r - sum) / u_rr
+  auto store = [&](const Rec& q, double sum) {
+    const double base = (dinv || zl) ? zget(q.r) : (double)v[q.r];
+    const double zr = dinv ? (base - sum) * q.g : base - sum;
+    if (zl) zl[q.r] = zr; else z[q.r] = (S)zr;
+  };
+  // the two rows of a step: both sums reduced side by side (one latency chain, not two);
+  // padding slots (row -1) are uniform over the wave and contribute zeros
+  auto finish2 = [&](const Rec& q0, const Rec& q1) {
+    double s0 = (q0.r >= 0 && q0.c >= 0) ? q0.a * zget(q0.c) : 0.0;
+    double s1 = (q1.r >= 0 && q1.c >= 0) ? q1.a * zget(q1.c) : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o, 64);
+      s1 += __shfl_xor(s1, o, 64);
+    }
+    if (lane == 0) {
+      if (q0.r >= 0) store(q0, s0);
+      if (q1.r >= 0) store(q1, s1);
+    }
+  };
+  // three register sets, step t in set t mod 3, refilled (by loads, never by copies: a copy
+  // would wait for the load) with step t + 3 right after step t is done
+  Rec a0 = fetch(0, 0), a1 = fetch(0, 1), b0 = fetch(1, 0), b1 = fetch(1, 1), c0 = fetch(2, 0), c1 = fetch(2, 1);
+  for (int t = 0; t < nstep; t += 3) {
+    finish2(a0, a1);
+    a0 = fetch(t + 3, 0);
+    a1 = fetch(t + 3, 1);
+    __syncthreads();
+    if (t + 1 < nstep) {
+      finish2(b0, b1);
+      b0 = fetch(t + 4, 0);
+      b1 = fetch(t + 4, 1);
+      __syncthreads();
+    }
+    if (t + 2 < nstep) {
+      finish2(c0, c1);
+      c0 = fetch(t + 5, 0);
+      c1 = fetch(t + 5, 1);
+      __syncthreads();
+    }
+  }
+}
+
+// lds: the phase scratch, at least n doubles when P.ilu_lds (z is then formed there and copied
+// out at the end). Not inlined: the solve kernels' register allocation for the V-cycle path
+// stays as without it.
+template <class S>
+__device__ __attribute__((noinline)) void ilu_apply(const Problem& P, Cl& cl, const S* v, S* z, S* lds) {
+  if (cl.rank != 0) return;
+  double* zl = P.ilu_lds ? reinterpret_cast<double*>(lds) : nullptr;
+  if (zl) {
+    for (int i = threadIdx.x; i < P.n; i += BLOCK) zl[i] = (double)v[i];
     __syncthreads();
   }
-  for (int l = 0; l < P.ilu_nb; ++l) {
-    for (int q = P.ilu_bptr[l] + wave; q < P.ilu_bptr[l + 1]; q += NWAVE) {
-      const int i = P.ilu_brows[q];
-      double s = 0.0;
-      for (int e = P.ilu_uptr[i] + lane; e < P.ilu_uptr[i + 1]; e += 64) s += P.ilu_uval[e] * (double)z[P.ilu_ucol[e]];
-      s = wave_sum(s);
-      if (lane == 0) z[i] = (S)(((double)z[i] - s) * P.ilu_dinv[i]);
-    }
-    __syncthreads();
-  }
+  ilu_sweep<S>(P.ilu_nf, P.ilu_frow, P.ilu_fcol, P.ilu_fval, nullptr, v, z, zl);
+  ilu_sweep<S>(P.ilu_nb, P.ilu_brow, P.ilu_bcol, P.ilu_bval, P.ilu_dinv, v, z, zl);
+  if (zl)
+    for (int i = threadIdx.x; i < P.n; i += BLOCK) z[i] = (S)zl[i];
 }
 
 // z = M^-1 v in precision S. v and z are level-0 vectors distinct from each other and from
@@ -1424,7 +1483,7 @@ DEV void precond(const Problem& P, Cl& cl, const S* v, S* z, S* lds, PhaseClock*
     return;
   }
   if (P.pc == SA_PC_ILU0) {
-    ilu_apply<S>(P, cl, v, z);
+    ilu_apply<S>(P, cl, v, z, lds);
     csync(cl);
     return;
   }

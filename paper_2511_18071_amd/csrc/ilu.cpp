@@ -16,7 +16,10 @@
 //
 // Level schedule: the forward solve of row i needs the rows k < i of its L pattern, so row i
 // goes one level after the deepest of them; the backward solve likewise over U from the last
-// row up. Rows of one level are independent.
+// row up. Rows of one level are independent. The device reads each substitution as steps of
+// ILU_SLOTS rows in level order (a level split over several steps where it has more rows), one
+// record of ILU_REC (column, value) pairs per row: every address follows from the step number,
+// so a wavefront loads the rows of later steps before the current step's results exist.
 #include <math.h>
 
 #include <algorithm>
@@ -164,6 +167,38 @@ int ilu_still_water(int ncol, int nl, int periodic, const OperatorTables& tb, Il
   };
   f.nlev_f = schedule(true, f.fptr, f.frows);
   f.nlev_b = schedule(false, f.bptr, f.brows);
+  // steps of ILU_SLOTS rows (a level with more rows takes several steps: its rows are
+  // independent), one record per row
+  auto pack = [&](int nlev, const std::vector<int>& lp, const std::vector<int>& rows, const std::vector<int>& p,
+                  const std::vector<int>& cidx, const std::vector<double>& v, int& nstep, std::vector<int>& srow,
+                  std::vector<int>& pc, std::vector<double>& pv) {
+    nstep = 0;
+    for (int l = 0; l < nlev; ++l) nstep += (lp[l + 1] - lp[l] + ILU_SLOTS - 1) / ILU_SLOTS;
+    const size_t slots = (size_t)nstep * ILU_SLOTS;
+    srow.assign(slots, -1);
+    pc.assign(slots * ILU_REC, -1);
+    pv.assign(slots * ILU_REC, 0.0);
+    size_t s = 0;
+    for (int l = 0; l < nlev; ++l) {
+      const int cnt = lp[l + 1] - lp[l];
+      for (int q = 0; q < cnt; ++q, ++s) {
+        const int i = rows[lp[l] + q];
+        if (p[i + 1] - p[i] > ILU_REC) return false;
+        srow[s] = i;
+        for (int e = p[i]; e < p[i + 1]; ++e) {
+          pc[s * ILU_REC + (e - p[i])] = cidx[e];
+          pv[s * ILU_REC + (e - p[i])] = v[e];
+        }
+      }
+      s = (s + ILU_SLOTS - 1) / ILU_SLOTS * ILU_SLOTS;  // the next level starts a new step
+    }
+    return true;
+  };
+  if (!pack(f.nlev_f, f.fptr, f.frows, f.lptr, f.lcol, f.lval, f.nstep_f, f.frow, f.fcol, f.fval)) return -3;
+  if (!pack(f.nlev_b, f.bptr, f.brows, f.uptr, f.ucol, f.uval, f.nstep_b, f.brow, f.bcol, f.bval)) return -3;
+  f.bdinv.assign(f.brow.size(), 0.0);
+  for (size_t s = 0; s < f.brow.size(); ++s)
+    if (f.brow[s] >= 0) f.bdinv[s] = f.dinv[f.brow[s]];
   return 0;
 }
 

@@ -28,6 +28,7 @@ constexpr int LOGCAP = 4096;      // solve reports kept on the device
 constexpr int COARSE_MAX = 4096;  // largest coarsest-grid size solved by a dense inverse
 constexpr int CN_ROWS = 16;       // at most this many coarse rows per workgroup: the inverse is kept row by row
 constexpr int KWIN = 32;          // largest window of the randomized range finder
+constexpr int ILU_LDS_MAX = 16384; // unknowns up to which the ILU(0) substitutions keep z in LDS
 
 // Flags written by kernels (device int array).
 enum { FLAG_GEOM = 0, FLAG_NONFINITE = 1, FLAG_ABORT = 2, NFLAGS = 4 };
@@ -87,20 +88,19 @@ struct Problem {
   int pc, nu1, nu2, nlev, tail;   // tail: first level run by a single workgroup
   double omega;
   Level lev[MAXLEV];
-  // ILU(0) of the still-water operator (pc == SA_PC_ILU0): strictly lower L and strictly upper U
-  // by row, 1/u_ii, and the rows of each level of the forward and the backward substitution
-  const int SA_GLOBAL* ilu_lptr;
-  const int SA_GLOBAL* ilu_lcol;
-  const double SA_GLOBAL* ilu_lval;
-  const int SA_GLOBAL* ilu_uptr;
-  const int SA_GLOBAL* ilu_ucol;
-  const double SA_GLOBAL* ilu_uval;
-  const double SA_GLOBAL* ilu_dinv;
-  const int SA_GLOBAL* ilu_fptr;
-  const int SA_GLOBAL* ilu_frows;
-  const int SA_GLOBAL* ilu_bptr;
-  const int SA_GLOBAL* ilu_brows;
-  int ilu_nf, ilu_nb;
+  // ILU(0) of the still-water operator (pc == SA_PC_ILU0), per substitution (f: forward over
+  // the strictly lower L, b: backward over the strictly upper U): steps of 16 independent rows
+  // in level order, slot s of step t = row[16 t + s] (-1: padding), one record of 64 (column,
+  // value) pairs per slot (column -1 past the row's end); 1/u_ii per backward slot
+  const int SA_GLOBAL* ilu_frow;
+  const int SA_GLOBAL* ilu_fcol;
+  const double SA_GLOBAL* ilu_fval;
+  const int SA_GLOBAL* ilu_brow;
+  const int SA_GLOBAL* ilu_bcol;
+  const double SA_GLOBAL* ilu_bval;
+  const double SA_GLOBAL* ilu_dinv;   // per backward slot
+  int ilu_nf, ilu_nb;        // steps of the two substitutions
+  int ilu_lds;               // 1: z lives in the phase scratch (LDS) during the substitutions
   const double SA_GLOBAL* cinv;        // dense inverse of the coarsest operator, cn x cn (layout: cinv_rows)
   const float SA_GLOBAL* cinv32;       // its FP32 rounding (refinement path)
   int cn;

@@ -12,9 +12,10 @@
 // along sigma from the xs of its own column at the seven levels of the sigma window.
 //
 // One workgroup owns a tile of 32 chi-columns x 8 gamma-rows and walks up its columns level by
-// level: x of each level is staged once into a ring of seven levels in LDS, xs of each level is
-// formed once and kept for seven levels, and the output of level j is written as soon as the
-// xs of the top of its sigma window exists. Every input is read from HBM once (the halo from
+// level: x of each level is staged once into a ring of seven levels in LDS (the first seven in
+// one batch of loads, then each level's loads issued a level ahead), xs of each level is formed
+// once and kept for seven levels, and the output of level j is written as soon as the xs of the
+// top of its sigma window exists. Every input is read from HBM once (the halo from
 // neighbours' tiles, mostly from the caches), y written once: the kernel is bound by HBM traffic
 // and by its FP64 arithmetic (about 85 fused multiply-adds per node).
 #include <hip/hip_runtime.h>
@@ -170,7 +171,11 @@ extern "C" __global__ void __launch_bounds__(NT3) sa_operator3_kernel(Op3 P, con
   const int t = threadIdx.x;
   const int ncol = P.ncol, nrow = P.nrow, nl = P.nl, nz = P.nz;
   const long long np = P.nplane;
-  const int bx = blockIdx.x % P.ntx, by = blockIdx.x / P.ntx;
+  // the hardware hands consecutive workgroups to the eight XCDs in turn: give each XCD a
+  // contiguous run of tiles, so that neighbouring tiles meet in its L2
+  const int nb = gridDim.x, xcd = blockIdx.x % 8, per = nb / 8, extra = nb % 8;
+  const int tile = xcd * per + min(xcd, extra) + blockIdx.x / 8;
+  const int bx = tile % P.ntx, by = tile / P.ntx;
   const int c0 = bx * T3X - P.c_shift, r0 = by * T3Y - P.r_shift;
 
   for (int i = t; i < nl * 7; i += NT3) wsig[i] = P.wsig[i];
@@ -235,23 +240,43 @@ extern "C" __global__ void __launch_bounds__(NT3) sa_operator3_kernel(Op3 P, con
 
   const int rect_t = (tr + 3) * RW + tc + 3;
   const int rect_h = (hr + 3) * RW + hc + 3;
-  // level 0 of the input, in registers
-  double pre_t = tile_ok ? x[tplane] : 0.0;
-  double pre_h = halo_ok ? x[hplane] : 0.0;
+  // the first seven levels (the window of the first outputs, nl >= 7) in one batch of loads,
+  // the arms of level 0 with them
+  {
+    double pt[RING], ph[RING];
+#pragma unroll
+    for (int m = 0; m < RING; ++m) {
+      pt[m] = tile_ok ? x[(long long)m * np + tplane] : 0.0;
+      ph[m] = halo_ok ? x[(long long)m * np + hplane] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < RING; ++m) {
+      XR[m * (RH * RW) + rect_t] = pt[m];
+      if (t < NHALO) XR[m * (RH * RW) + rect_h] = ph[m];
+    }
+  }
+  double arm_next = arm_ok ? x[aplane] : 0.0;  // arms of the next level w to be formed
+  double pre_t = 0.0, pre_h = 0.0;              // the level after the staged ones
+  if (nl > RING) {
+    pre_t = tile_ok ? x[(long long)RING * np + tplane] : 0.0;
+    pre_h = halo_ok ? x[(long long)RING * np + hplane] : 0.0;
+  }
   int next_w = 0, next_j = 0;
   __syncthreads();
 
-  for (int lt = 0; lt < nl; ++lt) {
-    // stage level lt, then start the loads of level lt + 1
-    double* xr = XR + (lt % RING) * (RH * RW);
-    xr[rect_t] = pre_t;
-    if (t < NHALO) xr[rect_h] = pre_h;
-    if (lt + 1 < nl) {
-      const long long off = (long long)(lt + 1) * np;
-      pre_t = tile_ok ? x[off + tplane] : 0.0;
-      pre_h = halo_ok ? x[off + hplane] : 0.0;
+  for (int lt = RING - 1; lt < nl; ++lt) {
+    if (lt >= RING) {
+      // stage level lt, then start the loads of level lt + 1
+      double* xr = XR + (lt % RING) * (RH * RW);
+      xr[rect_t] = pre_t;
+      if (t < NHALO) xr[rect_h] = pre_h;
+      if (lt + 1 < nl) {
+        const long long off = (long long)(lt + 1) * np;
+        pre_t = tile_ok ? x[off + tplane] : 0.0;
+        pre_h = halo_ok ? x[off + hplane] : 0.0;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     while (next_w < nl && win_top(next_w, nl) == lt) {
       const int w = next_w++;
       // xs = D_sig x at level w over the tile and its three-column halo; x of the arms
@@ -268,8 +293,9 @@ extern "C" __global__ void __launch_bounds__(NT3) sa_operator3_kernel(Op3 P, con
         XSC[rect_t] = st;
         XSR[(w % RING) * NT3 + t] = st;
         if (t < NHALO) XSC[rect_h] = sh;
-        if (t < T3Y * 6) XAX[t] = arm_ok ? x[(long long)w * np + aplane] : 0.0;
-        else if (t < NHALO) XAY[t - T3Y * 6] = arm_ok ? x[(long long)w * np + aplane] : 0.0;
+        if (t < T3Y * 6) XAX[t] = arm_next;
+        else if (t < NHALO) XAY[t - T3Y * 6] = arm_next;
+        if (w + 1 < nl) arm_next = arm_ok ? x[(long long)(w + 1) * np + aplane] : 0.0;
       }
       __syncthreads();
       const double* xw = XR + (w % RING) * (RH * RW);
