@@ -940,6 +940,120 @@ DEV void phase_sweep(const Problem& P, Cl& cl, int l, const S* f, const S* uin, 
   }
 }
 
+// Two sweeps o = u1 + omega L^-1 (f - M u1), u1 = u + omega L^-1 (f - M u) in one pass, on a
+// periodic level whose columns share one set of line-solve constants: u (uin plus the
+// prolongated correction e) is staged with two columns each side, the first sweep runs on the
+// tile and one column each side, the second on the tile. The first sweep's halo columns repeat
+// the arithmetic of the neighbouring tiles' own first sweep, so o is the two-pass result bit for
+// bit, one pass and one barrier sooner. rc: the workgroup's resident block of this level (the
+// down pass's layout: columns c0 - 2 .. c0 + w + 1, the shared factors and gamma after them).
+template <class S, int TW = TM>
+DEV void phase_sweep2(const Problem& P, Cl& cl, int l, const S* f, const S* uin, const S* e, S* o, S* lds,
+                      const S* rc = nullptr) {
+  const Lv<S> L = level_view<S>(P, l);
+  const int nc = L.nc, nl = P.nl, nz = P.nz;
+  const int ncc = e ? P.lev[l + 1].ncol : 0;
+  constexpr int LW = TW + 4;   // u and column data: columns c0 - 2 .. c0 + w + 1
+  constexpr int LF = TW + 2;   // f and the residual: columns c0 - 1 .. c0 + w
+  S* su = lds;                 // LW x nl
+  S* sf = su + LW * nl;        // LF x nl
+  S* sr = sf + LF * nl;        // LF x nl
+  S* scd = sr + LF * nl;       // 4 x LW
+  S* sfac = scd + 4 * LW;      // 3 nl + 1: lo | pc | inv, gamma
+  const S* ccd = rc ? rc : scd;
+  const S* cfac = rc ? rc + 4 * LW : sfac;
+  const S om = S(P.omega);
+  for (int t = cl.rank; t < (nc + TW - 1) / TW; t += cl.G) {
+    const int c0 = t * TW, w = min(TW, nc - c0);
+    const int ww = w + 4;
+    // u (with the prolongated correction) over the two-column halo, f over the one-column
+    // halo: each thread owns one column of the rows it stages
+    {
+      const int RP = BLOCK / ww;
+      const int lc = threadIdx.x % ww, r0 = threadIdx.x / ww;
+      if (r0 < RP) {
+        const int cg = wrapc(c0 - 2 + lc, nc);
+        const bool fo = lc >= 1 && lc <= w + 2;
+        int i0 = 0, i1 = 0;
+        bool odd = false;
+        if (e) prolong_cols(P, nc, ncc, cg, i0, i1, odd);
+        constexpr int U = 3;
+        for (int rb = r0; rb < nl; rb += U * RP) {
+          S v[U], g[U];
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int r = rb + q * RP;
+            S tv = S(0);
+            if (r < nl) {
+              tv = uin ? uin[(size_t)r * nc + cg] : S(0);
+              if (e) {
+                const S* er = e + (size_t)r * ncc;
+                tv += odd ? S(0.5) * (er[i0] + er[i1]) : er[i0];
+              }
+            }
+            v[q] = tv;
+            g[q] = (fo && r < nl) ? f[(size_t)r * nc + cg] : S(0);
+          }
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int r = rb + q * RP;
+            if (r < nl) {
+              su[r * LW + lc] = v[q];
+              if (fo) sf[r * LF + lc - 1] = g[q];
+            }
+          }
+        }
+      }
+    }
+    if (!rc) {
+      // column data over the two-column halo and the one set of factors and gamma
+      const int nf = 3 * nl + 1;
+      const S fv = (int)threadIdx.x < nf ? uniform_factor(L, nl, threadIdx.x) : S(0);
+      staged_rows<16>(4, ww, [&](int q, int lc) -> S { return coldata(L, q, wrapc(c0 - 2 + lc, nc)); },
+                      [&](int q, int lc, S v) { scd[q * LW + lc] = v; });
+      if ((int)threadIdx.x < nf) sfac[threadIdx.x] = fv;
+    }
+    __syncthreads();
+    // first sweep on columns c0 - 1 .. c0 + w (unwrapped column cc sits at slot cc - c0 + 2)
+    {
+      auto U = [&](int cc, int jj) { return su[jj * LW + cc - c0 + 2]; };
+      auto CD = [&](int cc, int q) { return ccd[q * LW + cc - c0 + 2]; };
+      for (int i = threadIdx.x; i < LF * nl; i += BLOCK) {
+        const int j = i / LF, lf = i - j * LF;
+        if (lf < w + 2) sr[i] = sf[i] - m_apply<S>(P, nc, L.rdx, L.rds, S(1.0 - P.sig[j]), c0 - 1 + lf, j, U, CD);
+      }
+    }
+    __syncthreads();
+    const S gam = cfac[3 * nl];  // staged above (or resident)
+    if ((int)threadIdx.x < w + 2)
+      line_solve<S>(nz, gam, sr + threadIdx.x, LF, cfac, cfac + nl, cfac + 2 * nl, 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < LF * nl; i += BLOCK) {
+      const int j = i / LF, lf = i - j * LF;
+      if (lf < w + 2) su[j * LW + lf + 1] = su[j * LW + lf + 1] + om * sr[i];
+    }
+    __syncthreads();
+    // second sweep on the tile
+    {
+      auto U = [&](int cc, int jj) { return su[jj * LW + cc - c0 + 2]; };
+      auto CD = [&](int cc, int q) { return ccd[q * LW + cc - c0 + 2]; };
+      for (int i = threadIdx.x; i < LF * nl; i += BLOCK) {
+        const int j = i / LF, lf = i - j * LF;
+        if (lf >= 1 && lf <= w) sr[i] = sf[i] - m_apply<S>(P, nc, L.rdx, L.rds, S(1.0 - P.sig[j]), c0 - 1 + lf, j, U, CD);
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < w)
+      line_solve<S>(nz, gam, sr + threadIdx.x + 1, LF, cfac, cfac + nl, cfac + 2 * nl, 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < TW * nl; i += BLOCK) {
+      const int j = i / TW, lc = i - j * TW;
+      if (lc < w) o[(size_t)j * nc + c0 + lc] = su[j * LW + lc + 2] + om * sr[j * LF + lc + 1];
+    }
+    __syncthreads();
+  }
+}
+
 DEV void coarse_range(const Problem& P, int c0, int w, int nc, int ncc, int& Cfirst, int& Clast) {
   if (P.periodic) { Cfirst = (c0 + 1) / 2; Clast = (c0 + w - 1) / 2; return; }
   Cfirst = (c0 == 0) ? 0 : (c0 + 2) / 2;
@@ -1366,7 +1480,21 @@ DEV const S* mg_up(const Problem& P, Cl& cl, int l, const S* v, const S* e, S* z
   }
   const S* prev = A;
   const S* corr = e;
-  for (int s = 0; s < P.nu2; ++s) {
+  int s0 = 0;
+  // the first two post-sweeps in one pass on the cluster levels of a periodic problem whose
+  // columns share one set of factors (the output leaves A, which its neighbours still read)
+  if (P.nu2 >= 2 && P.periodic && L.fstride == 0 && parts >= 0 && cl.G > 1) {
+    S* nd = (l == 0 && P.nu2 == 2) ? z : B;
+    if (P.lev[l].tm == 32) phase_sweep2<S, 32>(P, cl, l, f, prev, corr, nd, lds, rc);
+    else phase_sweep2<S, TM>(P, cl, l, f, prev, corr, nd, lds, rc);
+    if (parts <= 0 || l == 0) csync(cl);
+    else if (P.nu2 > 2) lsync(cl, parts, l);
+    else lsync(cl, parts_up, l - 1);
+    prev = nd;
+    corr = nullptr;
+    s0 = 2;
+  }
+  for (int s = s0; s < P.nu2; ++s) {
     S* nd = (l == 0 && s == P.nu2 - 1) ? z : (prev == B ? A : B);
     if (P.lev[l].tm == 32) phase_sweep<S, 32>(P, cl, l, f, prev, corr, nd, lds, rc);
     else phase_sweep<S, TM>(P, cl, l, f, prev, corr, nd, lds, rc);
