@@ -21,6 +21,9 @@ Modules, each following the passage it cites:
 * ``rangefinder``   randomized range finder over a sliding window of solutions (Alg. 3)
 * ``rng``           the counter-based Gaussian stream that draws the sketch vectors
 * ``sequence``      the per-system driver: guess, solve, push the solution into the sketch
+* ``closedloop``    LSERK45 stepping of velocity and surface whose pressure systems feed the
+                     solver (Sec. 3, Alg. 1)
+* ``ilu``           ILU(0) of the still-water operator (Sec. 3's preconditioner)
 
 Parity status of each function is stated in its module header; a function without an
 independent pin says "parity unpinned".
