@@ -220,6 +220,28 @@ int64_t sa_op3d_size(const sa_op3d* op);
 int sa_op3d_workgroups(const sa_op3d* op);
 void sa_op3d_destroy(sa_op3d* op);
 
+/* ---- The closed loop (Sec. 3, Alg. 1) ---------------------------------------------------
+ * Low-storage Runge-Kutta (LSERK45) stepping of the velocity field (u, w) and the free surface
+ * of a periodic problem, whose mixed-stage pressure systems the problem then solves in sequence
+ * (with its options: guess, preconditioner, tolerance). Per stage, with rho = 1, no viscosity
+ * and gravity g = 9.81: the surface advances by the kinematic condition w - u D_chi eta; the
+ * right-hand side is grad^(i) . Q on the PDE rows, n . Q at the bed (n = (-h_chi, -1)) and 0 on
+ * the surface, Q = u / (beta_i dtau) + alpha_i K_u / dtau + F - (u . grad^(i-1)) u
+ * + (sigma / d^(i-1)) (D_tau eta) D_sigma u; after the solve u advances by
+ * K_u = alpha_i K_u + dtau (Q's force part - grad^(i-1) p). Velocities live on every node of the
+ * problem's grid (layout as sa_size), eta on its nx - 1 columns. The loop keeps a pointer to p
+ * (which must outlive it) and works on p's stream. */
+typedef struct sa_loop sa_loop;
+int sa_loop_create(sa_problem* p, double dtau, sa_loop** out);  /* SA_EARG: p not periodic, dtau <= 0 */
+/* eta (nx - 1), u, w (n values each) in `mem` memory; clears the Runge-Kutta registers; waits */
+int sa_loop_set_state(sa_loop* L, const double* eta, const double* u, const double* w, int32_t mem);
+/* one time step = five stages and five solves; infos (may be NULL) receives the five solve
+ * reports; waits for the stream. SA_NOCONV if a stage's solve did not converge (the state is then
+ * that of the stage before it), negative codes as sa_solve. */
+int sa_loop_step(sa_loop* L, sa_solve_info* infos);
+int sa_loop_get_state(sa_loop* L, double* eta, double* u, double* w, int32_t mem);
+void sa_loop_destroy(sa_loop* L);
+
 /* y = M^-1 x, the fixed still-water preconditioner of the problem. */
 int sa_apply_precond(sa_problem* p, const double* x, double* y, int32_t mem);
 

@@ -137,6 +137,11 @@ def _load():
         "sa_build_info": (C.c_char_p, []),
         "sa_get_phase_times": (C.c_int, [P, D, C.c_int32]),
         "sa_problem_footprint": (C.c_int, [C.POINTER(SaGrid), D, C.POINTER(SaOptions), C.POINTER(C.c_int64)]),
+        "sa_loop_create": (C.c_int, [P, C.c_double, C.POINTER(P)]),
+        "sa_loop_set_state": (C.c_int, [P, P, P, P, C.c_int32]),
+        "sa_loop_step": (C.c_int, [P, C.POINTER(SaSolveInfo)]),
+        "sa_loop_get_state": (C.c_int, [P, P, P, P, C.c_int32]),
+        "sa_loop_destroy": (None, [P]),
         "sa_op3d_create": (C.c_int, [C.POINTER(SaGrid3), D, P, C.POINTER(P)]),
         "sa_op3d_set_surface": (C.c_int, [P, P, P, C.c_int32]),
         "sa_op3d_apply": (C.c_int, [P, P, P, C.c_int32]),
@@ -650,3 +655,53 @@ class Operator3D:
 
     def sync(self):
         _check(lib.sa_op3d_sync(self._h))
+
+
+class ClosedLoop:
+    """LSERK45 stepping of a periodic problem's velocity field and surface (sa_loop_*): each
+    step makes five mixed-stage pressure systems and solves them with the problem's solver."""
+
+    def __init__(self, problem: "Problem", dtau: float):
+        handle = C.c_void_p()
+        _check(lib.sa_loop_create(problem._h, float(dtau), C.byref(handle)))
+        self._h = handle
+        self.problem = problem
+        self.n, self.ncol = problem.n, problem.ncol
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sa_loop_destroy(self._h)
+            self._h = None
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_state(self, eta, u, w):
+        pe, me, ke = _ptr(eta, self.ncol)
+        pu, mu, ku = _ptr(u, self.n)
+        pw, mw, kw = _ptr(w, self.n)
+        if not (me == mu == mw):
+            raise ValueError("eta, u and w must live in the same memory")
+        _check(lib.sa_loop_set_state(self._h, pe, pu, pw, me))
+
+    def step(self):
+        infos = (SaSolveInfo * 5)()
+        _check(lib.sa_loop_step(self._h, infos), allow=(SA_OK,))
+        return [SolveInfo.of(i) for i in infos]
+
+    def state(self):
+        eta, u, w = np.empty(self.ncol), np.empty(self.n), np.empty(self.n)
+        _check(lib.sa_loop_get_state(self._h, eta.ctypes.data_as(C.c_void_p), u.ctypes.data_as(C.c_void_p),
+                                     w.ctypes.data_as(C.c_void_p), SA_MEM_HOST))
+        return eta, u, w

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsawave.so")
-SOURCES = ["solve64.hip", "solve32.hip", "api.hip", "server.hip", "static_apply.hip", "operator3d.hip", "setup.cpp", "ilu.cpp"]
+SOURCES = ["solve64.hip", "solve32.hip", "api.hip", "server.hip", "static_apply.hip", "operator3d.hip", "closedloop.hip", "setup.cpp", "ilu.cpp"]
 ARCH = "gfx950"
 
 
