@@ -10,8 +10,10 @@ V-cycle preconditioner, FP64. The default workload is the large single simulatio
 (periodic 16385 x 33, n = 557 056, GMRES(40), rank 16). Inputs (surfaces at the stage times,
 manufactured right-hand sides b = A p* formed by the library's own operator) are resident in
 HBM before the timed region starts. The same steps are then solved from the previous
-solution (the paper's baseline) and from a cold start (the plain path). Prints one JSON line;
-progress goes to stderr.
+solution (the paper's baseline) and from a cold start (the plain path). Extra legs: the bar,
+FP32 refinement, ILU(0), and the closed loop (Alg. 1: right-hand sides from the velocity field
+of an Airy wave on the same grid, every guess mode). Prints one JSON line; progress goes to
+stderr.
 """
 from __future__ import annotations
 
@@ -229,6 +231,52 @@ def summary(w, r, nsol):
             "err_vs_pstar_max": float(r["err"][nw:].max()), "err_vs_pstar_median": float(np.median(r["err"][nw:]))}
 
 
+def closed_loop_leg(B, w, G, rtol, warmup_steps=2, steps=10, steepness=0.05):
+    """The closed loop (Alg. 1) on the workload's periodic grid: LSERK45 steps of size w.dtau
+    from an Airy wave of the carrier wavenumber (height steepness x wavelength), each stage's
+    pressure right-hand side built on the device from the velocity field and solved with the
+    guess mode under test, to relative residual rtol. Reports solves/s over the timed steps
+    (right-hand-side kernels and the per-stage report included), Arnoldi steps per solve, and
+    how far the final states of the modes lie apart."""
+    import torch
+    from paper_2511_18071_amd import workload as W
+    eta0, u0, w0 = W.airy_state(w, steepness)
+    out, finals = {}, {}
+    for mode in ("ewma", "previous", "cold"):
+        p = B.Problem.from_workload(w, stream=torch.cuda.current_stream(), cluster=G, guess=mode, rtol=rtol)
+        loop = B.ClosedLoop(p, w.dtau)
+        loop.set_state(eta0, u0, w0)
+        for _ in range(warmup_steps):
+            loop.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos, step_ms = [], []
+        for _ in range(steps):
+            t1 = time.perf_counter()
+            infos += loop.step()
+            step_ms.append(1e3 * (time.perf_counter() - t1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        finals[mode] = loop.state()
+        loop.close()
+        p.close()
+        its = np.array([i.iters for i in infos])
+        out[mode] = {"value": round(len(infos) / wall, 3), "iters_per_solve": round(float(its.mean()), 3),
+                     "ms_per_step": round(float(np.mean(step_ms)), 4),
+                     "max_relres": float(max(i.relres for i in infos)),
+                     "failed_solves": int(sum(1 for i in infos if i.status != 0 or i.relres > rtol))}
+        say(f"  closed loop rtol {rtol:g} {mode}: {out[mode]['value']:.2f} solves/s, {out[mode]['iters_per_solve']} steps/solve")
+    e_ref, u_ref, _ = finals["cold"]
+    diff = {m: float(max(np.abs(finals[m][0] - e_ref).max() / np.abs(e_ref).max(),
+                         np.abs(finals[m][1] - u_ref).max() / np.abs(u_ref).max())) for m in ("ewma", "previous")}
+    mass = abs(float(finals["ewma"][0].mean()) - float(eta0.mean())) / float(np.abs(eta0).max())
+    return dict(out, speedup_vs_previous=round(out["ewma"]["value"] / out["previous"]["value"], 3),
+                speedup_vs_plain=round(out["ewma"]["value"] / out["cold"]["value"], 3),
+                state_diff_vs_cold=diff, mean_surface_drift_rel=mass,
+                rtol=rtol, initial="Airy wave, carrier wavenumber, H/L = %g" % steepness, dtau=w.dtau,
+                steps=steps, warmup=warmup_steps, cluster_workgroups=G)
+
+
 def phase_breakdown(B, w, etas, bs, G, nsys=10):
     """Device time per phase of the first nsys EWMA solves (profile mode: the first workgroup
     reads the clock at each phase boundary)."""
@@ -374,6 +422,10 @@ def run_main(args):
         say("  phases done")
     del etas, bs, ps
     torch.cuda.empty_cache()
+    if not args.no_extra and w.bc == "periodic" and w.kind == "stream":
+        # at the benchmark's tolerance and at the paper's (1e-4, Sec. 5.2)
+        out[f"closed_loop_{w.name}"] = {f"rtol_{rt:g}": closed_loop_leg(B, w, G, rt) for rt in (w.rtol, 1e-4)}
+        say("  closed-loop leg done")
     if not args.no_extra and w.name != "bar_513x17":
         wb = W.get("bar_513x17")
         Gb = default_cluster(wb)

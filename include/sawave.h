@@ -227,8 +227,10 @@ void sa_op3d_destroy(sa_op3d* op);
  * and gravity g = 9.81: the surface advances by the kinematic condition w - u D_chi eta; the
  * right-hand side is grad^(i) . Q on the PDE rows, n . Q at the bed (n = (-h_chi, -1)) and 0 on
  * the surface, Q = u / (beta_i dtau) + alpha_i K_u / dtau + F - (u . grad^(i-1)) u
- * + (sigma / d^(i-1)) (D_tau eta) D_sigma u; after the solve u advances by
- * K_u = alpha_i K_u + dtau (Q's force part - grad^(i-1) p). Velocities live on every node of the
+ * + (sigma / d^(i-1)) (D_tau eta) D_sigma u. The problem solves for the dynamic pressure
+ * p_d = p - p_s, p_s = g d^(i-1) (1 - sigma) (right-hand side rhs - A p_s), as the solver of
+ * Sec. 1 does; after the solve u advances by K_u = alpha_i K_u + dtau (Q's force part -
+ * grad^(i-1) (p_s + p_d)). Velocities live on every node of the
  * problem's grid (layout as sa_size), eta on its nx - 1 columns. The loop keeps a pointer to p
  * (which must outlive it) and works on p's stream. */
 typedef struct sa_loop sa_loop;

@@ -12,10 +12,18 @@ mixed-stage problem grad^(i) . grad^(i-1) p = rhs is solved, where, with rho = 1
 on the PDE rows, n . Q on the bed rows (n = (-h_chi, -1), the Neumann condition of the
 discrete Neumann equation), 0 on the free-surface rows (p = 0); then K_u = alpha_i K_u +
 dtau (R - grad^(i-1) p) and u^(i) = u^(i-1) + beta_i K_u. The scheme is the paper's with the
-viscosity set to zero and gravity as the body force F = (0, -g).
+viscosity set to zero and gravity as the body force F = (0, -g). As in the solver the paper
+builds on (Sec. 1, Sec. 2.2), the system handed to the solver is the one for the dynamic
+pressure: with p_s = g d^(i-1) (1 - sigma), the hydrostatic pressure under the previous stage's
+surface, A p_d = rhs - A p_s and p = p_s + p_d. Up to the solve's tolerance p is the same; the
+solver sees the slowly varying dynamic part instead of a sequence dominated by the hydrostatic
+one, which the guess would otherwise spend its basis on.
 
 Readings (the paper leaves them open):
 
+* the dynamic-pressure form above (the paper names the decomposition p = p_s + p_d and says
+  its solver poses the stage problem for the dynamic pressure; p_s is taken under the surface
+  at which grad^(i-1) is evaluated, so that it vanishes on the free-surface rows);
 * velocities live on every node of the pressure grid, the ghost level below the bed included,
   and every node takes the same update (so that u^(i) = beta_i dtau (Q - grad^(i-1) p)
   everywhere and the discrete divergence of u^(i) at the PDE rows and n . u^(i) at the bed are
@@ -104,8 +112,12 @@ class ClosedLoop:
         ghost = np.nonzero(kind == 2)[0]
         bed = ghost + g.ncol
         rhs[ghost] = -geo_p["h_chi"][bed % g.ncol] * qx[bed] - qz[bed]
+        # the system is posed for the dynamic pressure p_d = p - p_s, p_s = g d^(i-1) (1 - sigma)
+        # the hydrostatic pressure under the previous stage's surface (zero on the surface)
+        ps = G * (geo_p["d"][None, :] * (1.0 - g.sig[:, None])).reshape(-1)
+        rhs = rhs - self.sim.operator(eta, eta_new) @ ps
         res = self.sim.solve(eta, eta_new, rhs)
-        p = res.x
+        p = res.x + ps
         self.Ku = a * self.Ku + dt * (rx - gx_p @ p)
         self.Kw = a * self.Kw + dt * (rz - gz_p @ p)
         self.u = u + b * self.Ku

@@ -8,7 +8,9 @@
 //   R = F - (u . grad^(i-1)) u + (sigma / d^(i-1)) f_eta D_sigma u;
 //   Q = u / (beta_i dtau) + alpha_i K_u / dtau + R;
 //   rhs = grad^(i) . Q (PDE rows), n . Q at the bed node (bed rows, n = (-h_chi, -1)), 0 (surface);
-//   p = A(eta^(i-1), eta^(i))^-1 rhs (the problem's solve, with its guess);
+//   p = p_s + p_d, p_s = g d^(i-1) (1 - sigma) the hydrostatic pressure under the previous
+//     stage's surface and p_d = A(eta^(i-1), eta^(i))^-1 (rhs - A p_s) the dynamic pressure
+//     (the problem's solve, with its guess: the sequence it sees is the dynamic part);
 //   K_u = alpha_i K_u + dtau (R - grad^(i-1) p); u^(i) = u^(i-1) + beta_i K_u,
 //
 // with grad = (D_chi + sigma_x D_sigma, (1/d) D_sigma) at the stated stage. Velocities live on
@@ -42,7 +44,7 @@ struct LoopArgs {
   const double* sig;   // nl
   const double* h;     // ncol
   const double* hchi;  // ncol
-  double *u, *w, *ku, *kw, *rx, *rz, *qx, *qz, *rhs, *p;
+  double *u, *w, *ku, *kw, *rx, *rz, *qx, *qz, *rhs, *p, *ps;
   double *eta, *eta_new, *keta, *feta;
   double* geo;  // 5 x ncol: 1/d prev, d_chi prev, 1/d cur, d_chi cur, h_chi
   double a, b, dt;
@@ -138,14 +140,29 @@ extern "C" __global__ void __launch_bounds__(LB) sa_loop_rhs_kernel(LoopArgs A) 
   A.rhs[i] = v;
 }
 
-// K_u = alpha K_u + dt (R - grad^(i-1) p), u += beta K_u (geometry of stage i - 1)
+// p_s = g d^(i-1) (1 - sigma) at every node
+extern "C" __global__ void __launch_bounds__(LB) sa_loop_hydrostatic_kernel(LoopArgs A) {
+  const int i = blockIdx.x * LB + threadIdx.x;
+  if (i >= A.n) return;
+  const int nc = A.ncol, j = i / nc, c = i - j * nc;
+  A.ps[i] = GRAV * (A.h[c] + A.eta[c]) * (1.0 - A.sig[j]);
+}
+
+// rhs -= A p_s (A p_s in qx, which the right-hand side no longer needs)
+extern "C" __global__ void __launch_bounds__(LB) sa_loop_dynamic_rhs_kernel(LoopArgs A) {
+  const int i = blockIdx.x * LB + threadIdx.x;
+  if (i >= A.n) return;
+  A.rhs[i] -= A.qx[i];
+}
+
+// K_u = alpha K_u + dt (R - grad^(i-1) p), u += beta K_u (geometry of stage i - 1), p = p_s + p_d
 extern "C" __global__ void __launch_bounds__(LB) sa_loop_update_kernel(LoopArgs A) {
   const int i = blockIdx.x * LB + threadIdx.x;
   if (i >= A.n) return;
   const int nc = A.ncol, j = i / nc, c = i - j * nc;
   const double id = A.geo[c], sx = (A.geo[4 * nc + c] - A.sig[j] * A.geo[nc + c]) * id;
-  const double ps = dsig(A, A.p, j, c);
-  const double px = dchi(A, A.p + (size_t)j * nc, c) + sx * ps, pz = id * ps;
+  const double psg = dsig(A, A.p, j, c) + dsig(A, A.ps, j, c);
+  const double px = dchi(A, A.p + (size_t)j * nc, c) + dchi(A, A.ps + (size_t)j * nc, c) + sx * psg, pz = id * psg;
   const double ku = A.a * A.ku[i] + A.dt * (A.rx[i] - px);
   const double kw = A.a * A.kw[i] + A.dt * (A.rz[i] - pz);
   A.ku[i] = ku;
@@ -170,8 +187,8 @@ extern "C" int sa_loop_create(sa_problem* p, double dtau, sa_loop** out) {
   L->p = p;
   L->dt = dtau;
   const size_t n = (size_t)p->n, nc = (size_t)p->ncol;
-  // u w ku kw rx rz qx qz rhs p (n each), eta eta_new keta feta (nc each), geo (5 nc)
-  const size_t doubles = 10 * n + 9 * nc;
+  // u w ku kw rx rz qx qz rhs p ps (n each), eta eta_new keta feta (nc each), geo (5 nc)
+  const size_t doubles = 11 * n + 9 * nc;
   if (hipMalloc((void**)&L->arena, doubles * 8) != hipSuccess) {
     delete L;
     return sa_fail(SA_EOOM, "sa_loop_create: %zu bytes of device memory", doubles * 8);
@@ -187,7 +204,7 @@ extern "C" int sa_loop_create(sa_problem* p, double dtau, sa_loop** out) {
   A.sig = (const double*)p->hp.sig; A.h = (const double*)p->hp.h; A.hchi = (const double*)p->hp.hchi;
   double* q = L->arena;
   A.u = q; q += n; A.w = q; q += n; A.ku = q; q += n; A.kw = q; q += n; A.rx = q; q += n; A.rz = q; q += n;
-  A.qx = q; q += n; A.qz = q; q += n; A.rhs = q; q += n; A.p = q; q += n;
+  A.qx = q; q += n; A.qz = q; q += n; A.rhs = q; q += n; A.p = q; q += n; A.ps = q; q += n;
   A.eta = q; q += nc; A.eta_new = q; q += nc; A.keta = q; q += nc; A.feta = q; q += nc; A.geo = q;
   A.dt = dtau;
   *out = L;
@@ -235,8 +252,15 @@ extern "C" int sa_loop_step(sa_loop* L, sa_solve_info* infos) {
     hipLaunchKernelGGL(sa_loop_force_kernel, dim3(gn), dim3(LB), 0, p->stream, A);
     hipLaunchKernelGGL(sa_loop_rhs_kernel, dim3(gn), dim3(LB), 0, p->stream, A);
     HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(sa_loop_hydrostatic_kernel, dim3(gn), dim3(LB), 0, p->stream, A);
+    HIPCHK(hipGetLastError());
     int rc = sa_set_surface(p, A.eta, A.eta_new, SA_MEM_DEVICE);
-    if (rc == SA_OK) rc = sa_push_rhs(p, A.rhs, SA_MEM_DEVICE);
+    if (rc == SA_OK) rc = sa_apply_operator(p, A.ps, A.qx, SA_MEM_DEVICE);
+    if (rc == SA_OK) {
+      hipLaunchKernelGGL(sa_loop_dynamic_rhs_kernel, dim3(gn), dim3(LB), 0, p->stream, A);
+      HIPCHK(hipGetLastError());
+      rc = sa_push_rhs(p, A.rhs, SA_MEM_DEVICE);
+    }
     sa_solve_info info{};
     if (rc == SA_OK) rc = sa_solve(p, &info, 0);
     if (infos) infos[s] = info;

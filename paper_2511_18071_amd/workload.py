@@ -374,6 +374,25 @@ def serving_mix(nsims: int = 256, seed: int = 5, nsys: int = 50, nx_range=(257, 
     return sims
 
 
+def airy_state(w: Workload, steepness: float, t: float = 0.0):
+    """Initial data of a closed-loop run on the periodic workload ``w``: a linear (Airy)
+    progressive wave at the workload's carrier wavenumber over its flat still-water depth h0,
+    of height steepness x wavelength, at time t. Returns eta at the physical columns and the
+    velocity components u, w at every node of the sigma grid of that surface (ghost level
+    included, level-major, column fastest), as the closed loop stores them."""
+    if w.bc != "periodic" or w.kind != "stream":
+        raise ValueError("closed-loop initial data are defined for the periodic stream workloads")
+    h0, kap = w.params["h0"], w.params["kappa0"]
+    amp = 0.5 * steepness * 2.0 * math.pi / kap
+    om = math.sqrt(G * kap * math.tanh(kap * h0))
+    ph = kap * w.x_phys() - om * t
+    eta = amp * np.cos(ph)
+    z = w.sigma_levels()[:, None] * (h0 + eta)[None, :] - h0
+    u = amp * om * np.cosh(kap * (z + h0)) / math.sinh(kap * h0) * np.cos(ph)[None, :]
+    v = amp * om * np.sinh(kap * (z + h0)) / math.sinh(kap * h0) * np.sin(ph)[None, :]
+    return eta, u.reshape(-1), v.reshape(-1)
+
+
 def get(name: str, seed: int | None = None) -> Workload:
     """Named workloads; ``seed`` replaces the workload's own seed (random phases of the
     surface harmonics, the bar's wave phase and the sketch stream), sizes unchanged.
