@@ -52,14 +52,22 @@ def _pair(B, nx, nz, waves, eta, u, w, dt, **kw):
     return g, ora, prob, loop
 
 
-@pytest.mark.parametrize("nx,nz,waves,steps", [(33, 9, 1, 8), (129, 17, 2, 4)])
-def test_closed_loop_matches_oracle(B, nx, nz, waves, steps):
-    _say(f"[closed loop] {nx} x {nz}, {waves} wavelength(s), {steps} steps")
+# the loop's kernels do not depend on the solver's options; these cases run them with the
+# paper's preconditioner, the range finder and the FP32 refinement path as well
+CASES = [(33, 9, 1, 8, {}), (129, 17, 2, 4, {}),
+         (33, 9, 1, 4, dict(precond="ilu0", guess="previous")),
+         (33, 9, 1, 4, dict(guess="range", window=12)),
+         (33, 9, 1, 4, dict(precision="fp32_ir"))]
+
+
+@pytest.mark.parametrize("nx,nz,waves,steps,kw", CASES)
+def test_closed_loop_matches_oracle(B, nx, nz, waves, steps, kw):
+    _say(f"[closed loop] {nx} x {nz}, {waves} wavelength(s), {steps} steps, {kw}")
     g = Grid(nx, nz, "periodic", 2 * np.pi * waves)
     amp, kappa = 1e-3 * waves, 1.0
     eta, u, w, om = linear_wave(g, 1.0, amp, kappa)
     dt = 2 * np.pi / om / 32
-    g, ora, prob, loop = _pair(B, nx, nz, waves, eta, u, w, dt)
+    g, ora, prob, loop = _pair(B, nx, nz, waves, eta, u, w, dt, **kw)
     gpu_its, ora_its = [], []
     for s in range(steps):
         infos = loop.step()
