@@ -121,8 +121,8 @@ def traffic_bytes(w, infos, pcv, k) -> float:
     guess            3k + 3   read Y_old and x, write Y_new, read b (block operator + Gram),
                               read Y_new, write x0
     r0 = b - A x0    3        read x0 and b, write r0
-    trigger M^-1 b   pcv + 1  one V-cycle and the norm of its output
-    cycle start      pcv + 1  V-cycle of r and its norm (once per cycle)
+    cycle start      pcv + 1  V-cycle of r and its norm (once per cycle; the first one also
+                              sets the check trigger)
     Arnoldi step j   2 + pcv + 3j + 8
                               operator (read v_j, write t), V-cycle, CGS2 in three passes over
                               V_0..V_j and w: dots (j+2), update + dots (j+3), update + norm (j+3)
@@ -134,7 +134,6 @@ def traffic_bytes(w, infos, pcv, k) -> float:
     for inf in infos:
         v = (3 * k + 3) + 3
         if inf.iters > 0:
-            v += pcv + 1
             cycles = inf.restarts + 1
             v += cycles * (pcv + 1)
             for step in range(inf.iters):

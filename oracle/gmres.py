@@ -7,9 +7,12 @@ restart cap are not stated in the paper; readings:
 * GMRES(m) on M^-1 A x = M^-1 b, Arnoldi with classical Gram-Schmidt applied twice
   (CGS2), Givens rotations on the Hessenberg matrix;
 * the decision is taken on the true residual: converged when ||b - A x|| <= rtol ||b||;
-  the Arnoldi estimate |g_{j+1}| only triggers a check, first when it drops below
-  rtol ||M^-1 b||; after a failed check the trigger threshold is lowered to
-  |g_{j+1}| rtol ||b|| / ||b - A x_j|| and the candidate is discarded;
+  the Arnoldi estimate |g_{j+1}| (a preconditioned residual norm) only triggers a check,
+  first when it drops below rtol ||b|| ||M^-1 r0|| / ||r0||, the first cycle's preconditioned
+  residual norm rescaled to the true residual's scale (so that no preconditioner application
+  is spent on b alone); after a failed check the trigger threshold is lowered by the same
+  rescaling with the checked candidate, to |g_{j+1}| rtol ||b|| / ||b - A x_j||, and the
+  candidate is discarded;
 * lucky breakdown when h_{j+1,j} <= 1e-14 ||M^-1 A v_j||: the candidate is formed, checked,
   and the cycle ends (restart from it if the check fails);
 * the iteration count is the number of Arnoldi steps over all cycles; x0 already inside
@@ -71,10 +74,12 @@ def gmres(A, b, x0, minv, m: int, rtol: float, max_restarts: int = 200):
     info.note("residual", rn, rtol * nb)
     if rn <= rtol * nb:
         return x, info
-    trigger = rtol * _nrm(minv(b))
+    trigger = None
     while True:
         z = minv(r)
         beta = _nrm(z)
+        if trigger is None:
+            trigger = rtol * beta * nb / rn
         V = np.zeros((m + 1, b.size))
         V[0] = z / beta
         H = np.zeros((m + 1, m))

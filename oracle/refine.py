@@ -8,9 +8,9 @@ J. Sci. Comput. 2018), whose candidates are checked on the FP64 residual the way
 checks its own. Written from that definition:
 
     r = b - A x0, stop at once if ||r|| <= rtol ||b||                (FP64)
-    trigger = rtol ||b|| ||M^-1 fl32(b / ||b||)||                   (FP32 V-cycle)
     repeat (one correction per pass; NOCONV after max_refine):
-        s = fl32(r / ||r||); a GMRES cycle of at most m steps on A d = s in which every
+        s = fl32(r / ||r||), g_0 = ||M^-1 s|| (FP32 V-cycle); at the first pass
+        trigger = rtol ||b|| g_0 (the trigger of ``gmres`` in this cycle's units); a GMRES cycle of at most m steps on A d = s in which every
         operator and preconditioner application and every basis vector is rounded to
         FP32 (Gram-Schmidt sums, Hessenberg, Givens FP64); after step j with estimate
         e = ||r|| |g_{j+1}|:
@@ -71,7 +71,7 @@ def solve(A, b, x0, minv, m: int, rtol: float, rtol_inner: float = 1e-4, max_ref
     info.history = []
     if rn <= rtol * nb:
         return x, info
-    trigger = rtol * nb * _nrm(rnd(minv(rnd(b / nb)))) if use_trigger else -1.0
+    trigger = None if use_trigger else -1.0
     brk = 1e-7 if inner is np.float32 else 1e-14
     while True:
         if info.refinements >= max_refine:
@@ -80,6 +80,8 @@ def solve(A, b, x0, minv, m: int, rtol: float, rtol_inner: float = 1e-4, max_ref
         info.refinements += 1
         z = rnd(minv(rnd(r / rn)))
         beta = _nrm(z)
+        if trigger is None:
+            trigger = rtol * nb * beta
         V = np.zeros((m + 1, b.size))
         V[0] = rnd(z / beta)
         H = np.zeros((m + 1, m))

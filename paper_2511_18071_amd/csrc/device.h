@@ -2316,11 +2316,13 @@ DEV double cluster_norm(const Problem& P, Cl& cl, const Smem& S, const T* v) {
 
 // Stages of a Krylov solve. Every preconditioner application of a solve goes through one call
 // site (the V-cycle is by far the largest piece of code): the stage says what it is applied to.
-enum { ST_TRIGGER = 0, ST_START = 1, ST_STEP = 2 };
+enum { ST_START = 1, ST_STEP = 2 };
 
 // FP64 restarted GMRES from P.x with residual P.r (left-preconditioned, CGS2, decisions on the
-// true residual): the check trigger starts at rtol ||M^-1 b||; a candidate x + V y is checked
-// on b - A x when the Arnoldi estimate reaches it, the trigger is lowered after a failed check;
+// true residual): the check trigger starts at rtol ||b|| ||M^-1 r0|| / ||r0|| (the first
+// cycle's preconditioned residual norm in the true residual's scale, no preconditioner
+// application of b); a candidate x + V y is checked on b - A x when the Arnoldi estimate
+// reaches it, the trigger is rescaled with the candidate's residual after a failed check;
 // lucky breakdown restarts from the checked candidate.
 DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, PhaseClock& clk,
                  sa_solve_info& info, double nb, double rn) {
@@ -2332,8 +2334,8 @@ DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, Ph
   double* r = P.r;
   double* rc = P.rc;
   double* V = P.V;
-  double trigger = 0.0;
-  int stage = ST_TRIGGER, j = 0;
+  double trigger = -1.0;  // set at the first cycle start
+  int stage = ST_START, j = 0;
   // line-solve constants kept in LDS for the whole solve (levels with one tile per workgroup)
   double* res = P.res_base >= 0 ? dyn_lds + P.res_base : nullptr;
   if (res) {
@@ -2345,13 +2347,10 @@ DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, Ph
     __syncthreads();
   }
   while (!aborted(cl)) {
-    const double* src = a.b;
-    double* dst = P.t;
+    const double* src = r;
+    double* dst = V;
     clk.tick(PH_OTHER);
-    if (stage == ST_START) {
-      src = r;
-      dst = V;
-    } else if (stage == ST_STEP) {
+    if (stage == ST_STEP) {
       info.iters += 1;
       phase_operator(P, cl, V + (size_t)j * n, S.vs[j], P.t, nullptr, S.big, S.red, 0);
       csync(cl);
@@ -2361,13 +2360,9 @@ DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, Ph
     }
     precond<double>(P, cl, src, dst, S.big, &clk, res);
     clk.tick(PH_PREC);
-    if (stage == ST_TRIGGER) {
-      trigger = rtol * cluster_norm(P, cl, S, (const double*)P.t);
-      stage = ST_START;
-      continue;
-    }
     if (stage == ST_START) {
       const double beta = cluster_norm(P, cl, S, (const double*)V);
+      if (trigger < 0.0) trigger = rtol * beta * nb / rn;
       if (tid == 0) {
         S.vs[0] = 1.0 / beta;
         S.g[0] = beta;
@@ -2442,7 +2437,7 @@ DEV void gmres64(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, Ph
 // Mixed precision: FP64 iterative refinement around FP32 GMRES cycles on A d = r / ||r||.
 // Operator, V-cycle and basis are FP32; Gram-Schmidt sums, Hessenberg and Givens are FP64.
 // Candidates x + ||r|| V y are checked on the FP64 residual b - A x with the trigger rule of
-// the FP64 path (first at rtol ||b|| ||M^-1 fl32(b / ||b||)||, lowered after a failed check);
+// the FP64 path (first at rtol ||b|| ||M^-1 fl32(r0 / ||r0||)||, rescaled after a failed check);
 // when the cycle reaches FP32 resolution (estimate down by rtol_inner, or h_{j+1,j} <=
 // 1e-7 ||w||) the checked candidate becomes the new x and the next correction starts from its
 // residual; a complete cycle adds its correction and starts the next one.
@@ -2458,8 +2453,8 @@ DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, P
   double* xc = P.xc;
   double* r = P.r;
   double* rc = P.rc;
-  double trigger = 0.0, beta = 0.0;
-  int stage = ST_TRIGGER, j = 0;
+  double trigger = -1.0, beta = 0.0;  // trigger: set at the first cycle start
+  int stage = ST_START, j = 0;
   // FP32 line-solve constants kept in LDS for the whole solve (levels with one tile per
   // workgroup)
   float* res = P.res_base >= 0 ? (float*)(dyn_lds + P.res_base) : nullptr;
@@ -2475,18 +2470,15 @@ DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, P
     const float* src = r32;
     float* dst = P.t32;
     clk.tick(PH_OTHER);
-    if (stage != ST_STEP) {  // fl32(b / ||b||) or fl32(r / ||r||)
-      if (stage == ST_START) {
-        if (info.refinements >= P.max_refine) {
-          info.status = SA_NOCONV;
-          break;
-        }
-        info.refinements += 1;
-        dst = V;
+    if (stage == ST_START) {  // fl32(r / ||r||)
+      if (info.refinements >= P.max_refine) {
+        info.status = SA_NOCONV;
+        break;
       }
-      const double* v = stage == ST_TRIGGER ? a.b : r;
-      const double sc = 1.0 / (stage == ST_TRIGGER ? nb : rn);
-      for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) r32[e] = float(v[e] * sc);
+      info.refinements += 1;
+      dst = V;
+      const double sc = 1.0 / rn;
+      for (size_t e = (size_t)cl.rank * BLOCK + tid; e < n; e += (size_t)cl.G * BLOCK) r32[e] = float(r[e] * sc);
       csync(cl);
     } else {
       info.iters += 1;
@@ -2498,13 +2490,9 @@ DEV void refine32(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S, P
     }
     precond<float>(P, cl, src, dst, lds, &clk, res);
     clk.tick(PH_PREC);
-    if (stage == ST_TRIGGER) {
-      trigger = rtol * nb * cluster_norm(P, cl, S, (const float*)P.t32);
-      stage = ST_START;
-      continue;
-    }
     if (stage == ST_START) {
       beta = cluster_norm(P, cl, S, (const float*)V);
+      if (trigger < 0.0) trigger = rtol * nb * beta;
       if (tid == 0) {
         S.vs[0] = 1.0 / beta;
         S.g[0] = beta;

@@ -65,8 +65,8 @@ def test_ilu_rejects_fp32_refinement(B):
 # least 3 % from its threshold
 ILU_SOLVE_CASES = [
     ("tiny_17x7", dict(precond="ilu0"), 10, 2),
-    ("periodic_65x9", dict(precond="ilu0"), 8, 7),
-    ("bar_65x9", dict(precond="ilu0"), 12, 5),
+    ("periodic_65x9", dict(precond="ilu0"), 8, 5),
+    ("bar_65x9", dict(precond="ilu0"), 12, 9),
     ("tiny_17x7", dict(precond="ilu0", guess="previous", restart=5), 6, 1),
     ("bar_65x9", dict(precond="ilu0", guess="range", window=8, k=4), 12, 2),
     ("bar_513x17", dict(precond="ilu0"), 8, None),

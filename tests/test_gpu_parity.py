@@ -192,9 +192,9 @@ def test_precond_one_level_is_exact_solve(B):
 # parity_rules, so a seed that drifts into a tie fails loudly instead of passing on an
 # allowance). Restarts are exercised with short restart lengths on preconditioned systems.
 SOLVE_CASES = [
-    ("tiny_17x7", dict(precond="line", nu1=1, omega=1.0, restart=5), 10, 12),
-    ("tiny_17x7", dict(precond="mg"), 10, 84),
-    ("tiny_17x7", dict(precond="mg", restart=4), 10, 25),
+    ("tiny_17x7", dict(precond="line", nu1=1, omega=1.0, restart=5), 10, 18),
+    ("tiny_17x7", dict(precond="mg"), 10, 39),
+    ("tiny_17x7", dict(precond="mg", restart=4), 10, 50),
     ("periodic_65x9", dict(), 20, 16),
     ("periodic_65x9", dict(restart=6), 12, 3),
     ("periodic_65x9", dict(guess="cold"), 6, 1),
@@ -206,9 +206,9 @@ SOLVE_CASES = [
     ("periodic_65x9", dict(coarse_max=40), 4, 9),
     ("bar_65x9", dict(coarse_max=50, cluster=2), 10, 2),
     # Alg. 3: V = X Omega over a sliding window of K solutions
-    ("tiny_17x7", dict(guess="range", window=6, k=3), 10, 5),
+    ("tiny_17x7", dict(guess="range", window=6, k=3), 10, 38),
     ("periodic_65x9", dict(guess="range", window=8, k=8), 12, 3),
-    ("bar_65x9", dict(guess="range", window=12, k=6), 16, 7),
+    ("bar_65x9", dict(guess="range", window=12, k=6), 16, 8),
     ("periodic_257x33", dict(guess="range", window=20, k=16), 16, None),
     ("bar_513x17", dict(guess="range", window=20, k=15), 8, None),
     ("periodic_257x33", dict(), 24, None),
