@@ -66,6 +66,7 @@ enum { SA_GUESS_COLD = 0, SA_GUESS_PREVIOUS = 1, SA_GUESS_EWMA = 2, SA_GUESS_RAN
 enum { SA_FP64 = 0, SA_FP32_IR = 1 };
 enum { SA_MEM_HOST = 0, SA_MEM_DEVICE = 1 };
 enum { SA_SYNC = 0, SA_ASYNC = 1 };
+enum { SA_DECAY_SOLVES = 0, SA_DECAY_TIME = 1 };
 
 /* Grid: nx points on [0, length] (inclusive), nz sigma levels from bed to surface. */
 typedef struct {
@@ -110,6 +111,12 @@ typedef struct {
   int32_t window;       /* SA_GUESS_RANGE: K, the solutions kept in the sliding window of   */
                         /* the randomized range finder (Alg. 3, V = X Omega with the k x K  */
                         /* Gaussian rows drawn as the solutions enter), k..32, default 16   */
+  int32_t decay;        /* units of the EWMA sketch's forgetting exponent (Alg. 4):         */
+                        /* SA_DECAY_SOLVES (default) Y <- r Y + x w^T per stored solution;  */
+                        /* SA_DECAY_TIME Y <- r^((tau_x - tau_prev) / decay_dtau) Y + x w^T */
+                        /* with the time labels of the stored solutions given by            */
+                        /* sa_set_time (Alg. 4's exponent in physical time); EWMA only      */
+  double decay_dtau;    /* SA_DECAY_TIME: the time unit of the exponent (> 0), default 1    */
 } sa_options;
 
 /* Per-solve report. iters counts Arnoldi steps over all cycles (FP32_IR: inner steps over
@@ -143,6 +150,14 @@ int sa_set_surface(sa_problem* p, const double* eta_prev, const double* eta_cur,
 
 /* Right-hand side b (n values). Host: copied. Device: referenced, not copied. */
 int sa_push_rhs(sa_problem* p, const double* b, int32_t mem);
+
+/* Time label tau of the system the next sa_solve solves (Alg. 4: the stage time whose
+ * differences the forgetting exponent counts), for decay = SA_DECAY_TIME. Required before
+ * every solve of such a problem (sa_solve returns SA_EARG without it); labels must not
+ * decrease from one solve to the next (SA_EARG, the label is not taken). SA_EARG for a problem
+ * with decay = SA_DECAY_SOLVES. Host-side bookkeeping only: the factor r^delta is computed on
+ * the host when the solution enters the sketch (at the next solve). */
+int sa_set_time(sa_problem* p, double tau);
 
 /* Solve A(eta_prev, eta_cur) x = b from the guess selected by the options, then store x in
  * the sketch (Alg. 4). SA_SYNC: waits and fills *info (may be NULL). SA_ASYNC: enqueues only;
@@ -345,7 +360,8 @@ void sa_server_destroy(sa_server* s);
  * its size). SA_EBUSY (nothing allocated) when its arena would exceed the HBM budget, unless
  * queue_admission is set: then *sim is valid at once, requests may be submitted, and the
  * simulation is created when it fits (sa_server_admitted). A simulation larger than the whole
- * budget is always refused. */
+ * budget is always refused. Requests carry no time labels: opt->decay must be
+ * SA_DECAY_SOLVES (SA_EARG otherwise). */
 int sa_server_open(sa_server* s, const sa_grid* grid, const double* h, const sa_options* opt, int32_t* sim);
 /* 1: the simulation holds its device arena; 0: waiting for admission; -1: no such simulation
  * (or its admission failed). */

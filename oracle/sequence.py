@@ -37,6 +37,8 @@ class Options:
     guess: str = "ewma"  # cold | previous | ewma | range (Alg. 3, V = X Omega)
     k: int = 8
     window: int = 16  # K, solutions kept by the range finder (guess = 'range')
+    decay: str = "solves"  # 'solves' | 'time' (EWMA: forgetting exponent in time, solve(tau=...))
+    decay_dtau: float = 1.0
     orthonormalize: bool = False  # range finder: V = Q
     r: float = 0.9
     seed: int = 0
@@ -64,7 +66,8 @@ class Simulation:
         self.minv = _precond.make(self.grid, self.h, opts.precond, opts.nu1, opts.nu2, opts.omega,
                                   opts.max_levels, opts.coarse_max)
         if opts.guess == "ewma":
-            self.sketch = EWMASketch(self.grid.n, opts.k, opts.r, opts.seed)
+            self.sketch = EWMASketch(self.grid.n, opts.k, opts.r, opts.seed,
+                                     opts.decay_dtau if opts.decay == "time" else None)
         elif opts.guess == "range":
             self.sketch = RangeFinder(self.grid.n, opts.window, opts.k, opts.seed, opts.orthonormalize)
         else:
@@ -93,7 +96,10 @@ class Simulation:
         V = self.sketch.basis() if o.guess == "range" else self.sketch.Y
         return guess(A, V, b, o.tau_drop, stats)
 
-    def solve(self, eta_prev, eta_cur, b) -> Result:
+    def solve(self, eta_prev, eta_cur, b, tau: float | None = None) -> Result:
+        """Solve the next system of the sequence; tau is its time label (decay = 'time')."""
+        if self.opts.decay == "time" and tau is None:
+            raise ValueError("decay='time' needs the time label of every system")
         A = self.operator(eta_prev, eta_cur)
         stats = {}
         x0, rank = self.initial_guess(A, b, stats)
@@ -103,7 +109,10 @@ class Simulation:
         else:
             x, info = _gmres.gmres(A, b, x0, self.minv, o.restart, o.rtol, o.max_restarts)
         if self.sketch is not None:
-            self.sketch.push(x)
+            if self.opts.decay == "time" and self.opts.guess == "ewma":
+                self.sketch.push(x, tau)
+            else:
+                self.sketch.push(x)
         self.x_prev = x
         self.solves += 1
         margins = dict(getattr(info, "margins", None) or {})

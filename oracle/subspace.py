@@ -5,7 +5,9 @@ R^k) and updates it after every solve by the rank-one recursion Y <- r^Delta Y +
 (Sec. 4.1.2). Alg. 2 takes V = Y (no orthonormalisation is needed, Sec. 4.1.1-4.1.2),
 solves z* = argmin ||A V z - b|| by QR (Sec. 4) and starts GMRES from x0 = V z*.
 
-Readings: Delta is one per stored solution (the forgetting exponent counts solves); the
+Readings: Delta is one per stored solution (the forgetting exponent counts solves) by
+default; with time labels (``push(x, tau)``, the option ``decay='time'``) it is the time since
+the last stored solution in units of ``decay_dtau``, Alg. 4's exponent in physical time; the
 least-squares problem is solved with Householder QR of the column-scaled W = A Y D
 (D = diag(1/||W e_j||)) taken column by column in order, dropping a column whose norm
 after projection out of the kept columns falls below ``tau_drop`` (the sketch becomes
@@ -30,14 +32,21 @@ TAU_DROP = 1e-7
 class EWMASketch:
     """Y in R^{n x k}, zero until the first solution is pushed."""
 
-    def __init__(self, n: int, k: int, r: float, seed: int):
+    def __init__(self, n: int, k: int, r: float, seed: int, decay_dtau: float | None = None):
         self.Y = np.zeros((n, k))
         self.k, self.r, self.seed = k, float(r), seed
+        self.decay_dtau = decay_dtau  # None: Delta = 1 per stored solution
         self.pushes = 0
+        self.tau = None  # time label of the last stored solution
 
-    def push(self, x):
+    def push(self, x, tau: float | None = None):
         w = np.array(rng.omega(self.seed, self.pushes, self.k))
-        self.Y = self.r * self.Y + np.outer(np.asarray(x, dtype=np.float64), w)
+        if self.decay_dtau is None:
+            f = self.r
+        else:
+            f = self.r if self.pushes == 0 else self.r ** ((tau - self.tau) / self.decay_dtau)
+            self.tau = tau
+        self.Y = f * self.Y + np.outer(np.asarray(x, dtype=np.float64), w)
         self.pushes += 1
 
 

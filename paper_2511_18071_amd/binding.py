@@ -23,6 +23,7 @@ SA_PERIODIC, SA_WALLS = 0, 1
 SA_PC = {"none": 0, "line": 1, "mg": 2, "ilu0": 3}
 SA_GUESS = {"cold": 0, "previous": 1, "ewma": 2, "range": 3}
 SA_PRECISION = {"fp64": 0, "fp32_ir": 1}
+SA_DECAY = {"solves": 0, "time": 1}
 SA_MEM_HOST, SA_MEM_DEVICE = 0, 1
 SA_SYNC, SA_ASYNC = 0, 1
 
@@ -39,6 +40,7 @@ class SaOptions(C.Structure):
         ("seed", C.c_uint64), ("n_init", C.c_int32), ("tau_drop", C.c_double),
         ("precision", C.c_int32), ("rtol_inner", C.c_double), ("max_refine", C.c_int32),
         ("cluster", C.c_int32), ("profile", C.c_int32), ("coarse_max", C.c_int32), ("window", C.c_int32),
+        ("decay", C.c_int32), ("decay_dtau", C.c_double),
     ]
 
 
@@ -118,6 +120,7 @@ def _load():
         "sa_ncol": (C.c_int32, [P]),
         "sa_set_surface": (C.c_int, [P, P, P, C.c_int32]),
         "sa_push_rhs": (C.c_int, [P, P, C.c_int32]),
+        "sa_set_time": (C.c_int, [P, C.c_double]),
         "sa_solve": (C.c_int, [P, C.POINTER(SaSolveInfo), C.c_int32]),
         "sa_read_log": (C.c_int, [P, C.POINTER(SaSolveInfo), C.c_int32, C.POINTER(C.c_int32)]),
         "sa_get_solution": (C.c_int, [P, P, C.c_int32]),
@@ -230,7 +233,7 @@ def make_options(**opts) -> SaOptions:
     """sa_options from keyword arguments (names of include/sawave.h; enum values by name)."""
     o = default_options()
     for key, val in opts.items():
-        names = {"precond": SA_PC, "guess": SA_GUESS, "precision": SA_PRECISION}.get(key)
+        names = {"precond": SA_PC, "guess": SA_GUESS, "precision": SA_PRECISION, "decay": SA_DECAY}.get(key)
         if names is not None and isinstance(val, str):
             val = names[val]
         if not hasattr(o, key):
@@ -332,6 +335,9 @@ class Problem:
         pb, mb, kb = _ptr(b, self.n)
         _check(lib.sa_push_rhs(self._h, pb, mb))
         self._keep_rhs = kb
+
+    def set_time(self, tau: float):
+        _check(lib.sa_set_time(self._h, float(tau)))
 
     # ---- solve ------------------------------------------------------------------------------
     def solve(self, sync: bool = True):

@@ -56,6 +56,8 @@ extern "C" void sa_default_options(sa_options* o) {
   o->profile = 0;
   o->coarse_max = 700;
   o->window = 16;
+  o->decay = SA_DECAY_SOLVES;
+  o->decay_dtau = 1.0;
 }
 
 extern "C" const char* sa_last_error(void) { return g_err.c_str(); }
@@ -186,6 +188,11 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   if (opt.guess == SA_GUESS_RANGE && (opt.window < opt.k || opt.window > KWIN))
     return sa_fail(SA_EARG, "sa_create: window must be in [k, %d]", KWIN);
   if (!(opt.r >= 0.0 && opt.r <= 1.0)) return sa_fail(SA_EARG, "sa_create: r must be in [0, 1]");
+  if (opt.decay != SA_DECAY_SOLVES && opt.decay != SA_DECAY_TIME) return sa_fail(SA_EARG, "sa_create: unknown decay");
+  if (opt.decay == SA_DECAY_TIME && opt.guess != SA_GUESS_EWMA)
+    return sa_fail(SA_EARG, "sa_create: SA_DECAY_TIME applies to the EWMA sketch only");
+  if (opt.decay == SA_DECAY_TIME && !(opt.decay_dtau > 0.0 && isfinite(opt.decay_dtau)))
+    return sa_fail(SA_EARG, "sa_create: decay_dtau must be positive");
   if (opt.precision != SA_FP64 && opt.precision != SA_FP32_IR) return sa_fail(SA_EARG, "sa_create: unknown precision");
   if (opt.precision == SA_FP32_IR && !(opt.rtol_inner > 0.0 && opt.rtol_inner < 1.0))
     return sa_fail(SA_EARG, "sa_create: rtol_inner must be in (0, 1)");
@@ -653,6 +660,15 @@ extern "C" int sa_push_rhs(sa_problem* p, const double* b, int32_t mem) {
   return SA_OK;
 }
 
+// Forgetting factor of the solution about to enter the sketch: r per stored solution, or r to
+// the time since the last stored solution in units of decay_dtau (an empty sketch takes any
+// factor).
+static double push_factor(const sa_problem* p) {
+  const sa_options& o = p->opt;
+  if (o.decay == SA_DECAY_TIME && p->pushes > 0) return pow(o.r, (p->t_unpushed - p->t_pushed) / o.decay_dtau);
+  return o.r;
+}
+
 static SolveArgs base_args(sa_problem* p) {
   SolveArgs a;
   memset(&a, 0, sizeof a);
@@ -678,6 +694,7 @@ SolveArgs sa_prepare_solve(sa_problem* p, bool* ewma_out) {
   const bool sk = ewma || range;
   a.push = sk && p->unpushed;
   if (a.push) splitmix_gaussians(o.seed, p->pushes, o.k, a.om);
+  if (a.push) a.r = push_factor(p);
   const int64_t pushes_after = p->pushes + (a.push ? 1 : 0);
   a.sketch_guess = sk && pushes_after > 0 && p->solves >= o.n_init;
   a.prev_guess = p->have_solution && (o.guess == SA_GUESS_PREVIOUS || (sk && !a.sketch_guess));
@@ -693,17 +710,31 @@ void sa_commit_solve(sa_problem* p, const SolveArgs& a) {
   if (a.push) {
     if (!a.range) p->ycur ^= 1;  // the EWMA sketch ping-pongs; the range finder's ring does not
     p->pushes += 1;
+    p->t_pushed = p->t_unpushed;
   }
+  p->t_unpushed = p->t_next;
+  p->t_set = false;
   p->unpushed = p->opt.guess == SA_GUESS_EWMA || p->opt.guess == SA_GUESS_RANGE;
   p->have_solution = true;
   p->solves += 1;
   p->log_pos += 1;
 }
 
+extern "C" int sa_set_time(sa_problem* p, double tau) {
+  if (!p) return sa_fail(SA_EARG, "sa_set_time: null problem");
+  if (p->opt.decay != SA_DECAY_TIME) return sa_fail(SA_EARG, "sa_set_time: the problem counts solutions, not time");
+  if (!isfinite(tau)) return sa_fail(SA_EARG, "sa_set_time: tau must be finite");
+  if (p->solves > 0 && tau < p->t_unpushed) return sa_fail(SA_EARG, "sa_set_time: time labels must not decrease");
+  p->t_next = tau;
+  p->t_set = true;
+  return SA_OK;
+}
+
 extern "C" int sa_solve(sa_problem* p, sa_solve_info* info, int32_t flags) {
   if (!p) return sa_fail(SA_EARG, "sa_solve: null problem");
   if (p->broken) return sa_fail(SA_EDEVICE, "problem unusable after a device error");
   if (!p->b || !p->eta_p || !p->eta_c) return sa_fail(SA_EARG, "sa_solve: set the surfaces and the right-hand side first");
+  if (p->opt.decay == SA_DECAY_TIME && !p->t_set) return sa_fail(SA_EARG, "sa_solve: SA_DECAY_TIME needs sa_set_time first");
   bool ewma = false;
   SolveArgs a = sa_prepare_solve(p, &ewma);
   BatchItem one;
@@ -771,9 +802,10 @@ struct StateHeader {
   char magic[8];
   int32_t version, guess, precision, k, window, nx, nz, bc;
   int64_t n, pushes, solves, log_pos;
-  int32_t unpushed, have_solution, pad[2];
+  int32_t unpushed, have_solution, decay, pad;
   double r;
   uint64_t seed;
+  double decay_dtau, t_unpushed, t_pushed;
 };
 constexpr char STATE_MAGIC[8] = {'S', 'A', 'W', 'A', 'V', 'E', 'S', 'T'};
 
@@ -801,12 +833,13 @@ extern "C" int sa_save_state(const sa_problem* pc, void* buf, size_t* len) {
   StateHeader h;
   memset(&h, 0, sizeof h);
   memcpy(h.magic, STATE_MAGIC, 8);
-  h.version = 1;
+  h.version = 2;
   h.guess = p->opt.guess; h.precision = p->opt.precision; h.k = p->opt.k; h.window = p->opt.window;
   h.nx = p->grid.nx; h.nz = p->grid.nz; h.bc = p->grid.bc;
   h.n = p->n; h.pushes = p->pushes; h.solves = p->solves; h.log_pos = p->log_pos;
   h.unpushed = p->unpushed ? 1 : 0; h.have_solution = p->have_solution ? 1 : 0;
   h.r = p->opt.r; h.seed = p->opt.seed;
+  h.decay = p->opt.decay; h.decay_dtau = p->opt.decay_dtau; h.t_unpushed = p->t_unpushed; h.t_pushed = p->t_pushed;
   char* out = (char*)buf;
   memcpy(out, &h, sizeof h);
   double* d = (double*)(out + sizeof h);
@@ -830,10 +863,11 @@ extern "C" int sa_load_state(sa_problem* p, const void* buf, size_t len) {
   StateHeader h;
   if (len < sizeof h) return sa_fail(SA_EARG, "sa_load_state: %zu bytes is no saved state", len);
   memcpy(&h, buf, sizeof h);
-  if (memcmp(h.magic, STATE_MAGIC, 8) != 0 || h.version != 1) return sa_fail(SA_EARG, "sa_load_state: not a saved state");
+  if (memcmp(h.magic, STATE_MAGIC, 8) != 0 || h.version != 2) return sa_fail(SA_EARG, "sa_load_state: not a saved state");
   if (h.n != p->n || h.nx != p->grid.nx || h.nz != p->grid.nz || h.bc != p->grid.bc || h.guess != p->opt.guess ||
       h.k != p->opt.k || (h.guess == SA_GUESS_RANGE && h.window != p->opt.window) || h.r != p->opt.r ||
-      h.seed != p->opt.seed || h.precision != p->opt.precision)
+      h.seed != p->opt.seed || h.precision != p->opt.precision || h.decay != p->opt.decay ||
+      (h.decay == SA_DECAY_TIME && h.decay_dtau != p->opt.decay_dtau))
     return sa_fail(SA_EARG, "sa_load_state: the state belongs to another grid or other options");
   if (len != sizeof h + state_doubles(p) * 8) return sa_fail(SA_EARG, "sa_load_state: truncated state");
   const double* d = (const double*)((const char*)buf + sizeof h);
@@ -853,6 +887,9 @@ extern "C" int sa_load_state(sa_problem* p, const void* buf, size_t len) {
   p->log_pos = p->log_read = h.log_pos;
   p->unpushed = h.unpushed != 0;
   p->have_solution = h.have_solution != 0;
+  p->t_unpushed = h.t_unpushed;
+  p->t_pushed = h.t_pushed;
+  p->t_set = false;
   return SA_OK;
 }
 
@@ -957,12 +994,14 @@ static int flush_push(sa_problem* p) {
   if (!p->unpushed || p->opt.guess != SA_GUESS_EWMA) return SA_OK;
   SolveArgs a = base_args(p);
   a.push = 1;
+  a.r = push_factor(p);
   splitmix_gaussians(p->opt.seed, p->pushes, p->opt.k, a.om);
   const int gb = (p->n + BLOCK - 1) / BLOCK;
   hipLaunchKernelGGL(sa_push_kernel, dim3(gb < 1024 ? gb : 1024), dim3(BLOCK), 0, p->stream, p->dp, a);
   HIPCHK(hipGetLastError());
   p->ycur ^= 1;
   p->pushes += 1;
+  p->t_pushed = p->t_unpushed;
   p->unpushed = false;
   return SA_OK;
 }

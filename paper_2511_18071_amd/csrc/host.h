@@ -53,6 +53,10 @@ struct sa_problem {
   int ycur = 0;
   int64_t pushes = 0, solves = 0;
   bool unpushed = false;         // the last solution is not in the sketch yet
+  // SA_DECAY_TIME: the label given for the next solve, the label of the solution not yet in
+  // the sketch and of the last solution pushed into it
+  double t_next = 0.0, t_unpushed = 0.0, t_pushed = 0.0;
+  bool t_set = false;
   bool have_solution = false;
   int64_t log_pos = 0, log_read = 0;
   bool broken = false;

@@ -315,6 +315,8 @@ extern "C" int sa_server_open(sa_server* s, const sa_grid* grid, const double* h
   std::lock_guard<std::mutex> lk(s->mu);
   sa_options opt;
   if (optin) opt = *optin; else sa_default_options(&opt);
+  if (opt.decay != SA_DECAY_SOLVES)
+    return sa_fail(SA_EARG, "sa_server_open: requests carry no time labels (SA_DECAY_SOLVES only)");
   const int budget = s->capacity / s->opt.max_inflight;
   if (opt.cluster <= 0) {
     const int ncol = grid->bc == SA_PERIODIC ? grid->nx - 1 : grid->nx + 2;

@@ -31,6 +31,33 @@ def test_streaming_equals_weighted_sum():
     assert np.allclose(sk.Y, ref, rtol=1e-13, atol=1e-13)
 
 
+def test_time_decay_equals_weighted_sum_over_time_labels():
+    """Alg. 4 with the exponent in time: Y = sum_l r^((tau_last - tau_l) / dtau) x_l omega_l^T
+    for non-uniform labels (the LSERK45 stage times of three steps); a recursion that took the
+    time since the first solution, or the label itself, instead of the time since the last
+    stored one fails this."""
+    n, k, r, seed, dt = 30, 4, 0.7, 5, 0.025
+    w = W.get("bar_65x9")
+    taus = [w.stage_times(s)[0] for s in range(15)]
+    assert len(set(np.round(np.diff(taus), 12))) > 2  # the stage spacing is not uniform
+    xs = np.random.default_rng(1).standard_normal((len(taus), n))
+    sk = EWMASketch(n, k, r, seed, decay_dtau=dt)
+    for x, t in zip(xs, taus):
+        sk.push(x, t)
+    ref = sum(r ** ((taus[-1] - taus[l]) / dt) * np.outer(xs[l], rng.omega(seed, l, k)) for l in range(len(xs)))
+    assert np.allclose(sk.Y, ref, rtol=1e-12, atol=1e-13)
+
+
+def test_time_decay_with_unit_spacing_is_the_per_solve_decay():
+    n, k, r, seed = 25, 3, 0.85, 2
+    xs = np.random.default_rng(2).standard_normal((7, n))
+    a, b = EWMASketch(n, k, r, seed), EWMASketch(n, k, r, seed, decay_dtau=2.0)
+    for i, x in enumerate(xs):
+        a.push(x)
+        b.push(x, 2.0 * i + 10.0)
+    assert np.array_equal(a.Y, b.Y)
+
+
 def _op(s=2):
     w = W.get("tiny_17x7")
     g = Grid(w.nx, w.nz, w.bc, w.length)
