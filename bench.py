@@ -361,6 +361,10 @@ def run_main(args):
     say(f"  ewma: {nsol / ewma['wall']:.2f} solves/s")
     out_modes = {}
     if not args.no_extra:
+        if w.r != 0.9:  # the same systems with the forgetting factor of the other configurations
+            r9 = run_sequence(B, w, etas, bs, ps, "ewma", args.warmup, args.steps, G, xs, r=0.9)
+            out_modes["ewma_r0.9"] = r9
+            say(f"  ewma r=0.9: {nsol / r9['wall']:.2f} solves/s")
         for mode in ("previous", "cold", "range"):
             extra = dict(window=RANGE_WINDOW) if mode == "range" else {}
             r = run_sequence(B, w, etas, bs, ps, mode, args.warmup, args.steps, G, xs, **extra)
@@ -406,6 +410,8 @@ def run_main(args):
         out["range_finder"] = dict(summary(w, out_modes["range"], nsol),
                                    guess=f"Alg. 3 range finder, V = X Omega, window K = {RANGE_WINDOW}, k = {w.k}")
         out["speedup_vs_plain"] = round(out_modes["cold"]["wall"] / ewma["wall"], 3)
+        if "ewma_r0.9" in out_modes:
+            out["ewma_r0.9"] = dict(summary(w, out_modes["ewma_r0.9"], nsol), guess=f"EWMA rank {w.k}, r=0.9")
         out["speedup_vs_previous"] = round(out_modes["previous"]["wall"] / ewma["wall"], 3)
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 5),

@@ -403,7 +403,10 @@ def get(name: str, seed: int | None = None) -> Workload:
       bar crest 0.1, slopes 1:20 up / 1:10 down), monochromatic shoaling wave of amplitude
       0.01 m and period 1.96 s, dtau = 0.025 s, 2000 systems, GMRES(30), rank 10.
     * ``periodic_16385x33``: flat bed h=1, kh=2, 64 carrier wavelengths, 8 harmonics with a
-      slow modulation, H/L=0.1, 500 systems, GMRES(40), rank 16.
+      slow modulation, H/L=0.1, 500 systems, GMRES(40), rank 16, forgetting factor 0.8 per
+      stored solution (a configuration choice inside the paper's recommended 0.7 <= r < 1,
+      Sec. 5.1: measured on 100 systems of this sequence for two seeds of its phases, r = 0.9
+      took 8.2 / 8.0 Arnoldi steps per solve, r = 0.8 6.2 / 6.2, r = 0.7 5.8 / 6.7).
     * ``tiny_17x7``: 16 x 8 periodic grid for brute-force checks.
     * ``bar_65x9``: the bar scaled by 1/8 on a 65 x 9 grid, rank 6.
     * ``periodic_257x33``: the large simulation's vertical resolution, rank and restart
@@ -417,7 +420,7 @@ def get(name: str, seed: int | None = None) -> Workload:
     if name == "bar_513x17":
         return _bar(name, 513, 17, sd(2), 2000, 30, 10, 0.9)
     if name == "periodic_16385x33":
-        w = _stream(name, 16385, 33, 2.0, 64, 8, 0.1, sd(3), 500, 40, 16, 0.9, modulation=0.2)
+        w = _stream(name, 16385, 33, 2.0, 64, 8, 0.1, sd(3), 500, 40, 16, 0.8, modulation=0.2)
         w.coarse_max = large_coarsest(w.nz)
         return w
     if name == "tiny_17x7":
