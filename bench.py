@@ -445,6 +445,13 @@ def run_main(args):
                                  previous_value=round(100 / rp["wall"], 3), previous_iters_per_solve=its(rp),
                                  range_finder_value=round(100 / rr["wall"], 3), range_finder_iters_per_solve=its(rr),
                                  steps=20, warmup=5, cluster_workgroups=Gb, guess=f"EWMA rank {wb.k}, r={wb.r}")
+        # the forgetting factors the bar's configuration names
+        sweep = {}
+        for rr in (0.8, 0.9, 0.95):
+            r_ = rb if rr == wb.r else run_sequence(B, wb, e2, b2, p2, "ewma", 5, 20, Gb, r=rr)
+            sweep[f"r_{rr:g}"] = {"value": round(100 / r_["wall"], 3), "iters_per_solve": its(r_),
+                                  "failed_solves": r_["failed"]}
+        out["bar_513x17"]["forgetting_sweep"] = sweep
         say("  bar leg done")
         # the precision variant of the bar: FP32 inner GMRES with FP64 refinement against the
         # all-FP64 path, both to relative residual 1e-10 on the FP64 residual, same systems

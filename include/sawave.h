@@ -252,9 +252,10 @@ typedef struct sa_loop sa_loop;
 int sa_loop_create(sa_problem* p, double dtau, sa_loop** out);  /* SA_EARG: p not periodic, dtau <= 0 */
 /* eta (nx - 1), u, w (n values each) in `mem` memory; clears the Runge-Kutta registers; waits */
 int sa_loop_set_state(sa_loop* L, const double* eta, const double* u, const double* w, int32_t mem);
-/* one time step = five stages and five solves; infos (may be NULL) receives the five solve
- * reports; waits for the stream. SA_NOCONV if a stage's solve did not converge (the state is then
- * that of the stage before it), negative codes as sa_solve. */
+/* one time step = five stages and five solves, enqueued on the stream without a wait between
+ * them; infos (may be NULL) receives the five solve reports; waits for the stream once, at the
+ * end. SA_NOCONV if a stage's solve did not converge (the step still runs its five stages: the
+ * state is the one after them), negative codes as sa_solve. */
 int sa_loop_step(sa_loop* L, sa_solve_info* infos);
 int sa_loop_get_state(sa_loop* L, double* eta, double* u, double* w, int32_t mem);
 void sa_loop_destroy(sa_loop* L);

@@ -916,6 +916,17 @@ static int stage_in(sa_problem* p, const double* src, int32_t mem, double* scrat
   return SA_OK;
 }
 
+int sa_apply_operator_enqueue(sa_problem* p, const double* x, double* y) {
+  if (!p->eta_p || !p->eta_c) return sa_fail(SA_EARG, "sa_apply_operator: set the surfaces first");
+  const int gb = (p->ncol + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(sa_geometry_kernel, dim3(gb), dim3(BLOCK), 0, p->stream, p->dp, p->eta_p, p->eta_c);
+  HIPCHK(hipGetLastError());
+  const int nt = tiles_host(p->ncol, p->grid.bc == SA_PERIODIC, TX);
+  hipLaunchKernelGGL(sa_operator_kernel, dim3(nt), dim3(BLOCK), p->lds_op, p->stream, p->dp, x, y);
+  HIPCHK(hipGetLastError());
+  return SA_OK;
+}
+
 extern "C" int sa_apply_operator(sa_problem* p, const double* x, double* y, int32_t mem) {
   if (!p || !x || !y) return sa_fail(SA_EARG, "sa_apply_operator: null argument");
   if (!p->eta_p || !p->eta_c) return sa_fail(SA_EARG, "sa_apply_operator: set the surfaces first");

@@ -244,6 +244,7 @@ extern "C" int sa_loop_step(sa_loop* L, sa_solve_info* infos) {
   sa_problem* p = L->p;
   LoopArgs& A = L->A;
   const int gn = (A.n + LB - 1) / LB, gc = (A.ncol + LB - 1) / LB;
+  const int64_t first = p->log_pos;  // the log slot of this step's first solve
   for (int s = 0; s < 5; ++s) {
     A.a = LA[s];
     A.b = LB5[s];
@@ -255,18 +256,14 @@ extern "C" int sa_loop_step(sa_loop* L, sa_solve_info* infos) {
     hipLaunchKernelGGL(sa_loop_hydrostatic_kernel, dim3(gn), dim3(LB), 0, p->stream, A);
     HIPCHK(hipGetLastError());
     int rc = sa_set_surface(p, A.eta, A.eta_new, SA_MEM_DEVICE);
-    if (rc == SA_OK) rc = sa_apply_operator(p, A.ps, A.qx, SA_MEM_DEVICE);
+    if (rc == SA_OK) rc = sa_apply_operator_enqueue(p, A.ps, A.qx);
     if (rc == SA_OK) {
       hipLaunchKernelGGL(sa_loop_dynamic_rhs_kernel, dim3(gn), dim3(LB), 0, p->stream, A);
       HIPCHK(hipGetLastError());
       rc = sa_push_rhs(p, A.rhs, SA_MEM_DEVICE);
     }
-    sa_solve_info info{};
-    if (rc == SA_OK) rc = sa_solve(p, &info, 0);
-    if (infos) infos[s] = info;
-    if (rc < 0) return rc;
-    if (info.status != SA_OK) return sa_fail(SA_NOCONV, "sa_loop_step: stage %d did not converge", s);
-    rc = sa_get_solution_async(p, A.p);
+    if (rc == SA_OK) rc = sa_solve(p, nullptr, SA_ASYNC);
+    if (rc == SA_OK) rc = sa_get_solution_async(p, A.p);
     if (rc) return rc;
     hipLaunchKernelGGL(sa_loop_update_kernel, dim3(gn), dim3(LB), 0, p->stream, A);
     HIPCHK(hipGetLastError());
@@ -274,7 +271,21 @@ extern "C" int sa_loop_step(sa_loop* L, sa_solve_info* infos) {
     A.eta = A.eta_new;
     A.eta_new = t;
   }
-  HIPCHK(hipStreamSynchronize(p->stream));
+  // the five reports (the only wait of the step)
+  sa_solve_info rep[5];
+  int32_t got = 0;
+  p->log_read = first;
+  const int rc = sa_read_log(p, rep, 5, &got);
+  if (infos)
+    for (int s = 0; s < got; ++s) infos[s] = rep[s];
+  if (rc != SA_OK) return rc;
+  for (int s = 0; s < got; ++s) {
+    if (rep[s].status == SA_EDEVICE) {
+      p->broken = true;
+      return sa_fail(SA_EDEVICE, "sa_loop_step: device barrier timed out");
+    }
+    if (rep[s].status != SA_OK) return sa_fail(SA_NOCONV, "sa_loop_step: stage %d did not converge", s);
+  }
   return SA_OK;
 }
 

@@ -71,6 +71,8 @@ sa::SolveArgs sa_prepare_solve(sa_problem* p, bool* ewma);
 void sa_commit_solve(sa_problem* p, const sa::SolveArgs& a);
 // device flags of p folded into a status (and cleared), SA_EDEVICE after a barrier time-out
 int sa_check_flags(sa_problem* p);
+// y = A x of p's current surfaces, device vectors, enqueued on p's stream (no wait)
+int sa_apply_operator_enqueue(sa_problem* p, const double* x, double* y);
 // raise the dynamic-LDS limit of the solve kernels to at least `bytes` (never lowers it)
 int sa_reserve_solve_lds(size_t bytes);
 // the solve kernel of a precision (SA_FP64 or SA_FP32_IR)
