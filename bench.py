@@ -365,9 +365,11 @@ def run_main(args):
             r9 = run_sequence(B, w, etas, bs, ps, "ewma", args.warmup, args.steps, G, xs, r=0.9)
             out_modes["ewma_r0.9"] = r9
             say(f"  ewma r=0.9: {nsol / r9['wall']:.2f} solves/s")
-        for mode in ("previous", "cold", "range"):
-            extra = dict(window=RANGE_WINDOW) if mode == "range" else {}
-            r = run_sequence(B, w, etas, bs, ps, mode, args.warmup, args.steps, G, xs, **extra)
+        for mode in ("previous", "cold", "range", "range_q"):
+            extra = dict(window=RANGE_WINDOW) if mode.startswith("range") else {}
+            if mode == "range_q":
+                extra["orthonormalize"] = 1
+            r = run_sequence(B, w, etas, bs, ps, mode.split("_")[0], args.warmup, args.steps, G, xs, **extra)
             out_modes[mode] = r
             say(f"  {mode}: {nsol / r['wall']:.2f} solves/s")
     value = nsol / ewma["wall"]
@@ -409,6 +411,8 @@ def run_main(args):
         out["plain"] = dict(sc, guess="cold (x0 = 0)")
         out["range_finder"] = dict(summary(w, out_modes["range"], nsol),
                                    guess=f"Alg. 3 range finder, V = X Omega, window K = {RANGE_WINDOW}, k = {w.k}")
+        out["range_finder_q"] = dict(summary(w, out_modes["range_q"], nsol),
+                                     guess=f"Alg. 3 range finder, V = Q (orthonormalised), window K = {RANGE_WINDOW}, k = {w.k}")
         out["speedup_vs_plain"] = round(out_modes["cold"]["wall"] / ewma["wall"], 3)
         if "ewma_r0.9" in out_modes:
             out["ewma_r0.9"] = dict(summary(w, out_modes["ewma_r0.9"], nsol), guess=f"EWMA rank {w.k}, r=0.9")
@@ -439,11 +443,13 @@ def run_main(args):
         rc = run_sequence(B, wb, e2, b2, p2, "cold", 5, 20, Gb)
         rp = run_sequence(B, wb, e2, b2, p2, "previous", 5, 20, Gb)
         rr = run_sequence(B, wb, e2, b2, p2, "range", 5, 20, Gb, window=RANGE_WINDOW)
+        rq = run_sequence(B, wb, e2, b2, p2, "range", 5, 20, Gb, window=RANGE_WINDOW, orthonormalize=1)
         its = lambda r: round(float(np.mean([i.iters for i in r["infos"]])), 3)
         out["bar_513x17"] = dict(summary(wb, rb, 100), plain_value=round(100 / rc["wall"], 3),
                                  plain_iters_per_solve=its(rc),
                                  previous_value=round(100 / rp["wall"], 3), previous_iters_per_solve=its(rp),
                                  range_finder_value=round(100 / rr["wall"], 3), range_finder_iters_per_solve=its(rr),
+                                 range_finder_q_value=round(100 / rq["wall"], 3), range_finder_q_iters_per_solve=its(rq),
                                  steps=20, warmup=5, cluster_workgroups=Gb, guess=f"EWMA rank {wb.k}, r={wb.r}")
         # the forgetting factors the bar's configuration names
         sweep = {}

@@ -117,6 +117,11 @@ typedef struct {
                         /* with the time labels of the stored solutions given by            */
                         /* sa_set_time (Alg. 4's exponent in physical time); EWMA only      */
   double decay_dtau;    /* SA_DECAY_TIME: the time unit of the exponent (> 0), default 1    */
+  int32_t orthonormalize; /* SA_GUESS_RANGE: 1 takes V = Q, the orthonormal factor of the   */
+                        /* sketch X Omega (Alg. 3), by a Cholesky factorisation of its      */
+                        /* double-double Gram taking columns in order and dropping one whose */
+                        /* projected norm (of the unit column) is below tau_drop; 0 (default)*/
+                        /* takes V = X Omega                                                 */
 } sa_options;
 
 /* Per-solve report. iters counts Arnoldi steps over all cycles (FP32_IR: inner steps over

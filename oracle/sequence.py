@@ -69,7 +69,8 @@ class Simulation:
             self.sketch = EWMASketch(self.grid.n, opts.k, opts.r, opts.seed,
                                      opts.decay_dtau if opts.decay == "time" else None)
         elif opts.guess == "range":
-            self.sketch = RangeFinder(self.grid.n, opts.window, opts.k, opts.seed, opts.orthonormalize)
+            self.sketch = RangeFinder(self.grid.n, opts.window, opts.k, opts.seed, opts.orthonormalize,
+                                      opts.tau_drop)
         else:
             self.sketch = None
         self.x_prev = None
@@ -93,7 +94,7 @@ class Simulation:
             return np.zeros(n), 0
         if o.guess == "previous" or self.sketch.pushes == 0 or self.solves < o.n_init:
             return prev.copy(), 0
-        V = self.sketch.basis() if o.guess == "range" else self.sketch.Y
+        V = self.sketch.basis(stats) if o.guess == "range" else self.sketch.Y
         return guess(A, V, b, o.tau_drop, stats)
 
     def solve(self, eta_prev, eta_cur, b, tau: float | None = None) -> Result:

@@ -40,7 +40,7 @@ class SaOptions(C.Structure):
         ("seed", C.c_uint64), ("n_init", C.c_int32), ("tau_drop", C.c_double),
         ("precision", C.c_int32), ("rtol_inner", C.c_double), ("max_refine", C.c_int32),
         ("cluster", C.c_int32), ("profile", C.c_int32), ("coarse_max", C.c_int32), ("window", C.c_int32),
-        ("decay", C.c_int32), ("decay_dtau", C.c_double),
+        ("decay", C.c_int32), ("decay_dtau", C.c_double), ("orthonormalize", C.c_int32),
     ]
 
 

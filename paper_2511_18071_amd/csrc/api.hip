@@ -189,6 +189,9 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
     return sa_fail(SA_EARG, "sa_create: window must be in [k, %d]", KWIN);
   if (!(opt.r >= 0.0 && opt.r <= 1.0)) return sa_fail(SA_EARG, "sa_create: r must be in [0, 1]");
   if (opt.decay != SA_DECAY_SOLVES && opt.decay != SA_DECAY_TIME) return sa_fail(SA_EARG, "sa_create: unknown decay");
+  if (opt.orthonormalize != 0 && opt.orthonormalize != 1) return sa_fail(SA_EARG, "sa_create: orthonormalize is 0 or 1");
+  if (opt.orthonormalize && opt.guess != SA_GUESS_RANGE)
+    return sa_fail(SA_EARG, "sa_create: orthonormalize applies to the range finder only");
   if (opt.decay == SA_DECAY_TIME && opt.guess != SA_GUESS_EWMA)
     return sa_fail(SA_EARG, "sa_create: SA_DECAY_TIME applies to the EWMA sketch only");
   if (opt.decay == SA_DECAY_TIME && !(opt.decay_dtau > 0.0 && isfinite(opt.decay_dtau)))
@@ -322,9 +325,12 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   // ILU(0): z in the phase scratch during the substitutions where it fits
   const bool ilu_lds = opt.precond == SA_PC_ILU0 && n <= ILU_LDS_MAX;
   if (ilu_lds && need_pc < (size_t)n) need_pc = (size_t)n;
+  // V = Q of the range finder: the sketch's Gram stages chunks of 512 elements of its k columns
+  const size_t need_qr = (opt.guess == SA_GUESS_RANGE && opt.orthonormalize) ? (size_t)k * 512 : 0;
   auto big_of = [&](size_t need_gram) {
     size_t big = need_op;
     if (need_gram > big) big = need_gram;
+    if (need_qr > big) big = need_qr;
     if (need_pc > big) big = need_pc;
     if (big < 2 * (size_t)BLOCK) big = 2 * (size_t)BLOCK;  // the Gram pass combines per-thread partials
     return big;
@@ -549,6 +555,7 @@ static int create_impl(const sa_grid* grid, const double* h, const sa_options* o
   P.Y[0] = (std::remove_reference_t<decltype(P.Y[0])>)(A + o_Y0); P.Y[1] = (std::remove_reference_t<decltype(P.Y[1])>)(A + o_Y1);
   P.Xr = (decltype(P.Xr))(A + o_Xr); P.Om = (decltype(P.Om))(A + o_Om); P.K = range ? opt.window : 0;
   P.k = k; P.m = m; P.max_restarts = opt.max_restarts; P.tau_drop = opt.tau_drop; P.txg = txg;
+  P.orth = opt.orthonormalize ? 1 : 0;
   P.partials = (decltype(P.partials))(A + o_part); P.bar = (decltype(P.bar))(A + o_bar); P.flags = (decltype(P.flags))(A + o_flags);
   P.log = (decltype(P.log))(A + o_log); P.G = G;
   p->dp = (Problem*)(A + o_prob);
@@ -802,7 +809,7 @@ struct StateHeader {
   char magic[8];
   int32_t version, guess, precision, k, window, nx, nz, bc;
   int64_t n, pushes, solves, log_pos;
-  int32_t unpushed, have_solution, decay, pad;
+  int32_t unpushed, have_solution, decay, orth;
   double r;
   uint64_t seed;
   double decay_dtau, t_unpushed, t_pushed;
@@ -839,7 +846,7 @@ extern "C" int sa_save_state(const sa_problem* pc, void* buf, size_t* len) {
   h.n = p->n; h.pushes = p->pushes; h.solves = p->solves; h.log_pos = p->log_pos;
   h.unpushed = p->unpushed ? 1 : 0; h.have_solution = p->have_solution ? 1 : 0;
   h.r = p->opt.r; h.seed = p->opt.seed;
-  h.decay = p->opt.decay; h.decay_dtau = p->opt.decay_dtau; h.t_unpushed = p->t_unpushed; h.t_pushed = p->t_pushed;
+  h.decay = p->opt.decay; h.decay_dtau = p->opt.decay_dtau; h.orth = p->opt.orthonormalize; h.t_unpushed = p->t_unpushed; h.t_pushed = p->t_pushed;
   char* out = (char*)buf;
   memcpy(out, &h, sizeof h);
   double* d = (double*)(out + sizeof h);
@@ -867,6 +874,7 @@ extern "C" int sa_load_state(sa_problem* p, const void* buf, size_t len) {
   if (h.n != p->n || h.nx != p->grid.nx || h.nz != p->grid.nz || h.bc != p->grid.bc || h.guess != p->opt.guess ||
       h.k != p->opt.k || (h.guess == SA_GUESS_RANGE && h.window != p->opt.window) || h.r != p->opt.r ||
       h.seed != p->opt.seed || h.precision != p->opt.precision || h.decay != p->opt.decay ||
+      h.orth != p->opt.orthonormalize ||
       (h.decay == SA_DECAY_TIME && h.decay_dtau != p->opt.decay_dtau))
     return sa_fail(SA_EARG, "sa_load_state: the state belongs to another grid or other options");
   if (len != sizeof h + state_doubles(p) * 8) return sa_fail(SA_EARG, "sa_load_state: truncated state");

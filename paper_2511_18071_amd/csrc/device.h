@@ -2124,6 +2124,154 @@ DEV int small_solve(const Problem& P, const double* red, double tau, double* z, 
   return rank;
 }
 
+// Gram V^T V of the range finder's sketch (V = X Omega, k columns of n) for its QR (V = Q):
+// chunks of CH elements of the k columns staged in LDS, the products exact and the sums
+// compensated as in phase_block_gram, items (pairs in row order) in red as hi, lo.
+DEV void phase_sketch_gram(const Problem& P, Cl& cl, const double* V, double* lds, double* red) {
+  constexpr int CH = 512;
+  const int k = P.k;
+  const size_t n = P.n;
+  const int npair = k * (k + 1) / 2;
+  const int Q = BLOCK / npair > 0 ? BLOCK / npair : 1;  // threads per item
+  const int item = threadIdx.x % npair, qq = threadIdx.x / npair;
+  const bool active = qq < Q;
+  int pa = 0, pb = 0;
+  {
+    int t = item, rowlen = k;
+    while (t >= rowlen) { t -= rowlen; ++pa; --rowlen; }
+    pb = pa + t;
+  }
+  double accS = 0.0, accC = 0.0;
+  for (size_t e0 = (size_t)cl.rank * CH; e0 < n; e0 += (size_t)cl.G * CH) {
+    const int cnt = (int)min((size_t)CH, n - e0);
+    for (int i = threadIdx.x; i < k * CH; i += BLOCK) {
+      const int c = i / CH, j = i - c * CH;
+      lds[i] = j < cnt ? V[(size_t)c * n + e0 + j] : 0.0;
+    }
+    __syncthreads();
+    if (active) {
+      const double* va = lds + pa * CH;
+      const double* vb = lds + pb * CH;
+      for (int p = qq; p < cnt; p += Q) {
+        const dd pr = two_prod(va[p], vb[p]);
+        const dd s = two_sum(accS, pr.hi);
+        accS = s.hi;
+        accC += s.lo + pr.lo;
+      }
+    }
+    __syncthreads();
+  }
+  double* sS = lds;
+  double* sC = lds + BLOCK;
+  sS[threadIdx.x] = active ? accS : 0.0;
+  sC[threadIdx.x] = active ? accC : 0.0;
+  __syncthreads();
+  if (threadIdx.x < npair) {
+    dd acc{0.0, 0.0};
+    for (int q = 0; q < Q; ++q) acc = dd_add(acc, quick_two_sum(sS[q * npair + threadIdx.x], sC[q * npair + threadIdx.x]));
+    red[2 * threadIdx.x] = acc.hi;
+    red[2 * threadIdx.x + 1] = acc.lo;
+  }
+  __syncthreads();
+}
+
+// The QR of the sketch from its Gram G: column scaling D = diag(G_aa)^-1/2, double-double
+// Cholesky L L^T = D G D taking columns in order and dropping a column whose pivot falls below
+// tau^2 (its projected unit norm below tau, the least squares' rule), then T = D L^-T over the
+// kept columns (zero columns for dropped ones), so that Q = V T has orthonormal columns. T
+// column-major (T[i + j k]) in t; every workgroup computes it from identical inputs.
+DEV void small_qr_factor(const Problem& P, const double* red, double tau, double* t, double* scr) {
+  const int k = P.k, tid = threadIdx.x;
+  double* gh = scr;            // k x k hi (lower part becomes L)
+  double* gl = gh + k * k;     // k x k lo
+  double* dsc = gl + k * k;    // k
+  int* kept = (int*)(dsc + k); // k
+  auto item = [&](int i, int j) {
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    return a * k - a * (a - 1) / 2 + (b - a);
+  };
+  if (tid < k) {
+    const double gii = red[2 * item(tid, tid)];
+    dsc[tid] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += BLOCK) {
+    const int i = e / k, j = e - i * k;
+    const int it = item(i, j);
+    const dd g = dd_mul_d(dd_mul_d(dd{red[2 * it], red[2 * it + 1]}, dsc[i]), dsc[j]);
+    gh[e] = g.hi;
+    gl[e] = g.lo;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      const dd d{gh[j * k + j], gl[j * k + j]};
+      const bool keep = dsc[j] > 0.0 && d.hi >= tau * tau;
+      kept[j] = keep;
+      const dd ljj = keep ? dd_sqrt(d) : dd{0.0, 0.0};
+      gh[j * k + j] = ljj.hi;
+      gl[j * k + j] = ljj.lo;
+    }
+    __syncthreads();
+    if (!kept[j]) continue;
+    const dd ljj{gh[j * k + j], gl[j * k + j]};
+    if (tid > j && tid < k) {
+      const dd lij = dd_div(dd{gh[tid * k + j], gl[tid * k + j]}, ljj);
+      gh[tid * k + j] = lij.hi;
+      gl[tid * k + j] = lij.lo;
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += BLOCK) {
+      const int i = e / k, l = e - i * k;
+      if (l > j && i >= l) {
+        const dd upd = dd_mul(dd{gh[i * k + j], gl[i * k + j]}, dd{gh[l * k + j], gl[l * k + j]});
+        const dd g = dd_sub(dd{gh[e], gl[e]}, upd);
+        gh[e] = g.hi;
+        gl[e] = g.lo;
+      }
+    }
+    __syncthreads();
+  }
+  // column j of L^-T (kept j): solve L^T y = e_j over the kept indices, y_i = 0 for i > j;
+  // one thread per column, back substitution from i = j down
+  if (tid < k) {
+    const int j = tid;
+    for (int i = 0; i < k; ++i) t[i + j * k] = 0.0;
+    if (kept[j]) {
+      dd y[KMAX];
+      for (int i = j; i >= 0; --i) {
+        if (!kept[i]) { y[i] = dd{0.0, 0.0}; continue; }
+        dd r = (i == j) ? dd{1.0, 0.0} : dd{0.0, 0.0};
+        for (int m = i + 1; m <= j; ++m)
+          if (kept[m]) r = dd_sub(r, dd_mul(dd{gh[m * k + i], gl[m * k + i]}, y[m]));
+        y[i] = dd_div(r, dd{gh[i * k + i], gl[i * k + i]});
+      }
+      for (int i = 0; i <= j; ++i) t[i + j * k] = kept[i] ? (y[i].hi + y[i].lo) * dsc[i] : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+// V <- V T in place, elementwise (T upper triangular, k x k column-major, in LDS)
+DEV void phase_apply_qr(const Problem& P, Cl& cl, double* V, const double* t) {
+  const int k = P.k;
+  const size_t n = P.n;
+  for (size_t e = (size_t)cl.rank * BLOCK + threadIdx.x; e < n; e += (size_t)cl.G * BLOCK) {
+    double v[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) v[c] = c < k ? V[(size_t)c * n + e] : 0.0;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      if (j < k) {
+        double q = 0.0;
+#pragma unroll
+        for (int i = 0; i <= j; ++i) q += v[i] * t[i + j * k];
+        V[(size_t)j * n + e] = q;
+      }
+    }
+  }
+}
+
 // x = Y z
 DEV void phase_sketch_combine(const Problem& P, Cl& cl, const double* Yn, const double* z) {
   const size_t n = P.n;
@@ -2203,6 +2351,14 @@ DEV bool solve_start(const Problem& P, Cl& cl, const SolveArgs& a, const Smem& S
     // block pass below then reads V as it is (no fused update)
     if (a.push || a.sketch_guess) {
       phase_range_form(P, cl, a, P.Y[0], S.big);
+      csync(cl);
+    }
+    if (P.orth && a.sketch_guess) {
+      // V = Q (Alg. 3's orthonormalised sketch): Gram, Cholesky with drop, V <- V D L^-T
+      phase_sketch_gram(P, cl, P.Y[0], S.big, S.red);
+      cluster_sum_dd(cl, S.red, P.k * (P.k + 1) / 2);
+      small_qr_factor(P, S.red, P.tau_drop, S.big, S.scr);
+      phase_apply_qr(P, cl, P.Y[0], S.big);
       csync(cl);
     }
     Yo = P.Y[0];

@@ -125,6 +125,7 @@ struct Problem {
   // sketch / options
   int k, m, max_restarts;
   int txg;                   // columns per tile of the block operator of the guess (16, 32, 64)
+  int orth;                  // range finder: V = Q, the orthonormalised sketch (Alg. 3)
   double tau_drop;
   int precision, max_refine;
   double rtol_inner;

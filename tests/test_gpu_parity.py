@@ -210,6 +210,12 @@ SOLVE_CASES = [
     ("periodic_65x9", dict(guess="range", window=8, k=8), 12, 3),
     ("bar_65x9", dict(guess="range", window=12, k=6), 16, 8),
     ("periodic_257x33", dict(guess="range", window=20, k=16), 16, None),
+    # Alg. 3 with V = Q, the orthonormalised sketch
+    ("tiny_17x7", dict(guess="range", window=6, k=3, orthonormalize=1), 10, 38),
+    ("periodic_65x9", dict(guess="range", window=8, k=8, orthonormalize=1), 12, 5),
+    ("bar_65x9", dict(guess="range", window=12, k=6, orthonormalize=1), 14, 22),
+    ("periodic_257x33", dict(guess="range", window=20, k=16, orthonormalize=1), 12, None),
+    ("bar_513x17", dict(guess="range", window=20, k=15, orthonormalize=1), 8, None),
     ("bar_513x17", dict(guess="range", window=20, k=15), 8, None),
     ("periodic_257x33", dict(), 24, None),
     ("periodic_257x33", dict(cluster=3), 12, None),

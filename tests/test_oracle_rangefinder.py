@@ -62,6 +62,26 @@ def test_q_and_sketch_give_the_same_guess():
     assert np.linalg.norm(out[0] - out[1]) <= 1e-10 * np.linalg.norm(out[1])
 
 
+def test_q_is_orthonormal_and_spans_the_sketch():
+    n = 60
+    xs = np.random.default_rng(5).standard_normal((9, n))
+    for K, k, pushed in ((8, 5, 9), (8, 6, 3)):
+        a = RangeFinder(n, K, k, seed=4)
+        q = RangeFinder(n, K, k, seed=4, orthonormalize=True)
+        for x in xs[:pushed]:
+            a.push(x)
+            q.push(x)
+        V, Q = a.basis(), q.basis()
+        # a window of fewer solutions than k gives that many columns, not rounding noise
+        assert Q.shape[1] == min(k, pushed)
+        assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() <= 1e-13
+        assert np.linalg.norm(V - Q @ (Q.T @ V)) <= 1e-12 * np.linalg.norm(V)
+        # ... and the same space as numpy's QR of the sketch when it has full rank
+        if pushed >= k:
+            Qn, _ = np.linalg.qr(V)
+            assert np.linalg.norm(Qn - Q @ (Q.T @ Qn)) <= 1e-12 * np.linalg.norm(Qn)
+
+
 def test_fischer_projection_when_k_equals_K():
     """Fixed A, k = K: span(X Omega) = span(X), so A x0 = argmin over span(A X) of ||. - b||."""
     w, g, A = _op()
