@@ -252,7 +252,9 @@ void sa_op3d_destroy(sa_op3d* op);
  * Sec. 1 does; after the solve u advances by K_u = alpha_i K_u + dtau (Q's force part -
  * grad^(i-1) (p_s + p_d)). Velocities live on every node of the
  * problem's grid (layout as sa_size), eta on its nx - 1 columns. The loop keeps a pointer to p
- * (which must outlive it) and works on p's stream. */
+ * (which must outlive it) and works on p's stream. With decay = SA_DECAY_TIME the loop labels
+ * the system of stage i of its n-th step (n from 0, counted since sa_loop_create) with the
+ * stage time (n + c_i) dtau of LSERK45 itself. */
 typedef struct sa_loop sa_loop;
 int sa_loop_create(sa_problem* p, double dtau, sa_loop** out);  /* SA_EARG: p not periodic, dtau <= 0 */
 /* eta (nx - 1), u, w (n values each) in `mem` memory; clears the Runge-Kutta registers; waits */

@@ -57,6 +57,9 @@ LSERK_A = [Fraction(0), Fraction(-567301805773, 1357537059087), Fraction(-240426
 LSERK_B = [Fraction(1432997174477, 9575080441755), Fraction(5161836677717, 13612068292357),
            Fraction(1720146321549, 2090206949498), Fraction(3134564353537, 4481467310338),
            Fraction(2277821191437, 14882151754819)]
+# stage times tau_n + c_i dtau
+LSERK_C = [Fraction(0), Fraction(1432997174477, 9575080441755), Fraction(2526269341429, 6820363962896),
+           Fraction(2006345519317, 3224310063776), Fraction(2802321613138, 2924317926251)]
 
 
 class ClosedLoop:
@@ -71,6 +74,7 @@ class ClosedLoop:
         self.u, self.w = np.array(u, dtype=np.float64), np.array(w, dtype=np.float64)
         self.dt = float(dtau)
         self.sim = sim
+        self.steps = 0  # completed steps: stage i of this step is at (steps + c_i) dtau
         self.Ku = np.zeros(grid.n)
         self.Kw = np.zeros(grid.n)
         self.Keta = np.zeros_like(self.eta)
@@ -116,7 +120,8 @@ class ClosedLoop:
         # the hydrostatic pressure under the previous stage's surface (zero on the surface)
         ps = G * (geo_p["d"][None, :] * (1.0 - g.sig[:, None])).reshape(-1)
         rhs = rhs - self.sim.operator(eta, eta_new) @ ps
-        res = self.sim.solve(eta, eta_new, rhs)
+        tau = (self.steps + float(LSERK_C[i])) * dt  # the system's time label (forgetting in time)
+        res = self.sim.solve(eta, eta_new, rhs, tau=tau if self.sim.opts.decay == "time" else None)
         p = res.x + ps
         self.Ku = a * self.Ku + dt * (rx - gx_p @ p)
         self.Kw = a * self.Kw + dt * (rz - gz_p @ p)
@@ -134,6 +139,7 @@ class ClosedLoop:
     def step(self):
         for i in range(5):
             self.stage(i)
+        self.steps += 1
 
 
 def linear_wave(grid: Grid, h: float, amp: float, kappa: float, t: float = 0.0):

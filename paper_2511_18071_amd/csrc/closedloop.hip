@@ -35,6 +35,9 @@ constexpr double LA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393
 constexpr double LB5[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
                            1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                            2277821191437.0 / 14882151754819.0};
+// stage times tau_n + c_i dtau (the time labels of the stage systems, for forgetting in time)
+constexpr double LC5[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                           2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
 
 struct LoopArgs {
   int ncol, nl, nz, n;
@@ -174,6 +177,7 @@ extern "C" __global__ void __launch_bounds__(LB) sa_loop_update_kernel(LoopArgs 
 struct sa_loop {
   sa_problem* p = nullptr;
   double dt = 0.0;
+  long long steps = 0;  // completed steps
   double* arena = nullptr;
   LoopArgs A{};
 };
@@ -262,6 +266,7 @@ extern "C" int sa_loop_step(sa_loop* L, sa_solve_info* infos) {
       HIPCHK(hipGetLastError());
       rc = sa_push_rhs(p, A.rhs, SA_MEM_DEVICE);
     }
+    if (rc == SA_OK && p->opt.decay == SA_DECAY_TIME) rc = sa_set_time(p, ((double)L->steps + LC5[s]) * L->dt);
     if (rc == SA_OK) rc = sa_solve(p, nullptr, SA_ASYNC);
     if (rc == SA_OK) rc = sa_get_solution_async(p, A.p);
     if (rc) return rc;
@@ -271,6 +276,7 @@ extern "C" int sa_loop_step(sa_loop* L, sa_solve_info* infos) {
     A.eta = A.eta_new;
     A.eta_new = t;
   }
+  L->steps += 1;
   // the five reports (the only wait of the step)
   sa_solve_info rep[5];
   int32_t got = 0;

@@ -57,7 +57,8 @@ def _pair(B, nx, nz, waves, eta, u, w, dt, **kw):
 CASES = [(33, 9, 1, 8, {}), (129, 17, 2, 4, {}),
          (33, 9, 1, 4, dict(precond="ilu0", guess="previous")),
          (33, 9, 1, 4, dict(guess="range", window=12)),
-         (33, 9, 1, 4, dict(precision="fp32_ir"))]
+         (33, 9, 1, 4, dict(precision="fp32_ir")),
+         (33, 9, 1, 4, dict(decay="time", decay_dtau=0.05))]
 
 
 @pytest.mark.parametrize("nx,nz,waves,steps,kw", CASES)
